@@ -1,0 +1,270 @@
+"""ctypes front end of the plain CPU oracle (``szsel_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py``.  The product package never imports it.
+
+The oracle follows arXiv:1806.08901 (Algorithm 1 with Sections 4 and 5) step by
+step in FP64; the conventions the paper leaves open are stated in the C source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "szsel_oracle.c")
+_LIB = os.path.join(_HERE, "libszsel_oracle.so")
+
+OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
+EB_ABS, EB_REL = 0, 1
+F32, F64 = 0, 1
+FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
+FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
+NBINS = 65536
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("flags", C.c_uint32), ("choice", C.c_int32),
+        ("vmin", C.c_double), ("vmax", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double),
+        ("minexp", C.c_int32), ("pad0", C.c_int32),
+        ("zfp_bitrate", C.c_double), ("zfp_mse", C.c_double), ("zfp_psnr", C.c_double),
+        ("zfp_nsb_mean", C.c_double), ("zfp_maxerr", C.c_double), ("zfp_sse", C.c_double),
+        ("zfp_bits", C.c_uint64), ("zfp_values", C.c_uint64), ("zfp_blocks", C.c_uint64),
+        ("zfp_nsb_total", C.c_uint64),
+        ("sz_delta", C.c_double), ("sz_inv_delta", C.c_double), ("sz_eb", C.c_double),
+        ("sz_entropy", C.c_double), ("sz_bitrate", C.c_double),
+        ("sz_psnr_model", C.c_double), ("sz_psnr_measured", C.c_double), ("sz_mse", C.c_double),
+        ("sz_maxerr", C.c_double), ("sz_sse", C.c_double),
+        ("sz_values", C.c_uint64), ("sz_unpredictable", C.c_uint64),
+        ("chosen_eb", C.c_double),
+    ]
+
+
+class Dump(C.Structure):
+    _fields_ = [
+        ("codes", C.c_void_p), ("zfp_bits", C.c_void_p), ("zfp_sse", C.c_void_p),
+        ("zfp_emax", C.c_void_p), ("sz_sse", C.c_void_p), ("hist", C.c_void_p),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        P, I64P, I32P = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+        L.orc_run.argtypes = [C.c_int, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
+                              C.c_double, C.POINTER(Result), C.POINTER(Dump)]
+        L.orc_range.argtypes = [P, C.c_int64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_num_sampled_blocks.argtypes = [I64P, C.c_int, I32P]
+        L.orc_num_sampled_blocks.restype = C.c_int64
+        L.orc_sampled_block_origin.argtypes = [I64P, C.c_int, I32P, C.c_int64, I64P]
+        L.orc_frexp_exponent.argtypes = [C.c_double]
+        L.orc_floor_log2.argtypes = [C.c_double]
+        L.orc_precision.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        for f in ("orc_fwd_lift", "orc_inv_lift"):
+            getattr(L, f).argtypes = [I64P, C.c_ssize_t, C.c_int]
+        for f in ("orc_fwd_xform", "orc_inv_xform"):
+            getattr(L, f).argtypes = [I64P, C.c_int, C.c_int]
+        L.orc_reorder_table.argtypes = [C.c_int, I32P]
+        L.orc_to_negabinary.argtypes = [C.c_int64, C.c_int]
+        L.orc_to_negabinary.restype = C.c_uint64
+        L.orc_from_negabinary.argtypes = [C.c_uint64, C.c_int]
+        L.orc_from_negabinary.restype = C.c_int64
+        L.orc_encode_planes.argtypes = [C.POINTER(C.c_uint64), C.c_int, C.c_int, C.c_int,
+                                        C.POINTER(C.c_uint8), C.c_int64]
+        L.orc_encode_planes.restype = C.c_int64
+        L.orc_zfp_block.argtypes = [C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]
+        L.orc_zfp_block.restype = C.c_uint32
+        L.orc_lorenzo.argtypes = [P, I64P, C.c_int, C.c_int, I64P]
+        L.orc_lorenzo.restype = C.c_double
+        L.orc_tree_sum.argtypes = [C.POINTER(C.c_double), C.c_int64]
+        L.orc_tree_sum.restype = C.c_double
+        L.orc_entropy.argtypes = [C.POINTER(C.c_uint32), C.c_int64, C.c_uint64]
+        L.orc_entropy.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _dtype_code(a: np.ndarray) -> int:
+    if a.dtype == np.float32:
+        return F32
+    if a.dtype == np.float64:
+        return F64
+    raise TypeError("oracle fields are float32 or float64, got %s" % a.dtype)
+
+
+def result_dict(r: Result) -> dict:
+    return {name: getattr(r, name) for name, _ in Result._fields_ if name != "pad0"}
+
+
+def run(op: int, field: np.ndarray, eb: float, eb_mode: int = EB_REL, stride=None,
+        sz_offset: float = 0.5, dump: bool = False):
+    """Run the estimator on a C-order numpy field.  Returns (result dict, dump dict|None)."""
+    field = np.ascontiguousarray(field)
+    nd = field.ndim
+    dims = np.array(field.shape, dtype=np.int64)
+    st = np.array(stride if stride is not None else [1] * nd, dtype=np.int32)
+    if st.shape != (nd,):
+        raise ValueError("stride needs one entry per axis")
+    out = Result()
+    dp = None
+    arrays = None
+    if dump:
+        nblk = num_sampled_blocks(field.shape, st)
+        size = 4 ** nd
+        arrays = {
+            "codes": np.zeros(nblk * size, np.uint16),
+            "zfp_bits": np.zeros(nblk, np.uint32),
+            "zfp_sse": np.zeros(nblk, np.float64),
+            "zfp_emax": np.zeros(nblk, np.int32),
+            "sz_sse": np.zeros(nblk, np.float64),
+            "hist": np.zeros(NBINS, np.uint32),
+        }
+        dp = Dump(*[arrays[k].ctypes.data for k, _ in Dump._fields_])
+    rc = lib().orc_run(op, field.ctypes.data, _ptr(dims, C.c_int64), nd, _dtype_code(field),
+                       float(eb), eb_mode, _ptr(st, C.c_int32), float(sz_offset), C.byref(out),
+                       C.byref(dp) if dp is not None else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return result_dict(out), arrays
+
+
+def select(field, eb, eb_mode=EB_REL, stride=None, sz_offset=0.5, dump=False):
+    return run(OP_SELECT, field, eb, eb_mode, stride, sz_offset, dump)
+
+
+# ---- pieces for the pin tests ----
+
+def value_range(field: np.ndarray):
+    field = np.ascontiguousarray(field)
+    lo, hi = C.c_double(), C.c_double()
+    bad = lib().orc_range(field.ctypes.data, field.size, _dtype_code(field), C.byref(lo), C.byref(hi))
+    return bool(bad), lo.value, hi.value
+
+
+def num_sampled_blocks(shape, stride) -> int:
+    d = np.array(shape, np.int64)
+    s = np.array(stride, np.int32)
+    return int(lib().orc_num_sampled_blocks(_ptr(d, C.c_int64), len(shape), _ptr(s, C.c_int32)))
+
+
+def sampled_block_origin(shape, stride, j):
+    d = np.array(shape, np.int64)
+    s = np.array(stride, np.int32)
+    o = np.zeros(len(shape), np.int64)
+    lib().orc_sampled_block_origin(_ptr(d, C.c_int64), len(shape), _ptr(s, C.c_int32), j,
+                                   _ptr(o, C.c_int64))
+    return tuple(int(v) for v in o)
+
+
+def frexp_exponent(m: float) -> int:
+    return lib().orc_frexp_exponent(m)
+
+
+def floor_log2(t: float) -> int:
+    return lib().orc_floor_log2(t)
+
+
+def precision(emax, minexp, nd, W) -> int:
+    return lib().orc_precision(emax, minexp, nd, W)
+
+
+def fwd_lift(v, W=32):
+    a = np.array(v, np.int64)
+    lib().orc_fwd_lift(_ptr(a, C.c_int64), 1, W)
+    return a
+
+
+def inv_lift(v, W=32):
+    a = np.array(v, np.int64)
+    lib().orc_inv_lift(_ptr(a, C.c_int64), 1, W)
+    return a
+
+
+def fwd_xform(c, nd, W=32):
+    a = np.array(c, np.int64).reshape(-1).copy()
+    lib().orc_fwd_xform(_ptr(a, C.c_int64), nd, W)
+    return a
+
+
+def inv_xform(c, nd, W=32):
+    a = np.array(c, np.int64).reshape(-1).copy()
+    lib().orc_inv_xform(_ptr(a, C.c_int64), nd, W)
+    return a
+
+
+def reorder_table(nd):
+    p = np.zeros(4 ** nd, np.int32)
+    lib().orc_reorder_table(nd, _ptr(p, C.c_int32))
+    return p
+
+
+def to_negabinary(c: int, W=32) -> int:
+    return int(lib().orc_to_negabinary(int(c), W))
+
+
+def from_negabinary(u: int, W=32) -> int:
+    return int(lib().orc_from_negabinary(int(u), W))
+
+
+def encode_planes(u, W, prec, want_bits=False):
+    a = np.array(u, np.uint64)
+    if want_bits:
+        cap = 64 * (2 * len(a) + 2)
+        bits = np.zeros(cap, np.uint8)
+        n = lib().orc_encode_planes(_ptr(a, C.c_uint64), len(a), W, prec, _ptr(bits, C.c_uint8), cap)
+        return int(n), bits[:n].copy()
+    return int(lib().orc_encode_planes(_ptr(a, C.c_uint64), len(a), W, prec, None, 0))
+
+
+def zfp_block(x, nd, dtype, minexp):
+    xv = np.array(x, np.float64).reshape(-1)
+    xh = np.zeros_like(xv)
+    sse, nsb, emax = C.c_double(), C.c_uint64(), C.c_int32()
+    bits = lib().orc_zfp_block(_ptr(xv, C.c_double), nd, dtype, minexp, _ptr(xh, C.c_double),
+                               C.byref(sse), C.byref(nsb), C.byref(emax))
+    return int(bits), xh, sse.value, int(nsb.value), int(emax.value)
+
+
+def lorenzo(field: np.ndarray, p):
+    field = np.ascontiguousarray(field)
+    d = np.array(field.shape, np.int64)
+    pp = np.array(p, np.int64)
+    return lib().orc_lorenzo(field.ctypes.data, _ptr(d, C.c_int64), field.ndim, _dtype_code(field),
+                             _ptr(pp, C.c_int64))
+
+
+def tree_sum(a) -> float:
+    v = np.ascontiguousarray(a, np.float64)
+    return lib().orc_tree_sum(_ptr(v, C.c_double), len(v))
+
+
+def entropy(hist, n=None) -> float:
+    h = np.ascontiguousarray(hist, np.uint32)
+    if n is None:
+        n = int(h.sum())
+    return lib().orc_entropy(_ptr(h, C.c_uint32), len(h), n)

@@ -1,0 +1,523 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed form
+from the paper, an exact algebraic identity, a library routine, a brute force
+on tiny inputs, or an independent procedure (e.g. a decoder of the emitted bit
+stream).  None of these call the HIP path.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+import oracle
+
+
+# ---------------------------------------------------------------------------
+# O1: value range (Algorithm 1, line 2)
+# ---------------------------------------------------------------------------
+
+def test_range_matches_numpy():
+    rng = np.random.default_rng(0)
+    for dt in (np.float32, np.float64):
+        x = (rng.standard_normal(10007) * 1e3).astype(dt)
+        bad, lo, hi = oracle.value_range(x)
+        assert not bad
+        assert lo == float(x.min()) and hi == float(x.max())
+
+
+@pytest.mark.parametrize("bad_value", [np.nan, np.inf, -np.inf])
+def test_range_flags_nonfinite(bad_value):
+    x = np.ones((8, 8), np.float32)
+    x[3, 5] = bad_value
+    r, _ = oracle.select(x, 1e-3)
+    assert r["flags"] & oracle.FLAG_NONFINITE
+    assert r["choice"] == -1
+
+
+# ---------------------------------------------------------------------------
+# O2: block sampling lattice (Section 4.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,stride", [((17, 9, 13), (2, 1, 3)), ((8, 23), (3, 1)), ((30,), (4,)),
+                                          ((12, 12, 12), (1, 1, 1))])
+def test_sampling_matches_brute_force(shape, stride):
+    nb = [n // 4 for n in shape]
+    brute = [tuple(4 * b for b in idx) for idx in itertools.product(*[range(n) for n in nb])
+             if all(b % s == 0 for b, s in zip(idx, stride))]
+    n = oracle.num_sampled_blocks(shape, stride)
+    assert n == len(brute)
+    assert [oracle.sampled_block_origin(shape, stride, j) for j in range(n)] == brute
+
+
+def test_sampling_counts_of_the_workloads():
+    # 512^3 at stride (5,4,1): 26 * 32 * 128 blocks, about 5% of 128^3
+    assert oracle.num_sampled_blocks((512, 512, 512), (5, 4, 1)) == 106496
+    # 1800 x 3600 at stride (20,1): 23 * 900 blocks, about 5% of 450 * 900
+    assert oracle.num_sampled_blocks((1800, 3600), (20, 1)) == 20700
+
+
+# ---------------------------------------------------------------------------
+# O3: exponents and block-floating-point
+# ---------------------------------------------------------------------------
+
+def test_exponent_matches_math_frexp():
+    rng = np.random.default_rng(1)
+    vals = list(np.abs(rng.standard_normal(2000)) * 10.0 ** rng.integers(-300, 300, 2000))
+    vals += [5e-324, 1e-310, 2.0 ** -1022, 1.0, 0.5, 2.0, 3.0, 1.7976931348623157e308,
+             float(np.float32(1e-45)), float(np.finfo(np.float32).tiny)]
+    for v in vals:
+        assert oracle.frexp_exponent(v) == math.frexp(v)[1]
+
+
+def test_floor_log2_brackets_tau():
+    rng = np.random.default_rng(2)
+    for t in list(10.0 ** rng.uniform(-300, 300, 2000)) + [1.0, 2.0, 0.25, 3.0, 5e-324]:
+        e = oracle.floor_log2(t)
+        assert math.ldexp(1.0, e) <= t < math.ldexp(1.0, e + 1)
+
+
+def test_bfp_is_exact_at_full_precision():
+    # At prec = W and a block whose values need at most P bits below 2^emax,
+    # conversion, transform, coding and decoding return the values exactly.
+    rng = np.random.default_rng(3)
+    for nd in (1, 2, 3):
+        for _ in range(50):
+            ints = rng.integers(-2 ** 20, 2 ** 20, 4 ** nd)
+            x = ints.astype(np.float64) * 2.0 ** -10
+            bits, xh, sse, nsb, emax = oracle.zfp_block(x, nd, oracle.F64, -1074)
+            assert np.array_equal(x, xh) and sse == 0.0
+
+
+# ---------------------------------------------------------------------------
+# O4: the decorrelating transform (Section 4.2, separable application)
+# ---------------------------------------------------------------------------
+
+A16 = np.array([[4, 4, 4, 4], [5, 1, -1, -5], [-4, 4, 4, -4], [-2, 6, -6, 2]], dtype=object)
+
+
+def _kron_power(nd):
+    m = np.array([[1]], dtype=object)
+    for _ in range(nd):
+        m = np.kron(m, A16)
+    return m
+
+
+@pytest.mark.parametrize("nd", [1, 2, 3])
+def test_lifting_equals_matrix_on_multiples_of_16(nd):
+    rng = np.random.default_rng(4 + nd)
+    M = _kron_power(nd)
+    scale = 16 ** nd
+    for _ in range(200):
+        x = rng.integers(-2 ** 29 // scale, 2 ** 29 // scale, 4 ** nd) * scale
+        want = M.dot(np.array([int(v) for v in x], dtype=object))
+        assert all(w % scale == 0 for w in want)
+        want = np.array([int(w // scale) for w in want])
+        for W in (32, 64):
+            assert np.array_equal(oracle.fwd_xform(x, nd, W), want)
+
+
+def test_inverse_then_forward_is_identity_exhaustive_small():
+    rng = np.random.default_rng(6)
+    for y in itertools.product(range(-6, 6), repeat=4):
+        assert list(oracle.fwd_lift(oracle.inv_lift(y))) == list(y)
+    for nd in (2, 3):
+        for _ in range(300):
+            y = rng.integers(-2 ** 26, 2 ** 26, 4 ** nd)
+            assert np.array_equal(oracle.fwd_xform(oracle.inv_xform(y, nd), nd), y)
+
+
+def test_forward_then_inverse_loses_only_low_bits():
+    # Each halving drops one low bit; the loss compounds over the d axes but
+    # stays a few units, against values of magnitude up to 2^29.
+    rng = np.random.default_rng(7)
+    for nd, bound in ((1, 3), (2, 12), (3, 40)):
+        worst = 0
+        for _ in range(500):
+            x = rng.integers(-2 ** 29, 2 ** 29, 4 ** nd)
+            worst = max(worst, int(np.abs(oracle.inv_xform(oracle.fwd_xform(x, nd), nd) - x).max()))
+        assert worst <= bound
+
+
+def test_constant_block_has_only_dc():
+    for nd in (1, 2, 3):
+        for v in (-12345, 0, 7, 2 ** 29 - 1):
+            c = oracle.fwd_xform(np.full(4 ** nd, v), nd)
+            assert c[0] == v and not c[1:].any()
+
+
+def test_transform_is_not_orthogonal():
+    # The paper's L2-invariance argument (Eq. 4, Theorem 1) needs an orthogonal
+    # matrix; ZFP's matrix is not (rows 2 and 4 are not orthogonal), which is
+    # why the error is measured after decoding, in the data domain.
+    A = np.array(A16, dtype=float) / 16.0
+    assert not np.allclose(A @ A.T, np.diag(np.diag(A @ A.T)))
+
+
+@pytest.mark.parametrize("t", [0.0, 0.25, 2 / math.pi * math.atan(1 / 3), 2 / math.pi * math.atan(0.5), 0.5])
+def test_parametric_bot_family_preserves_l2(t):
+    # Section 4.2: T(t) is orthogonal for every t, so ||T X||_2 = ||X||_2 (Eq. 4).
+    s, c = math.sqrt(2) * math.sin(math.pi / 2 * t), math.sqrt(2) * math.cos(math.pi / 2 * t)
+    T = 0.5 * np.array([[1, 1, 1, 1], [c, s, -s, -c], [1, -1, -1, 1], [s, -c, c, -s]])
+    X = np.random.default_rng(8).standard_normal((4, 16))
+    assert np.allclose(T @ T.T, np.eye(4))
+    assert math.isclose(np.linalg.norm(T @ X), np.linalg.norm(X), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# O5/O6: reorder and negabinary
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nd", [1, 2, 3])
+def test_reorder_is_a_sequency_order(nd):
+    p = oracle.reorder_table(nd)
+    assert sorted(p) == list(range(4 ** nd))
+    seq = [sum((int(i) >> (2 * a)) & 3 for a in range(nd)) for i in p]
+    assert seq == sorted(seq) and p[0] == 0 and p[-1] == 4 ** nd - 1
+
+
+def _negabinary_value(u, W):
+    return sum(((u >> k) & 1) * (-2) ** k for k in range(W))
+
+
+def test_negabinary_digits_reproduce_the_integer():
+    rng = np.random.default_rng(9)
+    vals = list(range(-70000, 70000, 7)) + [int(v) for v in rng.integers(-2 ** 30, 2 ** 30, 2000)]
+    for c in vals:
+        for W in (32, 64):
+            u = oracle.to_negabinary(c, W)
+            assert _negabinary_value(u, W) == c
+            assert oracle.from_negabinary(u, W) == c
+
+
+def test_negabinary_is_a_bijection_on_low_words():
+    seen = {}
+    for c in range(-2 ** 15, 2 ** 15):
+        u = oracle.to_negabinary(c, 32)
+        assert u not in seen
+        seen[u] = c
+
+
+# ---------------------------------------------------------------------------
+# O7: group-testing embedded coder (Section 5.2)
+# ---------------------------------------------------------------------------
+
+def _closed_form_cost(masks, size):
+    """Per-plane cost from popcount / highest set bit only (derived by hand from
+    the coder's definition; independent of the emitting loop)."""
+    total, acc = 0, 0
+    for m in masks:
+        n = acc.bit_length()  # 1 + msb of the planes coded so far
+        rest = m >> n
+        if rest == 0:
+            total += n + (1 if n < size else 0)
+        else:
+            p = m.bit_length() - 1
+            total += p + 1 + bin(rest).count("1") + (1 if p < size - 1 else -1)
+        acc |= m
+    return total
+
+
+def _decode(bits, size, nplanes):
+    """Reads the emitted stream back into per-plane masks."""
+    it = iter(bits)
+    masks, n = [], 0
+    for _ in range(nplanes):
+        plane = [0] * size
+        for i in range(n):
+            plane[i] = next(it)
+        pos = n
+        while pos < size:
+            if not next(it):
+                break
+            while pos < size - 1:
+                if next(it):
+                    break
+                pos += 1
+            plane[pos] = 1
+            pos += 1
+            n = pos
+        masks.append(sum(b << i for i, b in enumerate(plane)))
+    return masks
+
+
+def _values_from_masks(masks, size, W):
+    u = [0] * size
+    for j, m in enumerate(masks):
+        k = W - 1 - j
+        for i in range(size):
+            if (m >> i) & 1:
+                u[i] |= 1 << k
+    return u
+
+
+def _masks_from_values(u, W, nplanes):
+    return [sum(((int(v) >> (W - 1 - j)) & 1) << i for i, v in enumerate(u)) for j in range(nplanes)]
+
+
+def test_coder_exhaustive_four_values():
+    size, W = 4, 32
+    for nplanes in (1, 2, 3):
+        for code in range(1 << (size * nplanes)):
+            masks = [(code >> (size * j)) & 0xF for j in range(nplanes)]
+            u = _values_from_masks(masks, size, W)
+            nbits, bits = oracle.encode_planes(u, W, nplanes, want_bits=True)
+            assert nbits == _closed_form_cost(masks, size)
+            assert _decode([int(b) for b in bits], size, nplanes) == masks
+
+
+@pytest.mark.parametrize("size", [16, 64])
+def test_coder_random_masks(size):
+    rng = np.random.default_rng(10 + size)
+    for W in (32, 64):
+        for _ in range(400):
+            nplanes = int(rng.integers(1, 12))
+            dens = rng.random()
+            masks = [int(sum(int(b) << i for i, b in enumerate(rng.random(size) < dens ** (j + 1))))
+                     for j in range(nplanes)]
+            u = _values_from_masks(masks, size, W)
+            nbits, bits = oracle.encode_planes(u, W, nplanes, want_bits=True)
+            assert nbits == _closed_form_cost(masks, size)
+            assert _decode([int(b) for b in bits], size, nplanes) == masks
+
+
+def test_coder_is_embedded():
+    # Each extra plane appends to the stream (the embedded property): the cost
+    # of prec planes is the cost of prec-1 planes plus that plane's cost.
+    rng = np.random.default_rng(12)
+    u = [int(v) for v in rng.integers(0, 2 ** 32, 64, dtype=np.uint64)]
+    prev = 0
+    for prec in range(1, 33):
+        cur = oracle.encode_planes(u, 32, prec)
+        assert cur >= prev
+        _, bits = oracle.encode_planes(u, 32, prec, want_bits=True)
+        _, pbits = oracle.encode_planes(u, 32, prec - 1, want_bits=True) if prec > 1 else (0, np.zeros(0))
+        assert np.array_equal(bits[:len(pbits)], pbits)
+        prev = cur
+
+
+def test_full_precision_round_trip_of_block_coefficients():
+    # Encoding all W planes and decoding the stream gives every coefficient back.
+    rng = np.random.default_rng(13)
+    for nd in (2, 3):
+        size = 4 ** nd
+        for _ in range(20):
+            c = rng.integers(-2 ** 29, 2 ** 29, size)
+            y = oracle.fwd_xform(c, nd)
+            perm = oracle.reorder_table(nd)
+            u = [oracle.to_negabinary(int(y[p]), 32) for p in perm]
+            nbits, bits = oracle.encode_planes(u, 32, 32, want_bits=True)
+            back = _values_from_masks(_decode([int(b) for b in bits], size, 32), size, 32)
+            assert back == u
+
+
+# ---------------------------------------------------------------------------
+# O8: ZFP block decode and error (fixed-accuracy design bound)
+# ---------------------------------------------------------------------------
+
+def test_empty_and_zero_precision_blocks_cost_one_bit():
+    for nd in (1, 2, 3):
+        bits, xh, sse, nsb, emax = oracle.zfp_block(np.zeros(4 ** nd), nd, oracle.F32, -10)
+        assert bits == 1 and not xh.any() and sse == 0.0
+        x = np.full(4 ** nd, 1e-9)  # far below the tolerance 2^10
+        bits, xh, sse, nsb, emax = oracle.zfp_block(x, nd, oracle.F64, 10)
+        assert bits == 1 and not xh.any() and math.isclose(sse, 4 ** nd * 1e-18)
+
+
+def test_zfp_error_within_tolerance_when_precision_is_not_clamped():
+    rng = np.random.default_rng(14)
+    for nd in (1, 2, 3):
+        for trial in range(400):
+            size = 4 ** nd
+            kind = trial % 4
+            if kind == 0:
+                x = rng.standard_normal(size)
+            elif kind == 1:
+                x = np.cumsum(rng.standard_normal(size))
+            elif kind == 2:
+                x = rng.standard_normal(size) * 10.0 ** rng.integers(-5, 5, size)
+            else:
+                x = np.sin(np.arange(size) * rng.random()) + 1e-3 * rng.standard_normal(size)
+            for dt, W in ((oracle.F32, 32), (oracle.F64, 64)):
+                xv = x.astype(np.float32).astype(np.float64) if dt == oracle.F32 else x
+                for tau in (1e-1, 1e-3, 1e-5, 1e-7, 1e-10):
+                    me = oracle.floor_log2(tau)
+                    bits, xh, sse, nsb, emax = oracle.zfp_block(xv, nd, dt, me)
+                    if oracle.precision(emax, me, nd, W) < W:
+                        assert np.abs(xv - xh).max() <= tau
+
+
+def test_zfp_block_sse_is_sum_of_squared_errors():
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal(64)
+    bits, xh, sse, nsb, emax = oracle.zfp_block(x, 3, oracle.F64, oracle.floor_log2(1e-3))
+    assert math.isclose(sse, float(np.sum((x - xh) ** 2)), rel_tol=1e-12)
+    assert emax == math.frexp(np.abs(x).max())[1]
+
+
+# ---------------------------------------------------------------------------
+# O11: Lorenzo prediction (Section 4.1) -- d = mixed backward difference
+# ---------------------------------------------------------------------------
+
+def _mixed_backward_difference(X):
+    P = np.pad(X.astype(np.float64), [(1, 0)] * X.ndim)
+    for ax in range(X.ndim):
+        P = np.diff(P, axis=ax)
+    return P
+
+
+@pytest.mark.parametrize("shape", [(9,), (7, 6), (5, 6, 7)])
+def test_lorenzo_residual_is_mixed_difference_of_zero_padded_field(shape):
+    rng = np.random.default_rng(16)
+    X = rng.integers(-1000, 1000, shape).astype(np.float64)
+    D = _mixed_backward_difference(X)
+    for p in itertools.product(*[range(n) for n in shape]):
+        assert X[p] - oracle.lorenzo(X, p) == D[p]
+
+
+def test_lorenzo_linear_field_exact_where_at_most_d_minus_2_coordinates_are_zero():
+    for nd, coef in ((2, (3, -5, 7)), (3, (3, -5, 7, 11))):
+        shape = (6,) * nd
+        grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+        X = coef[-1] + sum(c * g for c, g in zip(coef, grids))
+        X = X.astype(np.float32)
+        for p in itertools.product(*[range(n) for n in shape]):
+            zeros = sum(1 for v in p if v == 0)
+            d = float(X[p]) - oracle.lorenzo(X, p)
+            if zeros <= nd - 2:
+                assert d == 0.0
+            else:
+                assert d != 0.0
+
+
+def test_lorenzo_trilinear_monomial_residual():
+    # d = Dx Dy Dz (x y z) = 1 at every interior point
+    g = np.meshgrid(*[np.arange(6.0)] * 3, indexing="ij")
+    X = g[0] * g[1] * g[2]
+    for p in itertools.product(range(1, 6), repeat=3):
+        assert X[p] - oracle.lorenzo(X, p) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# O12-O13: quantization codes and histogram (Section 5.1.4)
+# ---------------------------------------------------------------------------
+
+def test_hand_computed_codes_at_ties_and_escapes():
+    # 1-D, eb_abs = 0.5 so delta = 1 (SZ's delta = 2 eb).  Residuals are
+    # X[i] - X[i-1]; ties round away from zero.
+    X = np.array([0.0, 2.5, 0.0, 0.5, -32766.6, 0.0, 40000.0, 40000.0], np.float64)
+    r, dmp = oracle.run(oracle.OP_SZ, X, 0.5, oracle.EB_ABS, (1,), dump=True)
+    # residuals: 0, 2.5, -2.5, 0.5, -32767.1, 32766.6, 40000, 0
+    want = [32768, 32768 + 3, 32768 - 3, 32768 + 1, 32768 - 32767, 32768 + 32767, 0, 32768]
+    assert list(dmp["codes"]) == want
+    assert r["sz_unpredictable"] == 1
+    assert r["sz_delta"] == 1.0 and r["sz_eb"] == 0.5
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_sz_error_bound_and_histogram(dt):
+    from paper_1806_08901_amd import synth
+    X = synth.gaussian_bumps((24, 20, 28), seed=5).numpy().astype(dt)
+    for op in (oracle.OP_SZ, oracle.OP_SELECT):
+        r, dmp = oracle.run(op, X, 1e-4, oracle.EB_REL, (2, 1, 1), dump=True)
+        assert r["sz_maxerr"] <= r["sz_eb"]
+        assert np.array_equal(dmp["hist"], np.bincount(dmp["codes"], minlength=65536))
+        assert int(dmp["hist"].sum()) == r["sz_values"] == r["zfp_values"] or op == oracle.OP_SZ
+        assert dmp["hist"][0] == r["sz_unpredictable"]
+
+
+# ---------------------------------------------------------------------------
+# O14: entropy (Eq. 5; Eq. 9 reduces to Eq. 5 on the code histogram)
+# ---------------------------------------------------------------------------
+
+def test_entropy_closed_forms():
+    h = np.zeros(65536, np.uint32)
+    h[100] = 7
+    assert oracle.entropy(h) == 0.0
+    h[:] = 0
+    h[[5, 6, 7]] = [2, 1, 1]
+    assert oracle.entropy(h) == 1.5
+    for K in (2, 3, 7, 64, 1000, 65535):
+        h[:] = 0
+        h[:K] = 13
+        assert math.isclose(oracle.entropy(h), math.log2(K), rel_tol=1e-14)
+
+
+def test_entropy_matches_scipy_and_eq9():
+    rng = np.random.default_rng(17)
+    h = np.zeros(65536, np.uint32)
+    idx = 32768 + np.round(rng.standard_normal(200000) * 40).astype(int)
+    np.add.at(h, idx, 1)
+    n = int(h.sum())
+    H = oracle.entropy(h)
+    assert math.isclose(H, scipy.stats.entropy(h.astype(float), base=2), rel_tol=1e-12)
+    # Eq. 9 with P(m_i) = h_i / (n delta): -delta sum P log2 P - log2 delta
+    for delta in (1e-3, 0.5, 7.0):
+        P = h[h > 0] / (n * delta)
+        br9 = -delta * float(np.sum(P * np.log2(P))) - math.log2(delta)
+        assert math.isclose(H, br9, rel_tol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# O10, O15, O16: PSNR model and the selection (Eq. 10, Eq. 11, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("eb_rel", [1e-2, 1e-3, 1e-4, 1e-5, 1e-6])
+def test_sz_psnr_model_is_eq11(eb_rel):
+    from paper_1806_08901_amd import synth
+    X = synth.gaussian_bumps((16, 16, 16), seed=6).numpy()
+    r, _ = oracle.run(oracle.OP_SZ, X, eb_rel, oracle.EB_REL, (1, 1, 1))
+    assert math.isclose(r["sz_psnr_model"], -20 * math.log10(eb_rel) + 10 * math.log10(3), rel_tol=1e-12)
+
+
+def test_select_delta_matches_zfp_psnr():
+    from paper_1806_08901_amd import synth
+    X = synth.spectral((32, 32, 32), seed=7).numpy()
+    for eb in (1e-2, 1e-4, 1e-6):
+        r, _ = oracle.select(X, eb, stride=(2, 2, 1))
+        assert math.isclose(r["sz_psnr_model"], r["zfp_psnr"], rel_tol=1e-12)
+        assert r["choice"] == (0 if r["sz_bitrate"] < r["zfp_bitrate"] else 1)
+        assert r["chosen_eb"] == (r["sz_eb"] if r["choice"] == 0 else r["eb_abs"])
+
+
+def test_measured_sz_psnr_follows_uniform_error_model():
+    # Section 5.1.2: with many occupied bins the quantization error is uniform
+    # on [-delta/2, delta/2], MSE = delta^2/12.
+    rng = np.random.default_rng(18)
+    X = rng.standard_normal((32, 32, 32)).astype(np.float64)
+    r, _ = oracle.run(oracle.OP_SZ, X, 1e-4, oracle.EB_REL, (1, 1, 1))
+    assert abs(r["sz_psnr_measured"] - r["sz_psnr_model"]) < 0.1
+
+
+def test_degenerate_fields():
+    c = np.full((8, 8, 8), 3.25, np.float32)
+    r, _ = oracle.select(c, 1e-3)
+    assert r["flags"] & oracle.FLAG_CONSTANT and r["choice"] == 0
+    r, _ = oracle.select(np.arange(27, dtype=np.float32).reshape(3, 3, 3), 1e-3)
+    assert r["flags"] & oracle.FLAG_NO_BLOCKS and r["choice"] == 0
+    # piecewise constant per 4^3 block: ZFP decodes exactly, MSE = 0
+    blocks = np.arange(8, dtype=np.float32).reshape(2, 2, 2)
+    pc = np.kron(blocks, np.ones((4, 4, 4), np.float32))
+    r, _ = oracle.select(pc, 1e-3)
+    assert r["zfp_mse"] == 0.0 and r["flags"] & oracle.FLAG_ZERO_MSE
+    assert r["sz_delta"] == 2 * r["eb_abs"]
+    r, _ = oracle.select(np.linspace(0, 1e-10, 512).reshape(8, 8, 8), 1e-320)
+    assert r["flags"] & oracle.FLAG_BAD_EB
+
+
+def test_dumps_are_consistent_with_totals():
+    from paper_1806_08901_amd import synth
+    X = synth.gaussian_bumps((16, 20, 24), seed=8).numpy()
+    r, d = oracle.select(X, 1e-4, stride=(1, 2, 1), dump=True)
+    assert int(d["zfp_bits"].sum()) == r["zfp_bits"]
+    assert oracle.tree_sum(d["zfp_sse"]) == r["zfp_sse"]
+    assert oracle.tree_sum(d["sz_sse"]) == r["sz_sse"]
+
+
+def test_tree_sum_association():
+    a = [1e16, 1.0, -1e16, 1.0, 3.0]
+    # ((1e16 + 1) + (-1e16 + 1)) + (3 + 0) in binary64
+    assert oracle.tree_sum(a) == ((1e16 + 1.0) + (-1e16 + 1.0)) + 3.0
+    assert oracle.tree_sum([]) == 0.0
