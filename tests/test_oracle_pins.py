@@ -178,6 +178,17 @@ def test_reorder_is_a_sequency_order(nd):
     assert seq == sorted(seq) and p[0] == 0 and p[-1] == 4 ** nd - 1
 
 
+@pytest.mark.parametrize("nd", [1, 2, 3])
+def test_reorder_follows_the_stated_key(nd):
+    # Ascending (total sequency, sum of squared frequencies, slowest-axis
+    # frequency, ..., fastest-axis frequency).
+    def key(i):
+        f = [(int(i) >> (2 * a)) & 3 for a in range(nd)]
+        return (sum(f), sum(v * v for v in f)) + tuple(reversed(f))
+    keys = [key(i) for i in oracle.reorder_table(nd)]
+    assert keys == sorted(keys)
+
+
 def _negabinary_value(u, W):
     return sum(((u >> k) & 1) * (-2) ** k for k in range(W))
 
@@ -347,6 +358,46 @@ def test_zfp_error_within_tolerance_when_precision_is_not_clamped():
                     bits, xh, sse, nsb, emax = oracle.zfp_block(xv, nd, dt, me)
                     if oracle.precision(emax, me, nd, W) < W:
                         assert np.abs(xv - xh).max() <= tau
+
+
+@pytest.mark.parametrize("dt", [oracle.F32, oracle.F64])
+def test_zfp_block_decode_matches_decoding_the_emitted_stream(dt):
+    # Rebuild each block from the emitted bits alone: read the planes back,
+    # take the negabinary digits as sum d_k (-2)^k, undo the reorder and the
+    # transform, rescale by 2^(emax-P) and round to the field dtype.
+    W = 32 if dt == oracle.F32 else 64
+    P, E = W - 2, (8 if dt == oracle.F32 else 11)
+    rng = np.random.default_rng(19)
+    for nd in (1, 2, 3):
+        size = 4 ** nd
+        perm = oracle.reorder_table(nd)
+        for trial in range(60):
+            x = np.cumsum(rng.standard_normal(size)) * 10.0 ** rng.integers(-3, 3)
+            if dt == oracle.F32:
+                x = x.astype(np.float32).astype(np.float64)
+            tau = 10.0 ** rng.uniform(-8, 0)
+            me = oracle.floor_log2(tau)
+            bits, xh, sse, nsb, emax = oracle.zfp_block(x, nd, dt, me)
+            prec = oracle.precision(emax, me, nd, W)
+            if prec == 0:
+                assert bits == 1 and not xh.any()
+                continue
+            c = [int(math.ldexp(v, P - emax)) for v in x]
+            y = oracle.fwd_xform(c, nd, W)
+            u = [oracle.to_negabinary(int(y[p]), W) for p in perm]
+            nbits, stream = oracle.encode_planes(u, W, prec, want_bits=True)
+            assert bits == 1 + E + nbits
+            planes = _decode([int(b) for b in stream], size, prec)
+            ut = _values_from_masks(planes, size, W)
+            ct = [0] * size
+            for r, p in enumerate(perm):
+                v = _negabinary_value(ut[r], W)
+                ct[p] = (v + 2 ** (W - 1)) % 2 ** W - 2 ** (W - 1)
+            d = oracle.inv_xform(ct, nd, W)
+            want = np.array([math.ldexp(float(v), emax - P) for v in d])
+            if dt == oracle.F32:
+                want = want.astype(np.float32).astype(np.float64)
+            assert np.array_equal(want, xh)
 
 
 def test_zfp_block_sse_is_sum_of_squared_errors():
