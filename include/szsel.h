@@ -1,0 +1,181 @@
+/*
+ * szsel: sampling-based SZ-vs-ZFP rate-distortion estimation and selection on
+ * MI355X (gfx950), after Tao, Di, Liang, Chen, Cappello, "Optimizing Lossy
+ * Compression Rate-Distortion from Automatic Online Selection between SZ and
+ * ZFP" (arXiv:1806.08901).
+ *
+ * Every entry point below enqueues HIP kernels on the caller's stream; the
+ * whole estimator runs on the GPU.  Plain C ABI: device or host pointers and
+ * sizes only.
+ *
+ * Conventions shared by all entry points
+ *   field   device pointer to a C-order array (dims[0] slowest), binary32
+ *           (SZSEL_F32) or binary64 (SZSEL_F64).  Owned by the caller, who
+ *           keeps it alive and unmodified until the stream work completes.
+ *   dims    host array of ndims extents, each >= 1; ndims in {1, 2, 3}.
+ *   eb      error bound: absolute (SZSEL_EB_ABS) or relative to the field's
+ *           value range (SZSEL_EB_REL), Algorithm 1 line 2.  Must be > 0.
+ *   stride  host array of ndims block strides, each >= 1: the 4^d block with
+ *           block index b is sampled iff b_k mod stride[k] == 0 on every axis
+ *           (Section 4.3: a fixed distance per dimension).  NULL means 1 on
+ *           every axis (every block sampled).
+ *   out     host memory for the result (szsel_result), written by an
+ *           asynchronous device-to-host copy ordered on `stream`.  Read it
+ *           only after synchronising the stream.  Pinned memory keeps the call
+ *           fully asynchronous; pageable memory may make the copy synchronous.
+ *   stream  a hipStream_t cast to void* (NULL = the null stream).
+ *
+ * Errors: argument and launch errors are returned synchronously as negative
+ * SZSEL_E* codes, with text from szsel_last_error().  Conditions that depend
+ * on the data (non-finite values, a constant field, ...) are reported in
+ * szsel_result.flags.  No C++ exception crosses this interface.  A context is
+ * not thread-safe; calls on one context that run on different streams are
+ * ordered by the context itself (each call's workspace slot waits for the
+ * previous use of that slot).
+ */
+#ifndef SZSEL_H
+#define SZSEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct szsel_ctx szsel_ctx;
+
+enum { SZSEL_F32 = 0, SZSEL_F64 = 1 };
+enum { SZSEL_EB_ABS = 0, SZSEL_EB_REL = 1 };
+
+/* What one request computes. */
+enum {
+  SZSEL_OP_SZ = 0,       /* SZ side only, bin width delta = 2 eb_abs (Section 5.1.4) */
+  SZSEL_OP_ZFP = 1,      /* ZFP side only (Section 5.2) */
+  SZSEL_OP_SELECT = 2,   /* Algorithm 1: ZFP first, SZ at the delta of equal PSNR */
+  SZSEL_OP_FIXED_EB = 3  /* both sides at the same eb_abs, lower bit-rate wins
+                            (the fixed-maximum-error criterion of Section 6.4) */
+};
+
+enum {
+  SZSEL_OK = 0,
+  SZSEL_EINVAL = -1,  /* bad argument */
+  SZSEL_EDTYPE = -2,  /* unsupported dtype */
+  SZSEL_ENOMEM = -3,  /* workspace would exceed the context's budget */
+  SZSEL_EHIP = -4,    /* a HIP runtime call failed */
+  SZSEL_EBUSY = -5    /* batch larger than the context supports */
+};
+
+/* Data-dependent conditions, OR-ed into szsel_result.flags. */
+enum {
+  SZSEL_FLAG_CONSTANT = 1,    /* value range is 0: nothing to estimate, choice = SZ */
+  SZSEL_FLAG_NONFINITE = 2,   /* NaN or Inf in the field: nothing estimated, choice = -1 */
+  SZSEL_FLAG_ZERO_MSE = 4,    /* ZFP reproduced the samples exactly: delta = 2 eb_abs */
+  SZSEL_FLAG_EB_EXCEEDS = 8,  /* the SZ bound delta/2 is larger than eb_abs */
+  SZSEL_FLAG_NO_BLOCKS = 16,  /* no full 4^d block: nothing estimated, choice = SZ */
+  SZSEL_FLAG_BAD_EB = 32      /* eb_rel * value range is 0 or not finite */
+};
+
+/* Result of one request.  Bit-rates are bits per value, PSNRs in dB, MSEs in
+ * squared field units; *_sse are the raw sums the MSEs come from. */
+typedef struct {
+  uint32_t flags;
+  int32_t choice;             /* 0 = SZ, 1 = ZFP (Algorithm 1's selection bit); -1 if not selecting */
+  double vmin, vmax, vr, eb_abs;
+  int32_t minexp, pad0;       /* floor(log2(eb_abs)): ZFP's lowest coded bit plane */
+  /* ZFP side (Section 5.2): exact coder bits of the sampled blocks and the
+   * data-domain error after decoding them */
+  double zfp_bitrate, zfp_mse, zfp_psnr, zfp_nsb_mean, zfp_maxerr, zfp_sse;
+  uint64_t zfp_bits, zfp_values, zfp_blocks, zfp_nsb_total;
+  /* SZ side (Section 5.1): bin width, entropy of the Lorenzo/quantization
+   * codes (Eq. 5), bit-rate = entropy + offset + escapes, PSNR model (Eq. 10)
+   * and measured PSNR of the sampled points */
+  double sz_delta, sz_inv_delta, sz_eb, sz_entropy, sz_bitrate;
+  double sz_psnr_model, sz_psnr_measured, sz_mse, sz_maxerr, sz_sse;
+  uint64_t sz_values, sz_unpredictable;
+  double chosen_eb;           /* error bound handed to the chosen compressor */
+} szsel_result;
+
+/* One request of a batch (szsel_select_batch). */
+typedef struct {
+  const void *field;          /* device pointer, as above */
+  int64_t dims[3];            /* first ndims entries used */
+  int32_t ndims, dtype;
+  double eb;
+  int32_t eb_mode, op;        /* SZSEL_EB_*, SZSEL_OP_* */
+  int32_t stride[3];          /* first ndims entries used; 0 means 1 */
+  int32_t pad0;
+} szsel_request;
+
+/* Device buffers that receive per-sample values of the NEXT request (debug
+ * and parity testing).  Any pointer may be NULL.  Sizes: codes n_s uint16
+ * (sampled-block order, then in-block row-major); zfp_bits, zfp_emax,
+ * zfp_sse, sz_sse one entry per sampled block; hist 65536 uint32. */
+typedef struct {
+  uint16_t *codes;
+  uint32_t *zfp_bits;
+  double *zfp_sse;
+  int32_t *zfp_emax;
+  double *sz_sse;
+  uint32_t *hist;
+} szsel_debug;
+
+/* Creates a context on HIP device `hip_device`.  workspace_budget_bytes caps
+ * the device memory the context may allocate (0 = 1 GiB).  Returns SZSEL_OK
+ * and *ctx, or a negative code. */
+int szsel_create(szsel_ctx **ctx, int hip_device, size_t workspace_budget_bytes);
+
+/* Waits for the context's outstanding work and frees its device memory. */
+void szsel_destroy(szsel_ctx *ctx);
+
+/* SZ-side estimate (Section 5.1; Eq. 5, 9, 10, 11 with delta = 2 eb_abs). */
+int szsel_estimate_sz(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims, int dtype,
+                      double eb, int eb_mode, const int32_t *stride, szsel_result *out,
+                      void *stream);
+
+/* ZFP-side estimate (Section 5.2: embedded-coding bit count and the PSNR of
+ * the sampled blocks). */
+int szsel_estimate_zfp(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims,
+                       int dtype, double eb, int eb_mode, const int32_t *stride,
+                       szsel_result *out, void *stream);
+
+/* Algorithm 1: value range, block sampling, ZFP bit-rate and PSNR, the bin
+ * width delta with PSNR_sz = PSNR_zfp (Eq. 10), SZ bit-rate from the code
+ * histogram at delta, choice of the lower bit-rate (ties to ZFP). */
+int szsel_select(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims, int dtype,
+                 double eb, int eb_mode, const int32_t *stride, szsel_result *out, void *stream);
+
+/* Fixed-maximum-error selection (Section 6.4): SZ at delta = 2 eb_abs against
+ * ZFP at eb_abs, lower bit-rate wins. */
+int szsel_select_fixed_eb(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims,
+                          int dtype, double eb, int eb_mode, const int32_t *stride,
+                          szsel_result *out, void *stream);
+
+/* n requests of any shape, dtype, bound and op in one persistent launch
+ * (captured and replayed as a HIP graph when the same batch shape repeats).
+ * Requests that share a field pointer share one value-range scan.  out[i]
+ * receives the result of reqs[i]; each equals what the single-request entry
+ * point returns for the same request, bit for bit. */
+int szsel_select_batch(szsel_ctx *ctx, const szsel_request *reqs, int n, szsel_result *out,
+                       void *stream);
+
+/* Text of the last error on this context ("" if none). */
+const char *szsel_last_error(const szsel_ctx *ctx);
+
+/* Block strides that sample a fraction close to r_sp (0 < r_sp <= 1) of the
+ * full 4^d blocks, with stride 1 on the fastest axis (Section 4.3, the default
+ * rate being 5%).  Writes ndims strides; returns SZSEL_OK or SZSEL_EINVAL. */
+int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *stride_out);
+
+/* Options. SZSEL_OPT_SZ_OFFSET: bits per value added to the SZ entropy
+ * estimate (Section 6.2 sets it to 0.5; default 0.5). */
+enum { SZSEL_OPT_SZ_OFFSET = 1 };
+int szsel_set_option(szsel_ctx *ctx, int option, double value);
+
+/* Arms per-sample dumps for the next single-request call (NULL disarms). */
+int szsel_set_debug(szsel_ctx *ctx, const szsel_debug *dump);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SZSEL_H */

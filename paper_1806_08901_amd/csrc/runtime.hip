@@ -1,0 +1,368 @@
+// Host runtime behind the C ABI of include/szsel.h: argument checking,
+// request planning (tiles, grid sizes), workspace slots, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "batch.hpp"
+#include "launch.hpp"
+#include "szsel.h"
+
+using namespace szsel;
+
+namespace {
+
+constexpr int kSlots = 4;
+constexpr int kMaxRange = 4096;   // workgroups of a range pass
+constexpr int kMaxTiles = 65536;  // tiles per request
+
+struct Slot {
+  char *mem = nullptr;
+  ReqState *st = nullptr;
+  RangePart *rpart = nullptr;
+  TilePart *zpart = nullptr;
+  TilePart *spart = nullptr;
+  uint32_t *hist = nullptr;
+  szsel_result *res = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct SlotLayout {
+  size_t st, rpart, zpart, spart, hist, res, total;
+  SlotLayout() {
+    size_t o = 0;
+    st = o;
+    o = align_up(o + sizeof(ReqState), 256);
+    rpart = o;
+    o = align_up(o + sizeof(RangePart) * kMaxRange, 256);
+    zpart = o;
+    o = align_up(o + sizeof(TilePart) * kMaxTiles, 256);
+    spart = o;
+    o = align_up(o + sizeof(TilePart) * kMaxTiles, 256);
+    hist = o;
+    o = align_up(o + sizeof(uint32_t) * kBins, 256);
+    res = o;
+    o = align_up(o + sizeof(szsel_result), 256);
+    total = o;
+  }
+};
+
+}  // namespace
+
+struct szsel_ctx {
+  int device = 0;
+  int ncu = 256;
+  size_t budget = 0;
+  size_t used_bytes = 0;
+  Slot slots[kSlots];
+  int next = 0;
+  double sz_offset = 0.5;
+  szsel_debug dbg{};
+  bool dbg_armed = false;
+  std::string err;
+  BatchState *batch = nullptr;
+};
+
+namespace {
+
+int fail(szsel_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(szsel_ctx *c, hipError_t e, const char *what) {
+  return fail(c, SZSEL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+namespace szsel {
+
+int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
+                 int dtype, double eb, int eb_mode, const int32_t *stride, ReqDesc &r) {
+  if (!ctx) return SZSEL_EINVAL;
+  if (!field) return fail(ctx, SZSEL_EINVAL, "field is NULL");
+  if (!dims) return fail(ctx, SZSEL_EINVAL, "dims is NULL");
+  if (nd < 1 || nd > 3) return fail(ctx, SZSEL_EINVAL, "ndims must be 1, 2 or 3");
+  if (dtype != SZSEL_F32 && dtype != SZSEL_F64)
+    return fail(ctx, SZSEL_EDTYPE, "dtype must be SZSEL_F32 or SZSEL_F64");
+  if (op < SZSEL_OP_SZ || op > SZSEL_OP_FIXED_EB) return fail(ctx, SZSEL_EINVAL, "bad op");
+  if (!(eb > 0.0) || !std::isfinite(eb)) return fail(ctx, SZSEL_EINVAL, "eb must be > 0 and finite");
+  if (eb_mode != SZSEL_EB_ABS && eb_mode != SZSEL_EB_REL)
+    return fail(ctx, SZSEL_EINVAL, "eb_mode must be SZSEL_EB_ABS or SZSEL_EB_REL");
+  const size_t esz = dtype == SZSEL_F32 ? 4 : 8;
+  if ((uintptr_t)field % esz) return fail(ctx, SZSEL_EINVAL, "field is not aligned to its element size");
+  std::memset(&r, 0, sizeof(r));
+  r.field = field;
+  r.nd = nd;
+  r.dtype = dtype;
+  r.op = op;
+  r.eb_mode = eb_mode;
+  r.eb = eb;
+  r.sz_offset = ctx->sz_offset;
+  int64_t n = 1;
+  uint64_t nblk = 1;
+  for (int k = 0; k < nd; k++) {
+    if (dims[k] < 1) return fail(ctx, SZSEL_EINVAL, "every extent must be >= 1");
+    const int32_t s = stride ? stride[k] : 1;
+    if (s < 1) return fail(ctx, SZSEL_EINVAL, "every stride must be >= 1");
+    if (n > INT64_MAX / dims[k]) return fail(ctx, SZSEL_EINVAL, "field too large");
+    n *= dims[k];
+    r.dims[k] = dims[k];
+    r.stride[k] = s;
+    const int64_t nb = dims[k] / 4;
+    const int64_t ns = (nb + s - 1) / s;
+    if (ns > 0xFFFFFFFFll) return fail(ctx, SZSEL_EINVAL, "too many blocks along an axis");
+    r.nsel[k] = (uint32_t)ns;
+    nblk *= (uint64_t)ns;
+    if (nblk > 0xFFFFFFFFull) return fail(ctx, SZSEL_EINVAL, "more than 2^32 sampled blocks; use a larger stride");
+  }
+  r.n = n;
+  r.nblk = (int64_t)nblk;
+  const int bs = 1 << (2 * nd);
+  const int bpw = kWave / bs;
+  const int min_tile = kWaves * bpw;
+  int tile = nd == 3 ? 16 : (nd == 2 ? 64 : 256);
+  tile = std::max(tile, min_tile);
+  while ((int64_t)((nblk + tile - 1) / tile) > kMaxTiles && tile < kMaxTile) tile *= 2;
+  if ((int64_t)((nblk + tile - 1) / tile) > kMaxTiles)
+    return fail(ctx, SZSEL_EINVAL, "too many sampled blocks for one request; use a larger stride");
+  r.tile = tile;
+  r.ntiles = (int32_t)((nblk + tile - 1) / tile);
+  const int nt = std::max(1, r.ntiles);
+  r.nzfp = std::min(nt, 8 * ctx->ncu);
+  r.nsz = std::min(nt, 4 * ctx->ncu);
+  const int vn = 16 / (int)esz;
+  const int64_t per_wg = (int64_t)kThreads * vn * 4;
+  r.nrange = (int32_t)std::max<int64_t>(1, std::min<int64_t>((n + per_wg - 1) / per_wg,
+                                                              std::min(kMaxRange, 8 * ctx->ncu)));
+  return SZSEL_OK;
+}
+
+}  // namespace szsel
+
+namespace {
+
+int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd, int dtype,
+               double eb, int eb_mode, const int32_t *stride, szsel_result *out, void *stream) {
+  if (!ctx) return SZSEL_EINVAL;
+  if (!out) return fail(ctx, SZSEL_EINVAL, "out is NULL");
+  ReqDesc r;
+  int rc = plan_request(ctx, op, field, dims, nd, dtype, eb, eb_mode, stride, r);
+  if (rc != SZSEL_OK) return rc;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  Slot &sl = ctx->slots[ctx->next];
+  ctx->next = (ctx->next + 1) % kSlots;
+  if (sl.used) {
+    e = hipStreamWaitEvent(s, sl.done, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+  }
+  r.st = sl.st;
+  r.rpart = sl.rpart;
+  r.zpart = sl.zpart;
+  r.spart = sl.spart;
+  r.hist = sl.hist;
+  r.res = sl.res;
+  if (ctx->dbg_armed) {
+    r.dbg_codes = ctx->dbg.codes;
+    r.dbg_zbits = ctx->dbg.zfp_bits;
+    r.dbg_zsse = ctx->dbg.zfp_sse;
+    r.dbg_zemax = ctx->dbg.zfp_emax;
+    r.dbg_ssse = ctx->dbg.sz_sse;
+    r.dbg_hist = ctx->dbg.hist;
+    ctx->dbg_armed = false;
+  }
+  e = launch_request(r, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+  e = hipMemcpyAsync(out, sl.res, sizeof(szsel_result), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(result)");
+  e = hipEventRecord(sl.done, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+  sl.used = true;
+  ctx->err.clear();
+  return SZSEL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
+  if (!out) return SZSEL_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return SZSEL_EINVAL;
+  szsel_ctx *c = new (std::nothrow) szsel_ctx();
+  if (!c) return SZSEL_ENOMEM;
+  c->device = hip_device;
+  c->budget = budget ? budget : ((size_t)1 << 30);
+  hipError_t e = hipSetDevice(hip_device);
+  int ncu = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device);
+  if (e != hipSuccess) {
+    delete c;
+    return SZSEL_EHIP;
+  }
+  c->ncu = ncu > 0 ? ncu : 256;
+  const SlotLayout L;
+  if ((size_t)kSlots * L.total > c->budget) {
+    delete c;
+    return SZSEL_ENOMEM;
+  }
+  for (int k = 0; k < kSlots; k++) {
+    Slot &s = c->slots[k];
+    void *p = nullptr;
+    e = hipMalloc(&p, L.total);
+    if (e == hipSuccess) e = hipMemset(p, 0, L.total);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (p) (void)hipFree(p);
+      szsel_destroy(c);
+      return SZSEL_EHIP;
+    }
+    s.mem = (char *)p;
+    s.st = (ReqState *)(s.mem + L.st);
+    s.rpart = (RangePart *)(s.mem + L.rpart);
+    s.zpart = (TilePart *)(s.mem + L.zpart);
+    s.spart = (TilePart *)(s.mem + L.spart);
+    s.hist = (uint32_t *)(s.mem + L.hist);
+    s.res = (szsel_result *)(s.mem + L.res);
+    c->used_bytes += L.total;
+  }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    szsel_destroy(c);
+    return SZSEL_EHIP;
+  }
+  *out = c;
+  return SZSEL_OK;
+}
+
+void szsel_destroy(szsel_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (int k = 0; k < kSlots; k++) {
+    if (c->slots[k].mem) (void)hipFree(c->slots[k].mem);
+    if (c->slots[k].done) (void)hipEventDestroy(c->slots[k].done);
+  }
+  batch_destroy(c->batch);
+  delete c;
+}
+
+int szsel_estimate_sz(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb,
+                      int m, const int32_t *s, szsel_result *o, void *st) {
+  return run_single(c, SZSEL_OP_SZ, f, d, nd, dt, eb, m, s, o, st);
+}
+
+int szsel_estimate_zfp(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb,
+                       int m, const int32_t *s, szsel_result *o, void *st) {
+  return run_single(c, SZSEL_OP_ZFP, f, d, nd, dt, eb, m, s, o, st);
+}
+
+int szsel_select(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb, int m,
+                 const int32_t *s, szsel_result *o, void *st) {
+  return run_single(c, SZSEL_OP_SELECT, f, d, nd, dt, eb, m, s, o, st);
+}
+
+int szsel_select_fixed_eb(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb,
+                          int m, const int32_t *s, szsel_result *o, void *st) {
+  return run_single(c, SZSEL_OP_FIXED_EB, f, d, nd, dt, eb, m, s, o, st);
+}
+
+int szsel_select_batch(szsel_ctx *c, const szsel_request *reqs, int n, szsel_result *out,
+                       void *stream) {
+  if (!c) return SZSEL_EINVAL;
+  if (n < 0 || (n > 0 && (!reqs || !out))) return fail(c, SZSEL_EINVAL, "bad batch arguments");
+  if (n == 0) return SZSEL_OK;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  std::vector<ReqDesc> descs((size_t)n);
+  for (int i = 0; i < n; i++) {
+    const szsel_request &q = reqs[i];
+    int32_t st[3];
+    for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
+    int rc = plan_request(c, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, descs[i]);
+    if (rc != SZSEL_OK) {
+      c->err = "request " + std::to_string(i) + ": " + c->err;
+      return rc;
+    }
+  }
+  std::string msg;
+  int rc = batch_run(c->batch, c->device, c->ncu, c->budget, descs, out, (hipStream_t)stream, msg);
+  if (rc != SZSEL_OK) return fail(c, rc, msg);
+  c->err.clear();
+  return SZSEL_OK;
+}
+
+const char *szsel_last_error(const szsel_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int szsel_stride_for_rate(double r_sp, int nd, const int64_t *dims, int32_t *out) {
+  if (!(r_sp > 0.0) || r_sp > 1.0 || nd < 1 || nd > 3 || !dims || !out) return SZSEL_EINVAL;
+  int64_t nb[3];
+  for (int k = 0; k < nd; k++) {
+    if (dims[k] < 4) return SZSEL_EINVAL;
+    nb[k] = dims[k] / 4;
+  }
+  // stride 1 on the fastest axis (contiguous rows of blocks); search the
+  // slower axes for the fraction closest to r_sp in log ratio, with a small
+  // penalty on unbalanced strides (an even spread of samples), then the
+  // larger stride on the slowest axis
+  double best = INFINITY;
+  int32_t bs[3] = {1, 1, 1};
+  const int slow = nd - 1;
+  const int64_t lim0 = slow >= 1 ? nb[0] : 1, lim1 = slow >= 2 ? nb[1] : 1;
+  for (int64_t s0 = 1; s0 <= lim0; s0++) {
+    for (int64_t s1 = 1; s1 <= lim1; s1++) {
+      double frac = 1.0;
+      if (slow >= 1) frac *= (double)((nb[0] + s0 - 1) / s0) / (double)nb[0];
+      if (slow >= 2) frac *= (double)((nb[1] + s1 - 1) / s1) / (double)nb[1];
+      const double balance = slow >= 2 ? std::fabs(std::log((double)s0 / (double)s1)) : 0.0;
+      const double cost = std::fabs(std::log(frac / r_sp)) + 0.05 * balance - 1e-12 * (double)s0;
+      if (cost < best) {
+        best = cost;
+        bs[0] = (int32_t)s0;
+        bs[1] = (int32_t)s1;
+      }
+    }
+  }
+  for (int k = 0; k < nd; k++) out[k] = 1;
+  if (slow >= 1) out[0] = bs[0];
+  if (slow >= 2) out[1] = bs[1];
+  return SZSEL_OK;
+}
+
+int szsel_set_option(szsel_ctx *c, int option, double value) {
+  if (!c) return SZSEL_EINVAL;
+  if (option == SZSEL_OPT_SZ_OFFSET) {
+    if (!std::isfinite(value)) return fail(c, SZSEL_EINVAL, "offset must be finite");
+    c->sz_offset = value;
+    return SZSEL_OK;
+  }
+  return fail(c, SZSEL_EINVAL, "unknown option");
+}
+
+int szsel_set_debug(szsel_ctx *c, const szsel_debug *d) {
+  if (!c) return SZSEL_EINVAL;
+  if (d) {
+    c->dbg = *d;
+    c->dbg_armed = true;
+  } else {
+    c->dbg_armed = false;
+  }
+  return SZSEL_OK;
+}
+
+}  // extern "C"

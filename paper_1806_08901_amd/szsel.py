@@ -1,0 +1,244 @@
+"""Thin ctypes binding of libszsel.so (the C ABI of include/szsel.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+kernels.  PyTorch supplies device memory (``tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  There is no CPU fallback: if
+the library is not built or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libszsel.so")
+
+F32, F64 = 0, 1
+EB_ABS, EB_REL = 0, 1
+OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
+FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
+FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
+OPT_SZ_OFFSET = 1
+NBINS = 65536
+
+
+class SzselError(RuntimeError):
+    pass
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("flags", C.c_uint32), ("choice", C.c_int32),
+        ("vmin", C.c_double), ("vmax", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double),
+        ("minexp", C.c_int32), ("pad0", C.c_int32),
+        ("zfp_bitrate", C.c_double), ("zfp_mse", C.c_double), ("zfp_psnr", C.c_double),
+        ("zfp_nsb_mean", C.c_double), ("zfp_maxerr", C.c_double), ("zfp_sse", C.c_double),
+        ("zfp_bits", C.c_uint64), ("zfp_values", C.c_uint64), ("zfp_blocks", C.c_uint64),
+        ("zfp_nsb_total", C.c_uint64),
+        ("sz_delta", C.c_double), ("sz_inv_delta", C.c_double), ("sz_eb", C.c_double),
+        ("sz_entropy", C.c_double), ("sz_bitrate", C.c_double),
+        ("sz_psnr_model", C.c_double), ("sz_psnr_measured", C.c_double), ("sz_mse", C.c_double),
+        ("sz_maxerr", C.c_double), ("sz_sse", C.c_double),
+        ("sz_values", C.c_uint64), ("sz_unpredictable", C.c_uint64),
+        ("chosen_eb", C.c_double),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("field", C.c_void_p), ("dims", C.c_int64 * 3), ("ndims", C.c_int32), ("dtype", C.c_int32),
+        ("eb", C.c_double), ("eb_mode", C.c_int32), ("op", C.c_int32), ("stride", C.c_int32 * 3),
+        ("pad0", C.c_int32),
+    ]
+
+
+class Debug(C.Structure):
+    _fields_ = [("codes", C.c_void_p), ("zfp_bits", C.c_void_p), ("zfp_sse", C.c_void_p),
+                ("zfp_emax", C.c_void_p), ("sz_sse", C.c_void_p), ("hist", C.c_void_p)]
+
+
+RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
+_SINGLE = ("szsel_estimate_sz", "szsel_estimate_zfp", "szsel_select", "szsel_select_fixed_eb")
+EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szsel_last_error",
+                     "szsel_stride_for_rate", "szsel_set_option", "szsel_set_debug")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libszsel.so and declares its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise SzselError("libszsel.so is not built (run __graft_entry__.build()); "
+                         "there is no CPU fallback")
+    L = C.CDLL(path)
+    P, I64P, I32P = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+    L.szsel_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_size_t]
+    L.szsel_destroy.argtypes = [P]
+    L.szsel_destroy.restype = None
+    for name in _SINGLE:
+        getattr(L, name).argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
+                                     C.POINTER(Result), P]
+    L.szsel_select_batch.argtypes = [P, C.POINTER(Request), C.c_int, C.POINTER(Result), P]
+    L.szsel_last_error.argtypes = [P]
+    L.szsel_last_error.restype = C.c_char_p
+    L.szsel_stride_for_rate.argtypes = [C.c_double, C.c_int, I64P, I32P]
+    L.szsel_set_option.argtypes = [P, C.c_int, C.c_double]
+    L.szsel_set_debug.argtypes = [P, C.POINTER(Debug)]
+    _lib = L
+    return L
+
+
+def stride_for_rate(r_sp: float, shape) -> tuple:
+    L = load_library()
+    nd = len(shape)
+    dims = (C.c_int64 * nd)(*shape)
+    out = (C.c_int32 * nd)()
+    rc = L.szsel_stride_for_rate(float(r_sp), nd, dims, out)
+    if rc != 0:
+        raise SzselError("szsel_stride_for_rate rejected r_sp=%r shape=%r" % (r_sp, shape))
+    return tuple(out)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise SzselError("fields are float32 or float64, got %s" % t.dtype)
+
+
+def _as_dict(r: Result) -> dict:
+    return {k: getattr(r, k) for k in RESULT_KEYS}
+
+
+class Context:
+    """One szsel context on one HIP device (not thread-safe)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        if not torch.cuda.is_available():
+            raise SzselError("no HIP device available; the estimator runs only on the GPU")
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.szsel_create(C.byref(h), device, budget_bytes)
+        if rc != 0:
+            raise SzselError("szsel_create failed with %d" % rc)
+        self.h = h
+        self._pinned = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.szsel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.szsel_last_error(self.h).decode()
+            raise SzselError("%s failed (%d): %s" % (what, rc, msg))
+
+    def _results(self, n: int):
+        """Pinned host buffer for n results (reused)."""
+        buf = self._pinned.get(n)
+        if buf is None:
+            t = torch.empty(n * C.sizeof(Result), dtype=torch.uint8, pin_memory=True)
+            buf = (t, (Result * n).from_address(t.data_ptr()))
+            self._pinned[n] = buf
+        return buf[1]
+
+    @staticmethod
+    def _stream(stream):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return s, C.c_void_p(s.cuda_stream)
+
+    def set_option(self, option: int, value: float):
+        self._check(self.lib.szsel_set_option(self.h, option, float(value)), "szsel_set_option")
+
+    def set_debug(self, dbg: dict | None):
+        """Arms per-sample dumps for the next single call.  ``dbg`` maps the
+        names of szsel_debug to device tensors."""
+        if dbg is None:
+            self._check(self.lib.szsel_set_debug(self.h, None), "szsel_set_debug")
+            return
+        d = Debug(*[dbg[k].data_ptr() if dbg.get(k) is not None else None
+                    for k, _ in Debug._fields_])
+        self._check(self.lib.szsel_set_debug(self.h, C.byref(d)), "szsel_set_debug")
+
+    # -- single requests ---------------------------------------------------
+    def run(self, op: int, field: torch.Tensor, eb: float, eb_mode: int = EB_REL, stride=None,
+            stream=None, sync: bool = True):
+        if not field.is_cuda or not field.is_contiguous():
+            raise SzselError("field must be a contiguous device tensor")
+        nd = field.dim()
+        dims = (C.c_int64 * nd)(*field.shape)
+        st = None if stride is None else (C.c_int32 * nd)(*stride)
+        out = self._results(1)
+        s, sp = self._stream(stream)
+        fn = getattr(self.lib, _SINGLE[op])
+        self._check(fn(self.h, C.c_void_p(field.data_ptr()), dims, nd, _dtype_code(field),
+                       float(eb), eb_mode, st, out, sp), _SINGLE[op])
+        if not sync:
+            return out
+        s.synchronize()
+        return _as_dict(out[0])
+
+    def estimate_sz(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
+        return self.run(OP_SZ, field, eb, eb_mode, stride, stream)
+
+    def estimate_zfp(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
+        return self.run(OP_ZFP, field, eb, eb_mode, stride, stream)
+
+    def select(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
+        return self.run(OP_SELECT, field, eb, eb_mode, stride, stream)
+
+    def select_fixed_eb(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
+        return self.run(OP_FIXED_EB, field, eb, eb_mode, stride, stream)
+
+    # -- batches -----------------------------------------------------------
+    def make_requests(self, items):
+        """items: iterable of (tensor, eb, eb_mode, stride, op)."""
+        items = list(items)
+        reqs = (Request * len(items))()
+        for q, (t, eb, mode, stride, op) in zip(reqs, items):
+            if not t.is_cuda or not t.is_contiguous():
+                raise SzselError("fields must be contiguous device tensors")
+            q.field = t.data_ptr()
+            for k, n in enumerate(t.shape):
+                q.dims[k] = n
+            q.ndims = t.dim()
+            q.dtype = _dtype_code(t)
+            q.eb = float(eb)
+            q.eb_mode = mode
+            q.op = op
+            for k in range(t.dim()):
+                q.stride[k] = 1 if stride is None else int(stride[k])
+        return reqs
+
+    def select_batch(self, items, stream=None, sync: bool = True, reqs=None):
+        if reqs is None:
+            reqs = self.make_requests(items)
+        n = len(reqs)
+        out = self._results(n)
+        s, sp = self._stream(stream)
+        self._check(self.lib.szsel_select_batch(self.h, reqs, n, out, sp), "szsel_select_batch")
+        if not sync:
+            return out
+        s.synchronize()
+        return [_as_dict(out[i]) for i in range(n)]

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every declared symbol (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1806_08901_amd import szsel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(szsel_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = szsel.load_library()
+    declared = _declared()
+    assert declared, "no declarations found"
+    assert declared == set(szsel.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_result_layout_matches_header():
+    # 2 x u32, 4 doubles, 2 x i32, 6 doubles, 4 u64, 10 doubles, 2 u64, 1 double
+    assert ctypes.sizeof(szsel.Result) == 8 + 32 + 8 + 48 + 32 + 80 + 16 + 8
+    assert ctypes.sizeof(szsel.Request) == 8 + 24 + 8 + 8 + 8 + 12 + 4
+
+
+@pytest.mark.parametrize("shape,rate,want", [
+    ((512, 512, 512), 0.05, (5, 4, 1)),
+    ((1800, 3600), 0.05, (20, 1)),
+    ((100, 500, 500), 0.05, None),
+    ((64, 64, 64), 1.0, (1, 1, 1)),
+])
+def test_stride_for_rate(shape, rate, want):
+    st = szsel.stride_for_rate(rate, shape)
+    assert st[-1] == 1
+    if want is not None:
+        assert st == want
+    nb = [n // 4 for n in shape]
+    frac = 1.0
+    for b, s in zip(nb, st):
+        frac *= -(-b // s) / b
+    assert 0.5 * rate <= frac <= 2.0 * rate
+
+
+def test_stride_for_rate_rejects_bad_input():
+    with pytest.raises(szsel.SzselError):
+        szsel.stride_for_rate(0.0, (64, 64))
+    with pytest.raises(szsel.SzselError):
+        szsel.stride_for_rate(0.05, (2, 64))
+
+
+def test_no_gpu_means_loud_failure():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(szsel.SzselError):
+        szsel.Context(0)
