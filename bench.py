@@ -1,0 +1,165 @@
+#!/usr/bin/env python
+"""Throughput of the SZ-vs-ZFP rate-distortion estimator and selector on one GPU.
+
+Workload (default): one 512^3 FP32 turbulent-like field (random-phase Fourier
+modes, amplitude ~ |k|^-5/3 for |k| <= 64, plus 1% white noise), a sweep of
+relative error bounds {1e-2, 1e-3, 1e-4, 1e-5, 1e-6}, block stride (5, 4, 1)
+(106,496 sampled 4x4x4 blocks, 5.08%), plain per-field launches: one step is
+five szsel_select calls (Algorithm 1 each, including its value-range scan of
+all 512 MiB and the result copy to pinned host memory).
+
+Metric: input GB/s = 5 x 512 MiB per step / GPU time of the step (HIP events
+on the stream the kernels run on), inputs resident in HBM.  Also reported:
+the range pass's achieved HBM bandwidth against the 8 TB/s peak (per-phase
+HIP events inside the library), per-call latency p50/p99, and the CPU oracle
+timed on the same field on one host core.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input GB/s through SZ+ZFP RD estimation+selection (batched vs plain); p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--latency-calls", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(fields would shard across GPUs by whole fields; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1806_08901_amd import synth, szsel
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    field = synth.workload_turb512(device=dev, n=n)
+    torch.cuda.synchronize()
+    ebs = list(synth.EB_SWEEP)
+    stride = (5, 4, 1)
+    nbytes = field.numel() * field.element_size()
+    ctx = szsel.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for eb in ebs:
+            ctx.run(szsel.OP_SELECT, field, eb, szsel.EB_REL, stride, sync=False)
+
+    # results of one step, kept for the oracle comparison
+    gpu_results = [ctx.select(field, eb, stride=stride) for eb in ebs]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    ms_step = ms_total / args.steps
+    value = len(ebs) * nbytes / (ms_step * 1e-3) / 1e9
+
+    # per-phase GPU time of the same steps (events recorded by the library)
+    ctx.set_option(szsel.OPT_PROFILE, 1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.set_option(szsel.OPT_PROFILE, 0)
+    range_ms = prof["range"][0] / max(1, prof["range"][1])
+    zfp_ms = prof["zfp"][0] / max(1, prof["zfp"][1])
+    sz_ms = prof["sz"][0] / max(1, prof["sz"][1])
+    achieved = nbytes / (range_ms * 1e-3) / 1e9
+
+    # latency of one synchronous select call (host wall clock)
+    lat = []
+    for k in range(args.latency_calls):
+        eb = ebs[k % len(ebs)]
+        t = time.perf_counter()
+        ctx.select(field, eb, stride=stride)
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat.sort()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "turb%d_sweep5_plain" % n,
+            "shape": [n, n, n], "field_dtype": "f32", "eb_rel": ebs, "stride": list(stride),
+            "sampled_blocks": int(gpu_results[0]["zfp_blocks"]),
+            "requests_per_step": len(ebs), "mode": "plain per-field launches (szsel_select)",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_range (value-range scan, all N values)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": nbytes, "avg_launch_ms": round(range_ms, 5),
+        },
+        "phases_ms": {"range": round(range_ms, 5), "zfp": round(zfp_ms, 5), "sz": round(sz_ms, 5)},
+        "latency_ms": {"p50": round(lat[len(lat) // 2], 4),
+                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+                       "calls": len(lat), "what": "one synchronous szsel_select on the field"},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        from tests.gpu_common import assert_matches_oracle
+        host = field.cpu().numpy()
+        t = time.perf_counter()
+        orc = [oracle.select(host, eb, stride=stride)[0] for eb in ebs]
+        cpu_s = time.perf_counter() - t
+        parity = True
+        for g, o in zip(gpu_results, orc):
+            try:
+                assert_matches_oracle(g, o)
+            except AssertionError:
+                parity = False
+        out["cpu_baseline"] = {
+            "value": round(len(ebs) * nbytes / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one full step: szsel_select semantics for the 5 error bounds on the same "
+                      "%d^3 field, single-threaded C oracle, %.1f s" % (n, cpu_s),
+        }
+        out["parity_with_oracle"] = parity
+    out["choices"] = [r["choice"] for r in gpu_results]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,35 +62,44 @@ __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   sz_finalize<T, D>(r, L.red);
 }
 
+static hipError_t mark(const hipEvent_t *ev, int k, hipStream_t s) {
+  return ev ? hipEventRecord(ev[k], s) : hipSuccess;
+}
+
 template <typename T, int D>
-static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s) {
+static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
+  hipError_t e = hipSuccess;
   if (r.op != SZSEL_OP_SZ) {
     hipLaunchKernelGGL((k_zfp<T, D>), dim3(r.nzfp), dim3(kThreads), 0, s, r);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if ((e = mark(ev, 2, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
     hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return mark(ev, 3, s);
 }
 
 template <typename T>
-static hipError_t launch_typed(const ReqDesc &r, hipStream_t s) {
-  hipLaunchKernelGGL((k_range<T>), dim3(r.nrange), dim3(kThreads), 0, s, r);
-  hipError_t e = hipGetLastError();
+static hipError_t launch_typed(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
+  hipError_t e = mark(ev, 0, s);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_range<T>), dim3(r.nrange), dim3(kThreads), 0, s, r);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = mark(ev, 1, s)) != hipSuccess) return e;
   switch (r.nd) {
-    case 1: return launch_tiles<T, 1>(r, s);
-    case 2: return launch_tiles<T, 2>(r, s);
-    default: return launch_tiles<T, 3>(r, s);
+    case 1: return launch_tiles<T, 1>(r, s, ev);
+    case 2: return launch_tiles<T, 2>(r, s, ev);
+    default: return launch_tiles<T, 3>(r, s, ev);
   }
 }
 
-hipError_t launch_request(const ReqDesc &r, hipStream_t s) {
-  return r.dtype == SZSEL_F32 ? launch_typed<float>(r, s) : launch_typed<double>(r, s);
+hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
+  return r.dtype == SZSEL_F32 ? launch_typed<float>(r, s, ev) : launch_typed<double>(r, s, ev);
 }
 
 }  // namespace szsel

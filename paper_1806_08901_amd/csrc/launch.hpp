@@ -7,7 +7,9 @@
 
 namespace szsel {
 
-// Enqueues the three kernels of one request on stream s.
-hipError_t launch_request(const ReqDesc &r, hipStream_t s);
+// Enqueues the kernels of one request on stream s.  When ev is not NULL,
+// ev[0..3] are recorded before the range pass, after it, after the ZFP pass
+// and after the SZ pass (phase timers).
+hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev = nullptr);
 
 }  // namespace szsel

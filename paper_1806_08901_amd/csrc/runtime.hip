@@ -70,6 +70,12 @@ struct szsel_ctx {
   bool dbg_armed = false;
   std::string err;
   BatchState *batch = nullptr;
+  // phase timers
+  bool prof = false;
+  std::vector<hipEvent_t> prof_events;  // 4 per recorded call
+  size_t prof_used = 0;                 // events in use (multiple of 4)
+  double prof_ms[3] = {0, 0, 0};
+  uint64_t prof_calls[3] = {0, 0, 0};
 };
 
 namespace {
@@ -152,6 +158,26 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
 
 namespace {
 
+constexpr size_t kProfEvents = 4 * 1024;
+
+// Accumulates the elapsed times of the recorded phase events and frees them.
+int profile_drain(szsel_ctx *c) {
+  for (size_t k = 0; k + 4 <= c->prof_used; k += 4) {
+    hipEvent_t *ev = &c->prof_events[k];
+    hipError_t e = hipEventSynchronize(ev[3]);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    for (int ph = 0; ph < 3; ph++) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+      c->prof_ms[ph] += ms;
+      c->prof_calls[ph] += 1;
+    }
+  }
+  c->prof_used = 0;
+  return SZSEL_OK;
+}
+
 int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd, int dtype,
                double eb, int eb_mode, const int32_t *stride, szsel_result *out, void *stream) {
   if (!ctx) return SZSEL_EINVAL;
@@ -183,7 +209,16 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
     r.dbg_hist = ctx->dbg.hist;
     ctx->dbg_armed = false;
   }
-  e = launch_request(r, s);
+  const hipEvent_t *ev = nullptr;
+  if (ctx->prof) {
+    if (ctx->prof_used + 4 > ctx->prof_events.size()) {
+      int rc2 = profile_drain(ctx);
+      if (rc2 != SZSEL_OK) return rc2;
+    }
+    ev = &ctx->prof_events[ctx->prof_used];
+    ctx->prof_used += 4;
+  }
+  e = launch_request(r, s, ev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   e = hipMemcpyAsync(out, sl.res, sizeof(szsel_result), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(result)");
@@ -259,6 +294,8 @@ void szsel_destroy(szsel_ctx *c) {
     if (c->slots[k].done) (void)hipEventDestroy(c->slots[k].done);
   }
   batch_destroy(c->batch);
+  for (auto &ev : c->prof_events)
+    if (ev) (void)hipEventDestroy(ev);
   delete c;
 }
 
@@ -351,7 +388,37 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
     c->sz_offset = value;
     return SZSEL_OK;
   }
+  if (option == SZSEL_OPT_PROFILE) {
+    const bool on = value != 0.0;
+    if (on && c->prof_events.empty()) {
+      (void)hipSetDevice(c->device);
+      c->prof_events.resize(kProfEvents, nullptr);
+      for (auto &ev : c->prof_events) {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+      }
+    }
+    if (!on && c->prof) {
+      int rc = profile_drain(c);
+      if (rc != SZSEL_OK) return rc;
+    }
+    c->prof = on;
+    return SZSEL_OK;
+  }
   return fail(c, SZSEL_EINVAL, "unknown option");
+}
+
+int szsel_profile_read(szsel_ctx *c, double *ms, uint64_t *calls) {
+  if (!c || !ms || !calls) return SZSEL_EINVAL;
+  int rc = profile_drain(c);
+  if (rc != SZSEL_OK) return rc;
+  for (int k = 0; k < 3; k++) {
+    ms[k] = c->prof_ms[k];
+    calls[k] = c->prof_calls[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_calls[k] = 0;
+  }
+  return SZSEL_OK;
 }
 
 int szsel_set_debug(szsel_ctx *c, const szsel_debug *d) {

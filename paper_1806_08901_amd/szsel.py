@@ -20,7 +20,7 @@ EB_ABS, EB_REL = 0, 1
 OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
 FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
 FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
-OPT_SZ_OFFSET = 1
+OPT_SZ_OFFSET, OPT_PROFILE = 1, 2
 NBINS = 65536
 
 
@@ -62,7 +62,8 @@ class Debug(C.Structure):
 RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
 _SINGLE = ("szsel_estimate_sz", "szsel_estimate_zfp", "szsel_select", "szsel_select_fixed_eb")
 EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szsel_last_error",
-                     "szsel_stride_for_rate", "szsel_set_option", "szsel_set_debug")
+                     "szsel_stride_for_rate", "szsel_set_option", "szsel_set_debug",
+                     "szsel_profile_read")
 
 _lib = None
 
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.szsel_stride_for_rate.argtypes = [C.c_double, C.c_int, I64P, I32P]
     L.szsel_set_option.argtypes = [P, C.c_int, C.c_double]
     L.szsel_set_debug.argtypes = [P, C.POINTER(Debug)]
+    L.szsel_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     _lib = L
     return L
 
@@ -170,6 +172,14 @@ class Context:
 
     def set_option(self, option: int, value: float):
         self._check(self.lib.szsel_set_option(self.h, option, float(value)), "szsel_set_option")
+
+    def profile_read(self):
+        """Per-phase GPU milliseconds and call counts since the last read:
+        {"range": (ms, n), "zfp": (ms, n), "sz": (ms, n)}."""
+        ms = (C.c_double * 3)()
+        n = (C.c_uint64 * 3)()
+        self._check(self.lib.szsel_profile_read(self.h, ms, n), "szsel_profile_read")
+        return {k: (ms[i], n[i]) for i, k in enumerate(("range", "zfp", "sz"))}
 
     def set_debug(self, dbg: dict | None):
         """Arms per-sample dumps for the next single call.  ``dbg`` maps the
