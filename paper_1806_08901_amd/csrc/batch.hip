@@ -30,18 +30,14 @@ int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<R
               szsel_result *out, hipStream_t s, std::string &msg) {
   (void)ncu;
   const size_t n = descs.size();
-  // layout: results first (one contiguous copy back), then per request
-  // state, range partials, tile partials and histogram
+  // layout: results first (one contiguous copy back), then one workspace
+  // region per request
   size_t off = align_up(sizeof(szsel_result) * n, 256);
   std::vector<size_t> base(n);
   for (size_t i = 0; i < n; i++) {
     const ReqDesc &r = descs[i];
     base[i] = off;
-    off = align_up(off + sizeof(ReqState), 256);
-    off = align_up(off + sizeof(RangePart) * (size_t)r.nrange, 256);
-    off = align_up(off + sizeof(TilePart) * (size_t)std::max(1, r.ntiles), 256);
-    off = align_up(off + sizeof(TilePart) * (size_t)std::max(1, r.ntiles), 256);
-    off = align_up(off + sizeof(uint32_t) * kBins, 256);
+    off = align_up(off + request_workspace_bytes(r.nrange, r.nzfp, r.nsz), 256);
   }
   const size_t need = off;
   if (!bs) {
@@ -80,17 +76,7 @@ int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<R
   szsel_result *res = (szsel_result *)bs->mem;
   for (size_t i = 0; i < n && e == hipSuccess; i++) {
     ReqDesc &r = descs[i];
-    char *b = bs->mem + base[i];
-    size_t o = 0;
-    r.st = (ReqState *)(b + o);
-    o = align_up(o + sizeof(ReqState), 256);
-    r.rpart = (RangePart *)(b + o);
-    o = align_up(o + sizeof(RangePart) * (size_t)r.nrange, 256);
-    r.zpart = (TilePart *)(b + o);
-    o = align_up(o + sizeof(TilePart) * (size_t)std::max(1, r.ntiles), 256);
-    r.spart = (TilePart *)(b + o);
-    o = align_up(o + sizeof(TilePart) * (size_t)std::max(1, r.ntiles), 256);
-    r.hist = (uint32_t *)(b + o);
+    bind_request_workspace(r, bs->mem + base[i], r.nrange, r.nzfp, r.nsz);
     r.res = res + i;
     e = launch_request(r, s);
   }

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "szsel.h"
 
 namespace szsel {
@@ -22,10 +24,44 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kBins = 65536;           // 65,535 symmetric bins plus the escape code 0
 constexpr int kRadius = 32768;
 constexpr int kMaxTile = 256;          // sampled blocks per tile
+constexpr int kMaxParts = 8192;        // workgroups of one pass (partials per pass)
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
                                 SZSEL_FLAG_NO_BLOCKS | SZSEL_FLAG_BAD_EB;
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup communication.  MI355X has 8 XCDs whose L2 caches are not
+// coherent with each other; an agent-scope fence makes the whole L2 write
+// back and costs ~0.2 us per workgroup, serialised.  Everything one
+// workgroup hands to another (partials, counters, per-request state) is
+// therefore accessed only through agent-scope atomics, which bypass the
+// non-coherent caches, and a workgroup waits for its own memory operations
+// to complete before it bumps a completion counter.
+// ---------------------------------------------------------------------------
+__device__ inline void put_u64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t get_u64(const uint64_t *p) {
+  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void put_u32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t get_u32(const uint32_t *p) {
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void put_f64(double *p, double v) {
+  put_u64((uint64_t *)p, (uint64_t)__double_as_longlong(v));
+}
+__device__ inline double get_f64(const double *p) {
+  return __longlong_as_double((long long)get_u64((const uint64_t *)p));
+}
+__device__ inline void put_i32(int32_t *p, int32_t v) { put_u32((uint32_t *)p, (uint32_t)v); }
+__device__ inline int32_t get_i32(const int32_t *p) { return (int32_t)get_u32((const uint32_t *)p); }
+
+// Blocks until every memory operation this thread issued has completed.
+__device__ inline void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Per-request state shared by the kernels of one request (device memory).
 struct alignas(64) ReqState {
@@ -37,38 +73,33 @@ struct alignas(64) ReqState {
   uint32_t pad;
 };
 
-struct RangePart {
-  double lo, hi;
-  uint32_t bad, pad0;
-  uint64_t pad1;
-};
-
-struct TilePart {
-  double sse, maxerr;
-  uint64_t bits;  // ZFP: coder bits of the tile; SZ: unused
-  uint64_t cnt;   // ZFP: significant bits; SZ: unpredictable points
+// One entry per workgroup of a pass (structure of arrays, coalesced reads).
+struct Parts {
+  double *sse;   // ZFP/SZ: squared-error subtree of the workgroup; range: min
+  double *err;   // ZFP/SZ: max |error|;                              range: max
+  uint64_t *a;   // ZFP: coder bits; SZ: unpredictable points; range: non-finite flag
+  uint64_t *b;   // ZFP: significant bits
 };
 
 // Everything a kernel needs about one request (passed by value).
 struct ReqDesc {
   const void *field;
   int64_t dims[3];
-  int64_t n;      // number of values
-  int64_t nblk;   // number of sampled blocks
+  int64_t n;       // number of values
+  int64_t nblk;    // number of sampled blocks
   uint32_t nsel[3];
   int32_t stride[3];
   int32_t nd, dtype, op, eb_mode;
   double eb, sz_offset;
-  int32_t tile;    // sampled blocks per tile (power of two, >= one round of 4 waves)
-  int32_t ntiles;
-  int32_t nrange;  // workgroups of the range pass
-  int32_t nsz;     // workgroups of the SZ pass
-  int32_t nzfp;    // workgroups of the ZFP pass
+  int32_t zblk;    // sampled blocks per ZFP workgroup (power of two)
+  int32_t nzfp;    // ZFP workgroups = ceil(nblk / zblk)
+  int32_t sblk;    // sampled blocks per SZ workgroup (power of two)
+  int32_t nsz;     // SZ workgroups
+  int64_t rchunk;  // values per range workgroup (multiple of 16 bytes)
+  int32_t nrange;  // range workgroups
   int32_t pad0;
   ReqState *st;
-  RangePart *rpart;
-  TilePart *zpart;
-  TilePart *spart;
+  Parts rp, zp, sp;
   uint32_t *hist;
   szsel_result *res;
   uint16_t *dbg_codes;
@@ -238,36 +269,6 @@ __device__ inline V group_isum(V v) {
 #pragma unroll
   for (int s = 1; s < WIDTH; s <<= 1) v += __shfl_xor(v, s);
   return v;
-}
-
-// Adjacent-pair tree over a[0..n) padded with +0.0, computed by the whole
-// workgroup (kThreads threads).  Thread t reduces the aligned chunk
-// [t*C, (t+1)*C) with a binary-counter pass (which associates like the tree),
-// then the wave butterfly and the fixed combine of the 4 wave results.
-// Every thread returns the total.  `sh` is kWaves doubles of LDS.
-__device__ inline double wg_tree_sum(const double *a, int64_t n, double *sh) {
-  int64_t p = 1;
-  while (p < n) p <<= 1;
-  const int64_t chunk = p > kThreads ? p / kThreads : 1;
-  const int t = threadIdx.x;
-  double stk[40];
-  int sp = 0;
-  const int64_t beg = (int64_t)t * chunk;
-  for (int64_t k = 0; k < chunk; k++) {
-    const int64_t idx = beg + k;
-    double v = idx < n ? a[idx] : 0.0;
-    for (int64_t m = k; m & 1; m >>= 1) v = stk[--sp] + v;
-    stk[sp++] = v;
-  }
-  double v = stk[0];
-  v = group_tree_sum<kWave>(v);
-  const int w = t / kWave;
-  __syncthreads();
-  if ((t & (kWave - 1)) == 0) sh[w] = v;
-  __syncthreads();
-  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  __syncthreads();
-  return r;
 }
 
 // ---------------------------------------------------------------------------

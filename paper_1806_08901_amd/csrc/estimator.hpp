@@ -1,10 +1,17 @@
-// The estimator's per-tile work and per-request finalizers, shared by the
-// plain per-request kernels and the persistent batch kernel.
+// The estimator's device work, shared by the per-request kernels and the
+// persistent batch kernel:
+//   * range pass: min/max/non-finite over all N values, one contiguous chunk
+//     per workgroup (Algorithm 1, line 2);
+//   * ZFP pass: every sampled block through block-floating-point, transform,
+//     reorder, negabinary, embedded-coding count and decode (Sections 4.2, 5.2);
+//   * SZ pass: Lorenzo prediction, quantization codes and their histogram
+//     (Sections 4.1, 5.1);
+// each followed by a finalizer run by the last workgroup to finish.
 //
-// Section references are to arXiv:1806.08901.
+// Every workgroup of the ZFP and SZ passes owns an aligned, power-of-two
+// chunk of consecutive sampled blocks and reduces it to one partial, so the
+// partial sums are exact subtrees of the adjacent-pair tree over all blocks.
 #pragma once
-
-#include <type_traits>
 
 #include "device.hpp"
 
@@ -17,21 +24,42 @@ template <int D> struct Order {
   static constexpr OrderTable<D> table{};
 };
 
-// LDS scratch of one workgroup for a tile.
+// LDS of one workgroup: per-block values of the current tile, and the
+// binary-counter stack that folds tile sums into the workgroup's subtree.
 struct TileLds {
   double sse[kMaxTile];
   double err[kMaxTile];
-  uint32_t a[kMaxTile];   // ZFP: bits; SZ: unpredictable count
-  uint32_t b[kMaxTile];   // ZFP: significant bits
+  uint32_t a[kMaxTile];
+  uint32_t b[kMaxTile];
   double red[kWaves];
+  double stk[24];
+  double maxerr;
+  uint64_t sa, sb;
+  int sp;
+  uint32_t pushes;
+  int last;
 };
 
 __device__ inline bool skip_request(const ReqState *st) {
-  return (__atomic_load_n(&st->flags, __ATOMIC_RELAXED) & kSkipFlags) != 0;
+  return (get_u32(&st->flags) & kSkipFlags) != 0;
+}
+
+// Last-workgroup detection: true in every thread of the workgroup that
+// completes `counter` to `total`.  Each thread first waits for its own
+// memory operations (atomic partial stores, histogram atomics) to complete.
+__device__ inline bool last_to_finish(uint32_t *counter, uint32_t total, int *s_flag) {
+  wait_memory();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = old == total - 1;
+  }
+  __syncthreads();
+  return *s_flag != 0;
 }
 
 // ===========================================================================
-// Value range (Algorithm 1, line 2): min/max over ALL values, non-finite scan
+// Value range (Algorithm 1, line 2)
 // ===========================================================================
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -40,105 +68,83 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { using V = f32x4; static constexpr int N = 4; };
 template <> struct Vec16<double> { using V = f64x2; static constexpr int N = 2; };
 
-template <typename T>
-__device__ inline bool nonfinite(T v) {
-  using Q = Prec<T>;
-  const auto b = Q::bits(v);
-  constexpr int EBITS = Q::W - 1 - Q::MANT;
-  return ((b >> Q::MANT) & ((1u << EBITS) - 1)) == ((1u << EBITS) - 1);
-}
-
+// Running min, max and the largest magnitude bit pattern (high word for
+// binary64): a value is NaN or infinite iff its magnitude bits reach the
+// all-ones exponent, so one integer max per value replaces a compare.
 template <typename T>
 struct RangeAcc {
   T lo, hi;
-  bool bad;
-  __device__ RangeAcc() : lo(INFINITY), hi(-INFINITY), bad(false) {}
+  uint32_t amax;
+  __device__ RangeAcc() : lo(INFINITY), hi(-INFINITY), amax(0u) {}
   __device__ void add(T v) {
     lo = fmin(lo, v);
     hi = fmax(hi, v);
-    bad |= nonfinite(v);
+    if constexpr (sizeof(T) == 4)
+      amax = max(amax, __float_as_uint(v) & 0x7fffffffu);
+    else
+      amax = max(amax, (uint32_t)((uint64_t)__double_as_longlong(v) >> 32) & 0x7fffffffu);
   }
 };
 
-// Scans values [beg, end) of the field: vector part with 16-byte loads, the
-// unaligned head/tail element by element.  `lane0`/`nlanes` index the threads
-// taking part.
+// Scans values [beg, end) with the threads of one workgroup: 16-byte
+// non-temporal loads, 8 per thread in flight, unaligned head/tail singly.
 template <typename T>
-__device__ inline void range_scan(const T *x, int64_t beg, int64_t end, int64_t lane0,
-                                  int64_t nlanes, RangeAcc<T> &acc) {
+__device__ inline void range_scan(const T *x, int64_t beg, int64_t end, RangeAcc<T> &acc) {
   using V = typename Vec16<T>::V;
   constexpr int VN = Vec16<T>::N;
+  constexpr int U = 8;
+  const int64_t lane = threadIdx.x;
   const uintptr_t a = (uintptr_t)(x + beg);
   int64_t head = (int64_t)(((16 - (a & 15)) & 15) / sizeof(T));
   if (head > end - beg) head = end - beg;
   const int64_t nvec = (end - beg - head) / VN;
   const V *xv = (const V *)(x + beg + head);
-  int64_t i = lane0;
-  for (; i + 3 * nlanes < nvec; i += 4 * nlanes) {
-    const V v0 = __builtin_nontemporal_load(xv + i);
-    const V v1 = __builtin_nontemporal_load(xv + i + nlanes);
-    const V v2 = __builtin_nontemporal_load(xv + i + 2 * nlanes);
-    const V v3 = __builtin_nontemporal_load(xv + i + 3 * nlanes);
-    if constexpr (VN == 4) {
-      acc.add(v0.x); acc.add(v0.y); acc.add(v0.z); acc.add(v0.w);
-      acc.add(v1.x); acc.add(v1.y); acc.add(v1.z); acc.add(v1.w);
-      acc.add(v2.x); acc.add(v2.y); acc.add(v2.z); acc.add(v2.w);
-      acc.add(v3.x); acc.add(v3.y); acc.add(v3.z); acc.add(v3.w);
-    } else {
-      acc.add(v0.x); acc.add(v0.y); acc.add(v1.x); acc.add(v1.y);
-      acc.add(v2.x); acc.add(v2.y); acc.add(v3.x); acc.add(v3.y);
+  int64_t i = lane;
+  for (; i + (U - 1) * kThreads < nvec; i += U * kThreads) {
+    V v[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) v[k] = __builtin_nontemporal_load(xv + i + k * kThreads);
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+#pragma unroll
+      for (int e = 0; e < VN; e++) acc.add(v[k][e]);
     }
   }
-  for (; i < nvec; i += nlanes) {
+  for (; i < nvec; i += kThreads) {
     const V v = __builtin_nontemporal_load(xv + i);
-    if constexpr (VN == 4) {
-      acc.add(v.x); acc.add(v.y); acc.add(v.z); acc.add(v.w);
-    } else {
-      acc.add(v.x); acc.add(v.y);
-    }
+#pragma unroll
+    for (int e = 0; e < VN; e++) acc.add(v[e]);
   }
   const int64_t tail0 = beg + head + nvec * VN;
-  if (lane0 < head) acc.add(x[beg + lane0]);
-  if (lane0 < end - tail0) acc.add(x[tail0 + lane0]);
+  if (lane < head) acc.add(x[beg + lane]);
+  if (lane < end - tail0) acc.add(x[tail0 + lane]);
 }
 
-// Workgroup reduction of the accumulators; thread 0 gets the result.
+// Workgroup min/max/amax; every thread returns the workgroup's values.
 template <typename T>
-__device__ inline RangePart range_reduce_wg(RangeAcc<T> acc, double *sh_lo, double *sh_hi,
-                                            uint32_t *sh_bad) {
-  double lo = (double)acc.lo, hi = (double)acc.hi;
-  uint32_t bad = acc.bad ? 1u : 0u;
+__device__ inline void range_reduce_wg(RangeAcc<T> acc, double &lo, double &hi, uint32_t &amax) {
+  lo = (double)acc.lo;
+  hi = (double)acc.hi;
+  amax = acc.amax;
 #pragma unroll
   for (int s = 1; s < kWave; s <<= 1) {
     lo = fmin(lo, __shfl_xor(lo, s));
     hi = fmax(hi, __shfl_xor(hi, s));
-    bad |= (uint32_t)__shfl_xor((int)bad, s);
+    amax = max(amax, (uint32_t)__shfl_xor((int)amax, s));
   }
+  __shared__ double s_lo[kWaves], s_hi[kWaves];
+  __shared__ uint32_t s_am[kWaves];
   const int w = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    sh_lo[w] = lo;
-    sh_hi[w] = hi;
-    sh_bad[w] = bad;
+    s_lo[w] = lo;
+    s_hi[w] = hi;
+    s_am[w] = amax;
   }
   __syncthreads();
-  RangePart p{};
-  if (threadIdx.x == 0) {
-    p.lo = sh_lo[0];
-    p.hi = sh_hi[0];
-    p.bad = sh_bad[0];
-    for (int k = 1; k < kWaves; k++) {
-      p.lo = fmin(p.lo, sh_lo[k]);
-      p.hi = fmax(p.hi, sh_hi[k]);
-      p.bad |= sh_bad[k];
-    }
-  }
+  lo = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
+  hi = fmax(fmax(s_hi[0], s_hi[1]), fmax(s_hi[2], s_hi[3]));
+  amax = max(max(s_am[0], s_am[1]), max(s_am[2], s_am[3]));
   __syncthreads();
-  return p;
-}
-
-__device__ inline void zero_result(szsel_result *res) {
-  uint64_t *w = (uint64_t *)res;
-  for (size_t k = 0; k < sizeof(szsel_result) / 8; k++) w[k] = 0;
 }
 
 // Turns the min/max of the whole field into the request's state and the
@@ -146,9 +152,10 @@ __device__ inline void zero_result(szsel_result *res) {
 __device__ inline void range_finalize_one(const ReqDesc &r, double lo, double hi, bool bad) {
   ReqState *st = r.st;
   szsel_result *res = r.res;
-  zero_result(res);
+  uint64_t *w = (uint64_t *)res;
+  for (size_t k = 0; k < sizeof(szsel_result) / 8; k++) put_u64(w + k, 0);
   const bool selecting = r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB;
-  res->choice = -1;
+  int32_t choice = -1;
   uint32_t flags = 0;
   double vr = 0.0, eb_abs = 0.0;
   int minexp = 0;
@@ -166,26 +173,61 @@ __device__ inline void range_finalize_one(const ReqDesc &r, double lo, double hi
       flags = SZSEL_FLAG_NO_BLOCKS;
     else
       minexp = floor_log2_bits(eb_abs);
-    if (flags && selecting) res->choice = 0;
+    if (flags && selecting) choice = 0;
   }
-  res->vmin = lo;
-  res->vmax = hi;
-  res->vr = vr;
-  res->eb_abs = eb_abs;
-  res->minexp = minexp;
-  res->flags = flags;
-  st->vmin = lo;
-  st->vmax = hi;
-  st->vr = vr;
-  st->eb_abs = eb_abs;
-  st->minexp = minexp;
+  put_f64(&res->vmin, lo);
+  put_f64(&res->vmax, hi);
+  put_f64(&res->vr, vr);
+  put_f64(&res->eb_abs, eb_abs);
+  put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
+  put_u64((uint64_t *)&res->minexp, (uint64_t)(uint32_t)minexp);
+  put_f64(&st->vmin, lo);
+  put_f64(&st->vmax, hi);
+  put_f64(&st->vr, vr);
+  put_f64(&st->eb_abs, eb_abs);
+  put_i32(&st->minexp, minexp);
   // SZ's own bin width (Section 5.1.4: delta = 2 eb_abs) unless Algorithm 1
   // derives it from the ZFP estimate later.
   const double delta = 2.0 * eb_abs;
-  st->delta = delta;
-  st->inv = 1.0 / delta;
-  st->eb_sz = 0.5 * delta;
-  __atomic_store_n(&st->flags, flags, __ATOMIC_RELAXED);
+  put_f64(&st->delta, delta);
+  put_f64(&st->inv, 1.0 / delta);
+  put_f64(&st->eb_sz, 0.5 * delta);
+  put_u32(&st->flags, flags);
+}
+
+// Whole range pass of workgroup `w` of `nwg`: scan, partial, and (last
+// workgroup) the finalizer.
+template <typename T>
+__device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
+  RangeAcc<T> acc;
+  const int64_t beg = (int64_t)w * r.rchunk;
+  const int64_t end = min(r.n, beg + r.rchunk);
+  if (beg < end) range_scan<T>((const T *)r.field, beg, end, acc);
+  double lo, hi;
+  uint32_t amax;
+  range_reduce_wg<T>(acc, lo, hi, amax);
+  if (threadIdx.x == 0) {
+    put_f64(r.rp.sse + w, lo);
+    put_f64(r.rp.err + w, hi);
+    put_u64(r.rp.a + w, amax >= (sizeof(T) == 4 ? 0x7f800000u : 0x7ff00000u) ? 1u : 0u);
+  }
+  if (!last_to_finish(&r.st->range_done, (uint32_t)r.nrange, &L.last)) return;
+  double tlo = INFINITY, thi = -INFINITY;
+  uint32_t bad = 0;
+  for (int k = threadIdx.x; k < r.nrange; k += kThreads) {
+    tlo = fmin(tlo, get_f64(r.rp.sse + k));
+    thi = fmax(thi, get_f64(r.rp.err + k));
+    bad |= (uint32_t)get_u64(r.rp.a + k);
+  }
+  RangeAcc<double> t;
+  t.lo = tlo;
+  t.hi = thi;
+  t.amax = bad;
+  range_reduce_wg<double>(t, lo, hi, amax);
+  if (threadIdx.x == 0) {
+    range_finalize_one(r, lo, hi, amax != 0);
+    put_u32(&r.st->range_done, 0);
+  }
 }
 
 // ===========================================================================
@@ -300,11 +342,13 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   return out;
 }
 
-// Reduces the tile's per-block values in LDS (adjacent tree for the SSE).
-// Returns on thread 0: sse, maxerr, sum a, sum b.
+// Reduces the tile's per-block values in LDS (adjacent tree for the SSE)
+// with wave 0; results valid on thread 0.
 __device__ inline void tile_reduce(TileLds &L, int tile, double &sse, double &maxerr,
                                    uint64_t &sa, uint64_t &sb) {
-  // wave 0: each lane folds its aligned group of tile/64 entries
+  sse = 0.0;
+  maxerr = 0.0;
+  sa = sb = 0;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     const int c = tile > kWave ? tile / kWave : 1;
@@ -329,28 +373,56 @@ __device__ inline void tile_reduce(TileLds &L, int tile, double &sse, double &ma
       a = (uint64_t)L.a[k] + L.a[k + 1] + L.a[k + 2] + L.a[k + 3];
       b = (uint64_t)L.b[k] + L.b[k + 1] + L.b[k + 2] + L.b[k + 3];
     }
-    v = group_tree_sum<kWave>(v);
-    m = group_max<kWave>(m);
-    a = group_isum<kWave>(a);
-    b = group_isum<kWave>(b);
-    sse = v;
-    maxerr = m;
-    sa = a;
-    sb = b;
+    sse = group_tree_sum<kWave>(v);
+    maxerr = group_max<kWave>(m);
+    sa = group_isum<kWave>(a);
+    sb = group_isum<kWave>(b);
   }
 }
 
-// One tile of sampled blocks through the ZFP side; writes zpart[t].
+// Workgroup accumulator over its tiles (thread 0): the SSE subtrees of the
+// tiles are folded with a binary counter, which associates exactly like the
+// adjacent-pair tree over the workgroup's aligned chunk.
+__device__ inline void wg_acc_reset(TileLds &L) {
+  if (threadIdx.x == 0) {
+    L.sp = 0;
+    L.pushes = 0;
+    L.maxerr = 0.0;
+    L.sa = L.sb = 0;
+  }
+}
+
+__device__ inline void wg_acc_push(TileLds &L, double sse, double maxerr, uint64_t sa, uint64_t sb) {
+  if (threadIdx.x == 0) {
+    double v = sse;
+    for (uint32_t m = L.pushes; m & 1; m >>= 1) v = L.stk[--L.sp] + v;
+    L.stk[L.sp++] = v;
+    L.pushes++;
+    L.maxerr = fmax(L.maxerr, maxerr);
+    L.sa += sa;
+    L.sb += sb;
+  }
+}
+
+__device__ inline void wg_acc_store(TileLds &L, const Parts &p, int w) {
+  if (threadIdx.x == 0) {
+    put_f64(p.sse + w, L.stk[0]);
+    put_f64(p.err + w, L.maxerr);
+    put_u64(p.a + w, L.sa);
+    put_u64(p.b + w, L.sb);
+  }
+}
+
+// One tile (<= kMaxTile blocks starting at `base`) of the ZFP side.
 template <typename T, int D>
-__device__ inline void zfp_tile(const ReqDesc &r, int t, int minexp, TileLds &L) {
+__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, int tile, int minexp, TileLds &L) {
   constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
   const T *x = (const T *)r.field;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
   const int perm_i = Order<D>::table.perm[i];
   const int inv_i = Order<D>::table.inv[i];
-  const int rounds = r.tile / (kWaves * BPW);
-  const int64_t base = (int64_t)t * r.tile;
+  const int rounds = tile / (kWaves * BPW);
   for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
@@ -376,101 +448,122 @@ __device__ inline void zfp_tile(const ReqDesc &r, int t, int minexp, TileLds &L)
   __syncthreads();
   double sse, maxerr;
   uint64_t sa, sb;
-  tile_reduce(L, r.tile, sse, maxerr, sa, sb);
-  if (threadIdx.x == 0) {
-    TilePart p;
-    p.sse = sse;
-    p.maxerr = maxerr;
-    p.bits = sa;
-    p.cnt = sb;
-    r.zpart[t] = p;
-  }
+  tile_reduce(L, tile, sse, maxerr, sa, sb);
+  wg_acc_push(L, sse, maxerr, sa, sb);
   __syncthreads();
 }
 
-// Sum of the tiles' partials: SSE by the adjacent tree, integers exactly.
-__device__ inline void tiles_total(const TilePart *part, int ntiles, double *sh, double &sse,
-                                   double &maxerr, uint64_t &bits, uint64_t &cnt) {
-  int64_t p = 1;
-  while (p < ntiles) p <<= 1;
-  const int64_t chunk = p > kThreads ? p / kThreads : 1;
-  const int t = threadIdx.x;
-  double stk[40];
-  int sp = 0;
+// Adjacent-pair tree (and max, integer sums) over the n per-workgroup
+// partials of a pass, by the whole workgroup with coalesced atomic loads:
+// thread t folds the aligned run [t*c, (t+1)*c), c = P/256 <= 32, in
+// registers, then the wave butterfly and the fixed combine of the 4 waves.
+__device__ inline void parts_total(const Parts &p, int n, TileLds &L, double &sse,
+                                   double &maxerr, uint64_t &sa, uint64_t &sb) {
+  int P = 1;
+  while (P < n) P <<= 1;
+  const int c = P > kThreads ? P / kThreads : 1;
+  const int beg = threadIdx.x * c;
+  double v[32];
   double m = 0.0;
-  uint64_t b = 0, c = 0;
-  const int64_t beg = (int64_t)t * chunk;
-  for (int64_t k = 0; k < chunk; k++) {
-    const int64_t idx = beg + k;
-    double v = 0.0;
-    if (idx < ntiles) {
-      const TilePart tp = part[idx];
-      v = tp.sse;
-      m = fmax(m, tp.maxerr);
-      b += tp.bits;
-      c += tp.cnt;
+  uint64_t a = 0, b = 0;
+#pragma unroll
+  for (int k = 0; k < 32; k++) {
+    const int idx = beg + k;
+    v[k] = 0.0;
+    if (k < c && idx < n) {
+      v[k] = get_f64(p.sse + idx);
+      m = fmax(m, get_f64(p.err + idx));
+      a += get_u64(p.a + idx);
+      b += get_u64(p.b + idx);
     }
-    for (int64_t q = k; q & 1; q >>= 1) v = stk[--sp] + v;
-    stk[sp++] = v;
   }
-  double v = group_tree_sum<kWave>(stk[0]);
+#pragma unroll
+  for (int s = 1; s < 32; s <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 32; k += 2 * s) v[k] = v[k] + v[k + s];
+  }
+  double t = group_tree_sum<kWave>(v[0]);
   m = group_max<kWave>(m);
+  a = group_isum<kWave>(a);
   b = group_isum<kWave>(b);
-  c = group_isum<kWave>(c);
   __shared__ double s_m[kWaves];
-  __shared__ uint64_t s_b[kWaves], s_c[kWaves];
-  const int w = t / kWave;
-  if ((t & (kWave - 1)) == 0) {
-    sh[w] = v;
+  __shared__ uint64_t s_a[kWaves], s_b[kWaves];
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    L.red[w] = t;
     s_m[w] = m;
+    s_a[w] = a;
     s_b[w] = b;
-    s_c[w] = c;
   }
   __syncthreads();
-  sse = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  sse = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
   maxerr = fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
-  bits = s_b[0] + s_b[1] + s_b[2] + s_b[3];
-  cnt = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+  sa = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+  sb = s_b[0] + s_b[1] + s_b[2] + s_b[3];
   __syncthreads();
 }
 
 // ZFP totals, PSNR_zfp and (for Algorithm 1) the SZ bin width delta whose
 // uniform-error PSNR equals PSNR_zfp (Eq. 10 inverted: delta = sqrt(12 MSE)).
 template <typename T, int D>
-__device__ inline void zfp_finalize(const ReqDesc &r, double *sh) {
+__device__ inline void zfp_finalize(const ReqDesc &r, TileLds &L) {
   double sse, maxerr;
   uint64_t bits, nsb;
-  tiles_total(r.zpart, r.ntiles, sh, sse, maxerr, bits, nsb);
+  parts_total(r.zp, r.nzfp, L, sse, maxerr, bits, nsb);
   if (threadIdx.x == 0) {
     constexpr int BS = 1 << (2 * D);
     ReqState *st = r.st;
     szsel_result *res = r.res;
     const double nv = (double)(r.nblk * BS);
     const double mse = sse / nv;
-    res->zfp_sse = sse;
-    res->zfp_mse = mse;
-    res->zfp_bits = bits;
-    res->zfp_values = (uint64_t)(r.nblk * BS);
-    res->zfp_blocks = (uint64_t)r.nblk;
-    res->zfp_nsb_total = nsb;
-    res->zfp_nsb_mean = (double)nsb / nv;
-    res->zfp_bitrate = (double)bits / nv;
-    res->zfp_maxerr = maxerr;
-    res->zfp_psnr = mse > 0.0 ? 20.0 * log10(st->vr) - 10.0 * log10(mse) : INFINITY;
+    const double vr = get_f64(&st->vr);
+    put_f64(&res->zfp_sse, sse);
+    put_f64(&res->zfp_mse, mse);
+    put_u64(&res->zfp_bits, bits);
+    put_u64(&res->zfp_values, (uint64_t)(r.nblk * BS));
+    put_u64(&res->zfp_blocks, (uint64_t)r.nblk);
+    put_u64(&res->zfp_nsb_total, nsb);
+    put_f64(&res->zfp_nsb_mean, (double)nsb / nv);
+    put_f64(&res->zfp_bitrate, (double)bits / nv);
+    put_f64(&res->zfp_maxerr, maxerr);
+    put_f64(&res->zfp_psnr, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
     if (r.op == SZSEL_OP_SELECT) {
       double delta;
       if (mse > 0.0) {
         delta = sqrt(12.0 * mse);
       } else {
-        delta = 2.0 * st->eb_abs;
-        res->flags |= SZSEL_FLAG_ZERO_MSE;
+        delta = 2.0 * get_f64(&st->eb_abs);
+        const uint64_t fc = get_u64((uint64_t *)&res->flags);
+        put_u64((uint64_t *)&res->flags, fc | SZSEL_FLAG_ZERO_MSE);
       }
-      st->delta = delta;
-      st->inv = 1.0 / delta;
-      st->eb_sz = 0.5 * delta;
+      put_f64(&st->delta, delta);
+      put_f64(&st->inv, 1.0 / delta);
+      put_f64(&st->eb_sz, 0.5 * delta);
     }
-    st->zfp_done = 0;
+    put_u32(&st->zfp_done, 0);
   }
+}
+
+// Whole ZFP pass of workgroup w.  Returns true in the workgroup that ran the
+// finalizer.
+template <typename T, int D>
+__device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
+  const int minexp = get_i32(&r.st->minexp);
+  const int tile = r.zblk < kMaxTile ? r.zblk : kMaxTile;
+  const int ntile = r.zblk / tile;
+  wg_acc_reset(L);
+  __syncthreads();
+  for (int k = 0; k < ntile; k++) {
+    const int64_t base = (int64_t)w * r.zblk + (int64_t)k * tile;
+    if (base < r.nblk)
+      zfp_tile<T, D>(r, base, tile, minexp, L);
+    else
+      wg_acc_push(L, 0.0, 0.0, 0, 0);
+  }
+  wg_acc_store(L, r.zp, w);
+  if (!last_to_finish(&r.st->zfp_done, (uint32_t)r.nzfp, &L.last)) return false;
+  zfp_finalize<T, D>(r, L);
+  return true;
 }
 
 // ===========================================================================
@@ -534,18 +627,16 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
   return 0;
 }
 
-// One tile of sampled blocks through the SZ side.  Codes go to the LDS
-// window s_hist (or straight to the global histogram outside it); the caller
-// flushes s_hist.  Writes spart[t].
+// One tile of the SZ side.  Codes go to the LDS window s_hist (or straight
+// to the global histogram outside it).
 template <typename T, int D>
-__device__ inline void sz_tile(const ReqDesc &r, int t, double delta, double inv, double ebsz,
-                               TileLds &L, uint32_t *s_hist) {
+__device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
+                               double ebsz, TileLds &L, uint32_t *s_hist) {
   constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
   const T *x = (const T *)r.field;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
-  const int rounds = r.tile / (kWaves * BPW);
-  const int64_t base = (int64_t)t * r.tile;
+  const int rounds = tile / (kWaves * BPW);
   for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
@@ -560,9 +651,9 @@ __device__ inline void sz_tile(const ReqDesc &r, int t, double delta, double inv
       const double pred = lorenzo_pred<T, D>(x, r, p);
       code = quantize<T>(xv, pred, delta, inv, ebsz, e2, ae);
       if (code) {
-        const int w = code - kHistLo;
-        if (w >= 0 && w < kHistWin)
-          atomicAdd(&s_hist[w], 1u);
+        const int wi = code - kHistLo;
+        if (wi >= 0 && wi < kHistWin)
+          atomicAdd(&s_hist[wi], 1u);
         else
           atomicAdd(&r.hist[code], 1u);
       }
@@ -582,15 +673,8 @@ __device__ inline void sz_tile(const ReqDesc &r, int t, double delta, double inv
   __syncthreads();
   double sse, maxerr;
   uint64_t sa, sb;
-  tile_reduce(L, r.tile, sse, maxerr, sa, sb);
-  if (threadIdx.x == 0) {
-    TilePart p;
-    p.sse = sse;
-    p.maxerr = maxerr;
-    p.bits = 0;
-    p.cnt = sa;
-    r.spart[t] = p;
-  }
+  tile_reduce(L, tile, sse, maxerr, sa, sb);
+  wg_acc_push(L, sse, maxerr, sa, sb);
   __syncthreads();
 }
 
@@ -611,79 +695,120 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
 // Entropy of the code histogram (Eq. 5 with P_i = h_i/n), the SZ bit-rate
 // (entropy + offset + W escape bits per unpredictable point, Section 6.2),
 // both PSNRs, and the selection of Algorithm 1 (lower bit-rate, ties to ZFP).
-// Leaves the global histogram zeroed for the next request.
+// The sum of h log2 h runs over 256 chunks of 256 bins: a wave reads a chunk
+// with one coalesced 4-bin load per lane and reduces it exactly like the
+// adjacent-pair tree; wave 0 then folds the 256 chunk sums.  Leaves the
+// global histogram zeroed for the next request.
 template <typename T, int D>
-__device__ inline void sz_finalize(const ReqDesc &r, double *sh) {
+__device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
   constexpr int BS = 1 << (2 * D);
   double sse, maxerr;
-  uint64_t dummy, unpred;
-  tiles_total(r.spart, r.ntiles, sh, sse, maxerr, dummy, unpred);
+  uint64_t unpred, unused;
+  parts_total(r.sp, r.nsz, L, sse, maxerr, unpred, unused);
   const double nv = (double)(r.nblk * BS);
-  // sum over the 65536 bins of h log2 h, adjacent tree: thread t folds the
-  // aligned chunk of 256 bins with a binary-counter pass
-  constexpr int chunk = kBins / kThreads;
-  const int t = threadIdx.x;
-  double stk[12];
-  int sp = 0;
-  for (int k = 0; k < chunk; k++) {
-    const int idx = t * chunk + k;
-    const uint32_t h = idx == 0 ? (uint32_t)unpred : r.hist[idx];
-    if (r.dbg_hist) r.dbg_hist[idx] = h;
-    double v = 0.0;
-    if (h) {
-      const double hd = (double)h;
-      v = hd * log2(hd);
-      r.hist[idx] = 0;
+  __shared__ double s_chunk[kBins / 256];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  constexpr int kChunks = kBins / 256;
+  for (int c0 = wave; c0 < kChunks; c0 += kWaves * 4) {
+    uint64_t w0[4], w1[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int c = c0 + u * kWaves;
+      const int bin = c * 256 + lane * 4;
+      w0[u] = get_u64((const uint64_t *)(r.hist + bin));
+      w1[u] = get_u64((const uint64_t *)(r.hist + bin + 2));
     }
-    for (int q = k; q & 1; q >>= 1) v = stk[--sp] + v;
-    stk[sp++] = v;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int c = c0 + u * kWaves;
+      const int bin = c * 256 + lane * 4;
+      uint32_t h[4] = {(uint32_t)w0[u], (uint32_t)(w0[u] >> 32), (uint32_t)w1[u],
+                       (uint32_t)(w1[u] >> 32)};
+      if (bin == 0) h[0] = (uint32_t)unpred;  // code 0: unpredictable points
+      double t[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const double hd = (double)h[e];
+        t[e] = h[e] ? hd * log2(hd) : 0.0;
+      }
+      if (r.dbg_hist) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) r.dbg_hist[bin + e] = h[e];
+      }
+      if (w0[u]) put_u64((uint64_t *)(r.hist + bin), 0);
+      if (w1[u]) put_u64((uint64_t *)(r.hist + bin + 2), 0);
+      double v = (t[0] + t[1]) + (t[2] + t[3]);
+      v = group_tree_sum<kWave>(v);
+      if (lane == 0) s_chunk[c] = v;
+    }
   }
-  double s = group_tree_sum<kWave>(stk[0]);
-  const int w = t / kWave;
   __syncthreads();
-  if ((t & (kWave - 1)) == 0) sh[w] = s;
-  __syncthreads();
-  if (t == 0) {
-    s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    ReqState *st = r.st;
-    szsel_result *res = r.res;
-    const double H = log2(nv) - s / nv;
-    double br = H + r.sz_offset;
-    br = br + ((double)unpred * (double)Prec<T>::W) / nv;
-    const double delta = st->delta;
-    res->sz_delta = delta;
-    res->sz_inv_delta = st->inv;
-    res->sz_eb = st->eb_sz;
-    res->sz_entropy = H;
-    res->sz_bitrate = br;
-    res->sz_sse = sse;
-    res->sz_mse = sse / nv;
-    res->sz_maxerr = maxerr;
-    res->sz_values = (uint64_t)(r.nblk * BS);
-    res->sz_unpredictable = unpred;
-    res->sz_psnr_model = 20.0 * log10(st->vr / delta) + 10.0 * log10(12.0);
-    res->sz_psnr_measured =
-        res->sz_mse > 0.0 ? 20.0 * log10(st->vr) - 10.0 * log10(res->sz_mse) : INFINITY;
-    if (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) {
-      res->choice = br < res->zfp_bitrate ? 0 : 1;
-      res->chosen_eb = res->choice == 0 ? st->eb_sz : st->eb_abs;
-      if (st->eb_sz > st->eb_abs) res->flags |= SZSEL_FLAG_EB_EXCEEDS;
+  if (threadIdx.x < kWave) {
+    const int k = 4 * lane;
+    double v = (s_chunk[k] + s_chunk[k + 1]) + (s_chunk[k + 2] + s_chunk[k + 3]);
+    v = group_tree_sum<kWave>(v);
+    if (lane == 0) {
+      ReqState *st = r.st;
+      szsel_result *res = r.res;
+      const double H = log2(nv) - v / nv;
+      double br = H + r.sz_offset;
+      br = br + ((double)unpred * (double)Prec<T>::W) / nv;
+      const double delta = get_f64(&st->delta);
+      const double eb_sz = get_f64(&st->eb_sz);
+      const double eb_abs = get_f64(&st->eb_abs);
+      const double vr = get_f64(&st->vr);
+      const double mse = sse / nv;
+      put_f64(&res->sz_delta, delta);
+      put_f64(&res->sz_inv_delta, get_f64(&st->inv));
+      put_f64(&res->sz_eb, eb_sz);
+      put_f64(&res->sz_entropy, H);
+      put_f64(&res->sz_bitrate, br);
+      put_f64(&res->sz_sse, sse);
+      put_f64(&res->sz_mse, mse);
+      put_f64(&res->sz_maxerr, maxerr);
+      put_u64(&res->sz_values, (uint64_t)(r.nblk * BS));
+      put_u64(&res->sz_unpredictable, unpred);
+      put_f64(&res->sz_psnr_model, 20.0 * log10(vr / delta) + 10.0 * log10(12.0));
+      put_f64(&res->sz_psnr_measured, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
+      if (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) {
+        const double br_zfp = get_f64(&res->zfp_bitrate);
+        const int32_t choice = br < br_zfp ? 0 : 1;
+        uint32_t flags = (uint32_t)get_u64((uint64_t *)&res->flags);
+        if (eb_sz > eb_abs) flags |= SZSEL_FLAG_EB_EXCEEDS;
+        put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
+        put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
+      }
+      put_u32(&st->sz_done, 0);
     }
-    st->sz_done = 0;
   }
   __syncthreads();
 }
 
-// Last-workgroup detection: returns true in every thread of the workgroup
-// that completes `counter` to `total`.
-__device__ inline bool last_to_finish(uint32_t *counter, uint32_t total, int *s_flag) {
-  __threadfence();
+// Whole SZ pass of workgroup w (LDS window cleared on entry, flushed once at
+// the end).  Returns true in the workgroup that ran the finalizer.
+template <typename T, int D>
+__device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hist) {
+  const double delta = get_f64(&r.st->delta);
+  const double inv = get_f64(&r.st->inv);
+  const double ebsz = get_f64(&r.st->eb_sz);
+  const int tile = r.sblk < kMaxTile ? r.sblk : kMaxTile;
+  const int ntile = r.sblk / tile;
+  hist_clear(s_hist);
+  wg_acc_reset(L);
   __syncthreads();
-  if (threadIdx.x == 0) *s_flag = atomicAdd(counter, 1u) == total - 1;
+  for (int k = 0; k < ntile; k++) {
+    const int64_t base = (int64_t)w * r.sblk + (int64_t)k * tile;
+    if (base < r.nblk)
+      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist);
+    else
+      wg_acc_push(L, 0.0, 0.0, 0, 0);
+  }
   __syncthreads();
-  const bool last = *s_flag != 0;
-  if (last) __threadfence();
-  return last;
+  hist_flush(s_hist, r.hist);
+  wg_acc_store(L, r.sp, w);
+  if (!last_to_finish(&r.st->sz_done, (uint32_t)r.nsz, &L.last)) return false;
+  sz_finalize<T, D>(r, L);
+  return true;
 }
 
 }  // namespace szsel

@@ -11,55 +11,23 @@ namespace szsel {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
-  __shared__ double s_lo[kWaves], s_hi[kWaves];
-  __shared__ uint32_t s_bad[kWaves];
-  __shared__ int s_last;
-  RangeAcc<T> acc;
-  range_scan<T>((const T *)r.field, 0, r.n, (int64_t)blockIdx.x * kThreads + threadIdx.x,
-                (int64_t)gridDim.x * kThreads, acc);
-  const RangePart p = range_reduce_wg<T>(acc, s_lo, s_hi, s_bad);
-  if (threadIdx.x == 0) r.rpart[blockIdx.x] = p;
-  if (!last_to_finish(&r.st->range_done, gridDim.x, &s_last)) return;
-  RangeAcc<double> tot;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += kThreads) {
-    const RangePart q = r.rpart[k];
-    tot.lo = fmin(tot.lo, q.lo);
-    tot.hi = fmax(tot.hi, q.hi);
-    tot.bad |= q.bad != 0;
-  }
-  const RangePart all = range_reduce_wg<double>(tot, s_lo, s_hi, s_bad);
-  if (threadIdx.x == 0) {
-    range_finalize_one(r, all.lo, all.hi, all.bad != 0);
-    r.st->range_done = 0;
-  }
+  __shared__ TileLds L;
+  range_wg<T>(r, blockIdx.x, L);
 }
 
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
-  __shared__ int s_last;
   if (skip_request(r.st)) return;
-  const int minexp = r.st->minexp;
-  for (int t = blockIdx.x; t < r.ntiles; t += gridDim.x) zfp_tile<T, D>(r, t, minexp, L);
-  if (!last_to_finish(&r.st->zfp_done, gridDim.x, &s_last)) return;
-  zfp_finalize<T, D>(r, L.red);
+  zfp_wg<T, D>(r, blockIdx.x, L);
 }
 
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   __shared__ TileLds L;
   __shared__ uint32_t s_hist[kHistWin];
-  __shared__ int s_last;
   if (skip_request(r.st)) return;
-  const double delta = r.st->delta, inv = r.st->inv, ebsz = r.st->eb_sz;
-  hist_clear(s_hist);
-  __syncthreads();
-  for (int t = blockIdx.x; t < r.ntiles; t += gridDim.x)
-    sz_tile<T, D>(r, t, delta, inv, ebsz, L, s_hist);
-  __syncthreads();
-  hist_flush(s_hist, r.hist);
-  if (!last_to_finish(&r.st->sz_done, gridDim.x, &s_last)) return;
-  sz_finalize<T, D>(r, L.red);
+  sz_wg<T, D>(r, blockIdx.x, L, s_hist);
 }
 
 static hipError_t mark(const hipEvent_t *ev, int k, hipStream_t s) {
@@ -100,6 +68,42 @@ static hipError_t launch_typed(const ReqDesc &r, hipStream_t s, const hipEvent_t
 
 hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
   return r.dtype == SZSEL_F32 ? launch_typed<float>(r, s, ev) : launch_typed<double>(r, s, ev);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of one request
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static size_t parts_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * 8, 256) * 4; }
+
+size_t request_workspace_bytes(int nrange, int nzfp, int nsz) {
+  return align_up(sizeof(ReqState), 256) + parts_bytes(nrange) + parts_bytes(nzfp) +
+         parts_bytes(nsz) + align_up(sizeof(uint32_t) * kBins, 256) +
+         align_up(sizeof(szsel_result), 256);
+}
+
+static Parts bind_parts(char *&p, int n) {
+  const size_t one = align_up((size_t)(n > 0 ? n : 1) * 8, 256);
+  Parts q;
+  q.sse = (double *)p;
+  q.err = (double *)(p + one);
+  q.a = (uint64_t *)(p + 2 * one);
+  q.b = (uint64_t *)(p + 3 * one);
+  p += 4 * one;
+  return q;
+}
+
+void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz) {
+  char *p = base;
+  r.st = (ReqState *)p;
+  p += align_up(sizeof(ReqState), 256);
+  r.rp = bind_parts(p, nrange);
+  r.zp = bind_parts(p, nzfp);
+  r.sp = bind_parts(p, nsz);
+  r.hist = (uint32_t *)p;
+  p += align_up(sizeof(uint32_t) * kBins, 256);
+  r.res = (szsel_result *)p;
 }
 
 }  // namespace szsel

@@ -12,4 +12,10 @@ namespace szsel {
 // and after the SZ pass (phase timers).
 hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev = nullptr);
 
+// Device bytes of one request's workspace (state, per-workgroup partials of
+// the three passes, 65536-bin histogram, result) for the given pass sizes,
+// and the binding of a zero-initialised region of that size to r.
+size_t request_workspace_bytes(int nrange, int nzfp, int nsz);
+void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz);
+
 }  // namespace szsel

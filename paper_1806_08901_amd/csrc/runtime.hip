@@ -19,41 +19,11 @@ using namespace szsel;
 namespace {
 
 constexpr int kSlots = 4;
-constexpr int kMaxRange = 4096;   // workgroups of a range pass
-constexpr int kMaxTiles = 65536;  // tiles per request
 
 struct Slot {
   char *mem = nullptr;
-  ReqState *st = nullptr;
-  RangePart *rpart = nullptr;
-  TilePart *zpart = nullptr;
-  TilePart *spart = nullptr;
-  uint32_t *hist = nullptr;
-  szsel_result *res = nullptr;
   hipEvent_t done = nullptr;
   bool used = false;
-};
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct SlotLayout {
-  size_t st, rpart, zpart, spart, hist, res, total;
-  SlotLayout() {
-    size_t o = 0;
-    st = o;
-    o = align_up(o + sizeof(ReqState), 256);
-    rpart = o;
-    o = align_up(o + sizeof(RangePart) * kMaxRange, 256);
-    zpart = o;
-    o = align_up(o + sizeof(TilePart) * kMaxTiles, 256);
-    spart = o;
-    o = align_up(o + sizeof(TilePart) * kMaxTiles, 256);
-    hist = o;
-    o = align_up(o + sizeof(uint32_t) * kBins, 256);
-    res = o;
-    o = align_up(o + sizeof(szsel_result), 256);
-    total = o;
-  }
 };
 
 }  // namespace
@@ -134,23 +104,35 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   }
   r.n = n;
   r.nblk = (int64_t)nblk;
+  // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
+  // consecutive sampled blocks, at least one round of 4 waves, sized for
+  // about 8 (ZFP) or 4 (SZ, which also flushes an LDS histogram) workgroups
+  // per CU, and never more than kMaxParts workgroups.
   const int bs = 1 << (2 * nd);
-  const int bpw = kWave / bs;
-  const int min_tile = kWaves * bpw;
-  int tile = nd == 3 ? 16 : (nd == 2 ? 64 : 256);
-  tile = std::max(tile, min_tile);
-  while ((int64_t)((nblk + tile - 1) / tile) > kMaxTiles && tile < kMaxTile) tile *= 2;
-  if ((int64_t)((nblk + tile - 1) / tile) > kMaxTiles)
-    return fail(ctx, SZSEL_EINVAL, "too many sampled blocks for one request; use a larger stride");
-  r.tile = tile;
-  r.ntiles = (int32_t)((nblk + tile - 1) / tile);
-  const int nt = std::max(1, r.ntiles);
-  r.nzfp = std::min(nt, 8 * ctx->ncu);
-  r.nsz = std::min(nt, 4 * ctx->ncu);
-  const int vn = 16 / (int)esz;
-  const int64_t per_wg = (int64_t)kThreads * vn * 4;
-  r.nrange = (int32_t)std::max<int64_t>(1, std::min<int64_t>((n + per_wg - 1) / per_wg,
-                                                              std::min(kMaxRange, 8 * ctx->ncu)));
+  const int min_chunk = kWaves * (kWave / bs);
+  auto chunk_for = [&](int target_wgs) {
+    const uint64_t want = (nblk + (uint64_t)target_wgs - 1) / (uint64_t)target_wgs;
+    uint64_t c = (uint64_t)min_chunk;
+    while (c < want) c <<= 1;
+    while ((nblk + c - 1) / c > (uint64_t)kMaxParts) c <<= 1;
+    return c;
+  };
+  const uint64_t zc = chunk_for(8 * ctx->ncu), sc = chunk_for(4 * ctx->ncu);
+  if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
+  r.zblk = (int32_t)zc;
+  r.sblk = (int32_t)sc;
+  r.nzfp = (int32_t)std::max<uint64_t>(1, (nblk + zc - 1) / zc);
+  r.nsz = (int32_t)std::max<uint64_t>(1, (nblk + sc - 1) / sc);
+  // range pass: contiguous chunks of whole 16-byte vectors, about 2
+  // workgroups per CU, at least 8 vectors per thread
+  const int64_t vn = 16 / (int64_t)esz;
+  const int64_t quantum = (int64_t)kThreads * vn;
+  int64_t chunk = (n + 2 * ctx->ncu - 1) / (2 * ctx->ncu);
+  chunk = std::max<int64_t>(chunk, 8 * quantum);
+  chunk = (chunk + quantum - 1) / quantum * quantum;
+  r.rchunk = chunk;
+  r.nrange = (int32_t)((n + chunk - 1) / chunk);
+  if (r.nrange > kMaxParts) return fail(ctx, SZSEL_EINVAL, "field too large for one request");
   return SZSEL_OK;
 }
 
@@ -194,12 +176,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
     e = hipStreamWaitEvent(s, sl.done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
   }
-  r.st = sl.st;
-  r.rpart = sl.rpart;
-  r.zpart = sl.zpart;
-  r.spart = sl.spart;
-  r.hist = sl.hist;
-  r.res = sl.res;
+  bind_request_workspace(r, sl.mem, kMaxParts, kMaxParts, kMaxParts);
   if (ctx->dbg_armed) {
     r.dbg_codes = ctx->dbg.codes;
     r.dbg_zbits = ctx->dbg.zfp_bits;
@@ -220,7 +197,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   }
   e = launch_request(r, s, ev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
-  e = hipMemcpyAsync(out, sl.res, sizeof(szsel_result), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(out, r.res, sizeof(szsel_result), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(result)");
   e = hipEventRecord(sl.done, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
@@ -251,16 +228,16 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
     return SZSEL_EHIP;
   }
   c->ncu = ncu > 0 ? ncu : 256;
-  const SlotLayout L;
-  if ((size_t)kSlots * L.total > c->budget) {
+  const size_t slot_bytes = request_workspace_bytes(kMaxParts, kMaxParts, kMaxParts);
+  if ((size_t)kSlots * slot_bytes > c->budget) {
     delete c;
     return SZSEL_ENOMEM;
   }
   for (int k = 0; k < kSlots; k++) {
     Slot &s = c->slots[k];
     void *p = nullptr;
-    e = hipMalloc(&p, L.total);
-    if (e == hipSuccess) e = hipMemset(p, 0, L.total);
+    e = hipMalloc(&p, slot_bytes);
+    if (e == hipSuccess) e = hipMemset(p, 0, slot_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e != hipSuccess) {
       if (p) (void)hipFree(p);
@@ -268,13 +245,7 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
       return SZSEL_EHIP;
     }
     s.mem = (char *)p;
-    s.st = (ReqState *)(s.mem + L.st);
-    s.rpart = (RangePart *)(s.mem + L.rpart);
-    s.zpart = (TilePart *)(s.mem + L.zpart);
-    s.spart = (TilePart *)(s.mem + L.spart);
-    s.hist = (uint32_t *)(s.mem + L.hist);
-    s.res = (szsel_result *)(s.mem + L.res);
-    c->used_bytes += L.total;
+    c->used_bytes += slot_bytes;
   }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
