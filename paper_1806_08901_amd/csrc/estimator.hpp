@@ -274,46 +274,31 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   c = __shfl(c, gbase + perm_i);
   const U u = ((U)c + Q::NB) ^ Q::NB;
 
-  // group-testing embedded coding of planes W-1 .. kmin.  Per plane the cost
-  // follows from the plane mask alone: with n values already significant,
-  // m ones at positions >= n and the highest one at p, the plane costs
-  // n + [n < BS] bits if m == 0, else p + 1 + m + (p < BS-1 ? 1 : -1), and
-  // afterwards n = p + 1.
+  // Group-testing embedded coding of planes W-1 .. kmin, counted without
+  // running the coder.  With msb_j the highest set bit of coefficient j (-1
+  // for 0) and M_j = max_{j' >= j} msb_j' (suffix maximum in coding order),
+  // the coder emits
+  //     sum_j max(0, M_j - kmin + 1)            verbatim bits of significant values
+  //   + W - max(kmin, msb_{BS-1} + 1)           group tests that find nothing
+  //   + #{j : u_j != 0, msb_j = M_j >= kmin}    group tests that find a 1
+  //   - [msb_{BS-1} >= kmin]                    the implied final 1
+  // bits, because a plane's test finds exactly the coefficients whose msb is
+  // that plane and that no later coefficient exceeds.
   const int kmin = W - prec;
-  int kstop = kmin;
-  if constexpr (D < 3) {
+  const int msb = u ? (W - 1 - clz_u(u)) : -1;
+  int smax = msb;
 #pragma unroll
-    for (int s = BS; s < kWave; s <<= 1) kstop = min(kstop, __shfl_xor(kstop, s));
-  } else {
-    kstop = __builtin_amdgcn_readfirstlane(kstop);
-  }
-  const int sh = (D < 3) ? gbase : 0;
-  constexpr uint64_t bmask = BS == 64 ? ~0ull : ((1ull << (BS & 63)) - 1ull);
-  uint64_t acc = 0;
-  uint32_t cost = 0;
-  for (int k = W - 1; k >= kstop; --k) {
-    const uint64_t all = __ballot((int)((u >> k) & 1));
-    if (k >= kmin) {
-      const uint64_t m = (all >> sh) & bmask;
-      const int n = acc ? 64 - __clzll((long long)acc) : 0;
-      const uint64_t rest = n < 64 ? (m >> n) : 0ull;
-      if (rest == 0) {
-        cost += (uint32_t)(n + (n < BS ? 1 : 0));
-      } else {
-        const int p = 63 - __clzll((long long)m);
-        cost += (uint32_t)(p + 1 + __popcll(rest) + (p < BS - 1 ? 1 : -1));
-      }
-      acc |= m;
-    }
-  }
+  for (int s = 1; s < BS; s <<= 1) smax = max(smax, __shfl_down(smax, s, BS));
+  const int msb_last = __shfl(msb, gbase + BS - 1);
+  const uint32_t verb = (uint32_t)max(0, smax - kmin + 1);
+  const uint32_t found = (u != 0 && msb == smax && msb >= kmin) ? 1u : 0u;
+  const uint32_t sig = (uint32_t)max(0, msb - kmin + 1);  // significant bits (Section 5.2.1)
+  const uint32_t packed = group_isum<BS>((verb + found) | (sig << 16));
+  const int coder = (int)(packed & 0xFFFFu) + (W - max(kmin, msb_last + 1)) - (msb_last >= kmin ? 1 : 0);
   ZfpBlockOut<T, D> out;
   out.emax = empty ? INT32_MIN : emax;
-  out.bits = prec == 0 ? 1u : (uint32_t)(1 + Q::E) + cost;
-
-  // significant bits within the coded planes (Section 5.2.1)
-  const int msb = u ? (W - 1 - clz_u(u)) : -1;
-  const uint32_t nsb = (prec > 0 && msb >= kmin) ? (uint32_t)(msb - kmin + 1) : 0u;
-  out.nsb = group_isum<BS>(nsb);
+  out.bits = prec == 0 ? 1u : (uint32_t)(1 + Q::E + coder);
+  out.nsb = prec == 0 ? 0u : (packed >> 16);
 
   // decode at the cutoff: drop planes below kmin, invert every step
   U keep;
