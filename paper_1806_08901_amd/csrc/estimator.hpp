@@ -17,7 +17,7 @@
 
 namespace szsel {
 
-constexpr int kHistWin = 8192;    // LDS histogram window around the zero code
+constexpr int kHistWin = 4096;    // LDS histogram window around the zero code
 constexpr int kHistLo = kRadius - kHistWin / 2;
 
 template <int D> struct Order {
@@ -28,13 +28,8 @@ template <int D> struct Order {
 // binary-counter stack that folds tile sums into the workgroup's subtree.
 struct TileLds {
   double sse[kMaxTile];
-  double err[kMaxTile];
-  uint32_t a[kMaxTile];
-  uint32_t b[kMaxTile];
   double red[kWaves];
   double stk[24];
-  double maxerr;
-  uint64_t sa, sb;
   int sp;
   uint32_t pushes;
   int last;
@@ -234,10 +229,13 @@ __device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
 // ZFP side (Sections 4.2 and 5.2) on one wave-group of 4^D lanes per block
 // ===========================================================================
 
+// Per-lane results of one block: the lane's share of the block's coder bits
+// and significant bits (their sums over the block are the block's values),
+// its squared and absolute data-domain error, and the block exponent.
 template <typename T, int D>
 struct ZfpBlockOut {
   uint32_t bits, nsb;
-  double sse, maxerr;
+  double e2, ae;
   int emax;
 };
 
@@ -293,12 +291,12 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   const uint32_t verb = (uint32_t)max(0, smax - kmin + 1);
   const uint32_t found = (u != 0 && msb == smax && msb >= kmin) ? 1u : 0u;
   const uint32_t sig = (uint32_t)max(0, msb - kmin + 1);  // significant bits (Section 5.2.1)
-  const uint32_t packed = group_isum<BS>((verb + found) | (sig << 16));
-  const int coder = (int)(packed & 0xFFFFu) + (W - max(kmin, msb_last + 1)) - (msb_last >= kmin ? 1 : 0);
+  const uint32_t blockwide =
+      prec == 0 ? 1u : (uint32_t)(1 + Q::E + (W - max(kmin, msb_last + 1)) - (msb_last >= kmin ? 1 : 0));
   ZfpBlockOut<T, D> out;
   out.emax = empty ? INT32_MIN : emax;
-  out.bits = prec == 0 ? 1u : (uint32_t)(1 + Q::E + coder);
-  out.nsb = prec == 0 ? 0u : (packed >> 16);
+  out.bits = (prec == 0 ? 0u : verb + found) + (i == 0 ? blockwide : 0u);
+  out.nsb = prec == 0 ? 0u : sig;
 
   // decode at the cutoff: drop planes below kmin, invert every step
   U keep;
@@ -322,119 +320,127 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   T xh = (T)ldexp((double)d, emax - Q::P);
   if (prec == 0) xh = (T)0;
   const double e = (double)xv - (double)xh;
-  out.sse = group_tree_sum<BS>(e * e);
-  out.maxerr = group_max<BS>(fabs(e));
+  out.e2 = e * e;
+  out.ae = fabs(e);
   return out;
 }
 
-// Reduces the tile's per-block values in LDS (adjacent tree for the SSE)
-// with wave 0; results valid on thread 0.
-__device__ inline void tile_reduce(TileLds &L, int tile, double &sse, double &maxerr,
-                                   uint64_t &sa, uint64_t &sb) {
-  sse = 0.0;
-  maxerr = 0.0;
-  sa = sb = 0;
+// Adjacent-pair tree over the tile's per-block SSE values in LDS (wave 0);
+// the result is valid on thread 0.
+__device__ inline double tile_sse(const TileLds &L, int tile) {
+  double sse = 0.0;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     const int c = tile > kWave ? tile / kWave : 1;
-    double v = 0.0, m = 0.0;
-    uint64_t a = 0, b = 0;
+    double v = 0.0;
     if (c == 1) {
-      if (lane < tile) {
-        v = L.sse[lane];
-        m = L.err[lane];
-        a = L.a[lane];
-        b = L.b[lane];
-      }
+      if (lane < tile) v = L.sse[lane];
     } else if (c == 2) {
       v = L.sse[2 * lane] + L.sse[2 * lane + 1];
-      m = fmax(L.err[2 * lane], L.err[2 * lane + 1]);
-      a = (uint64_t)L.a[2 * lane] + L.a[2 * lane + 1];
-      b = (uint64_t)L.b[2 * lane] + L.b[2 * lane + 1];
     } else {
       const int k = 4 * lane;
       v = (L.sse[k] + L.sse[k + 1]) + (L.sse[k + 2] + L.sse[k + 3]);
-      m = fmax(fmax(L.err[k], L.err[k + 1]), fmax(L.err[k + 2], L.err[k + 3]));
-      a = (uint64_t)L.a[k] + L.a[k + 1] + L.a[k + 2] + L.a[k + 3];
-      b = (uint64_t)L.b[k] + L.b[k + 1] + L.b[k + 2] + L.b[k + 3];
     }
     sse = group_tree_sum<kWave>(v);
-    maxerr = group_max<kWave>(m);
-    sa = group_isum<kWave>(a);
-    sb = group_isum<kWave>(b);
   }
+  return sse;
 }
 
-// Workgroup accumulator over its tiles (thread 0): the SSE subtrees of the
-// tiles are folded with a binary counter, which associates exactly like the
-// adjacent-pair tree over the workgroup's aligned chunk.
+// Workgroup accumulators.  The SSE subtrees of the tiles are folded on
+// thread 0 with a binary counter, which associates exactly like the
+// adjacent-pair tree over the workgroup's aligned chunk.  Integer counts and
+// the maximum error are order-free: each lane accumulates its own and the
+// workgroup reduces them once at the end.
+struct LaneAcc {
+  uint32_t a, b;
+  double maxerr;
+  __device__ LaneAcc() : a(0u), b(0u), maxerr(0.0) {}
+};
+
 __device__ inline void wg_acc_reset(TileLds &L) {
   if (threadIdx.x == 0) {
     L.sp = 0;
     L.pushes = 0;
-    L.maxerr = 0.0;
-    L.sa = L.sb = 0;
   }
 }
 
-__device__ inline void wg_acc_push(TileLds &L, double sse, double maxerr, uint64_t sa, uint64_t sb) {
+__device__ inline void wg_acc_push(TileLds &L, double sse) {
   if (threadIdx.x == 0) {
     double v = sse;
     for (uint32_t m = L.pushes; m & 1; m >>= 1) v = L.stk[--L.sp] + v;
     L.stk[L.sp++] = v;
     L.pushes++;
-    L.maxerr = fmax(L.maxerr, maxerr);
-    L.sa += sa;
-    L.sb += sb;
   }
 }
 
-__device__ inline void wg_acc_store(TileLds &L, const Parts &p, int w) {
+__device__ inline void wg_acc_store(TileLds &L, const LaneAcc &acc, const Parts &p, int w) {
+  uint64_t a = group_isum<kWave>((uint64_t)acc.a);
+  uint64_t b = group_isum<kWave>((uint64_t)acc.b);
+  double m = group_max<kWave>(acc.maxerr);
+  __shared__ uint64_t s_a[kWaves], s_b[kWaves];
+  __shared__ double s_m[kWaves];
+  const int wv = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_a[wv] = a;
+    s_b[wv] = b;
+    s_m[wv] = m;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     put_f64(p.sse + w, L.stk[0]);
-    put_f64(p.err + w, L.maxerr);
-    put_u64(p.a + w, L.sa);
-    put_u64(p.b + w, L.sb);
+    put_f64(p.err + w, fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3])));
+    put_u64(p.a + w, s_a[0] + s_a[1] + s_a[2] + s_a[3]);
+    put_u64(p.b + w, s_b[0] + s_b[1] + s_b[2] + s_b[3]);
   }
 }
 
-// One tile (<= kMaxTile blocks starting at `base`) of the ZFP side.
+// Value of in-block point i of sampled block j (0 when j is past the end).
 template <typename T, int D>
-__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, int tile, int minexp, TileLds &L) {
+__device__ inline T load_block_value(const ReqDesc &r, int64_t j, int i) {
+  if (j >= r.nblk) return (T)0;
+  int64_t o[3], p[3];
+  block_origin<D>(r, (uint32_t)j, o);
+  point_coords<D>(o, i, p);
+  return ((const T *)r.field)[linear_index<D>(r, p)];
+}
+
+// One tile (<= kMaxTile blocks starting at `base`) of the ZFP side; the
+// next round's values are loaded while the current round is processed.
+template <typename T, int D>
+__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, int tile, int minexp, TileLds &L,
+                                LaneAcc &acc) {
   constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
-  const T *x = (const T *)r.field;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
   const int perm_i = Order<D>::table.perm[i];
   const int inv_i = Order<D>::table.inv[i];
   const int rounds = tile / (kWaves * BPW);
+  T xn = load_block_value<T, D>(r, base + wave * BPW + bw, i);
   for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
     const bool active = j < r.nblk;
-    T xv = (T)0;
-    if (active) {
-      int64_t o[3], p[3];
-      block_origin<D>(r, (uint32_t)j, o);
-      point_coords<D>(o, i, p);
-      xv = x[linear_index<D>(r, p)];
-    }
+    const T xv = xn;
+    if (rd + 1 < rounds) xn = load_block_value<T, D>(r, j + kWaves * BPW, i);
     const ZfpBlockOut<T, D> z = zfp_block<T, D>(xv, minexp, perm_i, inv_i, lane);
-    if (i == 0) {
-      L.sse[jl] = active ? z.sse : 0.0;
-      L.err[jl] = active ? z.maxerr : 0.0;
-      L.a[jl] = active ? z.bits : 0u;
-      L.b[jl] = active ? z.nsb : 0u;
-      if (active && r.dbg_zbits) r.dbg_zbits[j] = z.bits;
-      if (active && r.dbg_zsse) r.dbg_zsse[j] = z.sse;
-      if (active && r.dbg_zemax) r.dbg_zemax[j] = z.emax;
+    const double bsse = group_tree_sum<BS>(z.e2);
+    if (active) {
+      acc.a += z.bits;
+      acc.b += z.nsb;
+      acc.maxerr = fmax(acc.maxerr, z.ae);
     }
+    if (r.dbg_zbits) {
+      const uint32_t bbits = group_isum<BS>(z.bits);
+      if (active && i == 0) {
+        r.dbg_zbits[j] = bbits;
+        if (r.dbg_zsse) r.dbg_zsse[j] = bsse;
+        if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
+      }
+    }
+    if (i == 0) L.sse[jl] = active ? bsse : 0.0;
   }
   __syncthreads();
-  double sse, maxerr;
-  uint64_t sa, sb;
-  tile_reduce(L, tile, sse, maxerr, sa, sb);
-  wg_acc_push(L, sse, maxerr, sa, sb);
+  wg_acc_push(L, tile_sse(L, tile));
   __syncthreads();
 }
 
@@ -536,16 +542,17 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
   const int minexp = get_i32(&r.st->minexp);
   const int tile = r.zblk < kMaxTile ? r.zblk : kMaxTile;
   const int ntile = r.zblk / tile;
+  LaneAcc acc;
   wg_acc_reset(L);
   __syncthreads();
   for (int k = 0; k < ntile; k++) {
     const int64_t base = (int64_t)w * r.zblk + (int64_t)k * tile;
     if (base < r.nblk)
-      zfp_tile<T, D>(r, base, tile, minexp, L);
+      zfp_tile<T, D>(r, base, tile, minexp, L, acc);
     else
-      wg_acc_push(L, 0.0, 0.0, 0, 0);
+      wg_acc_push(L, 0.0);
   }
-  wg_acc_store(L, r.zp, w);
+  wg_acc_store(L, acc, r.zp, w);
   if (!last_to_finish(&r.st->zfp_done, (uint32_t)r.nzfp, &L.last)) return false;
   zfp_finalize<T, D>(r, L);
   return true;
@@ -556,33 +563,67 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
 // linear-scaling quantization, code histogram
 // ===========================================================================
 
+// The value of a point and its Lorenzo neighbours, in the order the
+// predictor adds them: single axes (slowest first), then pairs in
+// lexicographic order, then the triple.  Values outside the field are 0
+// (the lower-order predictor at borders).
 template <typename T, int D>
-__device__ inline double lorenzo_pred(const T *x, const ReqDesc &r, const int64_t p[3]) {
-  // terms: single axes (slowest first), then pairs in lexicographic order,
-  // then the triple; values outside the field are 0
+struct Stencil {
+  T x;
+  T v[(1 << D) - 1];
+};
+
+template <typename T, int D>
+__device__ inline Stencil<T, D> load_stencil(const ReqDesc &r, int64_t j, int i) {
+  Stencil<T, D> s;
+  s.x = (T)0;
+#pragma unroll
+  for (int k = 0; k < (1 << D) - 1; k++) s.v[k] = (T)0;
+  if (j >= r.nblk) return s;
+  const T *x = (const T *)r.field;
+  int64_t o[3], p[3];
+  block_origin<D>(r, (uint32_t)j, o);
+  point_coords<D>(o, i, p);
   if constexpr (D == 1) {
-    return p[0] > 0 ? (double)x[p[0] - 1] : 0.0;
+    s.x = x[p[0]];
+    if (p[0] > 0) s.v[0] = x[p[0] - 1];
   } else if constexpr (D == 2) {
     const int64_t nx = r.dims[1];
     const int64_t c = p[0] * nx + p[1];
     const bool y = p[0] > 0, xo = p[1] > 0;
-    const double v0 = y ? (double)x[c - nx] : 0.0;
-    const double v1 = xo ? (double)x[c - 1] : 0.0;
-    const double v01 = (y && xo) ? (double)x[c - nx - 1] : 0.0;
-    return (v0 + v1) - v01;
+    s.x = x[c];
+    if (y) s.v[0] = x[c - nx];
+    if (xo) s.v[1] = x[c - 1];
+    if (y && xo) s.v[2] = x[c - nx - 1];
   } else {
     const int64_t ny = r.dims[1], nx = r.dims[2];
     const int64_t sz = ny * nx;
     const int64_t c = (p[0] * ny + p[1]) * nx + p[2];
     const bool z = p[0] > 0, y = p[1] > 0, xo = p[2] > 0;
-    const double v0 = z ? (double)x[c - sz] : 0.0;
-    const double v1 = y ? (double)x[c - nx] : 0.0;
-    const double v2 = xo ? (double)x[c - 1] : 0.0;
-    const double v01 = (z && y) ? (double)x[c - sz - nx] : 0.0;
-    const double v02 = (z && xo) ? (double)x[c - sz - 1] : 0.0;
-    const double v12 = (y && xo) ? (double)x[c - nx - 1] : 0.0;
-    const double v012 = (z && y && xo) ? (double)x[c - sz - nx - 1] : 0.0;
-    return (((((v0 + v1) + v2) - v01) - v02) - v12) + v012;
+    s.x = x[c];
+    if (z) s.v[0] = x[c - sz];
+    if (y) s.v[1] = x[c - nx];
+    if (xo) s.v[2] = x[c - 1];
+    if (z && y) s.v[3] = x[c - sz - nx];
+    if (z && xo) s.v[4] = x[c - sz - 1];
+    if (y && xo) s.v[5] = x[c - nx - 1];
+    if (z && y && xo) s.v[6] = x[c - sz - nx - 1];
+  }
+  return s;
+}
+
+// Lorenzo prediction from the original neighbours (Section 4.1, with the
+// prediction taken from real rather than sampled neighbours, Section 4.3):
+// sum over non-empty axis subsets S of (-1)^(|S|+1) X[p - e_S].
+template <typename T, int D>
+__device__ inline double lorenzo_pred(const Stencil<T, D> &s) {
+  if constexpr (D == 1) {
+    return (double)s.v[0];
+  } else if constexpr (D == 2) {
+    return ((double)s.v[0] + (double)s.v[1]) - (double)s.v[2];
+  } else {
+    return (((((double)s.v[0] + (double)s.v[1]) + (double)s.v[2]) - (double)s.v[3]) -
+            (double)s.v[4]) - (double)s.v[5] + (double)s.v[6];
   }
 }
 
@@ -612,54 +653,67 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
   return 0;
 }
 
-// One tile of the SZ side.  Codes go to the LDS window s_hist (or straight
-// to the global histogram outside it).
+// Adds one to the histogram bin of `code` for every lane with `want`.  The
+// wave first counts the lanes that share the first wanting lane's code and
+// adds them with one atomic (most codes of a smooth field are equal), then
+// the remaining lanes add individually.  Bins near the zero code live in the
+// LDS window s_hist, the rest in the global histogram g.
+__device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint32_t *g) {
+  const uint64_t todo = __ballot(want);
+  if (!todo) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int leader = __ffsll((long long)todo) - 1;
+  const int lc = __builtin_amdgcn_readlane(code, leader);
+  const uint64_t same = __ballot(want && code == lc);
+  int c = -1;
+  uint32_t n = 1;
+  if (lane == leader) {
+    c = lc;
+    n = (uint32_t)__popcll(same);
+  } else if (want && code != lc) {
+    c = code;
+  }
+  if (c >= 0) {
+    const int wi = c - kHistLo;
+    if (wi >= 0 && wi < kHistWin)
+      atomicAdd(&s_hist[wi], n);
+    else
+      atomicAdd(&g[c], n);
+  }
+}
+
+// One tile of the SZ side; the next round's stencils are loaded while the
+// current round is processed.
 template <typename T, int D>
 __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
-                               double ebsz, TileLds &L, uint32_t *s_hist) {
+                               double ebsz, TileLds &L, uint32_t *s_hist, LaneAcc &acc) {
   constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
-  const T *x = (const T *)r.field;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
   const int rounds = tile / (kWaves * BPW);
+  Stencil<T, D> sn = load_stencil<T, D>(r, base + wave * BPW + bw, i);
   for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
     const bool active = j < r.nblk;
-    int code = 0;
+    const Stencil<T, D> sc = sn;
+    if (rd + 1 < rounds) sn = load_stencil<T, D>(r, j + kWaves * BPW, i);
     double e2 = 0.0, ae = 0.0;
+    const int code = active ? quantize<T>(sc.x, lorenzo_pred<T, D>(sc), delta, inv, ebsz, e2, ae) : 0;
+    hist_add(active && code != 0, code, s_hist, r.hist);
     if (active) {
-      int64_t o[3], p[3];
-      block_origin<D>(r, (uint32_t)j, o);
-      point_coords<D>(o, i, p);
-      const T xv = x[linear_index<D>(r, p)];
-      const double pred = lorenzo_pred<T, D>(x, r, p);
-      code = quantize<T>(xv, pred, delta, inv, ebsz, e2, ae);
-      if (code) {
-        const int wi = code - kHistLo;
-        if (wi >= 0 && wi < kHistWin)
-          atomicAdd(&s_hist[wi], 1u);
-        else
-          atomicAdd(&r.hist[code], 1u);
-      }
+      acc.a += code == 0 ? 1u : 0u;
+      acc.maxerr = fmax(acc.maxerr, ae);
       if (r.dbg_codes) r.dbg_codes[j * BS + i] = (uint16_t)code;
     }
     const double bsse = group_tree_sum<BS>(e2);
-    const double berr = group_max<BS>(ae);
-    const uint32_t unp = group_isum<BS>((uint32_t)(active && code == 0));
     if (i == 0) {
       L.sse[jl] = bsse;
-      L.err[jl] = berr;
-      L.a[jl] = unp;
-      L.b[jl] = 0;
       if (active && r.dbg_ssse) r.dbg_ssse[j] = bsse;
     }
   }
   __syncthreads();
-  double sse, maxerr;
-  uint64_t sa, sb;
-  tile_reduce(L, tile, sse, maxerr, sa, sb);
-  wg_acc_push(L, sse, maxerr, sa, sb);
+  wg_acc_push(L, tile_sse(L, tile));
   __syncthreads();
 }
 
@@ -778,19 +832,20 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   const double ebsz = get_f64(&r.st->eb_sz);
   const int tile = r.sblk < kMaxTile ? r.sblk : kMaxTile;
   const int ntile = r.sblk / tile;
+  LaneAcc acc;
   hist_clear(s_hist);
   wg_acc_reset(L);
   __syncthreads();
   for (int k = 0; k < ntile; k++) {
     const int64_t base = (int64_t)w * r.sblk + (int64_t)k * tile;
     if (base < r.nblk)
-      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist);
+      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist, acc);
     else
-      wg_acc_push(L, 0.0, 0.0, 0, 0);
+      wg_acc_push(L, 0.0);
   }
   __syncthreads();
   hist_flush(s_hist, r.hist);
-  wg_acc_store(L, r.sp, w);
+  wg_acc_store(L, acc, r.sp, w);
   if (!last_to_finish(&r.st->sz_done, (uint32_t)r.nsz, &L.last)) return false;
   sz_finalize<T, D>(r, L);
   return true;

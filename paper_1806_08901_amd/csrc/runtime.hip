@@ -106,8 +106,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   r.nblk = (int64_t)nblk;
   // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
   // consecutive sampled blocks, at least one round of 4 waves, sized for
-  // about 8 (ZFP) or 4 (SZ, which also flushes an LDS histogram) workgroups
-  // per CU, and never more than kMaxParts workgroups.
+  // about 8 workgroups per CU, and never more than kMaxParts workgroups.
   const int bs = 1 << (2 * nd);
   const int min_chunk = kWaves * (kWave / bs);
   auto chunk_for = [&](int target_wgs) {
@@ -117,7 +116,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     while ((nblk + c - 1) / c > (uint64_t)kMaxParts) c <<= 1;
     return c;
   };
-  const uint64_t zc = chunk_for(8 * ctx->ncu), sc = chunk_for(4 * ctx->ncu);
+  const uint64_t zc = chunk_for(8 * ctx->ncu), sc = chunk_for(8 * ctx->ncu);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
