@@ -25,6 +25,8 @@ constexpr int kBins = 65536;           // 65,535 symmetric bins plus the escape 
 constexpr int kRadius = 32768;
 constexpr int kMaxTile = 256;          // sampled blocks per tile
 constexpr int kMaxParts = 8192;        // workgroups of one pass (partials per pass)
+constexpr int kEntChunk = 256;         // histogram bins per workgroup of the entropy pass
+constexpr int kEntWgs = 65536 / kEntChunk;
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
@@ -67,10 +69,11 @@ __device__ inline void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
 struct alignas(64) ReqState {
   double vmin, vmax, vr, eb_abs;
   double delta, inv, eb_sz;
+  double sz_sse, sz_maxerr;  // SZ totals handed from the SZ pass to the entropy pass
+  uint64_t sz_unpred;
   int32_t minexp;
   uint32_t flags;
-  uint32_t range_done, zfp_done, sz_done;  // last-workgroup counters, reset by their finalizers
-  uint32_t pad;
+  uint32_t range_done, zfp_done, sz_done, ent_done;  // last-workgroup counters, reset by their finalizers
 };
 
 // One entry per workgroup of a pass (structure of arrays, coalesced reads).
@@ -100,6 +103,7 @@ struct ReqDesc {
   int32_t pad0;
   ReqState *st;
   Parts rp, zp, sp;
+  double *ent;     // one h log2 h subtree per 256-bin chunk of the histogram
   uint32_t *hist;
   szsel_result *res;
   uint16_t *dbg_codes;

@@ -731,94 +731,85 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
   }
 }
 
-// Entropy of the code histogram (Eq. 5 with P_i = h_i/n), the SZ bit-rate
-// (entropy + offset + W escape bits per unpredictable point, Section 6.2),
-// both PSNRs, and the selection of Algorithm 1 (lower bit-rate, ties to ZFP).
-// The sum of h log2 h runs over 256 chunks of 256 bins: a wave reads a chunk
-// with one coalesced 4-bin load per lane and reduces it exactly like the
-// adjacent-pair tree; wave 0 then folds the 256 chunk sums.  Leaves the
-// global histogram zeroed for the next request.
-template <typename T, int D>
+// SZ totals of the request (last SZ workgroup): squared-error tree over the
+// workgroups' subtrees, maximum error, unpredictable count.
 __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
-  constexpr int BS = 1 << (2 * D);
   double sse, maxerr;
   uint64_t unpred, unused;
   parts_total(r.sp, r.nsz, L, sse, maxerr, unpred, unused);
-  const double nv = (double)(r.nblk * BS);
-  __shared__ double s_chunk[kBins / 256];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  constexpr int kChunks = kBins / 256;
-  for (int c0 = wave; c0 < kChunks; c0 += kWaves * 4) {
-    uint64_t w0[4], w1[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int c = c0 + u * kWaves;
-      const int bin = c * 256 + lane * 4;
-      w0[u] = get_u64((const uint64_t *)(r.hist + bin));
-      w1[u] = get_u64((const uint64_t *)(r.hist + bin + 2));
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int c = c0 + u * kWaves;
-      const int bin = c * 256 + lane * 4;
-      uint32_t h[4] = {(uint32_t)w0[u], (uint32_t)(w0[u] >> 32), (uint32_t)w1[u],
-                       (uint32_t)(w1[u] >> 32)};
-      if (bin == 0) h[0] = (uint32_t)unpred;  // code 0: unpredictable points
-      double t[4];
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const double hd = (double)h[e];
-        t[e] = h[e] ? hd * log2(hd) : 0.0;
-      }
-      if (r.dbg_hist) {
-#pragma unroll
-        for (int e = 0; e < 4; e++) r.dbg_hist[bin + e] = h[e];
-      }
-      if (w0[u]) put_u64((uint64_t *)(r.hist + bin), 0);
-      if (w1[u]) put_u64((uint64_t *)(r.hist + bin + 2), 0);
-      double v = (t[0] + t[1]) + (t[2] + t[3]);
-      v = group_tree_sum<kWave>(v);
-      if (lane == 0) s_chunk[c] = v;
-    }
+  if (threadIdx.x == 0) {
+    put_f64(&r.st->sz_sse, sse);
+    put_f64(&r.st->sz_maxerr, maxerr);
+    put_u64(&r.st->sz_unpred, unpred);
+    put_u32(&r.st->sz_done, 0);
   }
+}
+
+// Entropy pass, workgroup c of 256: the adjacent-pair subtree of h log2 h
+// over bins [256c, 256c+256) (one bin per thread: the wave butterfly, then
+// the fixed combine of the 4 waves), clearing the bins for the next request.
+// The last workgroup folds the 256 subtrees and finishes the request:
+// entropy (Eq. 5 with P_i = h_i/n), SZ bit-rate (entropy + offset + W escape
+// bits per unpredictable point, Section 6.2), both PSNRs and the selection
+// of Algorithm 1 (lower bit-rate wins, ties go to ZFP).
+template <typename T, int D>
+__device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
+  constexpr int BS = 1 << (2 * D);
+  const int t = threadIdx.x;
+  const int bin = c * kEntChunk + t;
+  const uint64_t unpred = get_u64(&r.st->sz_unpred);
+  uint32_t h = r.hist[bin];
+  if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
+  if (r.dbg_hist) r.dbg_hist[bin] = h;
+  if (h && bin) r.hist[bin] = 0;
+  const double hd = (double)h;
+  double v = h ? hd * log2(hd) : 0.0;
+  v = group_tree_sum<kWave>(v);
+  const int w = t / kWave;
+  if ((t & (kWave - 1)) == 0) L.red[w] = v;
   __syncthreads();
-  if (threadIdx.x < kWave) {
-    const int k = 4 * lane;
-    double v = (s_chunk[k] + s_chunk[k + 1]) + (s_chunk[k + 2] + s_chunk[k + 3]);
-    v = group_tree_sum<kWave>(v);
-    if (lane == 0) {
-      ReqState *st = r.st;
-      szsel_result *res = r.res;
-      const double H = log2(nv) - v / nv;
-      double br = H + r.sz_offset;
-      br = br + ((double)unpred * (double)Prec<T>::W) / nv;
-      const double delta = get_f64(&st->delta);
-      const double eb_sz = get_f64(&st->eb_sz);
-      const double eb_abs = get_f64(&st->eb_abs);
-      const double vr = get_f64(&st->vr);
-      const double mse = sse / nv;
-      put_f64(&res->sz_delta, delta);
-      put_f64(&res->sz_inv_delta, get_f64(&st->inv));
-      put_f64(&res->sz_eb, eb_sz);
-      put_f64(&res->sz_entropy, H);
-      put_f64(&res->sz_bitrate, br);
-      put_f64(&res->sz_sse, sse);
-      put_f64(&res->sz_mse, mse);
-      put_f64(&res->sz_maxerr, maxerr);
-      put_u64(&res->sz_values, (uint64_t)(r.nblk * BS));
-      put_u64(&res->sz_unpredictable, unpred);
-      put_f64(&res->sz_psnr_model, 20.0 * log10(vr / delta) + 10.0 * log10(12.0));
-      put_f64(&res->sz_psnr_measured, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
-      if (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) {
-        const double br_zfp = get_f64(&res->zfp_bitrate);
-        const int32_t choice = br < br_zfp ? 0 : 1;
-        uint32_t flags = (uint32_t)get_u64((uint64_t *)&res->flags);
-        if (eb_sz > eb_abs) flags |= SZSEL_FLAG_EB_EXCEEDS;
-        put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
-        put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
-      }
-      put_u32(&st->sz_done, 0);
+  if (t == 0) put_f64(r.ent + c, (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]));
+  __syncthreads();
+  if (!last_to_finish(&r.st->ent_done, (uint32_t)kEntWgs, &L.last)) return;
+  v = get_f64(r.ent + t);
+  v = group_tree_sum<kWave>(v);
+  if ((t & (kWave - 1)) == 0) L.red[w] = v;
+  __syncthreads();
+  if (t == 0) {
+    const double s = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
+    ReqState *st = r.st;
+    szsel_result *res = r.res;
+    const double nv = (double)(r.nblk * BS);
+    const double sse = get_f64(&st->sz_sse);
+    const double H = log2(nv) - s / nv;
+    double br = H + r.sz_offset;
+    br = br + ((double)unpred * (double)Prec<T>::W) / nv;
+    const double delta = get_f64(&st->delta);
+    const double eb_sz = get_f64(&st->eb_sz);
+    const double eb_abs = get_f64(&st->eb_abs);
+    const double vr = get_f64(&st->vr);
+    const double mse = sse / nv;
+    put_f64(&res->sz_delta, delta);
+    put_f64(&res->sz_inv_delta, get_f64(&st->inv));
+    put_f64(&res->sz_eb, eb_sz);
+    put_f64(&res->sz_entropy, H);
+    put_f64(&res->sz_bitrate, br);
+    put_f64(&res->sz_sse, sse);
+    put_f64(&res->sz_mse, mse);
+    put_f64(&res->sz_maxerr, get_f64(&st->sz_maxerr));
+    put_u64(&res->sz_values, (uint64_t)(r.nblk * BS));
+    put_u64(&res->sz_unpredictable, unpred);
+    put_f64(&res->sz_psnr_model, 20.0 * log10(vr / delta) + 10.0 * log10(12.0));
+    put_f64(&res->sz_psnr_measured, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
+    if (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) {
+      const double br_zfp = get_f64(&res->zfp_bitrate);
+      const int32_t choice = br < br_zfp ? 0 : 1;
+      uint32_t flags = (uint32_t)get_u64((uint64_t *)&res->flags);
+      if (eb_sz > eb_abs) flags |= SZSEL_FLAG_EB_EXCEEDS;
+      put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
+      put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
     }
+    put_u32(&st->ent_done, 0);
   }
   __syncthreads();
 }
@@ -847,7 +838,7 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   hist_flush(s_hist, r.hist);
   wg_acc_store(L, acc, r.sp, w);
   if (!last_to_finish(&r.st->sz_done, (uint32_t)r.nsz, &L.last)) return false;
-  sz_finalize<T, D>(r, L);
+  sz_finalize(r, L);
   return true;
 }
 

@@ -2,7 +2,8 @@
 //   k_range : value range over all N values (Algorithm 1, line 2)
 //   k_zfp   : ZFP bits and decoded error of the sampled blocks (Section 5.2)
 //   k_sz    : Lorenzo/quantization codes and their histogram (Section 5.1)
-// Each ends in a last-workgroup finalizer, so one request is three launches
+//   k_ent   : entropy of the histogram, SZ bit-rate, selection (Eq. 5, Alg. 1)
+// Each ends in a last-workgroup finalizer, so one request is four launches
 // with no host round trip.
 #include "estimator.hpp"
 #include "launch.hpp"
@@ -30,6 +31,13 @@ __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   sz_wg<T, D>(r, blockIdx.x, L, s_hist);
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_ent(ReqDesc r) {
+  __shared__ TileLds L;
+  if (skip_request(r.st)) return;
+  ent_wg<T, D>(r, blockIdx.x, L);
+}
+
 static hipError_t mark(const hipEvent_t *ev, int k, hipStream_t s) {
   return ev ? hipEventRecord(ev[k], s) : hipSuccess;
 }
@@ -45,6 +53,9 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
   if ((e = mark(ev, 2, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
     hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -79,8 +90,8 @@ static size_t parts_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * 8, 
 
 size_t request_workspace_bytes(int nrange, int nzfp, int nsz) {
   return align_up(sizeof(ReqState), 256) + parts_bytes(nrange) + parts_bytes(nzfp) +
-         parts_bytes(nsz) + align_up(sizeof(uint32_t) * kBins, 256) +
-         align_up(sizeof(szsel_result), 256);
+         parts_bytes(nsz) + align_up(sizeof(double) * kEntWgs, 256) +
+         align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256);
 }
 
 static Parts bind_parts(char *&p, int n) {
@@ -101,6 +112,8 @@ void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int ns
   r.rp = bind_parts(p, nrange);
   r.zp = bind_parts(p, nzfp);
   r.sp = bind_parts(p, nsz);
+  r.ent = (double *)p;
+  p += align_up(sizeof(double) * kEntWgs, 256);
   r.hist = (uint32_t *)p;
   p += align_up(sizeof(uint32_t) * kBins, 256);
   r.res = (szsel_result *)p;
