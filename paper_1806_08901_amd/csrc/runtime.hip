@@ -108,7 +108,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // consecutive sampled blocks, at least one round of 4 waves, sized for
   // about 8 workgroups per CU, and never more than kMaxParts workgroups.
   const int bs = 1 << (2 * nd);
-  const int min_chunk = kWaves * (kWave / bs);
+  const int min_chunk = kWaves * 4 * (kWave / bs);  // one staged tile
   auto chunk_for = [&](int target_wgs) {
     const uint64_t want = (nblk + (uint64_t)target_wgs - 1) / (uint64_t)target_wgs;
     uint64_t c = (uint64_t)min_chunk;
