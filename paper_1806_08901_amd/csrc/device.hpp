@@ -91,6 +91,8 @@ struct ReqDesc {
   int64_t n;       // number of values
   int64_t nblk;    // number of sampled blocks
   uint32_t nsel[3];
+  uint32_t dmul[3];    // nsel[k] division by multiply-shift (Granlund-Montgomery)
+  uint32_t dsh[3];     // shift pair: (sh1) | (sh2 << 8)
   int32_t stride[3];
   int32_t nd, dtype, op, eb_mode;
   double eb, sz_offset;
@@ -276,16 +278,162 @@ __device__ inline V group_isum(V v) {
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes and
+// the gfx950 permlane swaps across rows.  Lane maps (checked on the device):
+// quad_perm picks within each aligned group of 4 lanes, row_shl:s reads lane
+// i+s of the same row (own value past the row's end), row_ror:s reads lane
+// (i-s) mod 16, row_mirror reads 15-i, row_half_mirror reads 7-i within each
+// half row; permlane16/32 swaps exchange lanes i and i^16 / i^32.
+// ---------------------------------------------------------------------------
+constexpr int kDppQuad1032 = 0xB1;   // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppQuad2301 = 0x4E;   // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppQuad3210 = 0x1B;   // quad_perm [3,2,1,0]: lane ^ 3
+constexpr int kDppQuad1233 = 0xF9;   // quad_perm [1,2,3,3]: shift down 1 in a quad
+constexpr int kDppQuad2323 = 0xEE;   // quad_perm [2,3,2,3]: shift down 2 in a quad
+constexpr int kDppRowShl1 = 0x101, kDppRowShl2 = 0x102, kDppRowShl4 = 0x104, kDppRowShl8 = 0x108;
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowHalfMirror = 0x141;
+
+template <int CTRL>
+__device__ inline uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline uint64_t dpp(uint64_t v) {
+  return (uint64_t)dpp<CTRL>((uint32_t)v) | ((uint64_t)dpp<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+template <int CTRL>
+__device__ inline int32_t dpp(int32_t v) { return (int32_t)dpp<CTRL>((uint32_t)v); }
+template <int CTRL>
+__device__ inline int64_t dpp(int64_t v) { return (int64_t)dpp<CTRL>((uint64_t)v); }
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  return __longlong_as_double((long long)dpp<CTRL>((uint64_t)__double_as_longlong(v)));
+}
+
+__device__ inline uint32_t xor16(uint32_t v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16) ? p[0] : p[1];
+}
+__device__ inline uint32_t xor32(uint32_t v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (threadIdx.x & 32) ? p[0] : p[1];
+}
+__device__ inline uint64_t xor16(uint64_t v) {
+  return (uint64_t)xor16((uint32_t)v) | ((uint64_t)xor16((uint32_t)(v >> 32)) << 32);
+}
+__device__ inline uint64_t xor32(uint64_t v) {
+  return (uint64_t)xor32((uint32_t)v) | ((uint64_t)xor32((uint32_t)(v >> 32)) << 32);
+}
+__device__ inline int32_t xor16(int32_t v) { return (int32_t)xor16((uint32_t)v); }
+__device__ inline int32_t xor32(int32_t v) { return (int32_t)xor32((uint32_t)v); }
+__device__ inline int64_t xor16(int64_t v) { return (int64_t)xor16((uint64_t)v); }
+__device__ inline int64_t xor32(int64_t v) { return (int64_t)xor32((uint64_t)v); }
+
+// Value held by the lane whose coordinate along `AXIS` of the 4^d block
+// (lane = 16 z + 4 y + x) is c ^ X, for X in {1, 2, 3}.
+template <int AXIS, int X, typename V>
+__device__ inline V axis_xchg(V v) {
+  if constexpr (AXIS == 0) {
+    return dpp<X == 1 ? kDppQuad1032 : (X == 2 ? kDppQuad2301 : kDppQuad3210)>(v);
+  } else if constexpr (AXIS == 1) {
+    if constexpr (X == 1) return dpp<kDppQuad3210>(dpp<kDppRowHalfMirror>(v));
+    else if constexpr (X == 2) return dpp<kDppRowRor8>(v);
+    else return dpp<kDppQuad3210>(dpp<kDppRowMirror>(v));
+  } else {
+    if constexpr (X == 1) return xor16(v);
+    else if constexpr (X == 2) return xor32(v);
+    else return xor16(xor32(v));
+  }
+}
+
+// Maximum over each aligned group of W lanes, in every lane of the group.
+template <int W, typename V>
+__device__ inline V group_allmax(V v) {
+  V o = dpp<kDppQuad1032>(v); v = o > v ? o : v;
+  o = dpp<kDppQuad2301>(v); v = o > v ? o : v;
+  if constexpr (W >= 16) {
+    o = dpp<kDppRowHalfMirror>(v); v = o > v ? o : v;
+    o = dpp<kDppRowMirror>(v); v = o > v ? o : v;
+  }
+  if constexpr (W == 64) {
+    o = xor16(v); v = o > v ? o : v;
+    o = xor32(v); v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Suffix maximum within each aligned group of W lanes: lane i gets the
+// maximum over lanes i .. end of its group.
+template <int W>
+__device__ inline int group_suffix_max(int v) {
+  if constexpr (W == 4) {
+    v = max(v, dpp<kDppQuad1233>(v));
+    v = max(v, dpp<kDppQuad2323>(v));
+    return v;
+  } else {
+    v = max(v, dpp<kDppRowShl1>(v));
+    v = max(v, dpp<kDppRowShl2>(v));
+    v = max(v, dpp<kDppRowShl4>(v));
+    v = max(v, dpp<kDppRowShl8>(v));
+    if constexpr (W == 64) {
+      // add the maxima of the later rows (their first lanes hold them now)
+      const int r1 = __builtin_amdgcn_readlane(v, 16);
+      const int r2 = __builtin_amdgcn_readlane(v, 32);
+      const int r3 = __builtin_amdgcn_readlane(v, 48);
+      const int row = (threadIdx.x >> 4) & 3;
+      const int later = row == 0 ? max(r1, max(r2, r3)) : (row == 1 ? max(r2, r3) : (row == 2 ? r3 : INT32_MIN));
+      v = max(v, later);
+    }
+    return v;
+  }
+}
+
+// Adjacent-pair tree over each aligned group of W lanes (the association of
+// the tree over the group's values in lane order).  The result is valid in
+// the group's first lane (in every lane for W = 64).
+template <int W>
+__device__ inline double group_tree_first(double v) {
+  if constexpr (W == 4) {
+    v = v + dpp<kDppQuad1233>(v);
+    v = v + dpp<kDppQuad2323>(v);
+    return v;
+  } else {
+    v = v + dpp<kDppRowShl1>(v);
+    v = v + dpp<kDppRowShl2>(v);
+    v = v + dpp<kDppRowShl4>(v);
+    v = v + dpp<kDppRowShl8>(v);
+    if constexpr (W == 64) {
+      const uint64_t b = (uint64_t)__double_as_longlong(v);
+      auto rd = [&](int l) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+      };
+      v = (rd(0) + rd(16)) + (rd(32) + rd(48));
+    }
+    return v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Sampled-block addressing
 // ---------------------------------------------------------------------------
+// n / d for the divisor whose (multiplier, shifts) the host precomputed:
+// t = mulhi(m, n), q = (t + ((n - t) >> sh1)) >> sh2.
+__device__ inline uint32_t fast_div(uint32_t n, uint32_t m, uint32_t sh) {
+  const uint32_t t = __umulhi(m, n);
+  return (t + ((n - t) >> (sh & 0xff))) >> (sh >> 8);
+}
+
 template <int D>
 __device__ inline void block_origin(const ReqDesc &r, uint32_t j, int64_t o[3]) {
   // row-major over the sampled-block lattice, last axis fastest
 #pragma unroll
   for (int k = D - 1; k >= 0; k--) {
-    const uint32_t ns = r.nsel[k];
-    const uint32_t q = j / ns;
-    const uint32_t jk = j - q * ns;
+    const uint32_t q = k > 0 ? fast_div(j, r.dmul[k], r.dsh[k]) : 0u;
+    const uint32_t jk = j - q * r.nsel[k];
     j = q;
     o[k] = 4 * (int64_t)jk * r.stride[k];
   }

@@ -338,6 +338,56 @@ struct ZfpBlockOut {
   int emax;
 };
 
+// Forward 4-point lift along one axis of the block, one coefficient per
+// lane (coord = the lane's coordinate on that axis).  Same factorisation as
+// the lifting steps: the outer pair (x0, x3) and inner pair (x1, x2) are
+// averaged/differenced by the lanes holding them, the lanes then swap their
+// (average, difference) with the neighbour pair, and every lane finishes
+// the transform and keeps its own output.
+template <int AXIS, typename I>
+__device__ inline I fwd_lift_axis(I c, int coord) {
+  const I p3 = axis_xchg<AXIS, 3>(c);
+  const bool low = coord <= 1;
+  const I first = low ? c : p3, second = low ? p3 : c;
+  const I sA = wadd(first, second) >> 1;
+  const I dA = wsub(first, sA);
+  const I sB = axis_xchg<AXIS, 1>(sA), dB = axis_xchg<AXIS, 1>(dA);
+  const bool outer = coord == 0 || coord == 3;
+  const I s03 = outer ? sA : sB, d03 = outer ? dA : dB;
+  const I s12 = outer ? sB : sA, d12 = outer ? dB : dA;
+  const I y0 = wadd(s03, s12) >> 1;
+  const I y2 = wsub(s12, y0);
+  const I dm = wadd(d03, d12) >> 1;
+  const I dd = wsub(d03, dm);
+  const I y3 = wsub(dm >> 1, dd);
+  const I y1 = wsub(dm, y3 >> 1);
+  return coord == 0 ? y0 : coord == 1 ? y1 : coord == 2 ? y2 : y3;
+}
+
+// Inverse lift along one axis: even lanes rebuild (s03, s12) from (y0, y2),
+// odd lanes (d03, d12) from (y1, y3); one swap with the neighbour gives each
+// lane both halves of its output.
+template <int AXIS, typename I>
+__device__ inline I inv_lift_axis(I y, int coord) {
+  const I q = axis_xchg<AXIS, 2>(y);
+  const bool odd = coord & 1;
+  const I a = coord <= 1 ? y : q;
+  const I b = coord <= 1 ? q : y;
+  const I dm = wadd(a, b >> 1);
+  const I dd = wsub(dm >> 1, b);
+  const I P = odd ? wadd(dm, dd) : wsub(a, b);
+  const I Q = odd ? wsub(dm, dd) : wadd(a, b);
+  const I P1 = axis_xchg<AXIS, 1>(P), Q1 = axis_xchg<AXIS, 1>(Q);
+  const I s03 = odd ? P1 : P, s12 = odd ? Q1 : Q;
+  const I d03 = odd ? P : P1, d12 = odd ? Q : Q1;
+  switch (coord) {
+    case 0: return wadd(s03, d03);
+    case 1: return wadd(s12, d12);
+    case 2: return wsub(s12, d12);
+    default: return wsub(s03, d03);
+  }
+}
+
 template <typename T, int D>
 __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int inv_i, int lane) {
   using Q = Prec<T>;
@@ -350,23 +400,17 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
 
   // block-floating-point: common exponent of the largest magnitude
   const U mag = Q::bits(xv) & ~(U(1) << (W - 1));
-  const U mmax = group_max<BS>(mag);
+  const U mmax = group_allmax<BS>(mag);
   const bool empty = mmax == 0;
   const int emax = empty ? 0 : frexp_exponent_bits<T>(mmax);
   int prec = emax - minexp + 2 * (D + 1);
   prec = empty ? 0 : (prec < 0 ? 0 : (prec > W ? W : prec));
   I c = bfp_int<T>(xv, emax);
 
-  // separable forward transform, fastest axis first
-#pragma unroll
-  for (int a = 0; a < D; a++) {
-    const int s = 1 << (2 * a);
-    const int coord = (i >> (2 * a)) & 3;
-    const int lb = gbase + i - coord * s;
-    const I v0 = __shfl(c, lb), v1 = __shfl(c, lb + s), v2 = __shfl(c, lb + 2 * s),
-            v3 = __shfl(c, lb + 3 * s);
-    c = fwd_lift_pick(v0, v1, v2, v3, coord);
-  }
+  // separable forward transform, fastest axis first (Section 4.2)
+  c = fwd_lift_axis<0>(c, i & 3);
+  if constexpr (D >= 2) c = fwd_lift_axis<1>(c, (i >> 2) & 3);
+  if constexpr (D == 3) c = fwd_lift_axis<2>(c, (i >> 4) & 3);
   // sequency order, then negabinary digits
   c = __shfl(c, gbase + perm_i);
   const U u = ((U)c + Q::NB) ^ Q::NB;
@@ -380,21 +424,19 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   //   + #{j : u_j != 0, msb_j = M_j >= kmin}    group tests that find a 1
   //   - [msb_{BS-1} >= kmin]                    the implied final 1
   // bits, because a plane's test finds exactly the coefficients whose msb is
-  // that plane and that no later coefficient exceeds.
+  // that plane and that no later coefficient exceeds.  Each lane returns its
+  // share; the block's last lane adds the block-wide terms.
   const int kmin = W - prec;
   const int msb = u ? (W - 1 - clz_u(u)) : -1;
-  int smax = msb;
-#pragma unroll
-  for (int s = 1; s < BS; s <<= 1) smax = max(smax, __shfl_down(smax, s, BS));
-  const int msb_last = __shfl(msb, gbase + BS - 1);
+  const int smax = group_suffix_max<BS>(msb);
   const uint32_t verb = (uint32_t)max(0, smax - kmin + 1);
   const uint32_t found = (u != 0 && msb == smax && msb >= kmin) ? 1u : 0u;
   const uint32_t sig = (uint32_t)max(0, msb - kmin + 1);  // significant bits (Section 5.2.1)
   const uint32_t blockwide =
-      prec == 0 ? 1u : (uint32_t)(1 + Q::E + (W - max(kmin, msb_last + 1)) - (msb_last >= kmin ? 1 : 0));
+      prec == 0 ? 1u : (uint32_t)(1 + Q::E + (W - max(kmin, msb + 1)) - (msb >= kmin ? 1 : 0));
   ZfpBlockOut<T, D> out;
   out.emax = empty ? INT32_MIN : emax;
-  out.bits = (prec == 0 ? 0u : verb + found) + (i == 0 ? blockwide : 0u);
+  out.bits = (prec == 0 ? 0u : verb + found) + (i == BS - 1 ? blockwide : 0u);
   out.nsb = prec == 0 ? 0u : sig;
 
   // decode at the cutoff: drop planes below kmin, invert every step
@@ -407,15 +449,9 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
     keep = ~((U(1) << kmin) - 1);
   I d = (I)(((u & keep) ^ Q::NB) - Q::NB);
   d = __shfl(d, gbase + inv_i);
-#pragma unroll
-  for (int a = D - 1; a >= 0; a--) {
-    const int s = 1 << (2 * a);
-    const int coord = (i >> (2 * a)) & 3;
-    const int lb = gbase + i - coord * s;
-    const I v0 = __shfl(d, lb), v1 = __shfl(d, lb + s), v2 = __shfl(d, lb + 2 * s),
-            v3 = __shfl(d, lb + 3 * s);
-    d = inv_lift_pick(v0, v1, v2, v3, coord);
-  }
+  if constexpr (D == 3) d = inv_lift_axis<2>(d, (i >> 4) & 3);
+  if constexpr (D >= 2) d = inv_lift_axis<1>(d, (i >> 2) & 3);
+  d = inv_lift_axis<0>(d, i & 3);
   T xh = (T)ldexp((double)d, emax - Q::P);
   if (prec == 0) xh = (T)0;
   const double e = (double)xv - (double)xh;
@@ -510,7 +546,7 @@ __device__ inline void zfp_tile(const ReqDesc &r, int64_t base, const T *box, in
     const bool active = j < r.nblk;
     const T xv = box[jl * S::HB + i];
     const ZfpBlockOut<T, D> z = zfp_block<T, D>(xv, minexp, perm_i, inv_i, lane);
-    const double bsse = group_tree_sum<BS>(z.e2);
+    const double bsse = group_tree_first<BS>(z.e2);
     if (active) {
       acc.a += z.bits;
       acc.b += z.nsb;
@@ -802,7 +838,7 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, const T *box, dou
       acc.maxerr = fmax(acc.maxerr, ae);
       if (r.dbg_codes) r.dbg_codes[j * BS + i] = (uint16_t)code;
     }
-    const double bsse = group_tree_sum<BS>(e2);
+    const double bsse = group_tree_first<BS>(e2);
     if (i == 0) {
       L.sse[jl] = bsse;
       if (active && r.dbg_ssse) r.dbg_ssse[j] = bsse;

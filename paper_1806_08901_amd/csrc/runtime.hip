@@ -99,6 +99,17 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     const int64_t ns = (nb + s - 1) / s;
     if (ns > 0xFFFFFFFFll) return fail(ctx, SZSEL_EINVAL, "too many blocks along an axis");
     r.nsel[k] = (uint32_t)ns;
+    // multiply-shift constants for dividing block indices by nsel[k]
+    // (Granlund and Montgomery, PLDI 1994): l = ceil(log2 d),
+    // m = floor(2^32 (2^l - d) / d) + 1, shifts min(l, 1) and max(l - 1, 0)
+    {
+      const uint64_t d = ns > 0 ? (uint64_t)ns : 1;
+      int l = 0;
+      while ((1ull << l) < d) l++;
+      const uint64_t m = (((uint64_t)1 << 32) * ((1ull << l) - d)) / d + 1;
+      r.dmul[k] = (uint32_t)m;
+      r.dsh[k] = (uint32_t)(l < 1 ? l : 1) | ((uint32_t)(l > 1 ? l - 1 : 0) << 8);
+    }
     nblk *= (uint64_t)ns;
     if (nblk > 0xFFFFFFFFull) return fail(ctx, SZSEL_EINVAL, "more than 2^32 sampled blocks; use a larger stride");
   }
