@@ -94,6 +94,7 @@ struct ReqDesc {
   uint32_t dmul[3];    // nsel[k] division by multiply-shift (Granlund-Montgomery)
   uint32_t dsh[3];     // shift pair: (sh1) | (sh2 << 8)
   int32_t stride[3];
+  int64_t nboff[7];    // element offsets of the Lorenzo neighbours, in predictor term order
   int32_t nd, dtype, op, eb_mode;
   double eb, sz_offset;
   int32_t zblk;    // sampled blocks per ZFP workgroup (power of two)
@@ -295,9 +296,11 @@ constexpr int kDppRowRor8 = 0x128;
 constexpr int kDppRowMirror = 0x140;
 constexpr int kDppRowHalfMirror = 0x141;
 
+// Lanes whose source lies outside the row read 0 (bound_ctrl); every use
+// below either never reads such lanes or is neutral to 0.
 template <int CTRL>
 __device__ inline uint32_t dpp(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
 }
 template <int CTRL>
 __device__ inline uint64_t dpp(uint64_t v) {
@@ -365,7 +368,8 @@ __device__ inline V group_allmax(V v) {
 }
 
 // Suffix maximum within each aligned group of W lanes: lane i gets the
-// maximum over lanes i .. end of its group.
+// maximum over lanes i .. end of its group.  Values must be >= 0 (lanes past
+// the end of a row read 0).
 template <int W>
 __device__ inline int group_suffix_max(int v) {
   if constexpr (W == 4) {
@@ -383,7 +387,7 @@ __device__ inline int group_suffix_max(int v) {
       const int r2 = __builtin_amdgcn_readlane(v, 32);
       const int r3 = __builtin_amdgcn_readlane(v, 48);
       const int row = (threadIdx.x >> 4) & 3;
-      const int later = row == 0 ? max(r1, max(r2, r3)) : (row == 1 ? max(r2, r3) : (row == 2 ? r3 : INT32_MIN));
+      const int later = row == 0 ? max(r1, max(r2, r3)) : (row == 1 ? max(r2, r3) : (row == 2 ? r3 : 0));
       v = max(v, later);
     }
     return v;
@@ -437,6 +441,24 @@ __device__ inline void block_origin(const ReqDesc &r, uint32_t j, int64_t o[3]) 
     j = q;
     o[k] = 4 * (int64_t)jk * r.stride[k];
   }
+}
+
+// Linear index of the first point of sampled block j, and its coordinates.
+template <int D>
+__device__ inline int64_t block_base(const ReqDesc &r, uint32_t j, int64_t o[3]) {
+  block_origin<D>(r, j, o);
+  int64_t lin = o[0];
+#pragma unroll
+  for (int k = 1; k < D; k++) lin = lin * r.dims[k] + o[k];
+  return lin;
+}
+
+// Offset of in-block point i from the block's first point.
+template <int D>
+__device__ inline int64_t point_offset(const ReqDesc &r, int i) {
+  if constexpr (D == 1) return i;
+  else if constexpr (D == 2) return (int64_t)(i >> 2) * r.dims[1] + (i & 3);
+  else return ((int64_t)(i >> 4) * r.dims[1] + ((i >> 2) & 3)) * r.dims[2] + (i & 3);
 }
 
 // Point coordinates of in-block index i (row-major, last axis fastest).

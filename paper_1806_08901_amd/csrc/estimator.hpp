@@ -226,105 +226,6 @@ __device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
 }
 
 // ===========================================================================
-// Tile staging.  A tile is TILE consecutive sampled blocks (4 waves x 4 rounds
-// x blocks per wave).  The workgroup copies each block's box of (4+H)^D
-// values (H = 1 adds the Lorenzo halo at -1 on every axis, 0 outside the
-// field) from HBM to LDS with loads ordered so that the same row of
-// neighbouring blocks is contiguous in memory, and loads the next tile into
-// registers while it computes on the current one.
-// ===========================================================================
-template <typename T, int D, int H>
-struct Stager {
-  static constexpr int BS = 1 << (2 * D);
-  static constexpr int BPW = kWave / BS;
-  static constexpr int TILE = kWaves * 4 * BPW;
-  static constexpr int E = 4 + H;
-  static constexpr int HB = D == 1 ? E : (D == 2 ? E * E : E * E * E);
-  static constexpr int NV = TILE * HB;
-  static constexpr int NST = (NV + kThreads - 1) / kThreads;
-  T reg[NST];
-
-  // Block origins of the tile starting at `base` (INT64_MIN past the end).
-  __device__ static void origins(const ReqDesc &r, int64_t base, int64_t *org) {
-    for (int b = threadIdx.x; b < TILE; b += kThreads) {
-      const int64_t j = base + b;
-      int64_t o[3] = {0, 0, 0};
-      if (j < r.nblk) {
-        block_origin<D>(r, (uint32_t)j, o);
-      } else {
-        o[0] = INT64_MIN;
-      }
-#pragma unroll
-      for (int k = 0; k < D; k++) org[b * D + k] = o[k];
-    }
-  }
-
-  // Element e of the staging order: (box coordinates slow..., block, fastest).
-  __device__ static void decode(int e, int &b, int d[3]) {
-    d[D - 1] = e % E;
-    int q = e / E;
-    b = q % TILE;
-    q /= TILE;
-#pragma unroll
-    for (int k = D - 2; k >= 0; k--) {
-      d[k] = q % E;
-      q /= E;
-    }
-  }
-
-  __device__ static int box_index(int b, const int d[3]) {
-    int idx = 0;
-#pragma unroll
-    for (int k = 0; k < D; k++) idx = idx * E + d[k];
-    return b * HB + idx;
-  }
-
-  __device__ void issue(const ReqDesc &r, const int64_t *org) {
-    const T *x = (const T *)r.field;
-#pragma unroll
-    for (int k = 0; k < NST; k++) {
-      const int e = threadIdx.x + k * kThreads;
-      T v = (T)0;
-      if (e < NV) {
-        int b, d[3];
-        decode(e, b, d);
-        if (org[b * D] != INT64_MIN) {
-          bool inside = true;
-          int64_t lin = 0;
-#pragma unroll
-          for (int a = 0; a < D; a++) {
-            const int64_t c = org[b * D + a] - H + d[a];
-            inside = inside && c >= 0;
-            lin = a == 0 ? c : lin * r.dims[a] + c;
-          }
-          if (inside) v = x[lin];
-        }
-      }
-      reg[k] = v;
-    }
-  }
-
-  __device__ void store(T *box) const {
-#pragma unroll
-    for (int k = 0; k < NST; k++) {
-      const int e = threadIdx.x + k * kThreads;
-      if (e < NV) {
-        int b, d[3];
-        decode(e, b, d);
-        box[box_index(b, d)] = reg[k];
-      }
-    }
-  }
-};
-
-// LDS of the staged passes: one box buffer, origins of the next two tiles.
-template <typename T>
-struct StageLds {
-  T box[2000];
-  int64_t org[2][256];
-};
-
-// ===========================================================================
 // ZFP side (Sections 4.2 and 5.2) on one wave-group of 4^D lanes per block
 // ===========================================================================
 
@@ -428,7 +329,7 @@ __device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int 
   // share; the block's last lane adds the block-wide terms.
   const int kmin = W - prec;
   const int msb = u ? (W - 1 - clz_u(u)) : -1;
-  const int smax = group_suffix_max<BS>(msb);
+  const int smax = group_suffix_max<BS>(msb + 1) - 1;
   const uint32_t verb = (uint32_t)max(0, smax - kmin + 1);
   const uint32_t found = (u != 0 && msb == smax && msb >= kmin) ? 1u : 0u;
   const uint32_t sig = (uint32_t)max(0, msb - kmin + 1);  // significant bits (Section 5.2.1)
@@ -529,22 +430,33 @@ __device__ inline void wg_acc_store(TileLds &L, const LaneAcc &acc, const Parts 
   }
 }
 
-// One staged tile of the ZFP side: lane i of a block takes its value from
-// the block's box in LDS.
+// Value of in-block point i of sampled block j (0 when j is past the end).
 template <typename T, int D>
-__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, const T *box, int minexp,
-                                TileLds &L, LaneAcc &acc) {
-  using S = Stager<T, D, 0>;
-  constexpr int BS = S::BS, BPW = S::BPW;
+__device__ inline T load_block_value(const ReqDesc &r, int64_t j, int i) {
+  if (j >= r.nblk) return (T)0;
+  int64_t o[3];
+  const int64_t lin = block_base<D>(r, (uint32_t)j, o) + point_offset<D>(r, i);
+  return ((const T *)r.field)[lin];
+}
+
+// One tile (<= kMaxTile blocks starting at `base`) of the ZFP side; the
+// next round's values are loaded while the current round is processed.
+template <typename T, int D>
+__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, int tile, int minexp, TileLds &L,
+                                LaneAcc &acc) {
+  constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
   const int perm_i = Order<D>::table.perm[i];
   const int inv_i = Order<D>::table.inv[i];
-  for (int rd = 0; rd < 4; rd++) {
+  const int rounds = tile / (kWaves * BPW);
+  T xn = load_block_value<T, D>(r, base + wave * BPW + bw, i);
+  for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
     const bool active = j < r.nblk;
-    const T xv = box[jl * S::HB + i];
+    const T xv = xn;
+    if (rd + 1 < rounds) xn = load_block_value<T, D>(r, j + kWaves * BPW, i);
     const ZfpBlockOut<T, D> z = zfp_block<T, D>(xv, minexp, perm_i, inv_i, lane);
     const double bsse = group_tree_first<BS>(z.e2);
     if (active) {
@@ -563,7 +475,7 @@ __device__ inline void zfp_tile(const ReqDesc &r, int64_t base, const T *box, in
     if (i == 0) L.sse[jl] = active ? bsse : 0.0;
   }
   __syncthreads();
-  wg_acc_push(L, tile_sse(L, S::TILE));
+  wg_acc_push(L, tile_sse(L, tile));
   __syncthreads();
 }
 
@@ -658,45 +570,23 @@ __device__ inline void zfp_finalize(const ReqDesc &r, TileLds &L) {
   }
 }
 
-// The tile loop of a staged pass: stage tile 0, then for every tile store
-// the registers to LDS, start loading the next tile, and run `work` on the
-// tile in LDS.  Tiles past the request's end push empty subtrees so that the
-// workgroup's subtree covers its whole aligned chunk.
-template <typename T, int D, int H, typename Work>
-__device__ inline void staged_tiles(const ReqDesc &r, int64_t first, int ntile, StageLds<T> &SL,
-                                    TileLds &L, Work work) {
-  using S = Stager<T, D, H>;
-  S st;
-  S::origins(r, first, SL.org[0]);
-  __syncthreads();
-  st.issue(r, SL.org[0]);
-  for (int k = 0; k < ntile; k++) {
-    const int64_t base = first + (int64_t)k * S::TILE;
-    if (base >= r.nblk) {
-      wg_acc_push(L, 0.0);
-      continue;
-    }
-    __syncthreads();
-    st.store(SL.box);
-    if (k + 1 < ntile) S::origins(r, base + S::TILE, SL.org[(k + 1) & 1]);
-    __syncthreads();
-    if (k + 1 < ntile) st.issue(r, SL.org[(k + 1) & 1]);
-    work(base);
-  }
-}
-
 // Whole ZFP pass of workgroup w.  Returns true in the workgroup that ran the
 // finalizer.
 template <typename T, int D>
-__device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L, StageLds<T> &SL) {
+__device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
   const int minexp = get_i32(&r.st->minexp);
-  const int ntile = r.zblk / Stager<T, D, 0>::TILE;
+  const int tile = r.zblk < kMaxTile ? r.zblk : kMaxTile;
+  const int ntile = r.zblk / tile;
   LaneAcc acc;
   wg_acc_reset(L);
   __syncthreads();
-  staged_tiles<T, D, 0>(r, (int64_t)w * r.zblk, ntile, SL, L, [&](int64_t base) {
-    zfp_tile<T, D>(r, base, SL.box, minexp, L, acc);
-  });
+  for (int k = 0; k < ntile; k++) {
+    const int64_t base = (int64_t)w * r.zblk + (int64_t)k * tile;
+    if (base < r.nblk)
+      zfp_tile<T, D>(r, base, tile, minexp, L, acc);
+    else
+      wg_acc_push(L, 0.0);
+  }
   wg_acc_store(L, acc, r.zp, w);
   if (!last_to_finish(&r.st->zfp_done, (uint32_t)r.nzfp, &L.last)) return false;
   zfp_finalize<T, D>(r, L);
@@ -718,31 +608,35 @@ struct Stencil {
   T v[(1 << D) - 1];
 };
 
-// Stencil of in-block point i from the block's staged box (edge 5, the
-// point at box coordinates +1 on every axis).
 template <typename T, int D>
-__device__ inline Stencil<T, D> box_stencil(const T *bx, int i) {
+__device__ inline Stencil<T, D> load_stencil(const ReqDesc &r, int64_t j, int i) {
   Stencil<T, D> s;
-  if constexpr (D == 1) {
-    const int c = i + 1;
-    s.x = bx[c];
-    s.v[0] = bx[c - 1];
-  } else if constexpr (D == 2) {
-    const int c = ((i >> 2) + 1) * 5 + (i & 3) + 1;
-    s.x = bx[c];
-    s.v[0] = bx[c - 5];
-    s.v[1] = bx[c - 1];
-    s.v[2] = bx[c - 6];
-  } else {
-    const int c = (((i >> 4) + 1) * 5 + ((i >> 2) & 3) + 1) * 5 + (i & 3) + 1;
-    s.x = bx[c];
-    s.v[0] = bx[c - 25];
-    s.v[1] = bx[c - 5];
-    s.v[2] = bx[c - 1];
-    s.v[3] = bx[c - 30];
-    s.v[4] = bx[c - 26];
-    s.v[5] = bx[c - 6];
-    s.v[6] = bx[c - 31];
+  s.x = (T)0;
+#pragma unroll
+  for (int k = 0; k < (1 << D) - 1; k++) s.v[k] = (T)0;
+  if (j >= r.nblk) return s;
+  const T *x = (const T *)r.field;
+  int64_t o[3];
+  const int64_t lin = block_base<D>(r, (uint32_t)j, o) + point_offset<D>(r, i);
+  // bit k set: the point has a predecessor inside the field along axis k
+  uint32_t in = 0;
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    const int c = (i >> (2 * (D - 1 - k))) & 3;
+    in |= (o[k] + c > 0) ? (1u << k) : 0u;
+  }
+  s.x = x[lin];
+  // term t uses the axes of subset S_t; a neighbour outside the field is 0
+  // (every lane loads, from the point itself when the neighbour is outside)
+#pragma unroll
+  for (int t = 0; t < (1 << D) - 1; t++) {
+    uint32_t S;
+    if constexpr (D == 1) S = 1u;
+    else if constexpr (D == 2) S = t == 0 ? 1u : (t == 1 ? 2u : 3u);
+    else S = t == 0 ? 1u : t == 1 ? 2u : t == 2 ? 4u : t == 3 ? 3u : t == 4 ? 5u : t == 5 ? 6u : 7u;
+    const bool ok = (in & S) == S;
+    const T v = x[ok ? lin - r.nboff[t] : lin];
+    s.v[t] = ok ? v : (T)0;
   }
   return s;
 }
@@ -817,19 +711,22 @@ __device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint32_t 
   }
 }
 
-// One staged tile of the SZ side.
+// One tile of the SZ side; the next round's stencils are loaded while the
+// current round is processed.
 template <typename T, int D>
-__device__ inline void sz_tile(const ReqDesc &r, int64_t base, const T *box, double delta,
-                               double inv, double ebsz, TileLds &L, uint32_t *s_hist, LaneAcc &acc) {
-  using S = Stager<T, D, 1>;
-  constexpr int BS = S::BS, BPW = S::BPW;
+__device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
+                               double ebsz, TileLds &L, uint32_t *s_hist, LaneAcc &acc) {
+  constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
-  for (int rd = 0; rd < 4; rd++) {
+  const int rounds = tile / (kWaves * BPW);
+  Stencil<T, D> sn = load_stencil<T, D>(r, base + wave * BPW + bw, i);
+  for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
     const bool active = j < r.nblk;
-    const Stencil<T, D> sc = box_stencil<T, D>(box + jl * S::HB, i);
+    const Stencil<T, D> sc = sn;
+    if (rd + 1 < rounds) sn = load_stencil<T, D>(r, j + kWaves * BPW, i);
     double e2 = 0.0, ae = 0.0;
     const int code = active ? quantize<T>(sc.x, lorenzo_pred<T, D>(sc), delta, inv, ebsz, e2, ae) : 0;
     hist_add(active && code != 0, code, s_hist, r.hist);
@@ -845,7 +742,7 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, const T *box, dou
     }
   }
   __syncthreads();
-  wg_acc_push(L, tile_sse(L, S::TILE));
+  wg_acc_push(L, tile_sse(L, tile));
   __syncthreads();
 }
 
@@ -949,19 +846,23 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
 // Whole SZ pass of workgroup w (LDS window cleared on entry, flushed once at
 // the end).  Returns true in the workgroup that ran the finalizer.
 template <typename T, int D>
-__device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, StageLds<T> &SL,
-                             uint32_t *s_hist) {
+__device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hist) {
   const double delta = get_f64(&r.st->delta);
   const double inv = get_f64(&r.st->inv);
   const double ebsz = get_f64(&r.st->eb_sz);
-  const int ntile = r.sblk / Stager<T, D, 1>::TILE;
+  const int tile = r.sblk < kMaxTile ? r.sblk : kMaxTile;
+  const int ntile = r.sblk / tile;
   LaneAcc acc;
   hist_clear(s_hist);
   wg_acc_reset(L);
   __syncthreads();
-  staged_tiles<T, D, 1>(r, (int64_t)w * r.sblk, ntile, SL, L, [&](int64_t base) {
-    sz_tile<T, D>(r, base, SL.box, delta, inv, ebsz, L, s_hist, acc);
-  });
+  for (int k = 0; k < ntile; k++) {
+    const int64_t base = (int64_t)w * r.sblk + (int64_t)k * tile;
+    if (base < r.nblk)
+      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist, acc);
+    else
+      wg_acc_push(L, 0.0);
+  }
   __syncthreads();
   hist_flush(s_hist, r.hist);
   wg_acc_store(L, acc, r.sp, w);

@@ -19,18 +19,16 @@ __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
-  __shared__ StageLds<T> SL;
   if (skip_request(r.st)) return;
-  zfp_wg<T, D>(r, blockIdx.x, L, SL);
+  zfp_wg<T, D>(r, blockIdx.x, L);
 }
 
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   __shared__ TileLds L;
-  __shared__ StageLds<T> SL;
   __shared__ uint32_t s_hist[kHistWin];
   if (skip_request(r.st)) return;
-  sz_wg<T, D>(r, blockIdx.x, L, SL, s_hist);
+  sz_wg<T, D>(r, blockIdx.x, L, s_hist);
 }
 
 template <typename T, int D>

@@ -115,11 +115,29 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   }
   r.n = n;
   r.nblk = (int64_t)nblk;
+  // element offsets of the Lorenzo neighbours p - e_S, subsets in the
+  // predictor's term order (single axes slowest first, then pairs, then all)
+  {
+    int64_t st[3] = {0, 0, 0};
+    int64_t acc = 1;
+    for (int k = nd - 1; k >= 0; k--) {
+      st[k] = acc;
+      acc *= dims[k];
+    }
+    static const int kS1[1] = {1}, kS2[3] = {1, 2, 3}, kS3[7] = {1, 2, 4, 3, 5, 6, 7};
+    const int *sub = nd == 1 ? kS1 : (nd == 2 ? kS2 : kS3);
+    for (int t = 0; t < (1 << nd) - 1; t++) {
+      int64_t off = 0;
+      for (int k = 0; k < nd; k++)
+        if (sub[t] & (1 << k)) off += st[k];
+      r.nboff[t] = off;
+    }
+  }
   // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
   // consecutive sampled blocks, at least one round of 4 waves, sized for
   // about 8 workgroups per CU, and never more than kMaxParts workgroups.
   const int bs = 1 << (2 * nd);
-  const int min_chunk = kWaves * 4 * (kWave / bs);  // one staged tile
+  const int min_chunk = kWaves * (kWave / bs);  // one round of 4 waves
   auto chunk_for = [&](int target_wgs) {
     const uint64_t want = (nblk + (uint64_t)target_wgs - 1) / (uint64_t)target_wgs;
     uint64_t c = (uint64_t)min_chunk;
