@@ -121,7 +121,7 @@ typedef struct {
 } szsel_debug;
 
 /* Creates a context on HIP device `hip_device`.  workspace_budget_bytes caps
- * the device memory the context may allocate (0 = 1 GiB).  Returns SZSEL_OK
+ * the device memory the context may allocate (0 = 4 GiB).  Returns SZSEL_OK
  * and *ctx, or a negative code. */
 int szsel_create(szsel_ctx **ctx, int hip_device, size_t workspace_budget_bytes);
 

@@ -686,28 +686,41 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
 // wave first counts the lanes that share the first wanting lane's code and
 // adds them with one atomic (most codes of a smooth field are equal), then
 // the remaining lanes add individually.  Bins near the zero code live in the
-// LDS window s_hist, the rest in the global histogram g.
-__device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint32_t *g) {
-  const uint64_t todo = __ballot(want);
-  if (!todo) return;
+// LDS window s_hist.  Codes outside it (wide histograms at tight bounds) are
+// appended to the request's overflow list, one global atomic per wave, and
+// counted later by the overflow pass; when the list is full they fall back
+// to global atomics on the histogram.
+__device__ inline void hist_add(const ReqDesc &r, bool want, int code, uint32_t *s_hist) {
+  const int wi = code - kHistLo;
+  const bool inwin = want && wi >= 0 && wi < kHistWin;
+  const bool outwin = want && !inwin;
+  const uint64_t todo = __ballot(inwin);
   const int lane = threadIdx.x & (kWave - 1);
-  const int leader = __ffsll((long long)todo) - 1;
-  const int lc = __builtin_amdgcn_readlane(code, leader);
-  const uint64_t same = __ballot(want && code == lc);
-  int c = -1;
-  uint32_t n = 1;
-  if (lane == leader) {
-    c = lc;
-    n = (uint32_t)__popcll(same);
-  } else if (want && code != lc) {
-    c = code;
+  if (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lc = __builtin_amdgcn_readlane(code, leader);
+    const uint64_t same = __ballot(inwin && code == lc);
+    if (lane == leader)
+      atomicAdd(&s_hist[lc - kHistLo], (uint32_t)__popcll(same));
+    else if (inwin && code != lc)
+      atomicAdd(&s_hist[wi], 1u);
   }
-  if (c >= 0) {
-    const int wi = c - kHistLo;
-    if (wi >= 0 && wi < kHistWin)
-      atomicAdd(&s_hist[wi], n);
-    else
-      atomicAdd(&g[c], n);
+  const uint64_t ovf = __ballot(outwin);
+  if (ovf) {
+    const int leader = __ffsll((long long)ovf) - 1;
+    uint64_t base = 0;
+    if (lane == leader)
+      base = __hip_atomic_fetch_add(&r.st->ovf_count, (uint64_t)__popcll(ovf), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, leader);
+    if (outwin) {
+      const uint64_t below = ovf & ((1ull << lane) - 1ull);
+      const uint64_t slot = base + (uint64_t)__popcll(below);
+      if (slot < (uint64_t)r.ovf_cap)
+        r.ovf[slot] = (uint16_t)code;
+      else
+        atomicAdd(&r.hist[code], 1u);
+    }
   }
 }
 
@@ -729,7 +742,7 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
     if (rd + 1 < rounds) sn = load_stencil<T, D>(r, j + kWaves * BPW, i);
     double e2 = 0.0, ae = 0.0;
     const int code = active ? quantize<T>(sc.x, lorenzo_pred<T, D>(sc), delta, inv, ebsz, e2, ae) : 0;
-    hist_add(active && code != 0, code, s_hist, r.hist);
+    hist_add(r, active && code != 0, code, s_hist);
     if (active) {
       acc.a += code == 0 ? 1u : 0u;
       acc.maxerr = fmax(acc.maxerr, ae);
@@ -774,6 +787,30 @@ __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
   }
 }
 
+// Overflow pass, workgroup g of kOvfWgs: counts its slice of the overflow
+// list in LDS, 16384 bins per pass over the slice, and writes the dense
+// counts of all 65536 bins to its own slot (no atomics).
+__device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
+  const uint64_t total = min(get_u64(&r.st->ovf_count), (uint64_t)r.ovf_cap);
+  if (total == 0) return;
+  const uint64_t per = (total + kOvfWgs - 1) / kOvfWgs;
+  const uint64_t beg = (uint64_t)g * per;
+  const uint64_t end = min(total, beg + per);
+  uint32_t *slot = r.ovf_hist + (size_t)g * kBins;
+  for (int pass = 0; pass < kBins / kOvfBins; pass++) {
+    for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
+    __syncthreads();
+    const int lo = pass * kOvfBins;
+    for (uint64_t k = beg + threadIdx.x; k < end; k += kThreads) {
+      const int c = (int)r.ovf[k] - lo;
+      if (c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kOvfBins; b += kThreads) slot[lo + b] = s_cnt[b];
+    __syncthreads();
+  }
+}
+
 // Entropy pass, workgroup c of 256: the adjacent-pair subtree of h log2 h
 // over bins [256c, 256c+256) (one bin per thread: the wave butterfly, then
 // the fixed combine of the 4 waves), clearing the bins for the next request.
@@ -788,6 +825,12 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   const int bin = c * kEntChunk + t;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
   uint32_t h = r.hist[bin];
+  if (get_u64(&r.st->ovf_count) != 0) {  // add the overflow pass's counts
+    uint32_t o = 0;
+#pragma unroll 8
+    for (int g = 0; g < kOvfWgs; g++) o += r.ovf_hist[(size_t)g * kBins + bin];
+    h += o;
+  }
   if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
   if (r.dbg_hist) r.dbg_hist[bin] = h;
   if (h && bin) r.hist[bin] = 0;
@@ -838,6 +881,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
       put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
       put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
     }
+    put_u64(&st->ovf_count, 0);
     put_u32(&st->ent_done, 0);
   }
   __syncthreads();

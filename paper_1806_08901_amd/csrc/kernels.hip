@@ -2,9 +2,10 @@
 //   k_range : value range over all N values (Algorithm 1, line 2)
 //   k_zfp   : ZFP bits and decoded error of the sampled blocks (Section 5.2)
 //   k_sz    : Lorenzo/quantization codes and their histogram (Section 5.1)
+//   k_ovf   : counts the codes that fell outside the SZ pass's LDS window
 //   k_ent   : entropy of the histogram, SZ bit-rate, selection (Eq. 5, Alg. 1)
-// Each ends in a last-workgroup finalizer, so one request is four launches
-// with no host round trip.
+// Passes with a cross-workgroup total end in a last-workgroup finalizer; a
+// request is a chain of launches on one stream with no host round trip.
 #include "estimator.hpp"
 #include "launch.hpp"
 
@@ -31,6 +32,12 @@ __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   sz_wg<T, D>(r, blockIdx.x, L, s_hist);
 }
 
+__global__ __launch_bounds__(kThreads) void k_ovf(ReqDesc r) {
+  __shared__ uint32_t s_cnt[kOvfBins];
+  if (skip_request(r.st)) return;
+  ovf_wg(r, blockIdx.x, s_cnt);
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_ent(ReqDesc r) {
   __shared__ TileLds L;
@@ -53,6 +60,9 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
   if ((e = mark(ev, 2, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
     hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ovf, dim3(kOvfWgs), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
@@ -88,9 +98,11 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 static size_t parts_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * 8, 256) * 4; }
 
-size_t request_workspace_bytes(int nrange, int nzfp, int nsz) {
+size_t request_workspace_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
   return align_up(sizeof(ReqState), 256) + parts_bytes(nrange) + parts_bytes(nzfp) +
          parts_bytes(nsz) + align_up(sizeof(double) * kEntWgs, 256) +
+         align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256) +
+         align_up(sizeof(uint32_t) * kBins * kOvfWgs, 256) +
          align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256);
 }
 
@@ -105,7 +117,8 @@ static Parts bind_parts(char *&p, int n) {
   return q;
 }
 
-void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz) {
+void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz,
+                            int64_t ovf_cap) {
   char *p = base;
   r.st = (ReqState *)p;
   p += align_up(sizeof(ReqState), 256);
@@ -114,6 +127,11 @@ void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int ns
   r.sp = bind_parts(p, nsz);
   r.ent = (double *)p;
   p += align_up(sizeof(double) * kEntWgs, 256);
+  r.ovf = (uint16_t *)p;
+  r.ovf_cap = ovf_cap;
+  p += align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256);
+  r.ovf_hist = (uint32_t *)p;
+  p += align_up(sizeof(uint32_t) * kBins * kOvfWgs, 256);
   r.hist = (uint32_t *)p;
   p += align_up(sizeof(uint32_t) * kBins, 256);
   r.res = (szsel_result *)p;

@@ -15,7 +15,8 @@ hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev 
 // Device bytes of one request's workspace (state, per-workgroup partials of
 // the three passes, 65536-bin histogram, result) for the given pass sizes,
 // and the binding of a zero-initialised region of that size to r.
-size_t request_workspace_bytes(int nrange, int nzfp, int nsz);
-void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz);
+size_t request_workspace_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap);
+void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz,
+                            int64_t ovf_cap);
 
 }  // namespace szsel

@@ -204,7 +204,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
     e = hipStreamWaitEvent(s, sl.done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
   }
-  bind_request_workspace(r, sl.mem, kMaxParts, kMaxParts, kMaxParts);
+  bind_request_workspace(r, sl.mem, kMaxParts, kMaxParts, kMaxParts, kOvfCap);
   if (ctx->dbg_armed) {
     r.dbg_codes = ctx->dbg.codes;
     r.dbg_zbits = ctx->dbg.zfp_bits;
@@ -247,7 +247,7 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
   szsel_ctx *c = new (std::nothrow) szsel_ctx();
   if (!c) return SZSEL_ENOMEM;
   c->device = hip_device;
-  c->budget = budget ? budget : ((size_t)1 << 30);
+  c->budget = budget ? budget : ((size_t)4 << 30);
   hipError_t e = hipSetDevice(hip_device);
   int ncu = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device);
@@ -256,7 +256,7 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
     return SZSEL_EHIP;
   }
   c->ncu = ncu > 0 ? ncu : 256;
-  const size_t slot_bytes = request_workspace_bytes(kMaxParts, kMaxParts, kMaxParts);
+  const size_t slot_bytes = request_workspace_bytes(kMaxParts, kMaxParts, kMaxParts, kOvfCap);
   if ((size_t)kSlots * slot_bytes > c->budget) {
     delete c;
     return SZSEL_ENOMEM;
