@@ -19,11 +19,7 @@ struct BatchState {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Overflow-list capacity of one request: every sampled point, up to kOvfCap.
-static int64_t ovf_cap_of(const ReqDesc &r) {
-  const int64_t pts = r.nblk << (2 * r.nd);
-  return pts < kOvfCap ? (pts > 0 ? pts : 1) : kOvfCap;
-}
+
 
 void batch_destroy(BatchState *bs) {
   if (!bs) return;
@@ -43,7 +39,7 @@ int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<R
   for (size_t i = 0; i < n; i++) {
     const ReqDesc &r = descs[i];
     base[i] = off;
-    off = align_up(off + request_workspace_bytes(r.nrange, r.nzfp, r.nsz, ovf_cap_of(r)), 256);
+    off = align_up(off + request_bytes(r), 256);
   }
   const size_t need = off;
   if (!bs) {
@@ -82,7 +78,7 @@ int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<R
   szsel_result *res = (szsel_result *)bs->mem;
   for (size_t i = 0; i < n && e == hipSuccess; i++) {
     ReqDesc &r = descs[i];
-    bind_request_workspace(r, bs->mem + base[i], r.nrange, r.nzfp, r.nsz, ovf_cap_of(r));
+    bind_request_workspace(r, bs->mem + base[i], r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
     r.res = res + i;
     e = launch_request(r, s);
   }

@@ -27,9 +27,9 @@ constexpr int kMaxTile = 256;          // sampled blocks per tile
 constexpr int kMaxParts = 8192;        // workgroups of one pass (partials per pass)
 constexpr int kEntChunk = 256;         // histogram bins per workgroup of the entropy pass
 constexpr int kEntWgs = 65536 / kEntChunk;
-constexpr int kOvfWgs = 64;            // workgroups that count the overflow codes
-constexpr int kOvfBins = 16384;        // bins per LDS pass of the overflow count (4 passes)
-constexpr int64_t kOvfCap = 1ll << 24; // overflow codes one request may buffer
+constexpr int kOvfSlices = 32;         // overflow count: slices of the SZ workgroups ...
+constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
+constexpr int kOvfBins = kBins / kOvfRanges;
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
@@ -74,7 +74,7 @@ struct alignas(64) ReqState {
   double delta, inv, eb_sz;
   double sz_sse, sz_maxerr;  // SZ totals handed from the SZ pass to the entropy pass
   uint64_t sz_unpred;
-  uint64_t ovf_count;        // codes appended to the overflow list (reset by the entropy pass)
+  uint64_t ovf_count;        // codes in the overflow regions (set by the SZ finalizer)
   int32_t minexp;
   uint32_t flags;
   uint32_t range_done, zfp_done, sz_done, ent_done;  // last-workgroup counters, reset by their finalizers
@@ -111,9 +111,8 @@ struct ReqDesc {
   ReqState *st;
   Parts rp, zp, sp;
   double *ent;     // one h log2 h subtree per 256-bin chunk of the histogram
-  uint16_t *ovf;   // overflow list: codes outside the LDS window (ovf_cap entries)
-  int64_t ovf_cap;
-  uint32_t *ovf_hist;  // kOvfWgs dense 65536-bin counts of the overflow list
+  uint16_t *ovf;       // per SZ workgroup, sblk * 4^d codes that fell outside its LDS window
+  uint32_t *ovf_hist;  // kOvfSlices dense 65536-bin counts of the overflow codes
   uint32_t *hist;
   szsel_result *res;
   uint16_t *dbg_codes;

@@ -687,10 +687,10 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
 // adds them with one atomic (most codes of a smooth field are equal), then
 // the remaining lanes add individually.  Bins near the zero code live in the
 // LDS window s_hist.  Codes outside it (wide histograms at tight bounds) are
-// appended to the request's overflow list, one global atomic per wave, and
-// counted later by the overflow pass; when the list is full they fall back
-// to global atomics on the histogram.
-__device__ inline void hist_add(const ReqDesc &r, bool want, int code, uint32_t *s_hist) {
+// appended to the workgroup's own overflow region (`region`, counter *s_n in
+// LDS) and counted by the overflow pass.
+__device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t *region,
+                                uint32_t *s_n) {
   const int wi = code - kHistLo;
   const bool inwin = want && wi >= 0 && wi < kHistWin;
   const bool outwin = want && !inwin;
@@ -708,19 +708,10 @@ __device__ inline void hist_add(const ReqDesc &r, bool want, int code, uint32_t 
   const uint64_t ovf = __ballot(outwin);
   if (ovf) {
     const int leader = __ffsll((long long)ovf) - 1;
-    uint64_t base = 0;
-    if (lane == leader)
-      base = __hip_atomic_fetch_add(&r.st->ovf_count, (uint64_t)__popcll(ovf), __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    base = __shfl(base, leader);
-    if (outwin) {
-      const uint64_t below = ovf & ((1ull << lane) - 1ull);
-      const uint64_t slot = base + (uint64_t)__popcll(below);
-      if (slot < (uint64_t)r.ovf_cap)
-        r.ovf[slot] = (uint16_t)code;
-      else
-        atomicAdd(&r.hist[code], 1u);
-    }
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(s_n, (uint32_t)__popcll(ovf));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    if (outwin) region[base + (uint32_t)__popcll(ovf & ((1ull << lane) - 1ull))] = (uint16_t)code;
   }
 }
 
@@ -728,7 +719,8 @@ __device__ inline void hist_add(const ReqDesc &r, bool want, int code, uint32_t 
 // current round is processed.
 template <typename T, int D>
 __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
-                               double ebsz, TileLds &L, uint32_t *s_hist, LaneAcc &acc) {
+                               double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
+                               uint32_t *s_n, LaneAcc &acc) {
   constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = lane & (BS - 1), bw = lane / BS;
@@ -742,7 +734,7 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
     if (rd + 1 < rounds) sn = load_stencil<T, D>(r, j + kWaves * BPW, i);
     double e2 = 0.0, ae = 0.0;
     const int code = active ? quantize<T>(sc.x, lorenzo_pred<T, D>(sc), delta, inv, ebsz, e2, ae) : 0;
-    hist_add(r, active && code != 0, code, s_hist);
+    hist_add(active && code != 0, code, s_hist, region, s_n);
     if (active) {
       acc.a += code == 0 ? 1u : 0u;
       acc.maxerr = fmax(acc.maxerr, ae);
@@ -780,6 +772,7 @@ __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
   uint64_t unpred, unused;
   parts_total(r.sp, r.nsz, L, sse, maxerr, unpred, unused);
   if (threadIdx.x == 0) {
+    put_u64(&r.st->ovf_count, unused);
     put_f64(&r.st->sz_sse, sse);
     put_f64(&r.st->sz_maxerr, maxerr);
     put_u64(&r.st->sz_unpred, unpred);
@@ -787,28 +780,31 @@ __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
   }
 }
 
-// Overflow pass, workgroup g of kOvfWgs: counts its slice of the overflow
-// list in LDS, 16384 bins per pass over the slice, and writes the dense
-// counts of all 65536 bins to its own slot (no atomics).
+// Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: counts, in
+// LDS, the overflow codes of SZ workgroups [p n/32, (p+1) n/32) that lie in
+// code range q, and writes the dense counts of that range to slice p's
+// counts (no atomics).
+template <int D>
 __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
-  const uint64_t total = min(get_u64(&r.st->ovf_count), (uint64_t)r.ovf_cap);
-  if (total == 0) return;
-  const uint64_t per = (total + kOvfWgs - 1) / kOvfWgs;
-  const uint64_t beg = (uint64_t)g * per;
-  const uint64_t end = min(total, beg + per);
-  uint32_t *slot = r.ovf_hist + (size_t)g * kBins;
-  for (int pass = 0; pass < kBins / kOvfBins; pass++) {
-    for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
-    __syncthreads();
-    const int lo = pass * kOvfBins;
-    for (uint64_t k = beg + threadIdx.x; k < end; k += kThreads) {
-      const int c = (int)r.ovf[k] - lo;
+  constexpr int BS = 1 << (2 * D);
+  if (get_u64(&r.st->ovf_count) == 0) return;
+  const int p = g / kOvfRanges, q = g % kOvfRanges;
+  const int w0 = (int)(((int64_t)r.nsz * p) / kOvfSlices);
+  const int w1 = (int)(((int64_t)r.nsz * (p + 1)) / kOvfSlices);
+  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
+  __syncthreads();
+  const int lo = q * kOvfBins;
+  for (int w = w0; w < w1; w++) {
+    const uint32_t n = (uint32_t)get_u64(r.sp.b + w);
+    const uint16_t *reg = r.ovf + (size_t)w * r.sblk * BS;
+    for (uint32_t k = threadIdx.x; k < n; k += kThreads) {
+      const int c = (int)reg[k] - lo;
       if (c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < kOvfBins; b += kThreads) slot[lo + b] = s_cnt[b];
-    __syncthreads();
   }
+  __syncthreads();
+  uint32_t *out = r.ovf_hist + (size_t)p * kBins + lo;
+  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) out[b] = s_cnt[b];
 }
 
 // Entropy pass, workgroup c of 256: the adjacent-pair subtree of h log2 h
@@ -828,7 +824,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   if (get_u64(&r.st->ovf_count) != 0) {  // add the overflow pass's counts
     uint32_t o = 0;
 #pragma unroll 8
-    for (int g = 0; g < kOvfWgs; g++) o += r.ovf_hist[(size_t)g * kBins + bin];
+    for (int p = 0; p < kOvfSlices; p++) o += r.ovf_hist[(size_t)p * kBins + bin];
     h += o;
   }
   if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
@@ -881,7 +877,6 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
       put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
       put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
     }
-    put_u64(&st->ovf_count, 0);
     put_u32(&st->ent_done, 0);
   }
   __syncthreads();
@@ -896,20 +891,26 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   const double ebsz = get_f64(&r.st->eb_sz);
   const int tile = r.sblk < kMaxTile ? r.sblk : kMaxTile;
   const int ntile = r.sblk / tile;
+  constexpr int BS = 1 << (2 * D);
   LaneAcc acc;
+  __shared__ uint32_t s_n;
+  uint16_t *region = r.ovf + (size_t)w * r.sblk * BS;
   hist_clear(s_hist);
   wg_acc_reset(L);
+  if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   for (int k = 0; k < ntile; k++) {
     const int64_t base = (int64_t)w * r.sblk + (int64_t)k * tile;
     if (base < r.nblk)
-      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist, acc);
+      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist, region, &s_n, acc);
     else
       wg_acc_push(L, 0.0);
   }
   __syncthreads();
   hist_flush(s_hist, r.hist);
+  if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
   wg_acc_store(L, acc, r.sp, w);
+  if (threadIdx.x == 0) put_u64(r.sp.b + w, s_n);
   if (!last_to_finish(&r.st->sz_done, (uint32_t)r.nsz, &L.last)) return false;
   sz_finalize(r, L);
   return true;

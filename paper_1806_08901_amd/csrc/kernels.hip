@@ -32,10 +32,11 @@ __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   sz_wg<T, D>(r, blockIdx.x, L, s_hist);
 }
 
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_ovf(ReqDesc r) {
   __shared__ uint32_t s_cnt[kOvfBins];
   if (skip_request(r.st)) return;
-  ovf_wg(r, blockIdx.x, s_cnt);
+  ovf_wg<D>(r, blockIdx.x, s_cnt);
 }
 
 template <typename T, int D>
@@ -62,7 +63,7 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
     hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ovf, dim3(kOvfWgs), dim3(kThreads), 0, s, r);
+    hipLaunchKernelGGL((k_ovf<D>), dim3(kOvfSlices * kOvfRanges), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
@@ -102,7 +103,7 @@ size_t request_workspace_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
   return align_up(sizeof(ReqState), 256) + parts_bytes(nrange) + parts_bytes(nzfp) +
          parts_bytes(nsz) + align_up(sizeof(double) * kEntWgs, 256) +
          align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256) +
-         align_up(sizeof(uint32_t) * kBins * kOvfWgs, 256) +
+         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256) +
          align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256);
 }
 
@@ -128,10 +129,9 @@ void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int ns
   r.ent = (double *)p;
   p += align_up(sizeof(double) * kEntWgs, 256);
   r.ovf = (uint16_t *)p;
-  r.ovf_cap = ovf_cap;
   p += align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256);
   r.ovf_hist = (uint32_t *)p;
-  p += align_up(sizeof(uint32_t) * kBins * kOvfWgs, 256);
+  p += align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
   r.hist = (uint32_t *)p;
   p += align_up(sizeof(uint32_t) * kBins, 256);
   r.res = (szsel_result *)p;

@@ -22,6 +22,7 @@ constexpr int kSlots = 4;
 
 struct Slot {
   char *mem = nullptr;
+  size_t bytes = 0;
   hipEvent_t done = nullptr;
   bool used = false;
 };
@@ -200,11 +201,34 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   hipStream_t s = (hipStream_t)stream;
   Slot &sl = ctx->slots[ctx->next];
   ctx->next = (ctx->next + 1) % kSlots;
+  const size_t need = request_bytes(r);
+  if (need > sl.bytes) {  // grow the slot (waits for the device)
+    if (ctx->used_bytes - sl.bytes + need > ctx->budget)
+      return fail(ctx, SZSEL_ENOMEM, "request workspace exceeds the context's budget");
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    if (sl.mem) (void)hipFree(sl.mem);
+    ctx->used_bytes -= sl.bytes;
+    sl.mem = nullptr;
+    sl.bytes = 0;
+    sl.used = false;
+    void *p = nullptr;
+    e = hipMalloc(&p, need);
+    if (e == hipSuccess) e = hipMemset(p, 0, need);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      if (p) (void)hipFree(p);
+      return hip_fail(ctx, e, "workspace allocation");
+    }
+    sl.mem = (char *)p;
+    sl.bytes = need;
+    ctx->used_bytes += need;
+  }
   if (sl.used) {
     e = hipStreamWaitEvent(s, sl.done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
   }
-  bind_request_workspace(r, sl.mem, kMaxParts, kMaxParts, kMaxParts, kOvfCap);
+  bind_request_workspace(r, sl.mem, r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
   if (ctx->dbg_armed) {
     r.dbg_codes = ctx->dbg.codes;
     r.dbg_zbits = ctx->dbg.zfp_bits;
@@ -256,24 +280,13 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
     return SZSEL_EHIP;
   }
   c->ncu = ncu > 0 ? ncu : 256;
-  const size_t slot_bytes = request_workspace_bytes(kMaxParts, kMaxParts, kMaxParts, kOvfCap);
-  if ((size_t)kSlots * slot_bytes > c->budget) {
-    delete c;
-    return SZSEL_ENOMEM;
-  }
+  // slots are allocated on first use and grow with the requests they serve
   for (int k = 0; k < kSlots; k++) {
-    Slot &s = c->slots[k];
-    void *p = nullptr;
-    e = hipMalloc(&p, slot_bytes);
-    if (e == hipSuccess) e = hipMemset(p, 0, slot_bytes);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&c->slots[k].done, hipEventDisableTiming);
     if (e != hipSuccess) {
-      if (p) (void)hipFree(p);
       szsel_destroy(c);
       return SZSEL_EHIP;
     }
-    s.mem = (char *)p;
-    c->used_bytes += slot_bytes;
   }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
