@@ -99,12 +99,20 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 static size_t parts_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * 8, 256) * 4; }
 
-size_t request_workspace_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
-  return align_up(sizeof(ReqState), 256) + parts_bytes(nrange) + parts_bytes(nzfp) +
-         parts_bytes(nsz) + align_up(sizeof(double) * kEntWgs, 256) +
-         align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256) +
-         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256) +
-         align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256);
+
+// Fixed part: what must persist between requests at the same place (state
+// with its completion counters, the self-cleaning histogram) and the
+// fixed-size buffers.  Variable part: per-workgroup partials and overflow
+// regions, fully rewritten by every request.
+size_t request_fixed_bytes() {
+  return align_up(sizeof(ReqState), 256) + align_up(sizeof(uint32_t) * kBins, 256) +
+         align_up(sizeof(szsel_result), 256) + align_up(sizeof(double) * kEntWgs, 256) +
+         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
+}
+
+size_t request_var_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
+  return parts_bytes(nrange) + parts_bytes(nzfp) + parts_bytes(nsz) +
+         align_up(sizeof(uint16_t) * (size_t)(ovf_cap > 0 ? ovf_cap : 1), 256);
 }
 
 static Parts bind_parts(char *&p, int n) {
@@ -118,23 +126,22 @@ static Parts bind_parts(char *&p, int n) {
   return q;
 }
 
-void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz,
-                            int64_t ovf_cap) {
-  char *p = base;
+void bind_request_workspace(ReqDesc &r, char *fixed, char *var) {
+  char *p = fixed;
   r.st = (ReqState *)p;
   p += align_up(sizeof(ReqState), 256);
-  r.rp = bind_parts(p, nrange);
-  r.zp = bind_parts(p, nzfp);
-  r.sp = bind_parts(p, nsz);
-  r.ent = (double *)p;
-  p += align_up(sizeof(double) * kEntWgs, 256);
-  r.ovf = (uint16_t *)p;
-  p += align_up(sizeof(uint16_t) * (size_t)ovf_cap, 256);
-  r.ovf_hist = (uint32_t *)p;
-  p += align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
   r.hist = (uint32_t *)p;
   p += align_up(sizeof(uint32_t) * kBins, 256);
   r.res = (szsel_result *)p;
+  p += align_up(sizeof(szsel_result), 256);
+  r.ent = (double *)p;
+  p += align_up(sizeof(double) * kEntWgs, 256);
+  r.ovf_hist = (uint32_t *)p;
+  p = var;
+  r.rp = bind_parts(p, r.nrange);
+  r.zp = bind_parts(p, r.nzfp);
+  r.sp = bind_parts(p, r.nsz);
+  r.ovf = (uint16_t *)p;
 }
 
 }  // namespace szsel

@@ -12,20 +12,21 @@ namespace szsel {
 // and after the SZ pass (phase timers).
 hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev = nullptr);
 
-// Device bytes of one request's workspace (state, per-workgroup partials of
-// the three passes, 65536-bin histogram, result) for the given pass sizes,
-// and the binding of a zero-initialised region of that size to r.
-size_t request_workspace_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap);
+// Workspace of one request: a fixed part that must stay at the same place
+// from one request to the next (state and counters, the self-cleaning
+// histogram, result, chunk sums, overflow counts; zero-initialised once) and
+// a variable part (per-workgroup partials, overflow regions).
+size_t request_fixed_bytes();
+size_t request_var_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap);
+void bind_request_workspace(ReqDesc &r, char *fixed, char *var);
 
 // Overflow-region capacity of a planned request (sblk * 4^d codes per SZ
-// workgroup) and its total workspace size.
+// workgroup) and its variable workspace size.
 inline int64_t request_ovf_capacity(const ReqDesc &r) {
   return ((int64_t)r.nsz * r.sblk) << (2 * r.nd);
 }
-inline size_t request_bytes(const ReqDesc &r) {
-  return request_workspace_bytes(r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
+inline size_t request_var_bytes(const ReqDesc &r) {
+  return request_var_bytes(r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
 }
-void bind_request_workspace(ReqDesc &r, char *base, int nrange, int nzfp, int nsz,
-                            int64_t ovf_cap);
 
 }  // namespace szsel

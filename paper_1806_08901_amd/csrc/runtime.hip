@@ -201,7 +201,8 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   hipStream_t s = (hipStream_t)stream;
   Slot &sl = ctx->slots[ctx->next];
   ctx->next = (ctx->next + 1) % kSlots;
-  const size_t need = request_bytes(r);
+  const size_t fixed = request_fixed_bytes();
+  const size_t need = fixed + request_var_bytes(r);
   if (need > sl.bytes) {  // grow the slot (waits for the device)
     if (ctx->used_bytes - sl.bytes + need > ctx->budget)
       return fail(ctx, SZSEL_ENOMEM, "request workspace exceeds the context's budget");
@@ -228,7 +229,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
     e = hipStreamWaitEvent(s, sl.done, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
   }
-  bind_request_workspace(r, sl.mem, r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
+  bind_request_workspace(r, sl.mem, sl.mem + fixed);
   if (ctx->dbg_armed) {
     r.dbg_codes = ctx->dbg.codes;
     r.dbg_zbits = ctx->dbg.zfp_bits;
