@@ -27,7 +27,7 @@ constexpr int kMaxTile = 256;          // sampled blocks per tile
 constexpr int kMaxParts = 8192;        // workgroups of one pass (partials per pass)
 constexpr int kEntChunk = 256;         // histogram bins per workgroup of the entropy pass
 constexpr int kEntWgs = 65536 / kEntChunk;
-constexpr int kOvfSlices = 32;         // overflow count: slices of the SZ workgroups ...
+constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
 

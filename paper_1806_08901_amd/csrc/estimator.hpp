@@ -781,9 +781,10 @@ __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
 }
 
 // Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: counts, in
-// LDS, the overflow codes of SZ workgroups [p n/32, (p+1) n/32) that lie in
+// LDS, the overflow codes of SZ workgroups [p n/S, (p+1) n/S) that lie in
 // code range q, and writes the dense counts of that range to slice p's
-// counts (no atomics).
+// counts (no atomics).  The slice's regions are walked as one sequence of
+// 16-byte vectors (8 codes), 4 vectors in flight per thread.
 template <int D>
 __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   constexpr int BS = 1 << (2 * D);
@@ -794,13 +795,37 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
   __syncthreads();
   const int lo = q * kOvfBins;
-  for (int w = w0; w < w1; w++) {
-    const uint32_t n = (uint32_t)get_u64(r.sp.b + w);
-    const uint16_t *reg = r.ovf + (size_t)w * r.sblk * BS;
-    for (uint32_t k = threadIdx.x; k < n; k += kThreads) {
-      const int c = (int)reg[k] - lo;
-      if (c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
+  const int64_t cap = (int64_t)r.sblk * BS;     // codes per region (a multiple of 64)
+  const int64_t vpr = cap / 8;                  // vectors per region
+  const int64_t nv = (int64_t)(w1 - w0) * vpr;  // vectors of the slice
+  auto count = [&](uint4 v, int valid) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int c = (int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu) - lo;
+      if (e < valid && c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
     }
+  };
+  for (int64_t k0 = threadIdx.x; k0 < nv; k0 += 4 * kThreads) {
+    uint4 v[4];
+    int valid[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int64_t k = k0 + (int64_t)u * kThreads;
+      valid[u] = 0;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (k < nv) {
+        const int w = w0 + (int)(k / vpr);
+        const int64_t off = (k % vpr) * 8;
+        const int64_t n = (int64_t)get_u64(r.sp.b + w);
+        if (off < n) {
+          v[u] = *(const uint4 *)(r.ovf + (size_t)w * cap + off);
+          valid[u] = (int)min<int64_t>(8, n - off);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) count(v[u], valid[u]);
   }
   __syncthreads();
   uint32_t *out = r.ovf_hist + (size_t)p * kBins + lo;
