@@ -783,21 +783,36 @@ __device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
 // Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: counts, in
 // LDS, the overflow codes of SZ workgroups [p n/S, (p+1) n/S) that lie in
 // code range q, and writes the dense counts of that range to slice p's
-// counts (no atomics).  The slice's regions are walked as one sequence of
-// 16-byte vectors (8 codes), 4 vectors in flight per thread.
+// counts (no atomics).  The occupied 16-byte vectors (8 codes) of the
+// slice's regions are numbered through an LDS prefix sum of the regions'
+// vector counts, so the work follows the number of overflow codes; 4
+// vectors are in flight per thread.
+constexpr int kOvfMaxRegions = kMaxParts / kOvfSlices + 1;
+
 template <int D>
 __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   constexpr int BS = 1 << (2 * D);
   if (get_u64(&r.st->ovf_count) == 0) return;
+  __shared__ uint32_t s_n[kOvfMaxRegions], s_pre[kOvfMaxRegions + 1];
   const int p = g / kOvfRanges, q = g % kOvfRanges;
   const int w0 = (int)(((int64_t)r.nsz * p) / kOvfSlices);
   const int w1 = (int)(((int64_t)r.nsz * (p + 1)) / kOvfSlices);
+  const int nreg = w1 - w0;
   for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
+  for (int k = threadIdx.x; k < nreg; k += kThreads) s_n[k] = (uint32_t)get_u64(r.sp.b + w0 + k);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < nreg; k++) {
+      s_pre[k] = acc;
+      acc += (s_n[k] + 7) / 8;
+    }
+    s_pre[nreg] = acc;
+  }
   __syncthreads();
   const int lo = q * kOvfBins;
-  const int64_t cap = (int64_t)r.sblk * BS;     // codes per region (a multiple of 64)
-  const int64_t vpr = cap / 8;                  // vectors per region
-  const int64_t nv = (int64_t)(w1 - w0) * vpr;  // vectors of the slice
+  const int64_t cap = (int64_t)r.sblk * BS;  // codes per region (a multiple of 64)
+  const uint32_t nv = s_pre[nreg];
   auto count = [&](uint4 v, int valid) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -806,22 +821,23 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
       if (e < valid && c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
     }
   };
-  for (int64_t k0 = threadIdx.x; k0 < nv; k0 += 4 * kThreads) {
+  for (uint32_t k0 = threadIdx.x; k0 < nv; k0 += 4 * kThreads) {
     uint4 v[4];
     int valid[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const int64_t k = k0 + (int64_t)u * kThreads;
+      const uint32_t k = k0 + (uint32_t)u * kThreads;
       valid[u] = 0;
       v[u] = make_uint4(0, 0, 0, 0);
       if (k < nv) {
-        const int w = w0 + (int)(k / vpr);
-        const int64_t off = (k % vpr) * 8;
-        const int64_t n = (int64_t)get_u64(r.sp.b + w);
-        if (off < n) {
-          v[u] = *(const uint4 *)(r.ovf + (size_t)w * cap + off);
-          valid[u] = (int)min<int64_t>(8, n - off);
+        int lo_i = 0, hi_i = nreg - 1;  // last region with s_pre <= k
+        while (lo_i < hi_i) {
+          const int mid = (lo_i + hi_i + 1) >> 1;
+          if (s_pre[mid] <= k) lo_i = mid; else hi_i = mid - 1;
         }
+        const int64_t off = (int64_t)(k - s_pre[lo_i]) * 8;
+        v[u] = *(const uint4 *)(r.ovf + (size_t)(w0 + lo_i) * cap + off);
+        valid[u] = (int)min<int64_t>(8, (int64_t)s_n[lo_i] - off);
       }
     }
 #pragma unroll
