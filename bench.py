@@ -41,6 +41,34 @@ def parse():
     return ap.parse_args()
 
 
+def covered(n, nb_stride):
+    """Coordinates along one axis that the SZ pass reads: every sampled
+    block's 4 points plus the Lorenzo predecessor at -1, inside [0, n)."""
+    nb = n // 4
+    cells = set()
+    for j in range(0, nb, nb_stride):
+        for c in range(4 * j - 1, 4 * j + 4):
+            if 0 <= c < n:
+                cells.add(c)
+    return len(cells)
+
+
+def pass_bytes(shape, stride, itemsize, nblk):
+    """Algorithmic bytes each pass must move per launch: the range pass reads
+    every value once; the ZFP pass the sampled blocks' values; the SZ pass
+    the sampled values and their Lorenzo predecessors (unique values of the
+    sampled boxes extended by one cell toward the origin); the entropy pass
+    the 65536-bin histogram."""
+    n = 1
+    for d in shape:
+        n *= d
+    halo = 1
+    for d, s in zip(shape, stride):
+        halo *= covered(d, s)
+    return {"range": n * itemsize, "zfp": nblk * 4 ** len(shape) * itemsize,
+            "sz": halo * itemsize, "ent": 65536 * 4}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -90,10 +118,21 @@ def main():
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.set_option(szsel.OPT_PROFILE, 0)
-    range_ms = prof["range"][0] / max(1, prof["range"][1])
-    zfp_ms = prof["zfp"][0] / max(1, prof["zfp"][1])
-    sz_ms = prof["sz"][0] / max(1, prof["sz"][1])
-    achieved = nbytes / (range_ms * 1e-3) / 1e9
+    phase_ms = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
+    pbytes = pass_bytes((n, n, n), stride, field.element_size(), int(gpu_results[0]["zfp_blocks"]))
+    kernels = {"range": "k_range (value range over all N values)",
+               "zfp": "k_zfp (ZFP transform, coder count and decode of the sampled blocks)",
+               "sz": "k_sz (Lorenzo prediction, quantization codes, LDS histogram)",
+               "ovf": "k_ovf (counts of codes outside the LDS window)",
+               "ent": "k_ent (entropy, bit-rates, selection)"}
+    dominant = max(phase_ms, key=lambda k: phase_ms[k])
+    passes = {}
+    for k, ms in phase_ms.items():
+        entry = {"ms": round(ms, 5)}
+        if k in pbytes:
+            gbs = pbytes[k] / (ms * 1e-3) / 1e9
+            entry.update({"bytes": pbytes[k], "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        passes[k] = entry
 
     # latency of one synchronous select call (host wall clock)
     lat = []
@@ -125,12 +164,12 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "hbm", "kernel": "k_range (value-range scan, all N values)",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": nbytes, "avg_launch_ms": round(range_ms, 5),
+            "bound": "hbm", "kernel": kernels[dominant],
+            "achieved": passes[dominant].get("GB/s"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": passes[dominant].get("frac"), "traffic": None,
+            "bytes_per_launch": pbytes.get(dominant), "avg_launch_ms": round(phase_ms[dominant], 5),
         },
-        "phases_ms": {"range": round(range_ms, 5), "zfp": round(zfp_ms, 5), "sz": round(sz_ms, 5)},
+        "passes": passes,
         "latency_ms": {"p50": round(lat[len(lat) // 2], 4),
                        "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
                        "calls": len(lat), "what": "one synchronous szsel_select on the field"},

@@ -170,14 +170,15 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
 /* Options.
  * SZSEL_OPT_SZ_OFFSET: bits per value added to the SZ entropy estimate
  *   (Section 6.2 sets it to 0.5; default 0.5).
- * SZSEL_OPT_PROFILE: nonzero records HIP events around the range, ZFP and SZ
- *   passes of every single-request call (read with szsel_profile_read). */
+ * SZSEL_OPT_PROFILE: nonzero records HIP events between the passes of every
+ *   single-request call (read with szsel_profile_read). */
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* Phase timers: synchronises the recorded events and returns, per phase
- * (0 = range pass, 1 = ZFP pass, 2 = SZ pass), the summed GPU milliseconds
- * in ms[3] and the number of timed calls in calls[3]; then clears them. */
+ * (0 = range pass, 1 = ZFP pass, 2 = SZ pass, 3 = overflow count, 4 =
+ * entropy and selection), the summed GPU milliseconds in ms[5] and the
+ * number of timed calls in calls[5]; then clears them. */
 int szsel_profile_read(szsel_ctx *ctx, double *ms, uint64_t *calls);
 
 /* Arms per-sample dumps for the next single-request call (NULL disarms). */

@@ -63,14 +63,20 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
     hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if ((e = mark(ev, 3, s)) != hipSuccess) return e;
+  if (r.op != SZSEL_OP_ZFP) {
     hipLaunchKernelGGL((k_ovf<D>), dim3(kOvfSlices * kOvfRanges), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if ((e = mark(ev, 4, s)) != hipSuccess) return e;
+  if (r.op != SZSEL_OP_ZFP) {
     hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return mark(ev, 3, s);
+  return mark(ev, 5, s);
 }
 
 template <typename T>

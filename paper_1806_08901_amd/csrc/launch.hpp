@@ -8,8 +8,8 @@
 namespace szsel {
 
 // Enqueues the kernels of one request on stream s.  When ev is not NULL,
-// ev[0..3] are recorded before the range pass, after it, after the ZFP pass
-// and after the SZ pass (phase timers).
+// ev[0..5] are recorded before the range pass and after the range, ZFP, SZ,
+// overflow-count and entropy passes (phase timers).
 hipError_t launch_request(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // Workspace of one request: a fixed part that must stay at the same place

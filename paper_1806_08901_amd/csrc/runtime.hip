@@ -19,6 +19,8 @@ using namespace szsel;
 namespace {
 
 constexpr int kSlots = 4;
+constexpr int kPhases = 5;  // range, ZFP, SZ, overflow count, entropy
+constexpr int kEv = kPhases + 1;
 
 struct Slot {
   char *mem = nullptr;
@@ -43,10 +45,10 @@ struct szsel_ctx {
   BatchState *batch = nullptr;
   // phase timers
   bool prof = false;
-  std::vector<hipEvent_t> prof_events;  // 4 per recorded call
-  size_t prof_used = 0;                 // events in use (multiple of 4)
-  double prof_ms[3] = {0, 0, 0};
-  uint64_t prof_calls[3] = {0, 0, 0};
+  std::vector<hipEvent_t> prof_events;  // kPhases + 1 per recorded call
+  size_t prof_used = 0;                 // events in use
+  double prof_ms[kPhases] = {};
+  uint64_t prof_calls[kPhases] = {};
 };
 
 namespace {
@@ -169,15 +171,15 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
 
 namespace {
 
-constexpr size_t kProfEvents = 4 * 1024;
+constexpr size_t kProfEvents = kEv * 1024;
 
 // Accumulates the elapsed times of the recorded phase events and frees them.
 int profile_drain(szsel_ctx *c) {
-  for (size_t k = 0; k + 4 <= c->prof_used; k += 4) {
+  for (size_t k = 0; k + kEv <= c->prof_used; k += kEv) {
     hipEvent_t *ev = &c->prof_events[k];
-    hipError_t e = hipEventSynchronize(ev[3]);
+    hipError_t e = hipEventSynchronize(ev[kPhases]);
     if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-    for (int ph = 0; ph < 3; ph++) {
+    for (int ph = 0; ph < kPhases; ph++) {
       float ms = 0.f;
       e = hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
       if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
@@ -241,12 +243,12 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   }
   const hipEvent_t *ev = nullptr;
   if (ctx->prof) {
-    if (ctx->prof_used + 4 > ctx->prof_events.size()) {
+    if (ctx->prof_used + kEv > ctx->prof_events.size()) {
       int rc2 = profile_drain(ctx);
       if (rc2 != SZSEL_OK) return rc2;
     }
     ev = &ctx->prof_events[ctx->prof_used];
-    ctx->prof_used += 4;
+    ctx->prof_used += kEv;
   }
   e = launch_request(r, s, ev);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
@@ -425,7 +427,7 @@ int szsel_profile_read(szsel_ctx *c, double *ms, uint64_t *calls) {
   if (!c || !ms || !calls) return SZSEL_EINVAL;
   int rc = profile_drain(c);
   if (rc != SZSEL_OK) return rc;
-  for (int k = 0; k < 3; k++) {
+  for (int k = 0; k < kPhases; k++) {
     ms[k] = c->prof_ms[k];
     calls[k] = c->prof_calls[k];
     c->prof_ms[k] = 0.0;

@@ -173,13 +173,15 @@ class Context:
     def set_option(self, option: int, value: float):
         self._check(self.lib.szsel_set_option(self.h, option, float(value)), "szsel_set_option")
 
+    PHASES = ("range", "zfp", "sz", "ovf", "ent")
+
     def profile_read(self):
         """Per-phase GPU milliseconds and call counts since the last read:
-        {"range": (ms, n), "zfp": (ms, n), "sz": (ms, n)}."""
-        ms = (C.c_double * 3)()
-        n = (C.c_uint64 * 3)()
+        {"range": (ms, n), "zfp": ..., "sz": ..., "ovf": ..., "ent": ...}."""
+        ms = (C.c_double * 5)()
+        n = (C.c_uint64 * 5)()
         self._check(self.lib.szsel_profile_read(self.h, ms, n), "szsel_profile_read")
-        return {k: (ms[i], n[i]) for i, k in enumerate(("range", "zfp", "sz"))}
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.PHASES)}
 
     def set_debug(self, dbg: dict | None):
         """Arms per-sample dumps for the next single call.  ``dbg`` maps the
