@@ -30,6 +30,9 @@ constexpr int kEntWgs = 65536 / kEntChunk;
 constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
+constexpr int kGroup = 64;             // workgroups per completion group
+constexpr int kMaxGroups = kMaxParts / kGroup;
+enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
@@ -77,15 +80,29 @@ struct alignas(64) ReqState {
   uint64_t ovf_count;        // codes in the overflow regions (set by the SZ finalizer)
   int32_t minexp;
   uint32_t flags;
-  uint32_t range_done, zfp_done, sz_done, ent_done;  // last-workgroup counters, reset by their finalizers
 };
 
-// One entry per workgroup of a pass (structure of arrays, coalesced reads).
+// Completion counters of one pass.  Atomics on one address (one 128-byte
+// line) serialise at about 11 ns each on this part, so thousands of
+// workgroups counting on a single word would take tens of microseconds:
+// workgroups count in groups of kGroup, each group on its own line, and the
+// last workgroup of each group counts on `top`.  Every counter is reset by
+// the workgroup that completes it.
+struct alignas(128) LineCtr {
+  uint32_t v;
+};
+struct PassSync {
+  LineCtr top;
+  LineCtr group[kMaxGroups];
+};
+
+// One entry per workgroup (or completion group) of a pass, structure of
+// arrays.
 struct Parts {
-  double *sse;   // ZFP/SZ: squared-error subtree of the workgroup; range: min
-  double *err;   // ZFP/SZ: max |error|;                              range: max
+  double *sse;   // ZFP/SZ: squared-error subtree; range: min; entropy: h log2 h subtree
+  double *err;   // ZFP/SZ: max |error|;            range: max
   uint64_t *a;   // ZFP: coder bits; SZ: unpredictable points; range: non-finite flag
-  uint64_t *b;   // ZFP: significant bits
+  uint64_t *b;   // ZFP: significant bits; SZ: overflow codes
 };
 
 // Everything a kernel needs about one request (passed by value).
@@ -101,16 +118,18 @@ struct ReqDesc {
   int64_t nboff[7];    // element offsets of the Lorenzo neighbours, in predictor term order
   int32_t nd, dtype, op, eb_mode;
   double eb, sz_offset;
-  int32_t zblk;    // sampled blocks per ZFP workgroup (power of two)
+  int32_t zblk;    // sampled blocks per ZFP workgroup (power of two, >= 64: one per lane)
   int32_t nzfp;    // ZFP workgroups = ceil(nblk / zblk)
   int32_t sblk;    // sampled blocks per SZ workgroup (power of two)
   int32_t nsz;     // SZ workgroups
   int64_t rchunk;  // values per range workgroup (multiple of 16 bytes)
   int32_t nrange;  // range workgroups
-  int32_t pad0;
+  int32_t vec;     // 1: every row of 4 values starts 16-byte aligned (vector loads)
   ReqState *st;
+  PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;
-  double *ent;     // one h log2 h subtree per 256-bin chunk of the histogram
+  Parts ep;        // entropy pass: one h log2 h subtree per 256-bin chunk (sse slot)
+  Parts grp[kPasses];  // per pass, the partials of its completion groups
   uint16_t *ovf;       // per SZ workgroup, sblk * 4^d codes that fell outside its LDS window
   uint32_t *ovf_hist;  // kOvfSlices dense 65536-bin counts of the overflow codes
   uint32_t *hist;
@@ -273,6 +292,16 @@ __device__ inline V group_max(V v) {
   for (int s = 1; s < WIDTH; s <<= 1) {
     V o = __shfl_xor(v, s);
     v = o > v ? o : v;
+  }
+  return v;
+}
+
+template <int WIDTH, typename V>
+__device__ inline V group_min(V v) {
+#pragma unroll
+  for (int s = 1; s < WIDTH; s <<= 1) {
+    V o = __shfl_xor(v, s);
+    v = o < v ? o : v;
   }
   return v;
 }

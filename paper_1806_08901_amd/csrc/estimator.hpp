@@ -32,25 +32,111 @@ struct TileLds {
   double stk[24];
   int sp;
   uint32_t pushes;
-  int last;
+  int last, last2;
 };
 
 __device__ inline bool skip_request(const ReqState *st) {
   return (get_u32(&st->flags) & kSkipFlags) != 0;
 }
 
-// Last-workgroup detection: true in every thread of the workgroup that
-// completes `counter` to `total`.  Each thread first waits for its own
-// memory operations (atomic partial stores, histogram atomics) to complete.
-__device__ inline bool last_to_finish(uint32_t *counter, uint32_t total, int *s_flag) {
+// Partial result of a workgroup or a completion group: s is summed by the
+// adjacent-pair tree (or, for the range pass, minimised), m maximised, a and
+// b summed as integers.
+struct Part {
+  double s, m;
+  uint64_t a, b;
+};
+
+template <bool MINMAX>
+__device__ inline Part part_identity() {
+  Part v;
+  v.s = MINMAX ? INFINITY : 0.0;
+  v.m = MINMAX ? -INFINITY : 0.0;
+  v.a = 0;
+  v.b = 0;
+  return v;
+}
+
+__device__ inline void part_store(const Parts &p, int i, const Part &v) {
+  put_f64(p.sse + i, v.s);
+  put_f64(p.err + i, v.m);
+  put_u64(p.a + i, v.a);
+  put_u64(p.b + i, v.b);
+}
+
+__device__ inline Part part_load(const Parts &p, int i) {
+  Part v;
+  v.s = get_f64(p.sse + i);
+  v.m = get_f64(p.err + i);
+  v.a = get_u64(p.a + i);
+  v.b = get_u64(p.b + i);
+  return v;
+}
+
+// Left-to-right combination of two adjacent partials.
+template <bool MINMAX>
+__device__ inline Part part_combine(const Part &x, const Part &y) {
+  Part v;
+  v.s = MINMAX ? fmin(x.s, y.s) : x.s + y.s;
+  v.m = fmax(x.m, y.m);
+  v.a = x.a + y.a;
+  v.b = x.b + y.b;
+  return v;
+}
+
+// Combination of the 64 lanes' partials in lane order (the xor butterfly
+// associates like the adjacent-pair tree); the result is in every lane.
+template <bool MINMAX>
+__device__ inline Part part_wave(Part v) {
+  v.s = MINMAX ? group_min<kWave>(v.s) : group_tree_sum<kWave>(v.s);
+  v.m = group_max<kWave>(v.m);
+  v.a = group_isum<kWave>(v.a);
+  v.b = group_isum<kWave>(v.b);
+  return v;
+}
+
+// Completion of a pass of n <= kMaxParts workgroups, each of which has
+// stored its partial at its index of `p`.  The workgroups count in groups of
+// kGroup; the last workgroup of a group combines the group's partials
+// (an aligned subtree) into gp[g] and counts on the top counter; the last
+// group combines the group partials.  Agent-scope atomics only, no fences:
+// every thread first waits for its own memory operations.  Returns true in
+// every thread of the workgroup that holds the pass totals (in wave 0).
+template <bool MINMAX>
+__device__ inline bool pass_complete(const Parts &p, const Parts &gp, PassSync *sy, int w, int n,
+                                     TileLds &L, Part &tot) {
+  const int g = w / kGroup;
+  const int ng = (n + kGroup - 1) / kGroup;
+  const int gs = min(kGroup, n - g * kGroup);
   wait_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t old = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *s_flag = old == total - 1;
+    const uint32_t old = __hip_atomic_fetch_add(&sy->group[g].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    L.last = old == (uint32_t)gs - 1;
+    if (L.last) put_u32(&sy->group[g].v, 0);
   }
   __syncthreads();
-  return *s_flag != 0;
+  if (!L.last) return false;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const Part v = part_wave<MINMAX>(lane < gs ? part_load(p, g * kGroup + lane) : part_identity<MINMAX>());
+    if (lane == 0) part_store(gp, g, v);
+    wait_memory();
+    if (lane == 0) {
+      const uint32_t old = __hip_atomic_fetch_add(&sy->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      L.last2 = old == (uint32_t)ng - 1;
+      if (L.last2) put_u32(&sy->top.v, 0);
+    }
+  }
+  __syncthreads();
+  if (!L.last2) return false;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const Part x = 2 * lane < ng ? part_load(gp, 2 * lane) : part_identity<MINMAX>();
+    const Part y = 2 * lane + 1 < ng ? part_load(gp, 2 * lane + 1) : part_identity<MINMAX>();
+    tot = part_wave<MINMAX>(part_combine<MINMAX>(x, y));
+  }
+  return true;
 }
 
 // ===========================================================================
@@ -202,162 +288,240 @@ __device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
   uint32_t amax;
   range_reduce_wg<T>(acc, lo, hi, amax);
   if (threadIdx.x == 0) {
-    put_f64(r.rp.sse + w, lo);
-    put_f64(r.rp.err + w, hi);
-    put_u64(r.rp.a + w, amax >= (sizeof(T) == 4 ? 0x7f800000u : 0x7ff00000u) ? 1u : 0u);
+    Part v;
+    v.s = lo;
+    v.m = hi;
+    v.a = amax >= (sizeof(T) == 4 ? 0x7f800000u : 0x7ff00000u) ? 1u : 0u;
+    v.b = 0;
+    part_store(r.rp, w, v);
   }
-  if (!last_to_finish(&r.st->range_done, (uint32_t)r.nrange, &L.last)) return;
-  double tlo = INFINITY, thi = -INFINITY;
-  uint32_t bad = 0;
-  for (int k = threadIdx.x; k < r.nrange; k += kThreads) {
-    tlo = fmin(tlo, get_f64(r.rp.sse + k));
-    thi = fmax(thi, get_f64(r.rp.err + k));
-    bad |= (uint32_t)get_u64(r.rp.a + k);
-  }
-  RangeAcc<double> t;
-  t.lo = tlo;
-  t.hi = thi;
-  t.amax = bad;
-  range_reduce_wg<double>(t, lo, hi, amax);
-  if (threadIdx.x == 0) {
-    range_finalize_one(r, lo, hi, amax != 0);
-    put_u32(&r.st->range_done, 0);
-  }
+  Part tot;
+  if (!pass_complete<true>(r.rp, r.grp[kPassRange], r.sync + kPassRange, w, r.nrange, L, tot)) return;
+  if (threadIdx.x == 0) range_finalize_one(r, tot.s, tot.m, tot.a != 0);
 }
 
 // ===========================================================================
-// ZFP side (Sections 4.2 and 5.2) on one wave-group of 4^D lanes per block
+// ZFP side (Sections 4.2 and 5.2): one lane per sampled block
 // ===========================================================================
 
-// Per-lane results of one block: the lane's share of the block's coder bits
-// and significant bits (their sums over the block are the block's values),
-// its squared and absolute data-domain error, and the block exponent.
-template <typename T, int D>
-struct ZfpBlockOut {
-  uint32_t bits, nsb;
-  double e2, ae;
-  int emax;
-};
-
-// Forward 4-point lift along one axis of the block, one coefficient per
-// lane (coord = the lane's coordinate on that axis).  Same factorisation as
-// the lifting steps: the outer pair (x0, x3) and inner pair (x1, x2) are
-// averaged/differenced by the lanes holding them, the lanes then swap their
-// (average, difference) with the neighbour pair, and every lane finishes
-// the transform and keeps its own output.
-template <int AXIS, typename I>
-__device__ inline I fwd_lift_axis(I c, int coord) {
-  const I p3 = axis_xchg<AXIS, 3>(c);
-  const bool low = coord <= 1;
-  const I first = low ? c : p3, second = low ? p3 : c;
-  const I sA = wadd(first, second) >> 1;
-  const I dA = wsub(first, sA);
-  const I sB = axis_xchg<AXIS, 1>(sA), dB = axis_xchg<AXIS, 1>(dA);
-  const bool outer = coord == 0 || coord == 3;
-  const I s03 = outer ? sA : sB, d03 = outer ? dA : dB;
-  const I s12 = outer ? sB : sA, d12 = outer ? dB : dA;
+// Forward 4-point lift in place: average/difference the outer pair (x0, x3)
+// and the inner pair (x1, x2), then the two averages and the two
+// differences, then two shears between the last two outputs.  On multiples
+// of 16 it equals (1/16)[[4,4,4,4],[5,1,-1,-5],[-4,4,4,-4],[-2,6,-6,2]].
+template <typename I>
+__device__ inline void fwd_lift4(I &x0, I &x1, I &x2, I &x3) {
+  const I s03 = wadd(x0, x3) >> 1, d03 = wsub(x0, s03);
+  const I s12 = wadd(x1, x2) >> 1, d12 = wsub(x1, s12);
   const I y0 = wadd(s03, s12) >> 1;
   const I y2 = wsub(s12, y0);
   const I dm = wadd(d03, d12) >> 1;
   const I dd = wsub(d03, dm);
   const I y3 = wsub(dm >> 1, dd);
   const I y1 = wsub(dm, y3 >> 1);
-  return coord == 0 ? y0 : coord == 1 ? y1 : coord == 2 ? y2 : y3;
+  x0 = y0;
+  x1 = y1;
+  x2 = y2;
+  x3 = y3;
 }
 
-// Inverse lift along one axis: even lanes rebuild (s03, s12) from (y0, y2),
-// odd lanes (d03, d12) from (y1, y3); one swap with the neighbour gives each
-// lane both halves of its output.
-template <int AXIS, typename I>
-__device__ inline I inv_lift_axis(I y, int coord) {
-  const I q = axis_xchg<AXIS, 2>(y);
-  const bool odd = coord & 1;
-  const I a = coord <= 1 ? y : q;
-  const I b = coord <= 1 ? q : y;
-  const I dm = wadd(a, b >> 1);
-  const I dd = wsub(dm >> 1, b);
-  const I P = odd ? wadd(dm, dd) : wsub(a, b);
-  const I Q = odd ? wsub(dm, dd) : wadd(a, b);
-  const I P1 = axis_xchg<AXIS, 1>(P), Q1 = axis_xchg<AXIS, 1>(Q);
-  const I s03 = odd ? P1 : P, s12 = odd ? Q1 : Q;
-  const I d03 = odd ? P : P1, d12 = odd ? Q : Q1;
-  switch (coord) {
-    case 0: return wadd(s03, d03);
-    case 1: return wadd(s12, d12);
-    case 2: return wsub(s12, d12);
-    default: return wsub(s03, d03);
+// Inverse lift: undoes each forward step in reverse order.
+template <typename I>
+__device__ inline void inv_lift4(I &y0, I &y1, I &y2, I &y3) {
+  const I dm = wadd(y1, y3 >> 1);
+  const I dd = wsub(dm >> 1, y3);
+  const I d03 = wadd(dm, dd), d12 = wsub(dm, dd);
+  const I s12 = wadd(y0, y2), s03 = wsub(y0, y2);
+  y0 = wadd(s03, d03);
+  y1 = wadd(s12, d12);
+  y2 = wsub(s12, d12);
+  y3 = wsub(s03, d03);
+}
+
+// Separable block transform (Section 4.2): the 4-point lift along every
+// line of the block, fastest axis first; the inverse runs the axes in the
+// opposite order.
+template <int D, typename I>
+__device__ inline void fwd_xform(I (&c)[1 << (2 * D)]) {
+  constexpr int BS = 1 << (2 * D);
+#pragma unroll
+  for (int a = 0; a < D; a++) {
+    const int s = 1 << (2 * a);
+#pragma unroll
+    for (int i = 0; i < BS; i++)
+      if (((i >> (2 * a)) & 3) == 0) fwd_lift4(c[i], c[i + s], c[i + 2 * s], c[i + 3 * s]);
   }
 }
 
+template <int D, typename I>
+__device__ inline void inv_xform(I (&c)[1 << (2 * D)]) {
+  constexpr int BS = 1 << (2 * D);
+#pragma unroll
+  for (int a = D - 1; a >= 0; a--) {
+    const int s = 1 << (2 * a);
+#pragma unroll
+    for (int i = 0; i < BS; i++)
+      if (((i >> (2 * a)) & 3) == 0) inv_lift4(c[i], c[i + s], c[i + 2 * s], c[i + 3 * s]);
+  }
+}
+
+// Values of sampled block j in in-block row-major order (zeros past the
+// last block).  Rows of 4 values are read as 16-byte vectors when the
+// request's rows are 16-byte aligned.
 template <typename T, int D>
-__device__ inline ZfpBlockOut<T, D> zfp_block(T xv, int minexp, int perm_i, int inv_i, int lane) {
+__device__ inline void load_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)]) {
+  constexpr int BS = 1 << (2 * D);
+  if (j >= r.nblk) {
+#pragma unroll
+    for (int i = 0; i < BS; i++) x[i] = (T)0;
+    return;
+  }
+  int64_t o[3];
+  const T *p = (const T *)r.field + block_base<D>(r, (uint32_t)j, o);
+#pragma unroll
+  for (int q = 0; q < BS / 4; q++) {
+    int64_t off = 0;
+    if constexpr (D == 2) off = (int64_t)q * r.dims[1];
+    if constexpr (D == 3) off = ((int64_t)(q >> 2) * r.dims[1] + (q & 3)) * r.dims[2];
+    const T *row = p + off;
+    if (r.vec) {
+      if constexpr (sizeof(T) == 4) {
+        const f32x4 v = *(const f32x4 *)row;
+        x[4 * q] = v[0];
+        x[4 * q + 1] = v[1];
+        x[4 * q + 2] = v[2];
+        x[4 * q + 3] = v[3];
+      } else {
+        const f64x2 a = *(const f64x2 *)row, b = *(const f64x2 *)(row + 2);
+        x[4 * q] = a[0];
+        x[4 * q + 1] = a[1];
+        x[4 * q + 2] = b[0];
+        x[4 * q + 3] = b[1];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++) x[4 * q + e] = row[e];
+    }
+  }
+}
+
+// Block-floating-point integer trunc(x 2^(P - emax)).  For binary32 values
+// the scaling is exact in binary64 and the conversion truncates.
+template <typename T>
+__device__ inline typename Prec<T>::I bfp_value(T x, int emax) {
+  if constexpr (sizeof(T) == 4)
+    return (int32_t)ldexp((double)x, Prec<T>::P - emax);
+  else
+    return bfp_int<T>(x, emax);
+}
+
+// Results of one block: coder bits (headers included), significant bits,
+// data-domain squared error (adjacent-pair tree in in-block order), largest
+// absolute error, block exponent (INT32_MIN for an all-zero block).
+struct ZfpLane {
+  uint32_t bits, nsb;
+  double sse, maxerr;
+  int emax;
+};
+
+template <typename T, int D>
+__device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int32_t *minexp_p) {
   using Q = Prec<T>;
   using U = typename Q::U;
   using I = typename Q::I;
   constexpr int BS = 1 << (2 * D);
   constexpr int W = Q::W;
-  const int i = lane & (BS - 1);
-  const int gbase = lane - i;
+  // the block is read again for the error (L2 hits) rather than kept in
+  // registers beside its coefficients
+  constexpr bool kKeep = false;
+  T x[BS];
+  load_block<T, D>(r, j, x);
+  const int minexp = get_i32(minexp_p);  // read while the block is in flight
 
   // block-floating-point: common exponent of the largest magnitude
-  const U mag = Q::bits(xv) & ~(U(1) << (W - 1));
-  const U mmax = group_allmax<BS>(mag);
+  U mmax = 0;
+#pragma unroll
+  for (int i = 0; i < BS; i++) {
+    const U m = Q::bits(x[i]) & ~(U(1) << (W - 1));
+    mmax = m > mmax ? m : mmax;
+  }
   const bool empty = mmax == 0;
   const int emax = empty ? 0 : frexp_exponent_bits<T>(mmax);
   int prec = emax - minexp + 2 * (D + 1);
   prec = empty ? 0 : (prec < 0 ? 0 : (prec > W ? W : prec));
-  I c = bfp_int<T>(xv, emax);
+  I c[BS];
+#pragma unroll
+  for (int i = 0; i < BS; i++) c[i] = bfp_value<T>(x[i], emax);
 
-  // separable forward transform, fastest axis first (Section 4.2)
-  c = fwd_lift_axis<0>(c, i & 3);
-  if constexpr (D >= 2) c = fwd_lift_axis<1>(c, (i >> 2) & 3);
-  if constexpr (D == 3) c = fwd_lift_axis<2>(c, (i >> 4) & 3);
-  // sequency order, then negabinary digits
-  c = __shfl(c, gbase + perm_i);
-  const U u = ((U)c + Q::NB) ^ Q::NB;
+  // decorrelating transform, then negabinary digits (in place; the
+  // sequency order only decides the order in which the count reads them)
+  fwd_xform<D>(c);
+#pragma unroll
+  for (int i = 0; i < BS; i++) c[i] = (I)(((U)c[i] + Q::NB) ^ Q::NB);
 
   // Group-testing embedded coding of planes W-1 .. kmin, counted without
-  // running the coder.  With msb_j the highest set bit of coefficient j (-1
-  // for 0) and M_j = max_{j' >= j} msb_j' (suffix maximum in coding order),
-  // the coder emits
-  //     sum_j max(0, M_j - kmin + 1)            verbatim bits of significant values
-  //   + W - max(kmin, msb_{BS-1} + 1)           group tests that find nothing
-  //   + #{j : u_j != 0, msb_j = M_j >= kmin}    group tests that find a 1
-  //   - [msb_{BS-1} >= kmin]                    the implied final 1
+  // running the coder.  With msb_k the highest set bit of the coefficient
+  // at coding position k (-1 for 0) and M_k = max_{k' >= k} msb_k', the
+  // coder emits
+  //     sum_k max(0, M_k - kmin + 1)            verbatim bits of significant values
+  //   + W - max(kmin, msb_last + 1)             group tests that find nothing
+  //   + #{k : msb_k = M_k >= kmin}              group tests that find a 1
+  //   - [msb_last >= kmin]                      the implied final 1
   // bits, because a plane's test finds exactly the coefficients whose msb is
-  // that plane and that no later coefficient exceeds.  Each lane returns its
-  // share; the block's last lane adds the block-wide terms.
+  // that plane and that no later coefficient exceeds.  Below, m = msb + 1
+  // clamped at kmin, so that every term is a plain sum or maximum.
   const int kmin = W - prec;
-  const int msb = u ? (W - 1 - clz_u(u)) : -1;
-  const int smax = group_suffix_max<BS>(msb + 1) - 1;
-  const uint32_t verb = (uint32_t)max(0, smax - kmin + 1);
-  const uint32_t found = (u != 0 && msb == smax && msb >= kmin) ? 1u : 0u;
-  const uint32_t sig = (uint32_t)max(0, msb - kmin + 1);  // significant bits (Section 5.2.1)
-  const uint32_t blockwide =
-      prec == 0 ? 1u : (uint32_t)(1 + Q::E + (W - max(kmin, msb + 1)) - (msb >= kmin ? 1 : 0));
-  ZfpBlockOut<T, D> out;
+  int run = kmin;  // max of the clamped m over the later positions
+  uint32_t verb = 0, found = 0, sig = 0;
+  int m_last = 0;
+#pragma unroll
+  for (int k = BS - 1; k >= 0; k--) {
+    const U u = (U)c[Order<D>::table.perm[k]];
+    const int m = u ? W - clz_u(u) : 0;
+    if (k == BS - 1) m_last = m;
+    const int mc = m > kmin ? m : kmin;
+    found += (mc > kmin && mc >= run) ? 1u : 0u;
+    run = mc > run ? mc : run;
+    verb += (uint32_t)(run - kmin);
+    sig += (uint32_t)(mc - kmin);
+  }
+  ZfpLane out;
   out.emax = empty ? INT32_MIN : emax;
-  out.bits = (prec == 0 ? 0u : verb + found) + (i == BS - 1 ? blockwide : 0u);
-  out.nsb = prec == 0 ? 0u : sig;
+  out.bits = prec == 0 ? 1u
+                       : (uint32_t)(1 + Q::E + W - (m_last > kmin ? m_last : kmin) -
+                                    (m_last > kmin ? 1 : 0)) + verb + found;
+  out.nsb = prec == 0 ? 0u : sig;  // significant bits (Section 5.2.1)
 
-  // decode at the cutoff: drop planes below kmin, invert every step
-  U keep;
-  if (kmin >= W)
-    keep = 0;
-  else if (kmin == 0)
-    keep = ~U(0);
-  else
-    keep = ~((U(1) << kmin) - 1);
-  I d = (I)(((u & keep) ^ Q::NB) - Q::NB);
-  d = __shfl(d, gbase + inv_i);
-  if constexpr (D == 3) d = inv_lift_axis<2>(d, (i >> 4) & 3);
-  if constexpr (D >= 2) d = inv_lift_axis<1>(d, (i >> 2) & 3);
-  d = inv_lift_axis<0>(d, i & 3);
-  T xh = (T)ldexp((double)d, emax - Q::P);
-  if (prec == 0) xh = (T)0;
-  const double e = (double)xv - (double)xh;
-  out.e2 = e * e;
-  out.ae = fabs(e);
+  // decode at the cut-off: drop planes below kmin, invert every step
+  const U keep = kmin >= W ? U(0) : (~U(0) << kmin);
+#pragma unroll
+  for (int i = 0; i < BS; i++) c[i] = (I)((((U)c[i] & keep) ^ Q::NB) - Q::NB);
+  inv_xform<D>(c);
+  if constexpr (!kKeep) load_block<T, D>(r, j, x);
+
+  // data-domain error of the decoded block; squared errors summed by the
+  // adjacent-pair tree in in-block order (a binary counter over the values)
+  double stk[2 * D];
+  double maxerr = 0.0, sse = 0.0;
+#pragma unroll
+  for (int i = 0; i < BS; i++) {
+    T xh = (T)ldexp((double)c[i], emax - Q::P);
+    if (prec == 0) xh = (T)0;
+    const double e = (double)x[i] - (double)xh;
+    maxerr = fmax(maxerr, fabs(e));
+    double v = e * e;
+#pragma unroll
+    for (int l = 0; l < 2 * D; l++) {
+      if ((i >> l) & 1) {
+        v = stk[l] + v;
+      } else {
+        stk[l] = v;
+        break;
+      }
+    }
+    if (i == BS - 1) sse = v;
+  }
+  out.sse = sse;
+  out.maxerr = maxerr;
   return out;
 }
 
@@ -430,112 +594,12 @@ __device__ inline void wg_acc_store(TileLds &L, const LaneAcc &acc, const Parts 
   }
 }
 
-// Value of in-block point i of sampled block j (0 when j is past the end).
-template <typename T, int D>
-__device__ inline T load_block_value(const ReqDesc &r, int64_t j, int i) {
-  if (j >= r.nblk) return (T)0;
-  int64_t o[3];
-  const int64_t lin = block_base<D>(r, (uint32_t)j, o) + point_offset<D>(r, i);
-  return ((const T *)r.field)[lin];
-}
-
-// One tile (<= kMaxTile blocks starting at `base`) of the ZFP side; the
-// next round's values are loaded while the current round is processed.
-template <typename T, int D>
-__device__ inline void zfp_tile(const ReqDesc &r, int64_t base, int tile, int minexp, TileLds &L,
-                                LaneAcc &acc) {
-  constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int i = lane & (BS - 1), bw = lane / BS;
-  const int perm_i = Order<D>::table.perm[i];
-  const int inv_i = Order<D>::table.inv[i];
-  const int rounds = tile / (kWaves * BPW);
-  T xn = load_block_value<T, D>(r, base + wave * BPW + bw, i);
-  for (int rd = 0; rd < rounds; rd++) {
-    const int jl = (rd * kWaves + wave) * BPW + bw;
-    const int64_t j = base + jl;
-    const bool active = j < r.nblk;
-    const T xv = xn;
-    if (rd + 1 < rounds) xn = load_block_value<T, D>(r, j + kWaves * BPW, i);
-    const ZfpBlockOut<T, D> z = zfp_block<T, D>(xv, minexp, perm_i, inv_i, lane);
-    const double bsse = group_tree_first<BS>(z.e2);
-    if (active) {
-      acc.a += z.bits;
-      acc.b += z.nsb;
-      acc.maxerr = fmax(acc.maxerr, z.ae);
-    }
-    if (r.dbg_zbits) {
-      const uint32_t bbits = group_isum<BS>(z.bits);
-      if (active && i == 0) {
-        r.dbg_zbits[j] = bbits;
-        if (r.dbg_zsse) r.dbg_zsse[j] = bsse;
-        if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
-      }
-    }
-    if (i == 0) L.sse[jl] = active ? bsse : 0.0;
-  }
-  __syncthreads();
-  wg_acc_push(L, tile_sse(L, tile));
-  __syncthreads();
-}
-
-// Adjacent-pair tree (and max, integer sums) over the n per-workgroup
-// partials of a pass, by the whole workgroup with coalesced atomic loads:
-// thread t folds the aligned run [t*c, (t+1)*c), c = P/256 <= 32, in
-// registers, then the wave butterfly and the fixed combine of the 4 waves.
-__device__ inline void parts_total(const Parts &p, int n, TileLds &L, double &sse,
-                                   double &maxerr, uint64_t &sa, uint64_t &sb) {
-  int P = 1;
-  while (P < n) P <<= 1;
-  const int c = P > kThreads ? P / kThreads : 1;
-  const int beg = threadIdx.x * c;
-  double v[32];
-  double m = 0.0;
-  uint64_t a = 0, b = 0;
-#pragma unroll
-  for (int k = 0; k < 32; k++) {
-    const int idx = beg + k;
-    v[k] = 0.0;
-    if (k < c && idx < n) {
-      v[k] = get_f64(p.sse + idx);
-      m = fmax(m, get_f64(p.err + idx));
-      a += get_u64(p.a + idx);
-      b += get_u64(p.b + idx);
-    }
-  }
-#pragma unroll
-  for (int s = 1; s < 32; s <<= 1) {
-#pragma unroll
-    for (int k = 0; k < 32; k += 2 * s) v[k] = v[k] + v[k + s];
-  }
-  double t = group_tree_sum<kWave>(v[0]);
-  m = group_max<kWave>(m);
-  a = group_isum<kWave>(a);
-  b = group_isum<kWave>(b);
-  __shared__ double s_m[kWaves];
-  __shared__ uint64_t s_a[kWaves], s_b[kWaves];
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    L.red[w] = t;
-    s_m[w] = m;
-    s_a[w] = a;
-    s_b[w] = b;
-  }
-  __syncthreads();
-  sse = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
-  maxerr = fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
-  sa = s_a[0] + s_a[1] + s_a[2] + s_a[3];
-  sb = s_b[0] + s_b[1] + s_b[2] + s_b[3];
-  __syncthreads();
-}
-
 // ZFP totals, PSNR_zfp and (for Algorithm 1) the SZ bin width delta whose
 // uniform-error PSNR equals PSNR_zfp (Eq. 10 inverted: delta = sqrt(12 MSE)).
 template <typename T, int D>
-__device__ inline void zfp_finalize(const ReqDesc &r, TileLds &L) {
-  double sse, maxerr;
-  uint64_t bits, nsb;
-  parts_total(r.zp, r.nzfp, L, sse, maxerr, bits, nsb);
+__device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
+  const double sse = tot.s, maxerr = tot.m;
+  const uint64_t bits = tot.a, nsb = tot.b;
   if (threadIdx.x == 0) {
     constexpr int BS = 1 << (2 * D);
     ReqState *st = r.st;
@@ -566,30 +630,54 @@ __device__ inline void zfp_finalize(const ReqDesc &r, TileLds &L) {
       put_f64(&st->inv, 1.0 / delta);
       put_f64(&st->eb_sz, 0.5 * delta);
     }
-    put_u32(&st->zfp_done, 0);
   }
 }
 
-// Whole ZFP pass of workgroup w.  Returns true in the workgroup that ran the
-// finalizer.
+// Whole ZFP pass of workgroup w (one wave): rounds of 64 consecutive
+// sampled blocks of its aligned chunk, one block per lane; the round sums
+// (wave butterfly) are folded with the binary counter.  Returns true in the
+// workgroup that ran the finalizer.
 template <typename T, int D>
 __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
-  const int minexp = get_i32(&r.st->minexp);
-  const int tile = r.zblk < kMaxTile ? r.zblk : kMaxTile;
-  const int ntile = r.zblk / tile;
-  LaneAcc acc;
+  const int lane = threadIdx.x;
+  const int rounds = r.zblk / kWave;
+  uint32_t bits = 0, nsb = 0;
+  double maxerr = 0.0;
   wg_acc_reset(L);
-  __syncthreads();
-  for (int k = 0; k < ntile; k++) {
-    const int64_t base = (int64_t)w * r.zblk + (int64_t)k * tile;
-    if (base < r.nblk)
-      zfp_tile<T, D>(r, base, tile, minexp, L, acc);
-    else
+  for (int k = 0; k < rounds; k++) {
+    const int64_t base = (int64_t)w * r.zblk + (int64_t)k * kWave;
+    if (base >= r.nblk) {
       wg_acc_push(L, 0.0);
+      continue;
+    }
+    const int64_t j = base + lane;
+    const bool active = j < r.nblk;
+    const ZfpLane z = zfp_block_lane<T, D>(r, j, &r.st->minexp);
+    double s = 0.0;
+    if (active) {
+      bits += z.bits;
+      nsb += z.nsb;
+      maxerr = fmax(maxerr, z.maxerr);
+      s = z.sse;
+      if (r.dbg_zbits) r.dbg_zbits[j] = z.bits;
+      if (r.dbg_zsse) r.dbg_zsse[j] = z.sse;
+      if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
+    }
+    wg_acc_push(L, group_tree_sum<kWave>(s));
   }
-  wg_acc_store(L, acc, r.zp, w);
-  if (!last_to_finish(&r.st->zfp_done, (uint32_t)r.nzfp, &L.last)) return false;
-  zfp_finalize<T, D>(r, L);
+  Part v;
+  v.s = 0.0;
+  v.m = maxerr;
+  v.a = bits;
+  v.b = nsb;
+  v = part_wave<false>(v);
+  if (lane == 0) {
+    v.s = L.stk[0];
+    part_store(r.zp, w, v);
+  }
+  Part tot;
+  if (!pass_complete<false>(r.zp, r.grp[kPassZfp], r.sync + kPassZfp, w, r.nzfp, L, tot)) return false;
+  zfp_finalize<T, D>(r, tot);
   return true;
 }
 
@@ -767,16 +855,12 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
 
 // SZ totals of the request (last SZ workgroup): squared-error tree over the
 // workgroups' subtrees, maximum error, unpredictable count.
-__device__ inline void sz_finalize(const ReqDesc &r, TileLds &L) {
-  double sse, maxerr;
-  uint64_t unpred, unused;
-  parts_total(r.sp, r.nsz, L, sse, maxerr, unpred, unused);
+__device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
   if (threadIdx.x == 0) {
-    put_u64(&r.st->ovf_count, unused);
-    put_f64(&r.st->sz_sse, sse);
-    put_f64(&r.st->sz_maxerr, maxerr);
-    put_u64(&r.st->sz_unpred, unpred);
-    put_u32(&r.st->sz_done, 0);
+    put_u64(&r.st->ovf_count, tot.b);
+    put_f64(&r.st->sz_sse, tot.s);
+    put_f64(&r.st->sz_maxerr, tot.m);
+    put_u64(&r.st->sz_unpred, tot.a);
   }
 }
 
@@ -851,7 +935,8 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
 // Entropy pass, workgroup c of 256: the adjacent-pair subtree of h log2 h
 // over bins [256c, 256c+256) (one bin per thread: the wave butterfly, then
 // the fixed combine of the 4 waves), clearing the bins for the next request.
-// The last workgroup folds the 256 subtrees and finishes the request:
+// The completion tree folds the 256 subtrees and its last workgroup
+// finishes the request:
 // entropy (Eq. 5 with P_i = h_i/n), SZ bit-rate (entropy + offset + W escape
 // bits per unpredictable point, Section 6.2), both PSNRs and the selection
 // of Algorithm 1 (lower bit-rate wins, ties go to ZFP).
@@ -877,15 +962,15 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   const int w = t / kWave;
   if ((t & (kWave - 1)) == 0) L.red[w] = v;
   __syncthreads();
-  if (t == 0) put_f64(r.ent + c, (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]));
-  __syncthreads();
-  if (!last_to_finish(&r.st->ent_done, (uint32_t)kEntWgs, &L.last)) return;
-  v = get_f64(r.ent + t);
-  v = group_tree_sum<kWave>(v);
-  if ((t & (kWave - 1)) == 0) L.red[w] = v;
-  __syncthreads();
   if (t == 0) {
-    const double s = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
+    Part pc = part_identity<false>();
+    pc.s = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
+    part_store(r.ep, c, pc);
+  }
+  Part tot;
+  if (!pass_complete<false>(r.ep, r.grp[kPassEnt], r.sync + kPassEnt, c, kEntWgs, L, tot)) return;
+  if (t == 0) {
+    const double s = tot.s;
     ReqState *st = r.st;
     szsel_result *res = r.res;
     const double nv = (double)(r.nblk * BS);
@@ -918,9 +1003,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
       put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
       put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
     }
-    put_u32(&st->ent_done, 0);
   }
-  __syncthreads();
 }
 
 // Whole SZ pass of workgroup w (LDS window cleared on entry, flushed once at
@@ -951,9 +1034,9 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   hist_flush(s_hist, r.hist);
   if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
   wg_acc_store(L, acc, r.sp, w);
-  if (threadIdx.x == 0) put_u64(r.sp.b + w, s_n);
-  if (!last_to_finish(&r.st->sz_done, (uint32_t)r.nsz, &L.last)) return false;
-  sz_finalize(r, L);
+  Part tot;
+  if (!pass_complete<false>(r.sp, r.grp[kPassSz], r.sync + kPassSz, w, r.nsz, L, tot)) return false;
+  sz_finalize(r, tot);
   return true;
 }
 

@@ -17,8 +17,10 @@ __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
   range_wg<T>(r, blockIdx.x, L);
 }
 
+// Two waves per SIMD (at most 256 registers each) so that every wave of a
+// request's ZFP pass is resident at once.
 template <typename T, int D>
-__global__ __launch_bounds__(kThreads) void k_zfp(ReqDesc r) {
+__global__ __launch_bounds__(kWave, 2) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
   zfp_wg<T, D>(r, blockIdx.x, L);
@@ -54,7 +56,7 @@ template <typename T, int D>
 static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
   hipError_t e = hipSuccess;
   if (r.op != SZSEL_OP_SZ) {
-    hipLaunchKernelGGL((k_zfp<T, D>), dim3(r.nzfp), dim3(kThreads), 0, s, r);
+    hipLaunchKernelGGL((k_zfp<T, D>), dim3(r.nzfp), dim3(kWave), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -106,13 +108,16 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 static size_t parts_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * 8, 256) * 4; }
 
 
-// Fixed part: what must persist between requests at the same place (state
-// with its completion counters, the self-cleaning histogram) and the
-// fixed-size buffers.  Variable part: per-workgroup partials and overflow
-// regions, fully rewritten by every request.
+// Fixed part: what must persist between requests at the same place (state,
+// the completion counters, the self-cleaning histogram) and the fixed-size
+// buffers.  Variable part: per-workgroup partials and overflow regions,
+// fully rewritten by every request.
+static size_t group_parts_bytes() { return align_up((size_t)kMaxGroups * 8, 256) * 4; }
+
 size_t request_fixed_bytes() {
-  return align_up(sizeof(ReqState), 256) + align_up(sizeof(uint32_t) * kBins, 256) +
-         align_up(sizeof(szsel_result), 256) + align_up(sizeof(double) * kEntWgs, 256) +
+  return align_up(sizeof(ReqState), 256) + align_up(sizeof(PassSync) * kPasses, 256) +
+         align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256) +
+         parts_bytes(kEntWgs) + group_parts_bytes() * kPasses +
          align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
 }
 
@@ -136,12 +141,14 @@ void bind_request_workspace(ReqDesc &r, char *fixed, char *var) {
   char *p = fixed;
   r.st = (ReqState *)p;
   p += align_up(sizeof(ReqState), 256);
+  r.sync = (PassSync *)p;
+  p += align_up(sizeof(PassSync) * kPasses, 256);
   r.hist = (uint32_t *)p;
   p += align_up(sizeof(uint32_t) * kBins, 256);
   r.res = (szsel_result *)p;
   p += align_up(sizeof(szsel_result), 256);
-  r.ent = (double *)p;
-  p += align_up(sizeof(double) * kEntWgs, 256);
+  r.ep = bind_parts(p, kEntWgs);
+  for (int k = 0; k < kPasses; k++) r.grp[k] = bind_parts(p, kMaxGroups);
   r.ovf_hist = (uint32_t *)p;
   p = var;
   r.rp = bind_parts(p, r.nrange);

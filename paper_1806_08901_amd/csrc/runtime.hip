@@ -137,23 +137,28 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     }
   }
   // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
-  // consecutive sampled blocks, at least one round of 4 waves, sized for
-  // about 8 workgroups per CU, and never more than kMaxParts workgroups.
+  // consecutive sampled blocks, and a pass has at most kMaxParts workgroups.
+  // ZFP: one wave per workgroup and one block per lane, chunks of 64 blocks
+  // (the most waves).  SZ: at least one round of 4 waves, about 8
+  // workgroups per CU.
   const int bs = 1 << (2 * nd);
-  const int min_chunk = kWaves * (kWave / bs);  // one round of 4 waves
-  auto chunk_for = [&](int target_wgs) {
-    const uint64_t want = (nblk + (uint64_t)target_wgs - 1) / (uint64_t)target_wgs;
-    uint64_t c = (uint64_t)min_chunk;
+  auto chunk_for = [&](uint64_t min_chunk, uint64_t target_wgs, uint64_t max_wgs) {
+    const uint64_t want = (nblk + target_wgs - 1) / target_wgs;
+    uint64_t c = min_chunk;
     while (c < want) c <<= 1;
-    while ((nblk + c - 1) / c > (uint64_t)kMaxParts) c <<= 1;
+    while ((nblk + c - 1) / c > max_wgs) c <<= 1;
     return c;
   };
-  const uint64_t zc = chunk_for(8 * ctx->ncu), sc = chunk_for(8 * ctx->ncu);
+  const uint64_t zc = chunk_for(kWave, nblk / kWave + 1, kMaxParts);
+  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / bs), 8 * (uint64_t)ctx->ncu, kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
   r.nzfp = (int32_t)std::max<uint64_t>(1, (nblk + zc - 1) / zc);
   r.nsz = (int32_t)std::max<uint64_t>(1, (nblk + sc - 1) / sc);
+  // rows of 4 values start on 16-byte boundaries: aligned field, row
+  // length a multiple of 16 bytes / element size (blocks start at x = 4 b s)
+  r.vec = ((uintptr_t)field % 16 == 0 && (dims[nd - 1] * (int64_t)esz) % 16 == 0) ? 1 : 0;
   // range pass: contiguous chunks of whole 16-byte vectors, about 2
   // workgroups per CU, at least 8 vectors per thread
   const int64_t vn = 16 / (int64_t)esz;
