@@ -30,6 +30,7 @@ constexpr int kEntWgs = 65536 / kEntChunk;
 constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
+constexpr int kHistCopies = 16;        // global histogram copies (SZ workgroup w adds to copy w mod 16)
 constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
 enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
@@ -132,7 +133,7 @@ struct ReqDesc {
   Parts grp[kPasses];  // per pass, the partials of its completion groups
   uint16_t *ovf;       // per SZ workgroup, sblk * 4^d codes that fell outside its LDS window
   uint32_t *ovf_hist;  // kOvfSlices dense 65536-bin counts of the overflow codes
-  uint32_t *hist;
+  uint32_t *hist;      // kHistCopies x 65536 counts, left zeroed by the entropy pass
   szsel_result *res;
   uint16_t *dbg_codes;
   uint32_t *dbg_zbits;

@@ -946,7 +946,15 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   const int t = threadIdx.x;
   const int bin = c * kEntChunk + t;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
-  uint32_t h = r.hist[bin];
+  // the SZ workgroups' counts, spread over kHistCopies copies so that no
+  // bin takes more than 1/16 of the workgroups' atomics
+  uint32_t hc[kHistCopies];
+  uint32_t h = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; k++) {
+    hc[k] = r.hist[(size_t)k * kBins + bin];
+    h += hc[k];
+  }
   if (get_u64(&r.st->ovf_count) != 0) {  // add the overflow pass's counts
     uint32_t o = 0;
 #pragma unroll 8
@@ -955,7 +963,9 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   }
   if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
   if (r.dbg_hist) r.dbg_hist[bin] = h;
-  if (h && bin) r.hist[bin] = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; k++)
+    if (hc[k]) r.hist[(size_t)k * kBins + bin] = 0;
   const double hd = (double)h;
   double v = h ? hd * log2(hd) : 0.0;
   v = group_tree_sum<kWave>(v);
@@ -1031,7 +1041,7 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
       wg_acc_push(L, 0.0);
   }
   __syncthreads();
-  hist_flush(s_hist, r.hist);
+  hist_flush(s_hist, r.hist + (size_t)(w % kHistCopies) * kBins);
   if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
   wg_acc_store(L, acc, r.sp, w);
   Part tot;

@@ -116,7 +116,7 @@ static size_t group_parts_bytes() { return align_up((size_t)kMaxGroups * 8, 256)
 
 size_t request_fixed_bytes() {
   return align_up(sizeof(ReqState), 256) + align_up(sizeof(PassSync) * kPasses, 256) +
-         align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(szsel_result), 256) +
+         align_up(sizeof(uint32_t) * kBins * kHistCopies, 256) + align_up(sizeof(szsel_result), 256) +
          parts_bytes(kEntWgs) + group_parts_bytes() * kPasses +
          align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
 }
@@ -144,7 +144,7 @@ void bind_request_workspace(ReqDesc &r, char *fixed, char *var) {
   r.sync = (PassSync *)p;
   p += align_up(sizeof(PassSync) * kPasses, 256);
   r.hist = (uint32_t *)p;
-  p += align_up(sizeof(uint32_t) * kBins, 256);
+  p += align_up(sizeof(uint32_t) * kBins * kHistCopies, 256);
   r.res = (szsel_result *)p;
   p += align_up(sizeof(szsel_result), 256);
   r.ep = bind_parts(p, kEntWgs);
