@@ -364,52 +364,69 @@ __device__ inline void inv_xform(I (&c)[1 << (2 * D)]) {
   }
 }
 
-// Values of sampled block j in in-block row-major order (zeros past the
-// last block).  Rows of 4 values are read as 16-byte vectors when the
-// request's rows are 16-byte aligned.
-template <typename T, int D>
-__device__ inline void load_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)]) {
-  constexpr int BS = 1 << (2 * D);
-  if (j >= r.nblk) {
-#pragma unroll
-    for (int i = 0; i < BS; i++) x[i] = (T)0;
-    return;
-  }
-  int64_t o[3];
-  const T *p = (const T *)r.field + block_base<D>(r, (uint32_t)j, o);
-#pragma unroll
-  for (int q = 0; q < BS / 4; q++) {
-    int64_t off = 0;
-    if constexpr (D == 2) off = (int64_t)q * r.dims[1];
-    if constexpr (D == 3) off = ((int64_t)(q >> 2) * r.dims[1] + (q & 3)) * r.dims[2];
-    const T *row = p + off;
-    if (r.vec) {
-      if constexpr (sizeof(T) == 4) {
-        const f32x4 v = *(const f32x4 *)row;
-        x[4 * q] = v[0];
-        x[4 * q + 1] = v[1];
-        x[4 * q + 2] = v[2];
-        x[4 * q + 3] = v[3];
-      } else {
-        const f64x2 a = *(const f64x2 *)row, b = *(const f64x2 *)(row + 2);
-        x[4 * q] = a[0];
-        x[4 * q + 1] = a[1];
-        x[4 * q + 2] = b[0];
-        x[4 * q + 3] = b[1];
-      }
+// Values of sampled block j in in-block row-major order.  Rows of 4 values
+// are read as 16-byte vectors when the request's rows are 16-byte aligned.
+// A j past the last block reads block 0 (its results are discarded).
+template <typename T, int D, bool VEC>
+__device__ inline void load_block_row(const ReqDesc &r, const T *p, int q, T (&x)[1 << (2 * D)]) {
+  int64_t off = 0;
+  if constexpr (D == 2) off = (int64_t)q * r.dims[1];
+  if constexpr (D == 3) off = ((int64_t)(q >> 2) * r.dims[1] + (q & 3)) * r.dims[2];
+  const T *row = p + off;
+  if constexpr (VEC) {
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = *(const f32x4 *)row;
+      x[4 * q] = v[0];
+      x[4 * q + 1] = v[1];
+      x[4 * q + 2] = v[2];
+      x[4 * q + 3] = v[3];
     } else {
-#pragma unroll
-      for (int e = 0; e < 4; e++) x[4 * q + e] = row[e];
+      const f64x2 a = *(const f64x2 *)row, b = *(const f64x2 *)(row + 2);
+      x[4 * q] = a[0];
+      x[4 * q + 1] = a[1];
+      x[4 * q + 2] = b[0];
+      x[4 * q + 3] = b[1];
     }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) x[4 * q + e] = row[e];
   }
 }
 
-// Block-floating-point integer trunc(x 2^(P - emax)).  For binary32 values
-// the scaling is exact in binary64 and the conversion truncates.
+template <typename T, int D, bool VEC>
+__device__ inline void load_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)]) {
+  int64_t o[3];
+  const T *p = (const T *)r.field + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+#pragma unroll
+  for (int q = 0; q < (1 << (2 * D)) / 4; q++) load_block_row<T, D, VEC>(r, p, q, x);
+}
+
+// Rows [q0, q0 + n) of block j again, at an address made opaque and
+// dependent on `after` by an empty asm, so that the read is neither merged
+// with the first one nor issued before `after` is known.
+template <typename T, int D, bool VEC>
+__device__ inline void load_rows_of_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)], int q0,
+                                          int n, uint32_t after) {
+  int64_t o[3];
+  const T *p = (const T *)r.field + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+  asm volatile("" : "+v"(p) : "v"(after));
+#pragma unroll
+  for (int q = 0; q < (1 << (2 * D)) / 4; q++)
+    if (q >= q0 && q < q0 + n) load_block_row<T, D, VEC>(r, p, q, x);
+}
+
+// 2^e as a binary32 value, -126 <= e <= 127.
+__device__ inline float pow2f(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }
+
+// Block-floating-point integer trunc(x 2^(P - emax)).  Binary32: two exact
+// power-of-two scalings (s1 = 2^min(P - emax, 127), s2 = the rest, >= 1)
+// and a truncating conversion.  A product can only be inexact when it falls
+// below the normal range, and then the result is below 1 and truncates to 0
+// either way.  Binary64: from the bits.
 template <typename T>
-__device__ inline typename Prec<T>::I bfp_value(T x, int emax) {
+__device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s2) {
   if constexpr (sizeof(T) == 4)
-    return (int32_t)ldexp((double)x, Prec<T>::P - emax);
+    return (int32_t)((x * s1) * s2);
   else
     return bfp_int<T>(x, emax);
 }
@@ -423,18 +440,18 @@ struct ZfpLane {
   int emax;
 };
 
-template <typename T, int D>
+template <typename T, int D, bool VEC>
 __device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int32_t *minexp_p) {
   using Q = Prec<T>;
   using U = typename Q::U;
   using I = typename Q::I;
   constexpr int BS = 1 << (2 * D);
   constexpr int W = Q::W;
-  // the block is read again for the error (L2 hits) rather than kept in
-  // registers beside its coefficients
-  constexpr bool kKeep = false;
+  // binary32 blocks stay in registers for the error; binary64 blocks are
+  // read again (L2 hits) rather than kept beside their 64-bit coefficients
+  constexpr bool kKeep = sizeof(T) == 4;
   T x[BS];
-  load_block<T, D>(r, j, x);
+  load_block<T, D, VEC>(r, j, x);
   const int minexp = get_i32(minexp_p);  // read while the block is in flight
 
   // block-floating-point: common exponent of the largest magnitude
@@ -449,8 +466,10 @@ __device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int3
   int prec = emax - minexp + 2 * (D + 1);
   prec = empty ? 0 : (prec < 0 ? 0 : (prec > W ? W : prec));
   I c[BS];
+  const int sh = Q::P - emax;  // in [-98, 179] for binary32
+  const float s1 = pow2f(sh < 127 ? sh : 127), s2 = pow2f(sh < 127 ? 0 : sh - 127);
 #pragma unroll
-  for (int i = 0; i < BS; i++) c[i] = bfp_value<T>(x[i], emax);
+  for (int i = 0; i < BS; i++) c[i] = bfp_value<T>(x[i], emax, s1, s2);
 
   // decorrelating transform, then negabinary digits (in place; the
   // sequency order only decides the order in which the count reads them)
@@ -496,29 +515,44 @@ __device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int3
 #pragma unroll
   for (int i = 0; i < BS; i++) c[i] = (I)((((U)c[i] & keep) ^ Q::NB) - Q::NB);
   inv_xform<D>(c);
-  if constexpr (!kKeep) load_block<T, D>(r, j, x);
 
   // data-domain error of the decoded block; squared errors summed by the
-  // adjacent-pair tree in in-block order (a binary counter over the values)
+  // adjacent-pair tree in in-block order (a binary counter over the values).
+  // Binary64 blocks are read again in chunks of kChunk rows, each chunk's
+  // address depending on the previous chunk's result, so that at most one
+  // chunk is live beside the 64-bit coefficients.
+  constexpr int kRows = BS / 4;
+  constexpr int kChunk = kKeep ? kRows : (kRows > 4 ? 4 : kRows);
   double stk[2 * D];
   double maxerr = 0.0, sse = 0.0;
+  uint32_t after = (uint32_t)c[BS - 1];
 #pragma unroll
-  for (int i = 0; i < BS; i++) {
-    T xh = (T)ldexp((double)c[i], emax - Q::P);
-    if (prec == 0) xh = (T)0;
-    const double e = (double)x[i] - (double)xh;
-    maxerr = fmax(maxerr, fabs(e));
-    double v = e * e;
+  for (int q0 = 0; q0 < kRows; q0 += kChunk) {
+    if constexpr (!kKeep) load_rows_of_block<T, D, VEC>(r, j, x, q0, kChunk, after);
 #pragma unroll
-    for (int l = 0; l < 2 * D; l++) {
-      if ((i >> l) & 1) {
-        v = stk[l] + v;
-      } else {
-        stk[l] = v;
-        break;
+    for (int i = 4 * q0; i < 4 * (q0 + kChunk); i++) {
+      T xh = (T)ldexp((double)c[i], emax - Q::P);
+      if (prec == 0) xh = (T)0;
+      // an empty asm makes x[i] opaque here, so that its widening to
+      // binary64 is not hoisted up to the load (64 live doubles would spill)
+      T xi = x[i];
+      asm volatile("" : "+v"(xi));
+      const double e = (double)xi - (double)xh;
+      maxerr = fmax(maxerr, fabs(e));
+      double v = e * e;
+#pragma unroll
+      for (int l = 0; l < 2 * D; l++) {
+        if ((i >> l) & 1) {
+          v = stk[l] + v;
+        } else {
+          stk[l] = v;
+          break;
+        }
       }
+      if (i == BS - 1) sse = v;
+      if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
-    if (i == BS - 1) sse = v;
+    after = (uint32_t)__double_as_longlong(maxerr);
   }
   out.sse = sse;
   out.maxerr = maxerr;
@@ -637,7 +671,7 @@ __device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
 // sampled blocks of its aligned chunk, one block per lane; the round sums
 // (wave butterfly) are folded with the binary counter.  Returns true in the
 // workgroup that ran the finalizer.
-template <typename T, int D>
+template <typename T, int D, bool VEC>
 __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
   const int lane = threadIdx.x;
   const int rounds = r.zblk / kWave;
@@ -652,7 +686,7 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
     }
     const int64_t j = base + lane;
     const bool active = j < r.nblk;
-    const ZfpLane z = zfp_block_lane<T, D>(r, j, &r.st->minexp);
+    const ZfpLane z = zfp_block_lane<T, D, VEC>(r, j, &r.st->minexp);
     double s = 0.0;
     if (active) {
       bits += z.bits;
@@ -686,61 +720,120 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
 // linear-scaling quantization, code histogram
 // ===========================================================================
 
-// The value of a point and its Lorenzo neighbours, in the order the
-// predictor adds them: single axes (slowest first), then pairs in
-// lexicographic order, then the triple.  Values outside the field are 0
-// (the lower-order predictor at borders).
+// SZ side, one lane per row of 4 points along the fastest axis: 4^(D-1)
+// lanes per sampled block, 64 / 4^(D-1) blocks per wave.  A lane reads the
+// rows of its points' Lorenzo neighbours: for every subset m of the slower
+// axes the row displaced by one along the axes of m, each with the value
+// before the row (x - 1).  Values outside the field are 0 (the
+// lower-order predictor at borders).
 template <typename T, int D>
-struct Stencil {
-  T x;
-  T v[(1 << D) - 1];
+struct Rows {
+  static constexpr int NR = 1 << (D - 1);
+  T v[NR][5];     // [m][x + 1], m: bit k set = displaced along slower axis k
+  uint32_t keep;  // bit m: row m lies inside the field; bit NR: x - 1 does
 };
 
-template <typename T, int D>
-__device__ inline Stencil<T, D> load_stencil(const ReqDesc &r, int64_t j, int i) {
-  Stencil<T, D> s;
-  s.x = (T)0;
+// Reads one row of 4 values and the value before it.  Nothing is done with
+// the values here, so that the loads stay in flight until the round that
+// uses them (rows_mask zeroes what lies outside the field).
+template <typename T, bool VEC>
+__device__ inline void load_row(const T *p, T (&out)[5], bool left) {
+  if constexpr (VEC) {
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = *(const f32x4 *)p;
+      out[1] = v[0];
+      out[2] = v[1];
+      out[3] = v[2];
+      out[4] = v[3];
+    } else {
+      const f64x2 a = *(const f64x2 *)p, b = *(const f64x2 *)(p + 2);
+      out[1] = a[0];
+      out[2] = a[1];
+      out[3] = b[0];
+      out[4] = b[1];
+    }
+  } else {
 #pragma unroll
-  for (int k = 0; k < (1 << D) - 1; k++) s.v[k] = (T)0;
-  if (j >= r.nblk) return s;
+    for (int e = 0; e < 4; e++) out[1 + e] = p[e];
+  }
+  out[0] = p[left ? -1 : 0];
+}
+
+// Rows of lane row q of sampled block j (all zero past the last block).
+template <typename T, int D, bool VEC>
+__device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
+  Rows<T, D> s;
+  const bool in = j < r.nblk;
+  int64_t o[3] = {0, 0, 0};
+  // a block past the end reads block 0 (always present) and is masked out
+  const int64_t base = block_base<D>(r, in ? (uint32_t)j : 0u, o);
   const T *x = (const T *)r.field;
-  int64_t o[3];
-  const int64_t lin = block_base<D>(r, (uint32_t)j, o) + point_offset<D>(r, i);
-  // bit k set: the point has a predecessor inside the field along axis k
-  uint32_t in = 0;
-#pragma unroll
-  for (int k = 0; k < D; k++) {
-    const int c = (i >> (2 * (D - 1 - k))) & 3;
-    in |= (o[k] + c > 0) ? (1u << k) : 0u;
+  // the row's offset, the strides of the slower axes and whether the row
+  // has a predecessor inside the field along each of them
+  int64_t off = 0, st[2] = {0, 0};
+  bool has[2] = {false, false};
+  if constexpr (D == 2) {
+    off = (int64_t)q * r.dims[1];
+    st[0] = r.dims[1];
+    has[0] = o[0] + q > 0;
+  } else if constexpr (D == 3) {
+    const int z = q >> 2, y = q & 3;
+    st[0] = r.dims[1] * r.dims[2];
+    st[1] = r.dims[2];
+    off = (int64_t)z * st[0] + (int64_t)y * st[1];
+    has[0] = o[0] + z > 0;
+    has[1] = o[1] + y > 0;
   }
-  s.x = x[lin];
-  // term t uses the axes of subset S_t; a neighbour outside the field is 0
-  // (every lane loads, from the point itself when the neighbour is outside)
+  const bool left = o[D - 1] > 0;
+  const T *row = x + base + off;
+  uint32_t keep = (in && left) ? (1u << Rows<T, D>::NR) : 0u;
 #pragma unroll
-  for (int t = 0; t < (1 << D) - 1; t++) {
-    uint32_t S;
-    if constexpr (D == 1) S = 1u;
-    else if constexpr (D == 2) S = t == 0 ? 1u : (t == 1 ? 2u : 3u);
-    else S = t == 0 ? 1u : t == 1 ? 2u : t == 2 ? 4u : t == 3 ? 3u : t == 4 ? 5u : t == 5 ? 6u : 7u;
-    const bool ok = (in & S) == S;
-    const T v = x[ok ? lin - r.nboff[t] : lin];
-    s.v[t] = ok ? v : (T)0;
+  for (int m = 0; m < Rows<T, D>::NR; m++) {
+    bool ok = in;
+    int64_t d = 0;
+#pragma unroll
+    for (int k = 0; k < D - 1; k++)
+      if ((m >> k) & 1) {
+        ok = ok && has[k];
+        d += st[k];
+      }
+    keep |= ok ? (1u << m) : 0u;
+    // a missing row is read from the lane's own row and zeroed later
+    load_row<T, VEC>(ok ? row - d : row, s.v[m], left);
   }
+  s.keep = keep;
   return s;
 }
 
-// Lorenzo prediction from the original neighbours (Section 4.1, with the
-// prediction taken from real rather than sampled neighbours, Section 4.3):
-// sum over non-empty axis subsets S of (-1)^(|S|+1) X[p - e_S].
+// Zeroes the stencil values that lie outside the field (or past the last
+// block): the lower-order predictor at borders.
 template <typename T, int D>
-__device__ inline double lorenzo_pred(const Stencil<T, D> &s) {
+__device__ inline void rows_mask(Rows<T, D> &s) {
+  const bool left = (s.keep >> Rows<T, D>::NR) & 1u;
+#pragma unroll
+  for (int m = 0; m < Rows<T, D>::NR; m++) {
+    const bool ok = (s.keep >> m) & 1u;
+#pragma unroll
+    for (int e = 0; e < 5; e++) s.v[m][e] = (ok && (e > 0 || left)) ? s.v[m][e] : (T)0;
+  }
+}
+
+// Lorenzo prediction of point x of the lane's row (Section 4.1, from the
+// original neighbours as Section 4.3 prescribes): the sum over non-empty
+// axis subsets S of (-1)^(|S|+1) X[p - e_S], in FP64, terms in the order
+// single axes (slowest first), pairs in lexicographic order, the triple.
+template <typename T, int D>
+__device__ inline double lorenzo_row(const Rows<T, D> &s, int xi) {
+  const int c = xi + 1;
   if constexpr (D == 1) {
-    return (double)s.v[0];
+    return (double)s.v[0][c - 1];
   } else if constexpr (D == 2) {
-    return ((double)s.v[0] + (double)s.v[1]) - (double)s.v[2];
+    // {y}, {x}, {y,x}
+    return ((double)s.v[1][c] + (double)s.v[0][c - 1]) - (double)s.v[1][c - 1];
   } else {
-    return (((((double)s.v[0] + (double)s.v[1]) + (double)s.v[2]) - (double)s.v[3]) -
-            (double)s.v[4]) - (double)s.v[5] + (double)s.v[6];
+    // {z}, {y}, {x}, {z,y}, {z,x}, {y,x}, {z,y,x}; row index m: bit 0 = z, bit 1 = y
+    return (((((double)s.v[1][c] + (double)s.v[2][c]) + (double)s.v[0][c - 1]) - (double)s.v[3][c]) -
+            (double)s.v[1][c - 1]) - (double)s.v[2][c - 1] + (double)s.v[3][c - 1];
   }
 }
 
@@ -803,33 +896,45 @@ __device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t 
   }
 }
 
-// One tile of the SZ side; the next round's stencils are loaded while the
-// current round is processed.
-template <typename T, int D>
+// One tile of the SZ side (tile blocks starting at `base`): each round the
+// 4 waves take 4 * 64 / 4^(D-1) consecutive blocks; the next round's rows
+// are loaded while the current round is processed.  Per-block squared
+// errors: the lane's 4 points by the pair tree, then the block's lanes in
+// row order by the butterfly, i.e. the adjacent-pair tree in in-block
+// row-major order.
+template <typename T, int D, bool VEC>
 __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
                                double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
                                uint32_t *s_n, LaneAcc &acc) {
-  constexpr int BS = 1 << (2 * D), BPW = kWave / BS;
+  constexpr int BS = 1 << (2 * D), LPB = BS / 4, BPW = kWave / LPB;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int i = lane & (BS - 1), bw = lane / BS;
+  const int q = lane & (LPB - 1), bw = lane / LPB;
   const int rounds = tile / (kWaves * BPW);
-  Stencil<T, D> sn = load_stencil<T, D>(r, base + wave * BPW + bw, i);
+  Rows<T, D> sn = load_rows<T, D, VEC>(r, base + wave * BPW + bw, q);
   for (int rd = 0; rd < rounds; rd++) {
     const int jl = (rd * kWaves + wave) * BPW + bw;
     const int64_t j = base + jl;
     const bool active = j < r.nblk;
-    const Stencil<T, D> sc = sn;
-    if (rd + 1 < rounds) sn = load_stencil<T, D>(r, j + kWaves * BPW, i);
-    double e2 = 0.0, ae = 0.0;
-    const int code = active ? quantize<T>(sc.x, lorenzo_pred<T, D>(sc), delta, inv, ebsz, e2, ae) : 0;
-    hist_add(active && code != 0, code, s_hist, region, s_n);
-    if (active) {
-      acc.a += code == 0 ? 1u : 0u;
-      acc.maxerr = fmax(acc.maxerr, ae);
-      if (r.dbg_codes) r.dbg_codes[j * BS + i] = (uint16_t)code;
+    Rows<T, D> sc = sn;
+    if (rd + 1 < rounds) sn = load_rows<T, D, VEC>(r, j + kWaves * BPW, q);
+    rows_mask<T, D>(sc);
+    double e2[4];
+#pragma unroll
+    for (int xi = 0; xi < 4; xi++) {
+      double ae = 0.0;
+      e2[xi] = 0.0;
+      const int code =
+          active ? quantize<T>(sc.v[0][xi + 1], lorenzo_row<T, D>(sc, xi), delta, inv, ebsz, e2[xi], ae) : 0;
+      hist_add(active && code != 0, code, s_hist, region, s_n);
+      if (active) {
+        acc.a += code == 0 ? 1u : 0u;
+        acc.maxerr = fmax(acc.maxerr, ae);
+        if (r.dbg_codes) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code;
+      }
     }
-    const double bsse = group_tree_first<BS>(e2);
-    if (i == 0) {
+    double bsse = (e2[0] + e2[1]) + (e2[2] + e2[3]);
+    if constexpr (LPB > 1) bsse = group_tree_first<LPB>(bsse);
+    if (q == 0) {
       L.sse[jl] = bsse;
       if (active && r.dbg_ssse) r.dbg_ssse[j] = bsse;
     }
@@ -1018,7 +1123,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
 
 // Whole SZ pass of workgroup w (LDS window cleared on entry, flushed once at
 // the end).  Returns true in the workgroup that ran the finalizer.
-template <typename T, int D>
+template <typename T, int D, bool VEC>
 __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hist) {
   const double delta = get_f64(&r.st->delta);
   const double inv = get_f64(&r.st->inv);
@@ -1036,7 +1141,7 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   for (int k = 0; k < ntile; k++) {
     const int64_t base = (int64_t)w * r.sblk + (int64_t)k * tile;
     if (base < r.nblk)
-      sz_tile<T, D>(r, base, tile, delta, inv, ebsz, L, s_hist, region, &s_n, acc);
+      sz_tile<T, D, VEC>(r, base, tile, delta, inv, ebsz, L, s_hist, region, &s_n, acc);
     else
       wg_acc_push(L, 0.0);
   }

@@ -19,19 +19,20 @@ __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
 
 // Two waves per SIMD (at most 256 registers each) so that every wave of a
 // request's ZFP pass is resident at once.
-template <typename T, int D>
+// VEC: rows of 4 values start 16-byte aligned and are read as vectors.
+template <typename T, int D, bool VEC>
 __global__ __launch_bounds__(kWave, 2) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
-  zfp_wg<T, D>(r, blockIdx.x, L);
+  zfp_wg<T, D, VEC>(r, blockIdx.x, L);
 }
 
-template <typename T, int D>
+template <typename T, int D, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
   __shared__ TileLds L;
   __shared__ uint32_t s_hist[kHistWin];
   if (skip_request(r.st)) return;
-  sz_wg<T, D>(r, blockIdx.x, L, s_hist);
+  sz_wg<T, D, VEC>(r, blockIdx.x, L, s_hist);
 }
 
 template <int D>
@@ -56,13 +57,19 @@ template <typename T, int D>
 static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
   hipError_t e = hipSuccess;
   if (r.op != SZSEL_OP_SZ) {
-    hipLaunchKernelGGL((k_zfp<T, D>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    if (r.vec)
+      hipLaunchKernelGGL((k_zfp<T, D, true>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    else
+      hipLaunchKernelGGL((k_zfp<T, D, false>), dim3(r.nzfp), dim3(kWave), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if ((e = mark(ev, 2, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
-    hipLaunchKernelGGL((k_sz<T, D>), dim3(r.nsz), dim3(kThreads), 0, s, r);
+    if (r.vec)
+      hipLaunchKernelGGL((k_sz<T, D, true>), dim3(r.nsz), dim3(kThreads), 0, s, r);
+    else
+      hipLaunchKernelGGL((k_sz<T, D, false>), dim3(r.nsz), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -139,8 +139,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
   // consecutive sampled blocks, and a pass has at most kMaxParts workgroups.
   // ZFP: one wave per workgroup and one block per lane, chunks of 64 blocks
-  // (the most waves).  SZ: at least one round of 4 waves, about 8
-  // workgroups per CU.
+  // (the most waves).  SZ: at least one round of 4 waves.
   const int bs = 1 << (2 * nd);
   auto chunk_for = [&](uint64_t min_chunk, uint64_t target_wgs, uint64_t max_wgs) {
     const uint64_t want = (nblk + target_wgs - 1) / target_wgs;
@@ -150,7 +149,9 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     return c;
   };
   const uint64_t zc = chunk_for(kWave, nblk / kWave + 1, kMaxParts);
-  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / bs), 8 * (uint64_t)ctx->ncu, kMaxParts);
+  // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; at
+  // most 4 workgroups per CU so that all of them are resident at once
+  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)), 4 * (uint64_t)ctx->ncu, kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
