@@ -121,8 +121,9 @@ typedef struct {
 } szsel_debug;
 
 /* Creates a context on HIP device `hip_device`.  workspace_budget_bytes caps
- * the device memory the context may allocate (0 = 4 GiB).  Returns SZSEL_OK
- * and *ctx, or a negative code. */
+ * the device memory the context may allocate (0 = 16 GiB; a request needs
+ * about 21 MB plus 2 bytes per sampled value).  Returns SZSEL_OK and *ctx,
+ * or a negative code. */
 int szsel_create(szsel_ctx **ctx, int hip_device, size_t workspace_budget_bytes);
 
 /* Waits for the context's outstanding work and frees its device memory. */
@@ -151,11 +152,16 @@ int szsel_select_fixed_eb(szsel_ctx *ctx, const void *field, const int64_t *dims
                           int dtype, double eb, int eb_mode, const int32_t *stride,
                           szsel_result *out, void *stream);
 
-/* n requests of any shape, dtype, bound and op in one persistent launch
- * (captured and replayed as a HIP graph when the same batch shape repeats).
- * Requests that share a field pointer share one value-range scan.  out[i]
- * receives the result of reqs[i]; each equals what the single-request entry
- * point returns for the same request, bit for bit. */
+/* n <= 1024 requests of any shape, dtype, bound and op together: one launch
+ * per pass covers every request (grouped by dtype, rank and alignment),
+ * captured as a HIP graph and replayed while the batch shape repeats.
+ * Requests on the same field (same pointer, dtype and dims) share one
+ * value-range scan.  out[i] receives the result of reqs[i]; each equals what
+ * the single-request entry point returns for the same request, bit for bit.
+ * The context keeps 4 batch workspaces in rotation; a call that reuses one
+ * first waits (on the host) for the batch that last used it.  Errors:
+ * SZSEL_EINVAL (a request is invalid; the message names it), SZSEL_EBUSY
+ * (n > 1024), SZSEL_ENOMEM (workspace beyond the budget). */
 int szsel_select_batch(szsel_ctx *ctx, const szsel_request *reqs, int n, szsel_result *out,
                        void *stream);
 
@@ -171,8 +177,15 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  * SZSEL_OPT_SZ_OFFSET: bits per value added to the SZ entropy estimate
  *   (Section 6.2 sets it to 0.5; default 0.5).
  * SZSEL_OPT_PROFILE: nonzero records HIP events between the passes of every
- *   single-request call (read with szsel_profile_read). */
-enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2 };
+ *   single-request call (read with szsel_profile_read).
+ * SZSEL_OPT_AUTOTUNE: nonzero lets szsel_select_batch time a few launch
+ *   shapes (workgroups per request and pass) the first time it sees a batch
+ *   shape and keep the fastest; 0 (default) uses the fixed schedule.  The
+ *   results do not depend on it.
+ * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
+ *   HIP graph and replays it while the batch shape repeats. */
+enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
+       SZSEL_OPT_BATCH_GRAPH = 4 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* Phase timers: synchronises the recorded events and returns, per phase

@@ -1,109 +1,471 @@
-// Batched execution: every request gets its own workspace region so that all
-// of them can be in flight at once.
+// Batched execution: n requests of any shape, dtype, bound and op in one
+// launch per pass (and request class), captured as a HIP graph and replayed
+// while the batch keeps the same launch shape.
+//
+// Table order.  Requests are sorted by (dtype, ndims, vector alignment,
+// field, dims) so that every class of kernel template is a contiguous range
+// of the device table, and requests on the same field are adjacent: the
+// first of them scans the value range once for all (nshare), the others
+// get no range work items.  Results are written at the caller's indices.
+//
+// Workspace.  Each table entry owns a fixed part (state, counters,
+// histogram, ...; zeroed once, kept clean by the kernels) and a variable
+// part (partials, overflow regions).  Each batch state also holds the table
+// and the per-pass prefix counts (device), their pinned staging copy, and
+// the captured graph.
+//
+// Autotuning.  The launch shape knobs (Tune) never change the results; the
+// tuner times a few candidates per batch shape on the caller's stream and
+// keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <numeric>
 
 #include "batch.hpp"
 #include "launch.hpp"
 
+struct szsel_ctx;
+
 namespace szsel {
 
-struct BatchState {
-  char *fixed = nullptr;  // request_fixed_bytes() per request index, zeroed on allocation
-  size_t nfixed = 0;      // request indices the fixed buffer holds
-  char *var = nullptr;
-  size_t var_cap = 0;
-  szsel_result *res = nullptr;  // contiguous results for one copy back
-  size_t nres = 0;
-  hipEvent_t done = nullptr;
-  bool used = false;
+int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
+                 int dtype, double eb, int eb_mode, const int32_t *stride, const Tune &tu,
+                 ReqDesc &r);
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  std::vector<ReqDesc> tab;             // table order
+  std::vector<int> orig;                // caller index of each table entry
+  std::vector<uint32_t> first;          // kBatchPasses x (n + 1) prefix counts
+  std::vector<BatchLaunch> launches;    // in pass order (tab/first pointers filled at bind time)
+  std::vector<size_t> voff;             // variable workspace offset of each table entry
+  size_t var = 0;                       // variable workspace bytes
+  std::vector<uint64_t> sig;            // launch shape (graph reuse key)
 };
 
-static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-void batch_destroy(BatchState *bs) {
-  if (!bs) return;
-  if (bs->fixed) (void)hipFree(bs->fixed);
-  if (bs->var) (void)hipFree(bs->var);
-  if (bs->res) (void)hipFree(bs->res);
-  if (bs->done) (void)hipEventDestroy(bs->done);
-  delete bs;
+bool same_field(const ReqDesc &a, const ReqDesc &b) {
+  if (a.field != b.field || a.dtype != b.dtype || a.nd != b.nd) return false;
+  for (int k = 0; k < a.nd; k++)
+    if (a.dims[k] != b.dims[k]) return false;
+  return true;
 }
 
-static hipError_t grow(char *&buf, size_t &have, size_t want, bool zero) {
-  (void)hipDeviceSynchronize();
+// Plans every request with the knobs `tu` and lays out the table, prefix
+// counts and launches.
+int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, Plan &p,
+              std::string &msg) {
+  std::vector<ReqDesc> d((size_t)n);
+  for (int i = 0; i < n; i++) {
+    const szsel_request &q = reqs[i];
+    int32_t st[3];
+    for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
+    const int rc = plan_request(ctx, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, tu, d[i]);
+    if (rc != SZSEL_OK) {
+      msg = "request " + std::to_string(i) + ": ";
+      return rc;
+    }
+  }
+  std::vector<int> ord((size_t)n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    const ReqDesc &x = d[a], &y = d[b];
+    if (x.dtype != y.dtype) return x.dtype < y.dtype;
+    if (x.nd != y.nd) return x.nd < y.nd;
+    if (x.vec != y.vec) return x.vec > y.vec;
+    if (x.field != y.field) return (uintptr_t)x.field < (uintptr_t)y.field;
+    for (int k = 0; k < x.nd; k++)
+      if (x.dims[k] != y.dims[k]) return x.dims[k] < y.dims[k];
+    return false;
+  });
+  p.tab.resize((size_t)n);
+  p.orig = ord;
+  for (int k = 0; k < n; k++) p.tab[k] = d[ord[k]];
+  // range scans shared by runs of requests on the same field
+  std::vector<bool> owner((size_t)n, true);
+  for (int k = 0; k < n;) {
+    int e = k + 1;
+    while (e < n && same_field(p.tab[k], p.tab[e])) e++;
+    p.tab[k].nshare = e - k - 1;
+    for (int m = k + 1; m < e; m++) {
+      p.tab[m].nshare = 0;
+      owner[m] = false;
+    }
+    k = e;
+  }
+  // prefix counts of work items per pass
+  p.first.assign((size_t)kBatchPasses * (n + 1), 0);
+  for (int ps = 0; ps < kBatchPasses; ps++) {
+    uint32_t acc = 0;
+    for (int k = 0; k < n; k++) {
+      const ReqDesc &r = p.tab[k];
+      uint32_t c = 0;
+      switch (ps) {
+        case kBatchRange: c = owner[k] ? (uint32_t)r.nrange : 0u; break;
+        case kBatchZfp: c = r.op != SZSEL_OP_SZ ? (uint32_t)r.nzfp : 0u; break;
+        case kBatchSz: c = r.op != SZSEL_OP_ZFP ? (uint32_t)r.nsz : 0u; break;
+        case kBatchOvf: c = r.op != SZSEL_OP_ZFP ? (uint32_t)(kOvfSlices * kOvfRanges) : 0u; break;
+        default: c = r.op != SZSEL_OP_ZFP ? (uint32_t)kEntWgs : 0u; break;
+      }
+      p.first[(size_t)ps * (n + 1) + k] = acc;
+      acc += c;
+    }
+    p.first[(size_t)ps * (n + 1) + n] = acc;
+  }
+  // launches: per pass, one per contiguous class (dtype only for the range
+  // pass, whose kernel depends on nothing else)
+  p.launches.clear();
+  for (int ps = 0; ps < kBatchPasses; ps++) {
+    const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
+    for (int k = 0; k < n;) {
+      int e = k + 1;
+      auto same_class = [&](const ReqDesc &a, const ReqDesc &b) {
+        if (ps == kBatchRange) return a.dtype == b.dtype;
+        return a.dtype == b.dtype && a.nd == b.nd && a.vec == b.vec;
+      };
+      while (e < n && same_class(p.tab[k], p.tab[e])) e++;
+      BatchLaunch L;
+      L.pass = ps;
+      L.dtype = p.tab[k].dtype;
+      L.nd = p.tab[k].nd;
+      L.vec = p.tab[k].vec;
+      L.tab = nullptr;
+      L.first = nullptr;
+      L.c0 = k;
+      L.c1 = e;
+      L.items = f[e] - f[k];
+      if (L.items) p.launches.push_back(L);
+      k = e;
+    }
+  }
+  // variable workspace
+  p.voff.resize((size_t)n);
+  p.var = 0;
+  for (int k = 0; k < n; k++) {
+    p.voff[k] = p.var;
+    p.var = align_up(p.var + request_var_bytes(p.tab[k]), 256);
+  }
+  // launch shape: everything the captured graph depends on except the
+  // table contents (field pointers and bounds are uploaded on every call)
+  p.sig.clear();
+  p.sig.push_back((uint64_t)n);
+  for (int k = 0; k < n; k++) p.sig.push_back((uint64_t)p.orig[k]);
+  for (uint32_t v : p.first) p.sig.push_back(v);
+  for (const BatchLaunch &L : p.launches)
+    p.sig.push_back(((uint64_t)L.pass << 48) | ((uint64_t)L.dtype << 40) | ((uint64_t)L.nd << 32) |
+                    ((uint64_t)L.vec << 31) | ((uint64_t)L.c0 << 16) | (uint64_t)L.c1);
+  for (size_t v : p.voff) p.sig.push_back(v);
+  return SZSEL_OK;
+}
+
+// Shape of a batch independent of the knobs (the autotuner's cache key).
+std::vector<uint64_t> shape_key(const szsel_request *reqs, int n) {
+  std::vector<uint64_t> k;
+  k.push_back((uint64_t)n);
+  for (int i = 0; i < n; i++) {
+    const szsel_request &q = reqs[i];
+    k.push_back(((uint64_t)q.dtype << 8) | ((uint64_t)q.ndims << 4) | (uint64_t)q.op);
+    for (int a = 0; a < 3; a++) k.push_back((uint64_t)(a < q.ndims ? q.dims[a] : 0));
+    for (int a = 0; a < 3; a++) k.push_back((uint64_t)(a < q.ndims ? q.stride[a] : 0));
+    k.push_back(((uintptr_t)q.field % 16) ? 1u : 0u);
+    // requests on one field share a scan: record the first index using it
+    int same = i;
+    for (int j = 0; j < i; j++)
+      if (reqs[j].field == q.field) {
+        same = j;
+        break;
+      }
+    k.push_back((uint64_t)same);
+  }
+  return k;
+}
+
+hipError_t dev_grow(char *&buf, size_t &have, size_t want, bool zero) {
+  if (want <= have) return hipSuccess;
+  hipError_t e = hipDeviceSynchronize();
   if (buf) (void)hipFree(buf);
   buf = nullptr;
   have = 0;
-  void *p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
-  if (e == hipSuccess && zero) e = hipMemset(p, 0, want);
+  void *q = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&q, want);
+  if (e == hipSuccess && zero) e = hipMemset(q, 0, want);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    if (p) (void)hipFree(p);
+    if (q) (void)hipFree(q);
     return e;
   }
-  buf = (char *)p;
+  buf = (char *)q;
   have = want;
   return hipSuccess;
 }
 
-int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<ReqDesc> &descs,
-              szsel_result *out, hipStream_t s, std::string &msg) {
-  (void)ncu;
-  (void)device;
-  const size_t n = descs.size();
+}  // namespace
+
+struct BatchState {
+  char *fixed = nullptr;  // request_fixed_bytes() per table entry, zeroed on allocation
+  size_t fixed_cap = 0;
+  char *var = nullptr;
+  size_t var_cap = 0;
+  char *res = nullptr;  // results at the caller's indices
+  size_t res_cap = 0;
+  char *meta = nullptr;  // device table + prefix counts
+  size_t meta_cap = 0;
+  char *stage = nullptr;  // pinned staging copy of meta
+  size_t stage_cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+  hipStream_t cap = nullptr;  // private capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> sig;  // launch shape of the captured graph
+  std::vector<uint64_t> last_key;  // last batch shape, and its knobs
+  Tune last_tune;
+  bool have_last = false;
+};
+
+size_t batch_state_bytes(const BatchState *bs) {
+  return bs ? bs->fixed_cap + bs->var_cap + bs->res_cap + bs->meta_cap : 0;
+}
+
+void batch_destroy(BatchState *bs) {
+  if (!bs) return;
+  (void)hipDeviceSynchronize();
+  if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
+  if (bs->graph) (void)hipGraphDestroy(bs->graph);
+  if (bs->cap) (void)hipStreamDestroy(bs->cap);
+  if (bs->fixed) (void)hipFree(bs->fixed);
+  if (bs->var) (void)hipFree(bs->var);
+  if (bs->res) (void)hipFree(bs->res);
+  if (bs->meta) (void)hipFree(bs->meta);
+  if (bs->stage) (void)hipHostFree(bs->stage);
+  if (bs->done) (void)hipEventDestroy(bs->done);
+  delete bs;
+}
+
+namespace {
+
+struct Tuner {
+  std::map<std::vector<uint64_t>, Tune> best;
+};
+Tuner &tuner() {
+  static Tuner t;
+  return t;
+}
+
+// Makes the state's buffers large enough for plan p, binds every table
+// entry to its workspace and result, and writes the staging copy.
+hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
+  const size_t n = p.tab.size();
   const size_t fixed = request_fixed_bytes();
-  std::vector<size_t> voff(n);
-  size_t var = 0;
-  for (size_t i = 0; i < n; i++) {
-    voff[i] = var;
-    var = align_up(var + request_var_bytes(descs[i]), 256);
-  }
-  if (!bs) {
-    bs = new BatchState();
-    if (hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) != hipSuccess) {
-      msg = "hipEventCreate failed";
-      return SZSEL_EHIP;
-    }
-  }
-  const size_t want_fixed = n > bs->nfixed ? n : bs->nfixed;
-  const size_t total = want_fixed * fixed + (var > bs->var_cap ? var : bs->var_cap) +
-                       sizeof(szsel_result) * (n > bs->nres ? n : bs->nres);
+  const size_t tab_bytes = align_up(sizeof(ReqDesc) * n, 256);
+  const size_t meta = tab_bytes + sizeof(uint32_t) * p.first.size();
+  const size_t total = std::max(bs->fixed_cap, fixed * n) + std::max(bs->var_cap, p.var) +
+                       std::max(bs->res_cap, sizeof(szsel_result) * n) + std::max(bs->meta_cap, meta);
   if (total > budget) {
-    msg = "batch workspace of " + std::to_string(total) + " bytes exceeds the budget";
-    return SZSEL_ENOMEM;
+    msg = "batch workspace of " + std::to_string(total) + " bytes exceeds the context's budget";
+    return hipErrorOutOfMemory;
   }
   hipError_t e = hipSuccess;
-  if (n > bs->nfixed) {
-    size_t have = 0;
-    e = grow(bs->fixed, have, n * fixed, true);
-    bs->nfixed = e == hipSuccess ? n : 0;
-    bs->used = false;
-  }
-  if (e == hipSuccess && var > bs->var_cap) e = grow(bs->var, bs->var_cap, var, false);
-  if (e == hipSuccess && n > bs->nres) {
-    char *p = (char *)bs->res;
-    size_t have = 0;
-    e = grow(p, have, sizeof(szsel_result) * n, false);
-    bs->res = (szsel_result *)p;
-    bs->nres = e == hipSuccess ? n : 0;
+  if (fixed * n > bs->fixed_cap) e = dev_grow(bs->fixed, bs->fixed_cap, fixed * n, true);
+  if (e == hipSuccess) e = dev_grow(bs->var, bs->var_cap, p.var, false);
+  if (e == hipSuccess) e = dev_grow(bs->res, bs->res_cap, sizeof(szsel_result) * n, false);
+  if (e == hipSuccess) e = dev_grow(bs->meta, bs->meta_cap, meta, false);
+  if (e == hipSuccess && meta > bs->stage_cap) {
+    if (bs->stage) (void)hipHostFree(bs->stage);
+    bs->stage = nullptr;
+    bs->stage_cap = 0;
+    void *h = nullptr;
+    e = hipHostMalloc(&h, meta, hipHostMallocDefault);
+    if (e == hipSuccess) {
+      bs->stage = (char *)h;
+      bs->stage_cap = meta;
+    }
   }
   if (e != hipSuccess) {
     msg = std::string("batch workspace: ") + hipGetErrorString(e);
-    return SZSEL_ENOMEM;
+    return e;
   }
-  if (bs->used) e = hipStreamWaitEvent(s, bs->done, 0);
-  for (size_t i = 0; i < n && e == hipSuccess; i++) {
-    ReqDesc &r = descs[i];
-    bind_request_workspace(r, bs->fixed + i * fixed, bs->var + voff[i]);
-    r.res = bs->res + i;
-    e = launch_request(r, s);
+  szsel_result *res = (szsel_result *)bs->res;
+  for (size_t k = 0; k < n; k++) {
+    ReqDesc &r = p.tab[k];
+    bind_request_workspace(r, bs->fixed + k * fixed, bs->var + p.voff[k]);
+    r.res = res + p.orig[k];
+  }
+  const ReqDesc *dtab = (const ReqDesc *)bs->meta;
+  const uint32_t *dfirst = (const uint32_t *)(bs->meta + tab_bytes);
+  for (BatchLaunch &L : p.launches) {
+    L.tab = dtab;
+    L.first = dfirst + (size_t)L.pass * (n + 1);
+  }
+  std::memcpy(bs->stage, p.tab.data(), sizeof(ReqDesc) * n);
+  std::memcpy(bs->stage + tab_bytes, p.first.data(), sizeof(uint32_t) * p.first.size());
+  // buffer addresses are part of what a captured graph depends on
+  p.sig.push_back((uint64_t)(uintptr_t)bs->fixed);
+  p.sig.push_back((uint64_t)(uintptr_t)bs->var);
+  p.sig.push_back((uint64_t)(uintptr_t)bs->res);
+  p.sig.push_back((uint64_t)(uintptr_t)bs->meta);
+  p.sig.push_back((uint64_t)(uintptr_t)bs->stage);
+  return hipSuccess;
+}
+
+// Upload of the table and every launch of plan p, on stream s.
+hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s) {
+  const size_t n = p.tab.size();
+  const size_t meta = align_up(sizeof(ReqDesc) * n, 256) + sizeof(uint32_t) * p.first.size();
+  hipError_t e = hipMemcpyAsync(bs->meta, bs->stage, meta, hipMemcpyHostToDevice, s);
+  for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = launch_batch_pass(p.launches[k], s);
+  return e;
+}
+
+}  // namespace
+
+int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
+              szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg) {
+  if (n > kMaxBatch) {
+    msg = "batch of " + std::to_string(n) + " requests; at most " + std::to_string(kMaxBatch);
+    return SZSEL_EBUSY;
+  }
+  if (!bs) {
+    bs = new BatchState();
+    if (hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) != hipSuccess) {
+      msg = "batch state: event or stream creation failed";
+      return SZSEL_EHIP;
+    }
+  }
+  hipError_t e = hipSuccess;
+  // the previous use of this state (its staging buffer, workspace and
+  // results) must be finished before they are rewritten
+  if (bs->used) {
+    e = hipEventSynchronize(bs->done);
+    if (e != hipSuccess) {
+      msg = std::string("batch: ") + hipGetErrorString(e);
+      return SZSEL_EHIP;
+    }
+  }
+  // knobs: the tuned ones for this batch shape, else the defaults
+  const std::vector<uint64_t> key = shape_key(reqs, n);
+  Tune tu;
+  bool tuned = false;
+  if (bs->have_last && bs->last_key == key) {
+    tu = bs->last_tune;
+    tuned = true;
+  } else if (opt.autotune) {
+    auto it = tuner().best.find(key);
+    if (it != tuner().best.end()) {
+      tu = it->second;
+      tuned = true;
+    }
+  }
+  if (opt.autotune && !tuned) {
+    // coordinate search over the knobs, each candidate timed once after
+    // its plan is bound (results are identical for every candidate)
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+      msg = "autotune: event creation failed";
+      return SZSEL_EHIP;
+    }
+    auto time_of = [&](const Tune &c, float &ms) -> int {
+      Plan p;
+      int rc = make_plan(ctx, reqs, n, c, p, msg);
+      if (rc != SZSEL_OK) return rc;
+      if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
+      hipError_t q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
+      if (q == hipSuccess) q = hipEventRecord(t0, s);
+      if (q == hipSuccess) q = enqueue_plan(bs, p, s);
+      if (q == hipSuccess) q = hipEventRecord(t1, s);
+      if (q == hipSuccess) q = hipEventSynchronize(t1);
+      if (q == hipSuccess) q = hipEventElapsedTime(&ms, t0, t1);
+      if (q != hipSuccess) {
+        msg = std::string("autotune: ") + hipGetErrorString(q);
+        return SZSEL_EHIP;
+      }
+      return SZSEL_OK;
+    };
+    Tune cur;
+    float best_ms = 0.f;
+    int rc = time_of(cur, best_ms);
+    const int sz_opts[] = {1, 2, 4, 8};
+    const int zfp_opts[] = {64, 128, 256};
+    const int range_opts[] = {1, 2, 4};
+    for (int v : sz_opts) {
+      if (rc != SZSEL_OK || v == cur.sz_wgs_per_cu) continue;
+      Tune c = cur;
+      c.sz_wgs_per_cu = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    for (int v : zfp_opts) {
+      if (rc != SZSEL_OK || v == cur.zfp_chunk) continue;
+      Tune c = cur;
+      c.zfp_chunk = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    for (int v : range_opts) {
+      if (rc != SZSEL_OK || v == cur.range_wgs_per_cu) continue;
+      Tune c = cur;
+      c.range_wgs_per_cu = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc != SZSEL_OK) return rc;
+    tuner().best[key] = cur;
+    tu = cur;
+  }
+  bs->last_key = key;
+  bs->last_tune = tu;
+  bs->have_last = true;
+
+  Plan p;
+  int rc = make_plan(ctx, reqs, n, tu, p, msg);
+  if (rc != SZSEL_OK) return rc;
+  if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
+  if (opt.graph) {
+    if (!bs->exec || bs->sig != p.sig) {
+      if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
+      if (bs->graph) (void)hipGraphDestroy(bs->graph);
+      bs->exec = nullptr;
+      bs->graph = nullptr;
+      bs->sig.clear();
+      e = hipStreamBeginCapture(bs->cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = enqueue_plan(bs, p, bs->cap);
+        e = hipStreamEndCapture(bs->cap, &bs->graph);
+        if (e == hipSuccess) e = e2;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&bs->exec, bs->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        msg = std::string("batch graph capture: ") + hipGetErrorString(e);
+        return SZSEL_EHIP;
+      }
+      bs->sig = p.sig;
+    }
+    e = hipGraphLaunch(bs->exec, s);
+  } else {
+    e = enqueue_plan(bs, p, s);
   }
   if (e == hipSuccess)
-    e = hipMemcpyAsync(out, bs->res, sizeof(szsel_result) * n, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(out, bs->res, sizeof(szsel_result) * (size_t)n, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(bs->done, s);
   if (e != hipSuccess) {
     msg = std::string("batch launch: ") + hipGetErrorString(e);

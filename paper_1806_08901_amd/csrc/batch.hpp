@@ -8,15 +8,27 @@
 
 #include "device.hpp"
 
+struct szsel_ctx;
+
 namespace szsel {
 
 struct BatchState;
 
-// Runs every request of `descs` (already planned) on stream s and copies the
-// results to out[0..n).  `bs` is created or grown on demand.
-int batch_run(BatchState *&bs, int device, int ncu, size_t budget, std::vector<ReqDesc> &descs,
-              szsel_result *out, hipStream_t s, std::string &msg);
+struct BatchOptions {
+  bool autotune = false;  // time launch-shape candidates per batch shape, keep the fastest
+  bool graph = true;      // capture the launches as a HIP graph and replay it
+};
+
+// Plans and runs the n requests on stream s and copies the results to
+// out[0..n) (asynchronously).  `bs` is created or grown on demand; it is
+// reused only after its previous batch has finished.  `budget` caps its
+// device memory.
+int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
+              szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg);
 
 void batch_destroy(BatchState *bs);
+
+// Device bytes held by a batch state (0 for NULL).
+size_t batch_state_bytes(const BatchState *bs);
 
 }  // namespace szsel

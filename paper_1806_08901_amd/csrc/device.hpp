@@ -25,12 +25,14 @@ constexpr int kBins = 65536;           // 65,535 symmetric bins plus the escape 
 constexpr int kRadius = 32768;
 constexpr int kMaxTile = 256;          // sampled blocks per tile
 constexpr int kMaxParts = 8192;        // workgroups of one pass (partials per pass)
-constexpr int kEntChunk = 256;         // histogram bins per workgroup of the entropy pass
+constexpr int kEntPerThread = 4;       // histogram bins per thread of the entropy pass
+constexpr int kEntChunk = kThreads * kEntPerThread;  // bins per workgroup of the entropy pass
 constexpr int kEntWgs = 65536 / kEntChunk;
 constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
 constexpr int kHistCopies = 16;        // global histogram copies (SZ workgroup w adds to copy w mod 16)
+constexpr int kMaxBatch = 1024;        // requests per batch
 constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
 enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
@@ -126,6 +128,8 @@ struct ReqDesc {
   int64_t rchunk;  // values per range workgroup (multiple of 16 bytes)
   int32_t nrange;  // range workgroups
   int32_t vec;     // 1: every row of 4 values starts 16-byte aligned (vector loads)
+  int32_t nshare;  // batches: requests right after this one in the table that share its range scan
+  int32_t pad1;
   ReqState *st;
   PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;

@@ -297,7 +297,10 @@ __device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
   }
   Part tot;
   if (!pass_complete<true>(r.rp, r.grp[kPassRange], r.sync + kPassRange, w, r.nrange, L, tot)) return;
-  if (threadIdx.x == 0) range_finalize_one(r, tot.s, tot.m, tot.a != 0);
+  // this request and, in a batch, the requests on the same field that
+  // follow it in the table (one scan serves them all)
+  if (threadIdx.x == 0)
+    for (int d = 0; d <= r.nshare; d++) range_finalize_one((&r)[d], tot.s, tot.m, tot.a != 0);
 }
 
 // ===========================================================================
@@ -1037,9 +1040,9 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   for (int b = threadIdx.x; b < kOvfBins; b += kThreads) out[b] = s_cnt[b];
 }
 
-// Entropy pass, workgroup c of 256: the adjacent-pair subtree of h log2 h
-// over bins [256c, 256c+256) (one bin per thread: the wave butterfly, then
-// the fixed combine of the 4 waves), clearing the bins for the next request.
+// Entropy pass, workgroup c of 64: the adjacent-pair subtree of h log2 h
+// over bins [1024c, 1024c+1024) (4 consecutive bins per thread), clearing
+// the bins for the next request.
 // The completion tree folds the 256 subtrees and its last workgroup
 // finishes the request:
 // entropy (Eq. 5 with P_i = h_i/n), SZ bit-rate (entropy + offset + W escape
@@ -1049,30 +1052,39 @@ template <typename T, int D>
 __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   constexpr int BS = 1 << (2 * D);
   const int t = threadIdx.x;
-  const int bin = c * kEntChunk + t;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
-  // the SZ workgroups' counts, spread over kHistCopies copies so that no
-  // bin takes more than 1/16 of the workgroups' atomics
-  uint32_t hc[kHistCopies];
-  uint32_t h = 0;
+  const bool ovf = get_u64(&r.st->ovf_count) != 0;
+  double hv[kEntPerThread];
 #pragma unroll
-  for (int k = 0; k < kHistCopies; k++) {
-    hc[k] = r.hist[(size_t)k * kBins + bin];
-    h += hc[k];
-  }
-  if (get_u64(&r.st->ovf_count) != 0) {  // add the overflow pass's counts
-    uint32_t o = 0;
+  for (int k = 0; k < kEntPerThread; k++) {
+    const int bin = c * kEntChunk + t * kEntPerThread + k;
+    // the SZ workgroups' counts, spread over kHistCopies copies so that no
+    // bin takes more than 1/16 of the workgroups' atomics
+    uint32_t hc[kHistCopies];
+    uint32_t h = 0;
+#pragma unroll
+    for (int q = 0; q < kHistCopies; q++) {
+      hc[q] = r.hist[(size_t)q * kBins + bin];
+      h += hc[q];
+    }
+    if (ovf) {  // add the overflow pass's counts
+      uint32_t o = 0;
 #pragma unroll 8
-    for (int p = 0; p < kOvfSlices; p++) o += r.ovf_hist[(size_t)p * kBins + bin];
-    h += o;
-  }
-  if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
-  if (r.dbg_hist) r.dbg_hist[bin] = h;
+      for (int p = 0; p < kOvfSlices; p++) o += r.ovf_hist[(size_t)p * kBins + bin];
+      h += o;
+    }
+    if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
+    if (r.dbg_hist) r.dbg_hist[bin] = h;
 #pragma unroll
-  for (int k = 0; k < kHistCopies; k++)
-    if (hc[k]) r.hist[(size_t)k * kBins + bin] = 0;
-  const double hd = (double)h;
-  double v = h ? hd * log2(hd) : 0.0;
+    for (int q = 0; q < kHistCopies; q++)
+      if (hc[q]) r.hist[(size_t)q * kBins + bin] = 0;
+    const double hd = (double)h;
+    hv[k] = h ? hd * log2(hd) : 0.0;
+  }
+  // the thread's 4 consecutive bins, then the wave butterfly, then the
+  // fixed combine of the 4 waves: the chunk's aligned subtree
+  static_assert(kEntPerThread == 4, "four bins per thread");
+  double v = (hv[0] + hv[1]) + (hv[2] + hv[3]);
   v = group_tree_sum<kWave>(v);
   const int w = t / kWave;
   if ((t & (kWave - 1)) == 0) L.red[w] = v;

@@ -29,4 +29,26 @@ inline size_t request_var_bytes(const ReqDesc &r) {
   return request_var_bytes(r.nrange, r.nzfp, r.nsz, request_ovf_capacity(r));
 }
 
+// One launch of a batched pass over table entries [c0, c1) (see
+// batch_kernels.hip); `items` workgroups in total.
+enum { kBatchRange = 0, kBatchZfp, kBatchSz, kBatchOvf, kBatchEnt, kBatchPasses };
+struct BatchLaunch {
+  int pass, dtype, nd, vec;
+  const ReqDesc *tab;
+  const uint32_t *first;
+  int c0, c1;
+  uint32_t items;
+};
+hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
+
+// Launch shape knobs of the planner.  Any choice gives bit-identical
+// results (every reduction is an aligned subtree of the same fixed tree);
+// they only move the balance between parallelism and per-workgroup
+// overheads, which the batch autotuner measures.
+struct Tune {
+  int sz_wgs_per_cu = 4;     // SZ workgroups per CU for one request
+  int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
+  int range_wgs_per_cu = 2;  // range workgroups per CU for one request
+};
+
 }  // namespace szsel

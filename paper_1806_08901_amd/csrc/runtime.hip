@@ -19,6 +19,7 @@ using namespace szsel;
 namespace {
 
 constexpr int kSlots = 4;
+constexpr int kBatchSlots = 4;  // batch states in rotation (batches in flight)
 constexpr int kPhases = 5;  // range, ZFP, SZ, overflow count, entropy
 constexpr int kEv = kPhases + 1;
 
@@ -42,7 +43,10 @@ struct szsel_ctx {
   szsel_debug dbg{};
   bool dbg_armed = false;
   std::string err;
-  BatchState *batch = nullptr;
+  BatchState *batch[kBatchSlots] = {};
+  size_t batch_bytes[kBatchSlots] = {};
+  int bnext = 0;
+  BatchOptions bopt;
   // phase timers
   bool prof = false;
   std::vector<hipEvent_t> prof_events;  // kPhases + 1 per recorded call
@@ -67,7 +71,8 @@ int hip_fail(szsel_ctx *c, hipError_t e, const char *what) {
 namespace szsel {
 
 int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
-                 int dtype, double eb, int eb_mode, const int32_t *stride, ReqDesc &r) {
+                 int dtype, double eb, int eb_mode, const int32_t *stride, const Tune &tu,
+                 ReqDesc &r) {
   if (!ctx) return SZSEL_EINVAL;
   if (!field) return fail(ctx, SZSEL_EINVAL, "field is NULL");
   if (!dims) return fail(ctx, SZSEL_EINVAL, "dims is NULL");
@@ -148,10 +153,11 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     while ((nblk + c - 1) / c > max_wgs) c <<= 1;
     return c;
   };
-  const uint64_t zc = chunk_for(kWave, nblk / kWave + 1, kMaxParts);
+  const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
   // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; at
   // most 4 workgroups per CU so that all of them are resident at once
-  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)), 4 * (uint64_t)ctx->ncu, kMaxParts);
+  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)),
+                                (uint64_t)tu.sz_wgs_per_cu * (uint64_t)ctx->ncu, kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
@@ -160,11 +166,12 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // rows of 4 values start on 16-byte boundaries: aligned field, row
   // length a multiple of 16 bytes / element size (blocks start at x = 4 b s)
   r.vec = ((uintptr_t)field % 16 == 0 && (dims[nd - 1] * (int64_t)esz) % 16 == 0) ? 1 : 0;
-  // range pass: contiguous chunks of whole 16-byte vectors, about 2
-  // workgroups per CU, at least 8 vectors per thread
+  // range pass: contiguous chunks of whole 16-byte vectors, about
+  // range_wgs_per_cu workgroups per CU, at least 8 vectors per thread
   const int64_t vn = 16 / (int64_t)esz;
   const int64_t quantum = (int64_t)kThreads * vn;
-  int64_t chunk = (n + 2 * ctx->ncu - 1) / (2 * ctx->ncu);
+  const int64_t rw = (int64_t)tu.range_wgs_per_cu * ctx->ncu;
+  int64_t chunk = (n + rw - 1) / rw;
   chunk = std::max<int64_t>(chunk, 8 * quantum);
   chunk = (chunk + quantum - 1) / quantum * quantum;
   r.rchunk = chunk;
@@ -202,7 +209,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   if (!ctx) return SZSEL_EINVAL;
   if (!out) return fail(ctx, SZSEL_EINVAL, "out is NULL");
   ReqDesc r;
-  int rc = plan_request(ctx, op, field, dims, nd, dtype, eb, eb_mode, stride, r);
+  int rc = plan_request(ctx, op, field, dims, nd, dtype, eb, eb_mode, stride, Tune(), r);
   if (rc != SZSEL_OK) return rc;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -280,7 +287,7 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
   szsel_ctx *c = new (std::nothrow) szsel_ctx();
   if (!c) return SZSEL_ENOMEM;
   c->device = hip_device;
-  c->budget = budget ? budget : ((size_t)4 << 30);
+  c->budget = budget ? budget : ((size_t)16 << 30);
   hipError_t e = hipSetDevice(hip_device);
   int ncu = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device);
@@ -314,7 +321,7 @@ void szsel_destroy(szsel_ctx *c) {
     if (c->slots[k].mem) (void)hipFree(c->slots[k].mem);
     if (c->slots[k].done) (void)hipEventDestroy(c->slots[k].done);
   }
-  batch_destroy(c->batch);
+  for (int k = 0; k < kBatchSlots; k++) batch_destroy(c->batch[k]);
   for (auto &ev : c->prof_events)
     if (ev) (void)hipEventDestroy(ev);
   delete c;
@@ -347,20 +354,18 @@ int szsel_select_batch(szsel_ctx *c, const szsel_request *reqs, int n, szsel_res
   if (n == 0) return SZSEL_OK;
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  std::vector<ReqDesc> descs((size_t)n);
-  for (int i = 0; i < n; i++) {
-    const szsel_request &q = reqs[i];
-    int32_t st[3];
-    for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
-    int rc = plan_request(c, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, descs[i]);
-    if (rc != SZSEL_OK) {
-      c->err = "request " + std::to_string(i) + ": " + c->err;
-      return rc;
-    }
-  }
+  const int k = c->bnext;
+  c->bnext = (c->bnext + 1) % kBatchSlots;
+  // the batch states share the context's budget with the single-request slots
+  size_t others = c->used_bytes;
+  for (int q = 0; q < kBatchSlots; q++)
+    if (q != k) others += c->batch_bytes[q];
+  const size_t budget = c->budget > others ? c->budget - others : 0;
   std::string msg;
-  int rc = batch_run(c->batch, c->device, c->ncu, c->budget, descs, out, (hipStream_t)stream, msg);
-  if (rc != SZSEL_OK) return fail(c, rc, msg);
+  c->err.clear();
+  const int rc = batch_run(c, c->batch[k], budget, reqs, n, out, (hipStream_t)stream, c->bopt, msg);
+  c->batch_bytes[k] = batch_state_bytes(c->batch[k]);
+  if (rc != SZSEL_OK) return fail(c, rc, msg + c->err);
   c->err.clear();
   return SZSEL_OK;
 }
@@ -407,6 +412,14 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
   if (option == SZSEL_OPT_SZ_OFFSET) {
     if (!std::isfinite(value)) return fail(c, SZSEL_EINVAL, "offset must be finite");
     c->sz_offset = value;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_AUTOTUNE) {
+    c->bopt.autotune = value != 0.0;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_BATCH_GRAPH) {
+    c->bopt.graph = value != 0.0;
     return SZSEL_OK;
   }
   if (option == SZSEL_OPT_PROFILE) {

@@ -20,7 +20,7 @@ EB_ABS, EB_REL = 0, 1
 OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
 FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
 FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
-OPT_SZ_OFFSET, OPT_PROFILE = 1, 2
+OPT_SZ_OFFSET, OPT_PROFILE, OPT_AUTOTUNE, OPT_BATCH_GRAPH = 1, 2, 3, 4
 NBINS = 65536
 
 
@@ -244,10 +244,17 @@ class Context:
         return reqs
 
     def select_batch(self, items, stream=None, sync: bool = True, reqs=None):
+        """Runs the requests as one batch.  With sync=False the call returns
+        a fresh pinned array of Result, filled once the stream reaches it."""
         if reqs is None:
             reqs = self.make_requests(items)
         n = len(reqs)
-        out = self._results(n)
+        if sync:
+            out = self._results(n)
+        else:
+            t = torch.empty(max(1, n) * C.sizeof(Result), dtype=torch.uint8, pin_memory=True)
+            out = (Result * n).from_address(t.data_ptr())
+            self._keep = getattr(self, "_keep", [])[-15:] + [t]  # keep the buffer alive
         s, sp = self._stream(stream)
         self._check(self.lib.szsel_select_batch(self.h, reqs, n, out, sp), "szsel_select_batch")
         if not sync:

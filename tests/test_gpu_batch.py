@@ -1,0 +1,154 @@
+"""Batched execution (szsel_select_batch) against single requests and the oracle (needs a GPU).
+
+A batch runs one launch per pass over all of its requests, shares the
+value-range scan of requests on the same field, replays a captured HIP graph
+while the batch shape repeats and may autotune its launch shape; none of this
+may change a single bit of any result.
+"""
+import sys
+
+import pytest
+import torch
+
+import oracle
+from paper_1806_08901_amd import synth
+from tests.gpu_common import assert_matches_oracle
+
+pytestmark = pytest.mark.gpu
+
+OPS = [oracle.OP_SZ, oracle.OP_ZFP, oracle.OP_SELECT, oracle.OP_FIXED_EB]
+
+
+def _note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1806_08901_amd import szsel
+    c = szsel.Context(0)
+    yield c
+    c.close()
+
+
+def _fields():
+    base = synth.spectral((70, 90), slope=-2.0, seed=61).cuda()
+    return [
+        synth.spectral((40, 36, 44), seed=62).cuda(),
+        synth.spectral((33, 50, 47), slope=-3.0, seed=63, dtype=torch.float64).cuda(),
+        synth.spectral((60, 90), slope=-1.5, seed=64, dtype=torch.float64).cuda(),
+        base,
+        base.view(-1)[1:1 + 69 * 90].view(69, 90),  # 4-byte offset: rows not 16-byte aligned
+        synth.gaussian_bumps((1030,), sigma_range=(3.0, 30.0), seed=65).cuda(),
+        synth.spiky_constant((48, 64), frac=0.01, seed=66).cuda(),
+        torch.full((16, 20), 3.0, device="cuda"),  # constant field
+        synth.gaussian_bumps((24, 24, 24), seed=67).cuda(),
+    ]
+
+
+def _items(fields, ebs=(1e-2, 1e-4, 1e-6)):
+    items = []
+    for i, f in enumerate(fields):
+        for j, eb in enumerate(ebs):
+            st = (2,) + (1,) * (f.dim() - 1) if (i + j) % 3 == 0 else (1,) * f.dim()
+            items.append((f, eb, oracle.EB_REL, st, OPS[(i + j) % 4]))
+    return items
+
+
+def _singles(ctx, items):
+    return [ctx.run(op, f, eb, mode, st) for (f, eb, mode, st, op) in items]
+
+
+def test_mixed_batch_equals_single_calls(ctx):
+    items = _items(_fields())
+    _note("mixed batch of", len(items))
+    batch = ctx.select_batch(items)
+    for k, (b, s) in enumerate(zip(batch, _singles(ctx, items))):
+        assert b == s, "request %d" % k
+
+
+def test_batch_matches_oracle(ctx):
+    f3 = synth.spectral((28, 24, 36), slope=-2.0, seed=68)
+    f2 = synth.spectral((50, 66), slope=-2.5, seed=69, dtype=torch.float64)
+    items = [(f3.cuda(), 1e-3, oracle.EB_REL, (1, 1, 1), oracle.OP_SELECT),
+             (f2.cuda(), 1e-5, oracle.EB_REL, (2, 1), oracle.OP_SELECT),
+             (f3.cuda(), 2e-3, oracle.EB_ABS, (1, 2, 1), oracle.OP_FIXED_EB)]
+    batch = ctx.select_batch(items)
+    for (f, eb, mode, st, op), g, host in zip(items, batch, [f3, f2, f3]):
+        orc, _ = oracle.run(op, host.numpy(), eb, mode, st)
+        assert_matches_oracle(g, orc, "batch op %d eb %g" % (op, eb))
+
+
+def test_shared_range_scan_sweep(ctx):
+    """Five bounds on one field: one range scan serves all five."""
+    f = synth.spectral((64, 64, 64), slope=-5.0 / 3.0, seed=70).cuda()
+    items = [(f, eb, oracle.EB_REL, (2, 2, 1), oracle.OP_SELECT) for eb in synth.EB_SWEEP]
+    batch = ctx.select_batch(items)
+    assert batch == _singles(ctx, items)
+
+
+def test_graph_replays_follow_new_inputs(ctx):
+    """Same batch shape three times: the captured graph is replayed with new
+    bounds, new field contents and new field pointers, with eager work and
+    synchronisations in between; every replay must equal the single calls."""
+    fields = [synth.spectral((40, 36, 44), seed=71).cuda(), synth.spectral((60, 90), seed=72).cuda()]
+    for rep in range(3):
+        if rep == 1:
+            fields[0].mul_(1.5).add_(0.25)  # same pointer, new contents
+        if rep == 2:
+            fields = [f.clone() for f in fields]  # new pointers, same shapes
+        ebs = [(1e-2, 1e-4), (1e-3, 1e-5), (1e-4, 1e-6)][rep]
+        items = [(f, eb, oracle.EB_REL, (1,) * f.dim(), oracle.OP_SELECT) for f in fields for eb in ebs]
+        batch = ctx.select_batch(items)
+        torch.cuda.synchronize()
+        _ = torch.randn(1000, device="cuda").sum().item()  # unrelated eager work
+        assert batch == _singles(ctx, items), "replay %d" % rep
+
+
+def test_autotune_and_no_graph_give_the_same_results(ctx):
+    from paper_1806_08901_amd import szsel
+    items = _items(_fields()[:4], ebs=(1e-3, 1e-5))
+    ref = ctx.select_batch(items)
+    try:
+        ctx.set_option(szsel.OPT_AUTOTUNE, 1)
+        tuned = ctx.select_batch(items)
+        again = ctx.select_batch(items)
+        ctx.set_option(szsel.OPT_BATCH_GRAPH, 0)
+        eager = ctx.select_batch(items)
+    finally:
+        ctx.set_option(szsel.OPT_AUTOTUNE, 0)
+        ctx.set_option(szsel.OPT_BATCH_GRAPH, 1)
+    assert tuned == ref
+    assert again == ref
+    assert eager == ref
+
+
+def test_batches_in_flight_on_two_streams(ctx):
+    a_items = _items(_fields()[:3], ebs=(1e-3,))
+    b_items = _items(_fields()[3:6], ebs=(1e-4,))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    oa = ctx.select_batch(a_items, stream=s1, sync=False)
+    ob = ctx.select_batch(b_items, stream=s2, sync=False)
+    s1.synchronize()
+    s2.synchronize()
+    from paper_1806_08901_amd.szsel import _as_dict
+    ra = [_as_dict(oa[i]) for i in range(len(a_items))]
+    rb = [_as_dict(ob[i]) for i in range(len(b_items))]
+    assert ra == _singles(ctx, a_items)
+    assert rb == _singles(ctx, b_items)
+
+
+def test_batch_argument_errors(ctx):
+    from paper_1806_08901_amd import szsel
+    f = synth.spectral((20, 20), seed=73).cuda()
+    bad = [(f, 1e-3, oracle.EB_REL, (1, 1), oracle.OP_SELECT), (f, -1.0, oracle.EB_REL, (1, 1), oracle.OP_SELECT)]
+    with pytest.raises(szsel.SzselError, match="request 1"):
+        ctx.select_batch(bad)
+    too_many = [(f, 1e-3, oracle.EB_REL, (1, 1), oracle.OP_SELECT)] * 1025
+    with pytest.raises(szsel.SzselError, match="1024"):
+        ctx.select_batch(too_many)
+    # the context still works afterwards
+    good = [(f, 1e-3, oracle.EB_REL, (1, 1), oracle.OP_SELECT)]
+    assert ctx.select_batch(good) == _singles(ctx, good)
