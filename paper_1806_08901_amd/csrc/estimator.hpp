@@ -1054,36 +1054,48 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   const int t = threadIdx.x;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
   const bool ovf = get_u64(&r.st->ovf_count) != 0;
+  static_assert(kEntPerThread == 4, "four bins per thread, one 16-byte vector");
+  const int bin0 = c * kEntChunk + t * kEntPerThread;
+  // the SZ workgroups' counts, spread over kHistCopies copies so that no
+  // bin takes more than 1/16 of the workgroups' atomics; every copy's four
+  // bins are one 16-byte load, all issued before any is used
+  uint4 hc[kHistCopies];
+#pragma unroll
+  for (int q = 0; q < kHistCopies; q++) hc[q] = *(const uint4 *)(r.hist + (size_t)q * kBins + bin0);
+  uint32_t h[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < kHistCopies; q++) {
+    h[0] += hc[q].x;
+    h[1] += hc[q].y;
+    h[2] += hc[q].z;
+    h[3] += hc[q].w;
+  }
+  if (ovf) {  // add the overflow pass's counts
+#pragma unroll 8
+    for (int p = 0; p < kOvfSlices; p++) {
+      const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
+      h[0] += o.x;
+      h[1] += o.y;
+      h[2] += o.z;
+      h[3] += o.w;
+    }
+  }
+  if (bin0 == 0) h[0] = (uint32_t)unpred;  // code 0: the unpredictable points
+  if (r.dbg_hist) {
+#pragma unroll
+    for (int k = 0; k < kEntPerThread; k++) r.dbg_hist[bin0 + k] = h[k];
+  }
+#pragma unroll
+  for (int q = 0; q < kHistCopies; q++)
+    if (hc[q].x | hc[q].y | hc[q].z | hc[q].w) *(uint4 *)(r.hist + (size_t)q * kBins + bin0) = make_uint4(0, 0, 0, 0);
   double hv[kEntPerThread];
 #pragma unroll
   for (int k = 0; k < kEntPerThread; k++) {
-    const int bin = c * kEntChunk + t * kEntPerThread + k;
-    // the SZ workgroups' counts, spread over kHistCopies copies so that no
-    // bin takes more than 1/16 of the workgroups' atomics
-    uint32_t hc[kHistCopies];
-    uint32_t h = 0;
-#pragma unroll
-    for (int q = 0; q < kHistCopies; q++) {
-      hc[q] = r.hist[(size_t)q * kBins + bin];
-      h += hc[q];
-    }
-    if (ovf) {  // add the overflow pass's counts
-      uint32_t o = 0;
-#pragma unroll 8
-      for (int p = 0; p < kOvfSlices; p++) o += r.ovf_hist[(size_t)p * kBins + bin];
-      h += o;
-    }
-    if (bin == 0) h = (uint32_t)unpred;  // code 0: the unpredictable points
-    if (r.dbg_hist) r.dbg_hist[bin] = h;
-#pragma unroll
-    for (int q = 0; q < kHistCopies; q++)
-      if (hc[q]) r.hist[(size_t)q * kBins + bin] = 0;
-    const double hd = (double)h;
-    hv[k] = h ? hd * log2(hd) : 0.0;
+    const double hd = (double)h[k];
+    hv[k] = h[k] ? hd * log2(hd) : 0.0;
   }
   // the thread's 4 consecutive bins, then the wave butterfly, then the
   // fixed combine of the 4 waves: the chunk's aligned subtree
-  static_assert(kEntPerThread == 4, "four bins per thread");
   double v = (hv[0] + hv[1]) + (hv[2] + hv[3]);
   v = group_tree_sum<kWave>(v);
   const int w = t / kWave;
