@@ -10,9 +10,11 @@ all 512 MiB and the result copy to pinned host memory).
 
 Metric: input GB/s = 5 x 512 MiB per step / GPU time of the step (HIP events
 on the stream the kernels run on), inputs resident in HBM.  Also reported:
-the range pass's achieved HBM bandwidth against the 8 TB/s peak (per-phase
-HIP events inside the library), per-call latency p50/p99, and the CPU oracle
-timed on the same field on one host core.
+the slowest pass's achieved HBM bandwidth against the 8 TB/s peak (per-pass
+HIP events inside the library) and every pass the same way, per-call
+latency p50/p99, the same five requests run as one batch (szsel_select_batch,
+shared range scan, graph replay) with its speedup over the plain launches,
+and the CPU oracle timed on the same field on one host core.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -38,6 +40,7 @@ def parse():
     ap.add_argument("--latency-calls", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the batched launch shape")
     return ap.parse_args()
 
 
@@ -134,6 +137,36 @@ def main():
             entry.update({"bytes": pbytes[k], "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
         passes[k] = entry
 
+    # batched: the same five requests as one szsel_select_batch call (one
+    # launch per pass over all five, one shared range scan, graph replay)
+    items = [(field, eb, szsel.EB_REL, stride, szsel.OP_SELECT) for eb in ebs]
+    reqs = ctx.make_requests(items)
+    if args.autotune:
+        ctx.set_option(szsel.OPT_AUTOTUNE, 1)
+    batch_results = ctx.select_batch(items, reqs=reqs)  # plans, tunes, captures
+    batch_same = batch_results == gpu_results
+    bouts = [ctx.result_buffer(len(items)) for _ in range(4)]
+
+    def bstep(k):
+        ctx.select_batch(None, reqs=reqs, sync=False, out=bouts[k % 4])
+
+    for k in range(args.warmup):
+        bstep(k)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(args.steps):
+        bstep(k)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = t0.elapsed_time(t1) / args.steps
+    value_batch = len(ebs) * nbytes / (ms_batch * 1e-3) / 1e9
+    blat = []
+    for k in range(max(1, args.latency_calls // 5)):
+        t = time.perf_counter()
+        ctx.select_batch(None, reqs=reqs)
+        blat.append((time.perf_counter() - t) * 1e3)
+    blat.sort()
+
     # latency of one synchronous select call (host wall clock)
     lat = []
     for k in range(args.latency_calls):
@@ -170,6 +203,16 @@ def main():
             "bytes_per_launch": pbytes.get(dominant), "avg_launch_ms": round(phase_ms[dominant], 5),
         },
         "passes": passes,
+        "batched": {
+            "value": round(value_batch, 2), "unit": "GB/s", "ms_per_step": round(ms_batch, 4),
+            "speedup_vs_plain": round(value_batch / value, 3),
+            "mode": "the same 5 requests as one szsel_select_batch call: one launch per pass over "
+                    "all of them, one shared value-range scan, HIP graph replay",
+            "autotuned": bool(args.autotune), "results_equal_plain": bool(batch_same),
+            "latency_ms": {"p50": round(blat[len(blat) // 2], 4),
+                           "p99": round(blat[min(len(blat) - 1, int(0.99 * len(blat)))], 4),
+                           "calls": len(blat), "what": "one synchronous batch of the 5 requests"},
+        },
         "latency_ms": {"p50": round(lat[len(lat) // 2], 4),
                        "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
                        "calls": len(lat), "what": "one synchronous szsel_select on the field"},

@@ -243,18 +243,26 @@ class Context:
                 q.stride[k] = 1 if stride is None else int(stride[k])
         return reqs
 
-    def select_batch(self, items, stream=None, sync: bool = True, reqs=None):
+    def result_buffer(self, n: int):
+        """A pinned array of n Result for asynchronous calls."""
+        t = torch.empty(max(1, n) * C.sizeof(Result), dtype=torch.uint8, pin_memory=True)
+        out = (Result * n).from_address(t.data_ptr())
+        out._owner = t
+        return out
+
+    def select_batch(self, items, stream=None, sync: bool = True, reqs=None, out=None):
         """Runs the requests as one batch.  With sync=False the call returns
-        a fresh pinned array of Result, filled once the stream reaches it."""
+        `out` (or a fresh pinned array of Result), filled once the stream
+        reaches it."""
         if reqs is None:
             reqs = self.make_requests(items)
         n = len(reqs)
-        if sync:
+        if out is not None:
+            pass
+        elif sync:
             out = self._results(n)
         else:
-            t = torch.empty(max(1, n) * C.sizeof(Result), dtype=torch.uint8, pin_memory=True)
-            out = (Result * n).from_address(t.data_ptr())
-            self._keep = getattr(self, "_keep", [])[-15:] + [t]  # keep the buffer alive
+            out = self.result_buffer(n)
         s, sp = self._stream(stream)
         self._check(self.lib.szsel_select_batch(self.h, reqs, n, out, sp), "szsel_select_batch")
         if not sync:
