@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the batched launch shape")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device 5 times (scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,13 +74,57 @@ def pass_bytes(shape, stride, itemsize, nblk):
             "sz": halo * itemsize, "ent": 65536 * 4}
 
 
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration(torch):
+    """A plain copy of known size: each launch reads and writes COPY_BYTES."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 5}))
+
+
+def source_digest():
+    """Digest of the kernel sources, to tell whether recorded counters still
+    describe the current kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("device.hpp", "estimator.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1806_08901_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_traffic_turb512.md), or None when it is missing or was
+    taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_turb512.md")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("sources:"):
+                digest = line.split()[1]
+            if line.startswith("traffic:") and line.split()[1] == kernel:
+                val = int(line.split()[2])
+    return val if digest == source_digest() else None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(fields would shard across GPUs by whole fields; see DESIGN.md)", file=sys.stderr)
+              "(fields would shard across GPUs by whole fields, with no exchange)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     from paper_1806_08901_amd import synth, szsel
 
@@ -129,6 +175,7 @@ def main():
                "ovf": "k_ovf (counts of codes outside the LDS window)",
                "ent": "k_ent (entropy, bit-rates, selection)"}
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
+    kernel_names = {"range": "k_range", "zfp": "k_zfp", "sz": "k_sz", "ovf": "k_ovf", "ent": "k_ent"}
     passes = {}
     for k, ms in phase_ms.items():
         entry = {"ms": round(ms, 5)}
@@ -199,7 +246,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": kernels[dominant],
             "achieved": passes[dominant].get("GB/s"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": passes[dominant].get("frac"), "traffic": None,
+            "frac": passes[dominant].get("frac"), "traffic": recorded_traffic(kernel_names[dominant]),
             "bytes_per_launch": pbytes.get(dominant), "avg_launch_ms": round(phase_ms[dominant], 5),
         },
         "passes": passes,
