@@ -183,9 +183,21 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   shape and keep the fastest; 0 (default) uses the fixed schedule.  The
  *   results do not depend on it.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
- *   HIP graph and replays it while the batch shape repeats. */
+ *   HIP graph and replays it while the batch shape repeats.
+ * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the batch
+ *   schedule without autotuning (and the autotuner's starting point): SZ
+ *   workgroups per request in quarters of the CU count (1..256, default 16),
+ *   smallest ZFP chunk in sampled blocks (a power of two 64..65536, default
+ *   64), range workgroups per CU and request (1..64, default 2); 0 restores
+ *   the default.  Results do not depend on them.
+ * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
+ *   default 1; 0 restores it): the requests are dealt to that many groups
+ *   (requests on one field stay together), each running on its own stream,
+ *   and group g starts its range scans when group g-1's are done, so the
+ *   scans of later groups overlap the sampled passes of earlier ones. */
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
-       SZSEL_OPT_BATCH_GRAPH = 4 };
+       SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
+       SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* Phase timers: synchronises the recorded events and returns, per phase

@@ -39,6 +39,8 @@ namespace {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+constexpr int kMaxGroupsPerBatch = 8;
+
 struct Plan {
   std::vector<ReqDesc> tab;             // table order
   std::vector<int> orig;                // caller index of each table entry
@@ -47,6 +49,7 @@ struct Plan {
   std::vector<size_t> voff;             // variable workspace offset of each table entry
   size_t var = 0;                       // variable workspace bytes
   std::vector<uint64_t> sig;            // launch shape (graph reuse key)
+  int groups = 1;                       // request groups (streams)
 };
 
 bool same_field(const ReqDesc &a, const ReqDesc &b) {
@@ -58,7 +61,7 @@ bool same_field(const ReqDesc &a, const ReqDesc &b) {
 
 // Plans every request with the knobs `tu` and lays out the table, prefix
 // counts and launches.
-int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, Plan &p,
+int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const Tune &tu, Plan &p,
               std::string &msg) {
   std::vector<ReqDesc> d((size_t)n);
   for (int i = 0; i < n; i++) {
@@ -71,10 +74,44 @@ int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, 
       return rc;
     }
   }
+  // request groups: requests on one field stay together (they share the
+  // scan); fields are dealt to the groups largest first, each to the group
+  // with the least estimated work (range bytes plus 8 bytes per sampled value)
+  const int G = std::max(1, std::min(tu.groups, kMaxGroupsPerBatch));
+  std::vector<int> grp((size_t)n, 0);
+  if (G > 1) {
+    std::vector<int> unit((size_t)n, -1);
+    std::vector<double> ucost;
+    std::vector<int> urep;
+    for (int i = 0; i < n; i++) {
+      for (int j = 0; j < i && unit[i] < 0; j++)
+        if (same_field(d[i], d[j])) unit[i] = unit[j];
+      const double sampled = (double)d[i].nblk * (double)(1 << (2 * d[i].nd)) * 8.0;
+      if (unit[i] < 0) {
+        unit[i] = (int)ucost.size();
+        ucost.push_back((double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0) + sampled);
+        urep.push_back(i);
+      } else {
+        ucost[unit[i]] += sampled;
+      }
+    }
+    std::vector<int> uo(ucost.size());
+    std::iota(uo.begin(), uo.end(), 0);
+    std::stable_sort(uo.begin(), uo.end(), [&](int a, int b) { return ucost[a] > ucost[b]; });
+    std::vector<double> load((size_t)G, 0.0);
+    std::vector<int> ug(ucost.size(), 0);
+    for (int u : uo) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      ug[u] = g;
+      load[g] += ucost[u];
+    }
+    for (int i = 0; i < n; i++) grp[i] = ug[unit[i]];
+  }
   std::vector<int> ord((size_t)n);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
     const ReqDesc &x = d[a], &y = d[b];
+    if (grp[a] != grp[b]) return grp[a] < grp[b];
     if (x.dtype != y.dtype) return x.dtype < y.dtype;
     if (x.nd != y.nd) return x.nd < y.nd;
     if (x.vec != y.vec) return x.vec > y.vec;
@@ -85,12 +122,17 @@ int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, 
   });
   p.tab.resize((size_t)n);
   p.orig = ord;
-  for (int k = 0; k < n; k++) p.tab[k] = d[ord[k]];
+  p.groups = G;
+  std::vector<int> tg((size_t)n);
+  for (int k = 0; k < n; k++) {
+    p.tab[k] = d[ord[k]];
+    tg[k] = grp[ord[k]];
+  }
   // range scans shared by runs of requests on the same field
   std::vector<bool> owner((size_t)n, true);
   for (int k = 0; k < n;) {
     int e = k + 1;
-    while (e < n && same_field(p.tab[k], p.tab[e])) e++;
+    while (e < n && tg[e] == tg[k] && same_field(p.tab[k], p.tab[e])) e++;
     p.tab[k].nshare = e - k - 1;
     for (int m = k + 1; m < e; m++) {
       p.tab[m].nshare = 0;
@@ -124,12 +166,15 @@ int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, 
     const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
     for (int k = 0; k < n;) {
       int e = k + 1;
-      auto same_class = [&](const ReqDesc &a, const ReqDesc &b) {
-        if (ps == kBatchRange) return a.dtype == b.dtype;
-        return a.dtype == b.dtype && a.nd == b.nd && a.vec == b.vec;
+      auto same_class = [&](int a, int b) {
+        if (tg[a] != tg[b]) return false;
+        const ReqDesc &x = p.tab[a], &y = p.tab[b];
+        if (ps == kBatchRange) return x.dtype == y.dtype;
+        return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec;
       };
-      while (e < n && same_class(p.tab[k], p.tab[e])) e++;
+      while (e < n && same_class(k, e)) e++;
       BatchLaunch L;
+      L.group = tg[k];
       L.pass = ps;
       L.dtype = p.tab[k].dtype;
       L.nd = p.tab[k].nd;
@@ -139,6 +184,9 @@ int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, 
       L.c0 = k;
       L.c1 = e;
       L.items = f[e] - f[k];
+      L.grid = L.items;
+      if (ps == kBatchOvf) L.grid = std::min<uint32_t>(L.items, 2u * (uint32_t)ncu);
+      if (ps == kBatchEnt) L.grid = std::min<uint32_t>(L.items, 8u * (uint32_t)ncu);
       if (L.items) p.launches.push_back(L);
       k = e;
     }
@@ -154,11 +202,12 @@ int make_plan(szsel_ctx *ctx, const szsel_request *reqs, int n, const Tune &tu, 
   // table contents (field pointers and bounds are uploaded on every call)
   p.sig.clear();
   p.sig.push_back((uint64_t)n);
+  p.sig.push_back((uint64_t)G);
   for (int k = 0; k < n; k++) p.sig.push_back((uint64_t)p.orig[k]);
   for (uint32_t v : p.first) p.sig.push_back(v);
   for (const BatchLaunch &L : p.launches)
-    p.sig.push_back(((uint64_t)L.pass << 48) | ((uint64_t)L.dtype << 40) | ((uint64_t)L.nd << 32) |
-                    ((uint64_t)L.vec << 31) | ((uint64_t)L.c0 << 16) | (uint64_t)L.c1);
+    p.sig.push_back(((uint64_t)L.group << 59) | ((uint64_t)L.pass << 56) | ((uint64_t)L.dtype << 52) | ((uint64_t)L.nd << 48) |
+                    ((uint64_t)L.vec << 47) | ((uint64_t)L.grid << 24) | ((uint64_t)L.c0 << 12) | (uint64_t)L.c1);
   for (size_t v : p.voff) p.sig.push_back(v);
   return SZSEL_OK;
 }
@@ -220,11 +269,16 @@ struct BatchState {
   hipEvent_t done = nullptr;
   bool used = false;
   hipStream_t cap = nullptr;  // private capture stream
+  hipStream_t side[kMaxGroupsPerBatch - 1] = {};  // streams of request groups 1..
+  hipEvent_t fork = nullptr;
+  hipEvent_t scanned[kMaxGroupsPerBatch] = {};    // group g's range scans are done
+  hipEvent_t finished[kMaxGroupsPerBatch] = {};   // group g's last pass is done
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<uint64_t> sig;  // launch shape of the captured graph
   std::vector<uint64_t> last_key;  // last batch shape, and its knobs
   Tune last_tune;
+  bool last_auto = false;
   bool have_last = false;
 };
 
@@ -238,6 +292,13 @@ void batch_destroy(BatchState *bs) {
   if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
   if (bs->graph) (void)hipGraphDestroy(bs->graph);
   if (bs->cap) (void)hipStreamDestroy(bs->cap);
+  for (hipStream_t q : bs->side)
+    if (q) (void)hipStreamDestroy(q);
+  if (bs->fork) (void)hipEventDestroy(bs->fork);
+  for (int g = 0; g < kMaxGroupsPerBatch; g++) {
+    if (bs->scanned[g]) (void)hipEventDestroy(bs->scanned[g]);
+    if (bs->finished[g]) (void)hipEventDestroy(bs->finished[g]);
+  }
   if (bs->fixed) (void)hipFree(bs->fixed);
   if (bs->var) (void)hipFree(bs->var);
   if (bs->res) (void)hipFree(bs->res);
@@ -313,18 +374,37 @@ hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
   return hipSuccess;
 }
 
-// Upload of the table and every launch of plan p, on stream s.
+// Upload of the table and every launch of plan p, on stream s.  With G
+// request groups, group g runs on its own stream (s for group 0) and
+// starts its range scans when group g-1's are done, so that the scans run
+// one group at a time at full bandwidth while the earlier groups' sampled
+// passes (latency- and issue-bound) overlap them; s waits for every group.
 hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s) {
   const size_t n = p.tab.size();
   const size_t meta = align_up(sizeof(ReqDesc) * n, 256) + sizeof(uint32_t) * p.first.size();
   hipError_t e = hipMemcpyAsync(bs->meta, bs->stage, meta, hipMemcpyHostToDevice, s);
-  for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = launch_batch_pass(p.launches[k], s);
+  const int G = p.groups;
+  hipStream_t st[kMaxGroupsPerBatch];
+  st[0] = s;
+  for (int g = 1; g < G; g++) st[g] = bs->side[g - 1];
+  if (G > 1 && e == hipSuccess) e = hipEventRecord(bs->fork, s);
+  for (int g = 1; g < G && e == hipSuccess; g++) e = hipStreamWaitEvent(st[g], bs->fork, 0);
+  for (int g = 0; g < G && e == hipSuccess; g++) {
+    if (g > 0) e = hipStreamWaitEvent(st[g], bs->scanned[g - 1], 0);
+    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
+      if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = launch_batch_pass(p.launches[k], st[g]);
+    if (G > 1 && e == hipSuccess) e = hipEventRecord(bs->scanned[g], st[g]);
+    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
+      if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = launch_batch_pass(p.launches[k], st[g]);
+    if (G > 1 && g > 0 && e == hipSuccess) e = hipEventRecord(bs->finished[g], st[g]);
+  }
+  for (int g = 1; g < G && e == hipSuccess; g++) e = hipStreamWaitEvent(s, bs->finished[g], 0);
   return e;
 }
 
 }  // namespace
 
-int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
+int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
               szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg) {
   if (n > kMaxBatch) {
     msg = "batch of " + std::to_string(n) + " requests; at most " + std::to_string(kMaxBatch);
@@ -332,8 +412,16 @@ int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_reques
   }
   if (!bs) {
     bs = new BatchState();
-    if (hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&bs->fork, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) == hipSuccess;
+    for (int g = 0; g < kMaxGroupsPerBatch && ok; g++) {
+      ok = hipEventCreateWithFlags(&bs->scanned[g], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&bs->finished[g], hipEventDisableTiming) == hipSuccess;
+      if (ok && g + 1 < kMaxGroupsPerBatch)
+        ok = hipStreamCreateWithFlags(&bs->side[g], hipStreamNonBlocking) == hipSuccess;
+    }
+    if (!ok) {
       msg = "batch state: event or stream creation failed";
       return SZSEL_EHIP;
     }
@@ -350,9 +438,10 @@ int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_reques
   }
   // knobs: the tuned ones for this batch shape, else the defaults
   const std::vector<uint64_t> key = shape_key(reqs, n);
-  Tune tu;
+  Tune tu = opt.fixed;
   bool tuned = false;
-  if (bs->have_last && bs->last_key == key) {
+  if (bs->have_last && bs->last_key == key && bs->last_auto == opt.autotune &&
+      (opt.autotune || std::memcmp(&bs->last_tune, &opt.fixed, sizeof(Tune)) == 0)) {
     tu = bs->last_tune;
     tuned = true;
   } else if (opt.autotune) {
@@ -372,31 +461,48 @@ int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_reques
     }
     auto time_of = [&](const Tune &c, float &ms) -> int {
       Plan p;
-      int rc = make_plan(ctx, reqs, n, c, p, msg);
+      int rc = make_plan(ctx, ncu, reqs, n, c, p, msg);
       if (rc != SZSEL_OK) return rc;
       if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
       hipError_t q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
-      if (q == hipSuccess) q = hipEventRecord(t0, s);
-      if (q == hipSuccess) q = enqueue_plan(bs, p, s);
-      if (q == hipSuccess) q = hipEventRecord(t1, s);
-      if (q == hipSuccess) q = hipEventSynchronize(t1);
-      if (q == hipSuccess) q = hipEventElapsedTime(&ms, t0, t1);
+      ms = 1e30f;
+      for (int rep = 0; rep < 3 && q == hipSuccess; rep++) {  // best of 3
+        float one = 0.f;
+        q = hipEventRecord(t0, s);
+        if (q == hipSuccess) q = enqueue_plan(bs, p, s);
+        if (q == hipSuccess) q = hipEventRecord(t1, s);
+        if (q == hipSuccess) q = hipEventSynchronize(t1);
+        if (q == hipSuccess) q = hipEventElapsedTime(&one, t0, t1);
+        ms = std::min(ms, one);
+      }
       if (q != hipSuccess) {
         msg = std::string("autotune: ") + hipGetErrorString(q);
         return SZSEL_EHIP;
       }
       return SZSEL_OK;
     };
-    Tune cur;
+    Tune cur = opt.fixed;
     float best_ms = 0.f;
     int rc = time_of(cur, best_ms);
-    const int sz_opts[] = {1, 2, 4, 8};
+    const int group_opts[] = {1, 2, 4, 8};
+    const int sz_opts[] = {2, 4, 8, 16, 32};
     const int zfp_opts[] = {64, 128, 256};
     const int range_opts[] = {1, 2, 4};
-    for (int v : sz_opts) {
-      if (rc != SZSEL_OK || v == cur.sz_wgs_per_cu) continue;
+    for (int v : group_opts) {
+      if (rc != SZSEL_OK || v == cur.groups || v > n) continue;
       Tune c = cur;
-      c.sz_wgs_per_cu = v;
+      c.groups = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    for (int v : sz_opts) {
+      if (rc != SZSEL_OK || v == cur.sz_wgs_q) continue;
+      Tune c = cur;
+      c.sz_wgs_q = v;
       float ms = 0.f;
       rc = time_of(c, ms);
       if (rc == SZSEL_OK && ms < best_ms) {
@@ -434,10 +540,11 @@ int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_reques
   }
   bs->last_key = key;
   bs->last_tune = tu;
+  bs->last_auto = opt.autotune;
   bs->have_last = true;
 
   Plan p;
-  int rc = make_plan(ctx, reqs, n, tu, p, msg);
+  int rc = make_plan(ctx, ncu, reqs, n, tu, p, msg);
   if (rc != SZSEL_OK) return rc;
   if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
   if (opt.graph) {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "launch.hpp"
 
 struct szsel_ctx;
 
@@ -17,13 +18,14 @@ struct BatchState;
 struct BatchOptions {
   bool autotune = false;  // time launch-shape candidates per batch shape, keep the fastest
   bool graph = true;      // capture the launches as a HIP graph and replay it
+  Tune fixed;             // the schedule used without autotuning
 };
 
 // Plans and runs the n requests on stream s and copies the results to
 // out[0..n) (asynchronously).  `bs` is created or grown on demand; it is
 // reused only after its previous batch has finished.  `budget` caps its
 // device memory.
-int batch_run(szsel_ctx *ctx, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
+int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
               szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg);
 
 void batch_destroy(BatchState *bs);

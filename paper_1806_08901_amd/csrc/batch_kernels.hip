@@ -7,22 +7,30 @@
 
 namespace szsel {
 
-// Table entry of this workgroup's work item and the item's index within
-// its request: the prefix counts are staged in LDS and searched (entries
-// with no items are skipped by taking the last entry whose start is <= g).
-__device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t *s_first, int &local) {
-  const int n = c1 - c0;
-  for (int k = threadIdx.x; k <= n; k += blockDim.x) s_first[k] = first[c0 + k];
+// Stages the prefix counts first[c0..c1] of a launch in LDS.
+__device__ inline void batch_stage(const uint32_t *first, int c0, int c1, uint32_t *s_first) {
+  for (int k = threadIdx.x; k <= c1 - c0; k += blockDim.x) s_first[k] = first[c0 + k];
   __syncthreads();
-  const uint32_t g = s_first[0] + blockIdx.x;
-  int lo = 0, hi = n - 1;
+}
+
+// Table entry of work item g (counted from the launch's first item) and the
+// item's index within its request: the last entry whose start is <= g
+// (entries with no items are skipped that way).
+__device__ inline int batch_find(const uint32_t *s_first, int c0, int c1, uint32_t g, int &local) {
+  const uint32_t a = s_first[0] + g;
+  int lo = 0, hi = c1 - c0 - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (s_first[mid] <= g) lo = mid; else hi = mid - 1;
+    if (s_first[mid] <= a) lo = mid; else hi = mid - 1;
   }
-  local = (int)(g - s_first[lo]);
-  __syncthreads();
+  local = (int)(a - s_first[lo]);
   return c0 + lo;
+}
+
+// One work item per workgroup.
+__device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t *s_first, int &local) {
+  batch_stage(first, c0, c1, s_first);
+  return batch_find(s_first, c0, c1, blockIdx.x, local);
 }
 
 template <typename T>
@@ -57,31 +65,78 @@ __global__ __launch_bounds__(kThreads) void kb_sz(const ReqDesc *tab, const uint
   sz_wg<T, D, VEC>(r, local, L, s_hist);
 }
 
+// The overflow and entropy passes have many small items, most of which
+// (requests without overflow codes) end at once: a grid of a few
+// workgroups per CU loops over them instead of one workgroup per item.  The
+// overflow pass first keeps only the items that have work: every
+// workgroup reads the slice counts of the launch's requests (set by their
+// SZ finalizers) and numbers the kOvfRanges x S items of each by a scan.
 template <int D>
 __global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
   __shared__ uint32_t s_cnt[kOvfBins];
-  __shared__ uint32_t s_first[kMaxBatch + 1];
-  int local;
-  const int i = batch_item(first, c0, c1, s_first, local);
-  const ReqDesc &r = tab[i];
-  if (skip_request(r.st)) return;
-  ovf_wg<D>(r, local, s_cnt);
+  __shared__ uint32_t s_pre[kMaxBatch + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  const int n = c1 - c0, t = threadIdx.x;
+  constexpr int kPer = (kMaxBatch + kThreads - 1) / kThreads;  // requests per thread
+  uint32_t cnt[kPer], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; k++) {
+    const int i = t * kPer + k;
+    cnt[k] = 0;
+    if (i < n && first[c0 + i + 1] != first[c0 + i]) {
+      const ReqState *st = tab[c0 + i].st;
+      if (!skip_request(st)) cnt[k] = get_u32(&st->ovf_slices) * (uint32_t)kOvfRanges;
+    }
+    sum += cnt[k];
+  }
+  uint32_t inc = sum;
+  const int lane = t & (kWave - 1), wv = t / kWave;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == kWave - 1) s_wave[wv] = inc;
+  __syncthreads();
+  uint32_t base = inc - sum;
+  for (int q = 0; q < wv; q++) base += s_wave[q];
+#pragma unroll
+  for (int k = 0; k < kPer; k++) {
+    const int i = t * kPer + k;
+    if (i <= n) s_pre[i] = base;
+    base += cnt[k];
+  }
+  if (t == kThreads - 1 && n == kMaxBatch) s_pre[n] = base;
+  __syncthreads();
+  const uint32_t items = s_pre[n];
+  for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
+    int lo = 0, hi = n - 1;  // last request whose first item is <= g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    ovf_wg<D>(tab[c0 + lo], (int)(g - s_pre[lo]), s_cnt);
+    __syncthreads();
+  }
 }
 
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
-  int local;
-  const int i = batch_item(first, c0, c1, s_first, local);
-  const ReqDesc &r = tab[i];
-  if (skip_request(r.st)) return;
-  ent_wg<T, D>(r, local, L);
+  batch_stage(first, c0, c1, s_first);
+  const uint32_t items = s_first[c1 - c0] - s_first[0];
+  for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
+    int local;
+    const ReqDesc &r = tab[batch_find(s_first, c0, c1, g, local)];
+    if (!skip_request(r.st)) ent_wg<T, D>(r, local, L);
+    __syncthreads();
+  }
 }
 
 template <typename T, int D>
 static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
-  const dim3 grid(a.items);
+  const dim3 grid(a.grid ? a.grid : a.items);
   switch (a.pass) {
     case kBatchRange:
       hipLaunchKernelGGL((kb_range<T>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);

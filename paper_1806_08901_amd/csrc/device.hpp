@@ -31,7 +31,8 @@ constexpr int kEntWgs = 65536 / kEntChunk;
 constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
-constexpr int kHistCopies = 16;        // global histogram copies (SZ workgroup w adds to copy w mod 16)
+constexpr int kHistCopies = 16;        // most global histogram copies (SZ workgroup w adds to copy w mod nhc)
+constexpr int kOvfPerSlice = 65536;    // overflow codes per slice of the overflow count
 constexpr int kMaxBatch = 1024;        // requests per batch
 constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
@@ -83,6 +84,7 @@ struct alignas(64) ReqState {
   uint64_t ovf_count;        // codes in the overflow regions (set by the SZ finalizer)
   int32_t minexp;
   uint32_t flags;
+  uint32_t ovf_slices;       // slices the overflow pass counts them in (set by the SZ finalizer)
 };
 
 // Completion counters of one pass.  Atomics on one address (one 128-byte
@@ -129,7 +131,7 @@ struct ReqDesc {
   int32_t nrange;  // range workgroups
   int32_t vec;     // 1: every row of 4 values starts 16-byte aligned (vector loads)
   int32_t nshare;  // batches: requests right after this one in the table that share its range scan
-  int32_t pad1;
+  int32_t nhc;     // global histogram copies in use (power of two <= kHistCopies)
   ReqState *st;
   PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;

@@ -18,6 +18,7 @@
 namespace szsel {
 
 constexpr int kHistWin = 4096;    // LDS histogram window around the zero code
+constexpr int kOvfMaxRegions = kMaxParts / kOvfSlices + 1;  // SZ workgroups per overflow slice
 constexpr int kHistLo = kRadius - kHistWin / 2;
 
 template <int D> struct Order {
@@ -961,10 +962,70 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
   }
 }
 
+// Hands the workgroup's LDS window to the global histogram.  A narrow
+// window (few distinct codes) is added bin by bin with global atomics.  A
+// wide one, where one global atomic per distinct code would cost more than
+// counting its points again, is written back as codes into the
+// workgroup's overflow region (each thread expands 16 consecutive bins at
+// the offset an exclusive scan of the bin counts gives it), and the
+// overflow pass counts them in LDS.  `points` is the workgroup's number of
+// sampled points; the region holds that many codes.
+__device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *region, uint32_t *s_n,
+                                      uint32_t points, TileLds &L) {
+  constexpr int kPer = kHistWin / kThreads;  // 16 bins per thread
+  __shared__ uint32_t s_distinct, s_wave[kWaves];
+  const int t = threadIdx.x;
+  uint32_t nz = 0, sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; k++) {
+    const uint32_t v = s_hist[t * kPer + k];
+    nz += v ? 1u : 0u;
+    sum += v;
+  }
+  const uint32_t wnz = group_isum<kWave>(nz);
+  // inclusive scan of the per-thread sums within the wave (Hillis-Steele)
+  uint32_t inc = sum;
+  const int lane = t & (kWave - 1), wv = t / kWave;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == kWave - 1) s_wave[wv] = inc;
+  if (t == 0) s_distinct = 0;
+  __syncthreads();
+  if (lane == 0) atomicAdd(&s_distinct, wnz);
+  __syncthreads();
+  if (s_distinct * 4u <= points) {
+    hist_flush(s_hist, g);
+    return;
+  }
+  uint32_t base = *s_n + inc - sum;
+  for (int q = 0; q < wv; q++) base += s_wave[q];
+  for (int k = 0; k < kPer; k++) {
+    const int b = t * kPer + k;
+    const uint32_t v = s_hist[b];
+    for (uint32_t c = 0; c < v; c++) region[base + c] = (uint16_t)(kHistLo + b);
+    base += v;
+    s_hist[b] = 0;
+  }
+  __syncthreads();
+  if (t == kThreads - 1) *s_n = base;
+  __syncthreads();
+  (void)L;
+}
+
 // SZ totals of the request (last SZ workgroup): squared-error tree over the
 // workgroups' subtrees, maximum error, unpredictable count.
 __device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
   if (threadIdx.x == 0) {
+    // slices of the overflow count: about kOvfPerSlice codes each, and few
+    // enough SZ workgroups per slice for the overflow pass's LDS tables
+    const uint64_t want = (tot.b + kOvfPerSlice - 1) / kOvfPerSlice;
+    const uint64_t least = ((uint64_t)r.nsz + kOvfMaxRegions - 1) / kOvfMaxRegions;
+    uint64_t sl = want > least ? want : least;
+    sl = sl < 1 ? 1 : (sl > (uint64_t)kOvfSlices ? (uint64_t)kOvfSlices : sl);
+    put_u32(&r.st->ovf_slices, tot.b ? (uint32_t)sl : 0u);
     put_u64(&r.st->ovf_count, tot.b);
     put_f64(&r.st->sz_sse, tot.s);
     put_f64(&r.st->sz_maxerr, tot.m);
@@ -972,23 +1033,22 @@ __device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
   }
 }
 
-// Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: counts, in
-// LDS, the overflow codes of SZ workgroups [p n/S, (p+1) n/S) that lie in
-// code range q, and writes the dense counts of that range to slice p's
-// counts (no atomics).  The occupied 16-byte vectors (8 codes) of the
+// Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: for p below
+// the request's slice count S, counts, in LDS, the overflow codes of SZ
+// workgroups [p n/S, (p+1) n/S) that lie in code range q, and writes the
+// dense counts of that range to slice p's counts (no atomics).  The occupied 16-byte vectors (8 codes) of the
 // slice's regions are numbered through an LDS prefix sum of the regions'
 // vector counts, so the work follows the number of overflow codes; 4
 // vectors are in flight per thread.
-constexpr int kOvfMaxRegions = kMaxParts / kOvfSlices + 1;
-
 template <int D>
 __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   constexpr int BS = 1 << (2 * D);
-  if (get_u64(&r.st->ovf_count) == 0) return;
-  __shared__ uint32_t s_n[kOvfMaxRegions], s_pre[kOvfMaxRegions + 1];
   const int p = g / kOvfRanges, q = g % kOvfRanges;
-  const int w0 = (int)(((int64_t)r.nsz * p) / kOvfSlices);
-  const int w1 = (int)(((int64_t)r.nsz * (p + 1)) / kOvfSlices);
+  const int S = (int)get_u32(&r.st->ovf_slices);  // 0 when there is no overflow code
+  if (p >= S) return;
+  __shared__ uint32_t s_n[kOvfMaxRegions], s_pre[kOvfMaxRegions + 1];
+  const int w0 = (int)(((int64_t)r.nsz * p) / S);
+  const int w1 = (int)(((int64_t)r.nsz * (p + 1)) / S);
   const int nreg = w1 - w0;
   for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
   for (int k = threadIdx.x; k < nreg; k += kThreads) s_n[k] = (uint32_t)get_u64(r.sp.b + w0 + k);
@@ -1053,15 +1113,17 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   constexpr int BS = 1 << (2 * D);
   const int t = threadIdx.x;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
-  const bool ovf = get_u64(&r.st->ovf_count) != 0;
+  const int S = (int)get_u32(&r.st->ovf_slices);
+  const int nhc = r.nhc;
   static_assert(kEntPerThread == 4, "four bins per thread, one 16-byte vector");
   const int bin0 = c * kEntChunk + t * kEntPerThread;
-  // the SZ workgroups' counts, spread over kHistCopies copies so that no
-  // bin takes more than 1/16 of the workgroups' atomics; every copy's four
-  // bins are one 16-byte load, all issued before any is used
+  // the SZ workgroups' counts, spread over nhc copies so that no bin takes
+  // more than about 128 workgroups' atomics; every copy's four bins are one
+  // 16-byte load, all issued before any is used
   uint4 hc[kHistCopies];
 #pragma unroll
-  for (int q = 0; q < kHistCopies; q++) hc[q] = *(const uint4 *)(r.hist + (size_t)q * kBins + bin0);
+  for (int q = 0; q < kHistCopies; q++)
+    hc[q] = q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
   uint32_t h[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++) {
@@ -1070,9 +1132,9 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     h[2] += hc[q].z;
     h[3] += hc[q].w;
   }
-  if (ovf) {  // add the overflow pass's counts
+  {  // add the overflow pass's counts
 #pragma unroll 8
-    for (int p = 0; p < kOvfSlices; p++) {
+    for (int p = 0; p < S; p++) {
       const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
       h[0] += o.x;
       h[1] += o.y;
@@ -1087,7 +1149,8 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   }
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++)
-    if (hc[q].x | hc[q].y | hc[q].z | hc[q].w) *(uint4 *)(r.hist + (size_t)q * kBins + bin0) = make_uint4(0, 0, 0, 0);
+    if (q < nhc && (hc[q].x | hc[q].y | hc[q].z | hc[q].w))
+      *(uint4 *)(r.hist + (size_t)q * kBins + bin0) = make_uint4(0, 0, 0, 0);
   double hv[kEntPerThread];
 #pragma unroll
   for (int k = 0; k < kEntPerThread; k++) {
@@ -1170,7 +1233,10 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
       wg_acc_push(L, 0.0);
   }
   __syncthreads();
-  hist_flush(s_hist, r.hist + (size_t)(w % kHistCopies) * kBins);
+  const int64_t nb = min<int64_t>((int64_t)r.sblk, r.nblk - (int64_t)w * r.sblk);
+  hist_hand_over(s_hist, r.hist + (size_t)(w & (r.nhc - 1)) * kBins, region, &s_n,
+                 (uint32_t)(nb * BS), L);
+  __syncthreads();
   if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
   wg_acc_store(L, acc, r.sp, w);
   Part tot;

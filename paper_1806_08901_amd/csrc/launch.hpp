@@ -33,11 +33,12 @@ inline size_t request_var_bytes(const ReqDesc &r) {
 // batch_kernels.hip); `items` workgroups in total.
 enum { kBatchRange = 0, kBatchZfp, kBatchSz, kBatchOvf, kBatchEnt, kBatchPasses };
 struct BatchLaunch {
-  int pass, dtype, nd, vec;
+  int group, pass, dtype, nd, vec;
   const ReqDesc *tab;
   const uint32_t *first;
   int c0, c1;
-  uint32_t items;
+  uint32_t items;  // work items
+  uint32_t grid;   // workgroups (the overflow and entropy passes loop over their items)
 };
 hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 
@@ -46,9 +47,10 @@ hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 // they only move the balance between parallelism and per-workgroup
 // overheads, which the batch autotuner measures.
 struct Tune {
-  int sz_wgs_per_cu = 4;     // SZ workgroups per CU for one request
+  int sz_wgs_q = 16;         // SZ workgroups per request, in quarters of the CU count
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
   int range_wgs_per_cu = 2;  // range workgroups per CU for one request
+  int groups = 1;            // batches: request groups pipelined on parallel streams
 };
 
 }  // namespace szsel

@@ -154,15 +154,18 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     return c;
   };
   const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
-  // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; at
-  // most 4 workgroups per CU so that all of them are resident at once
+  // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; by
+  // default 4 workgroups per CU, all of them resident at once
   const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)),
-                                (uint64_t)tu.sz_wgs_per_cu * (uint64_t)ctx->ncu, kMaxParts);
+                                std::max<uint64_t>(1, (uint64_t)tu.sz_wgs_q * (uint64_t)ctx->ncu / 4), kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
   r.nzfp = (int32_t)std::max<uint64_t>(1, (nblk + zc - 1) / zc);
   r.nsz = (int32_t)std::max<uint64_t>(1, (nblk + sc - 1) / sc);
+  // global histogram copies: about 128 SZ workgroups flush into each
+  r.nhc = 1;
+  while (r.nhc < kHistCopies && (int64_t)r.nhc * 128 < r.nsz) r.nhc <<= 1;
   // rows of 4 values start on 16-byte boundaries: aligned field, row
   // length a multiple of 16 bytes / element size (blocks start at x = 4 b s)
   r.vec = ((uintptr_t)field % 16 == 0 && (dims[nd - 1] * (int64_t)esz) % 16 == 0) ? 1 : 0;
@@ -363,7 +366,7 @@ int szsel_select_batch(szsel_ctx *c, const szsel_request *reqs, int n, szsel_res
   const size_t budget = c->budget > others ? c->budget - others : 0;
   std::string msg;
   c->err.clear();
-  const int rc = batch_run(c, c->batch[k], budget, reqs, n, out, (hipStream_t)stream, c->bopt, msg);
+  const int rc = batch_run(c, c->ncu, c->batch[k], budget, reqs, n, out, (hipStream_t)stream, c->bopt, msg);
   c->batch_bytes[k] = batch_state_bytes(c->batch[k]);
   if (rc != SZSEL_OK) return fail(c, rc, msg + c->err);
   c->err.clear();
@@ -420,6 +423,29 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
   }
   if (option == SZSEL_OPT_BATCH_GRAPH) {
     c->bopt.graph = value != 0.0;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_BATCH_GROUPS) {
+    const int v = (int)value;
+    if (value != (double)v || v < 0 || v > 8) return fail(c, SZSEL_EINVAL, "request groups: 0 to 8");
+    c->bopt.fixed.groups = v ? v : Tune().groups;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_SZ_WGS || option == SZSEL_OPT_ZFP_CHUNK || option == SZSEL_OPT_RANGE_WGS) {
+    const Tune dflt;
+    const int v = (int)value;
+    if (value != (double)v || v < 0) return fail(c, SZSEL_EINVAL, "launch-shape values are non-negative integers");
+    if (option == SZSEL_OPT_SZ_WGS) {
+      if (v > 256) return fail(c, SZSEL_EINVAL, "SZ workgroups: at most 256 quarters of the CU count");
+      c->bopt.fixed.sz_wgs_q = v ? v : dflt.sz_wgs_q;
+    } else if (option == SZSEL_OPT_ZFP_CHUNK) {
+      if (v && (v < 64 || v > 65536 || (v & (v - 1))))
+        return fail(c, SZSEL_EINVAL, "ZFP chunk: a power of two from 64 to 65536");
+      c->bopt.fixed.zfp_chunk = v ? v : dflt.zfp_chunk;
+    } else {
+      if (v > 64) return fail(c, SZSEL_EINVAL, "range workgroups: at most 64 per CU");
+      c->bopt.fixed.range_wgs_per_cu = v ? v : dflt.range_wgs_per_cu;
+    }
     return SZSEL_OK;
   }
   if (option == SZSEL_OPT_PROFILE) {
