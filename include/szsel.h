@@ -209,6 +209,50 @@ int szsel_profile_read(szsel_ctx *ctx, double *ms, uint64_t *calls);
 /* Arms per-sample dumps for the next single-request call (NULL disarms). */
 int szsel_set_debug(szsel_ctx *ctx, const szsel_debug *dump);
 
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of snapshots (not a step of the paper's
+ * method; it runs the method online on snapshots as a simulation produces
+ * them, the in-situ setting of Section 3).
+ *
+ * The caller owns a device pool (pool, pool_bytes; 256-byte aligned).  A
+ * snapshot is admitted by reserving its bytes in the pool
+ * (szsel_server_reserve: first fit over 256-byte granules; SZSEL_EBUSY while
+ * the pool lacks room, SZSEL_ENOMEM if it never can).  The producer writes
+ * the snapshot's fields into the reservation, then submits its requests
+ * (every field must lie inside the reservation; producer_stream, if not
+ * NULL, is the stream the producer wrote on, and the estimation waits for
+ * it).  Submitted requests wait in one FIFO; each of `lanes` lanes (a stream
+ * with its own batch workspace of at most lane_workspace_bytes, 0 = 4 GiB)
+ * takes up to 64 waiting requests, from any number of snapshots, as one
+ * batch whenever it is free, so work that arrives while other work runs
+ * starts on the next free lane and overlaps it.  szsel_server_progress
+ * retires finished lanes (writing results to each snapshot's `out`, which
+ * must stay valid until the snapshot completes), releases completed
+ * snapshots' reservations and dispatches waiting requests; with wait != 0
+ * it first blocks until a busy lane finishes.  It returns the number of
+ * snapshots completed by the call, or a negative code.  Results are the
+ * same, bit for bit, as the single-request calls'.  Single-threaded: all
+ * calls from one host thread.  With ctx == NULL only the admission calls
+ * (reserve, cancel, stats) work: bookkeeping without a device. */
+typedef struct szsel_server szsel_server;
+int szsel_server_create(szsel_server **srv, szsel_ctx *ctx, void *pool, size_t pool_bytes, int lanes,
+                        size_t lane_workspace_bytes);
+void szsel_server_destroy(szsel_server *srv);
+int szsel_server_reserve(szsel_server *srv, size_t bytes, void **dev_ptr, uint64_t *ticket);
+/* Releases a reservation that was not submitted. */
+int szsel_server_cancel(szsel_server *srv, uint64_t ticket);
+int szsel_server_submit(szsel_server *srv, uint64_t ticket, const szsel_request *reqs, int n,
+                        szsel_result *out, void *producer_stream);
+int szsel_server_progress(szsel_server *srv, int wait);
+/* 1 (and *latency_ms = submit-to-completion time) once the snapshot is
+ * complete, after which the ticket is forgotten; 0 while it is not. */
+int szsel_server_status(szsel_server *srv, uint64_t ticket, double *latency_ms);
+/* stats[8]: batches launched, requests in them, snapshots completed,
+ * requests waiting, busy lanes, pool bytes reserved, pool bytes, largest
+ * free range. */
+int szsel_server_stats(const szsel_server *srv, uint64_t *stats);
+const char *szsel_server_last_error(const szsel_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,9 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
 
 void batch_destroy(BatchState *bs);
 
+// CU count of the context's device.
+int ctx_ncu(const szsel_ctx *ctx);
+
 // Device bytes held by a batch state (0 for NULL).
 size_t batch_state_bytes(const BatchState *bs);
 

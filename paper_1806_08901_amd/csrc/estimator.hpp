@@ -848,23 +848,20 @@ __device__ inline double lorenzo_row(const Rows<T, D> &s, int xi) {
 template <typename T>
 __device__ inline int quantize(T xv, double pred, double delta, double inv, double ebsz,
                                double &e2, double &ae) {
+  // branch-free: every lane computes the reconstruction and the tests only
+  // select the results (a code out of range computes with q = 0)
   const double xd = (double)xv;
   const double d = xd - pred;
   const double t = fabs(d) * inv + 0.5;
-  e2 = 0.0;
-  ae = 0.0;
-  if (t < (double)kRadius) {
-    int q = (int)floor(t);
-    if (d < 0.0) q = -q;
-    const T recon = (T)(pred + (double)q * delta);
-    const double e = xd - (double)recon;
-    if (fabs(e) <= ebsz) {
-      e2 = e * e;
-      ae = fabs(e);
-      return q + kRadius;
-    }
-  }
-  return 0;
+  const bool in = t < (double)kRadius;
+  int q = (int)floor(in ? t : 0.0);
+  if (d < 0.0) q = -q;
+  const T recon = (T)(pred + (double)q * delta);
+  const double e = xd - (double)recon;
+  const bool ok = in && fabs(e) <= ebsz;
+  e2 = ok ? e * e : 0.0;
+  ae = ok ? fabs(e) : 0.0;
+  return ok ? q + kRadius : 0;
 }
 
 // Adds one to the histogram bin of `code` for every lane with `want`.  The
@@ -922,18 +919,28 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
     Rows<T, D> sc = sn;
     if (rd + 1 < rounds) sn = load_rows<T, D, VEC>(r, j + kWaves * BPW, q);
     rows_mask<T, D>(sc);
-    double e2[4];
+    // the 4 points' predictions and codes first (independent chains the
+    // compiler can interleave), then their histogram updates
+    double e2[4], ae[4];
+    int code[4];
 #pragma unroll
     for (int xi = 0; xi < 4; xi++) {
-      double ae = 0.0;
       e2[xi] = 0.0;
-      const int code =
-          active ? quantize<T>(sc.v[0][xi + 1], lorenzo_row<T, D>(sc, xi), delta, inv, ebsz, e2[xi], ae) : 0;
-      hist_add(active && code != 0, code, s_hist, region, s_n);
+      ae[xi] = 0.0;
+      code[xi] = quantize<T>(sc.v[0][xi + 1], lorenzo_row<T, D>(sc, xi), delta, inv, ebsz, e2[xi], ae[xi]);
+      if (!active) {
+        code[xi] = 0;
+        e2[xi] = 0.0;
+        ae[xi] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int xi = 0; xi < 4; xi++) {
+      hist_add(active && code[xi] != 0, code[xi], s_hist, region, s_n);
       if (active) {
-        acc.a += code == 0 ? 1u : 0u;
-        acc.maxerr = fmax(acc.maxerr, ae);
-        if (r.dbg_codes) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code;
+        acc.a += code[xi] == 0 ? 1u : 0u;
+        acc.maxerr = fmax(acc.maxerr, ae[xi]);
+        if (r.dbg_codes) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code[xi];
       }
     }
     double bsse = (e2[0] + e2[1]) + (e2[2] + e2[3]);

@@ -70,6 +70,8 @@ int hip_fail(szsel_ctx *c, hipError_t e, const char *what) {
 
 namespace szsel {
 
+int ctx_ncu(const szsel_ctx *ctx) { return ctx ? ctx->ncu : 256; }
+
 int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
                  int dtype, double eb, int eb_mode, const int32_t *stride, const Tune &tu,
                  ReqDesc &r) {

@@ -1,0 +1,347 @@
+// Serving engine: continuous batching of snapshots of fields.
+//
+// The caller (the producer loop) owns a device pool.  A snapshot is admitted
+// by reserving its bytes in the pool (first-fit arena over 256-byte
+// granules); the producer writes its fields there and submits its requests.
+// Admitted requests wait in one FIFO.  The engine has L lanes, each a stream
+// with its own batch workspace: whenever a lane is free and requests are
+// waiting, the lane takes up to kServeBatch of them (from any number of
+// snapshots) as one batch.  Lanes run concurrently, so requests that arrive
+// while others are on the GPU start as soon as a lane frees up and overlap
+// them.  A snapshot completes when all of its requests have; its pool range
+// is then released, which may admit the next snapshot.
+//
+// Single-threaded: every call comes from the same host thread.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "batch.hpp"
+#include "launch.hpp"
+#include "szsel.h"
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t kGranule = 256;
+constexpr int kServeBatch = 64;  // requests per lane batch (bounds a lane's workspace)
+
+// First-fit allocator over [0, size) in granules, coalescing on release.
+struct Arena {
+  size_t size = 0, used = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(size_t bytes) {
+    size = bytes / kGranule * kGranule;
+    used = 0;
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t &off) {
+    const size_t want = (bytes + kGranule - 1) / kGranule * kGranule;
+    if (want == 0) return false;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < want) continue;
+      off = it->first;
+      const size_t rest = it->second - want;
+      free_.erase(it);
+      if (rest) free_[off + want] = rest;
+      used += want;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    const size_t len = (bytes + kGranule - 1) / kGranule * kGranule;
+    used -= len;
+    auto next = free_.lower_bound(off);
+    size_t o = off, l = len;
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == o) {
+        o = prev->first;
+        l += prev->second;
+        free_.erase(prev);
+      }
+    }
+    next = free_.lower_bound(o + l);
+    if (next != free_.end() && next->first == o + l) {
+      l += next->second;
+      free_.erase(next);
+    }
+    free_[o] = l;
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto &f : free_) m = std::max(m, f.second);
+    return m;
+  }
+};
+
+struct Snapshot {
+  size_t off = 0, bytes = 0;
+  bool submitted = false, done = false;
+  int remaining = 0;
+  szsel_result *out = nullptr;
+  hipEvent_t ready = nullptr;  // producer's writes are complete
+  double t_submit = 0.0, t_done = 0.0;
+};
+
+struct Pending {
+  uint64_t ticket;
+  int index;  // request index within its snapshot
+  szsel_request req;
+};
+
+struct Lane {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  szsel::BatchState *bs = nullptr;
+  szsel_result *res = nullptr;  // pinned, kServeBatch results
+  std::vector<std::pair<uint64_t, int>> parts;  // (ticket, index) of each request of the batch
+  uint64_t seq = 0;  // launch order
+  bool busy = false;
+};
+
+}  // namespace
+
+struct szsel_server {
+  szsel_ctx *ctx = nullptr;
+  int ncu = 256;
+  char *pool = nullptr;
+  Arena arena;
+  std::vector<Lane> lanes;
+  std::deque<Pending> queue;
+  std::map<uint64_t, Snapshot> snaps;
+  uint64_t next_ticket = 1;
+  std::string err;
+  szsel::BatchOptions bopt;  // eager launches: served batches rarely repeat a shape
+  size_t lane_budget = (size_t)4 << 30;
+  // statistics
+  uint64_t batches = 0, batched_requests = 0, snapshots_done = 0, launches = 0;
+};
+
+namespace {
+
+int sfail(szsel_server *s, int code, const std::string &m) {
+  s->err = m;
+  return code;
+}
+
+// Retires finished lanes: distributes their results, completes snapshots
+// and releases their pool ranges.  Returns the number of snapshots
+// completed.
+int retire(szsel_server *s, bool wait_one) {
+  int completed = 0;
+  if (wait_one) {  // the busy lane launched first
+    Lane *old = nullptr;
+    for (Lane &l : s->lanes)
+      if (l.busy && (!old || l.seq < old->seq)) old = &l;
+    if (old) (void)hipEventSynchronize(old->done);
+  }
+  for (Lane &l : s->lanes) {
+    if (!l.busy || hipEventQuery(l.done) != hipSuccess) continue;
+    const double t = now_ms();
+    for (size_t k = 0; k < l.parts.size(); k++) {
+      auto it = s->snaps.find(l.parts[k].first);
+      if (it == s->snaps.end()) continue;
+      Snapshot &sn = it->second;
+      sn.out[l.parts[k].second] = l.res[k];
+      if (--sn.remaining == 0) {
+        sn.done = true;
+        sn.t_done = t;
+        s->arena.release(sn.off, sn.bytes);
+        if (sn.ready) (void)hipEventDestroy(sn.ready);
+        sn.ready = nullptr;
+        s->snapshots_done++;
+        completed++;
+      }
+    }
+    l.parts.clear();
+    l.busy = false;
+  }
+  return completed;
+}
+
+// Packs waiting requests onto free lanes.
+int dispatch(szsel_server *s) {
+  for (Lane &l : s->lanes) {
+    if (s->queue.empty()) break;
+    if (l.busy) continue;
+    std::vector<szsel_request> reqs;
+    l.parts.clear();
+    std::vector<hipEvent_t> waits;
+    while (!s->queue.empty() && (int)reqs.size() < kServeBatch) {
+      Pending &p = s->queue.front();
+      Snapshot &sn = s->snaps[p.ticket];
+      if (sn.ready && (waits.empty() || waits.back() != sn.ready)) waits.push_back(sn.ready);
+      reqs.push_back(p.req);
+      l.parts.emplace_back(p.ticket, p.index);
+      s->queue.pop_front();
+    }
+    hipError_t e = hipSuccess;
+    for (hipEvent_t ev : waits)
+      if (e == hipSuccess) e = hipStreamWaitEvent(l.s, ev, 0);
+    if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("lane wait: ") + hipGetErrorString(e));
+    std::string msg;
+    const int rc = szsel::batch_run(s->ctx, s->ncu, l.bs, s->lane_budget, reqs.data(), (int)reqs.size(), l.res,
+                                    l.s, s->bopt, msg);
+    if (rc != SZSEL_OK) return sfail(s, rc, "batch: " + msg);
+    e = hipEventRecord(l.done, l.s);
+    if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    l.busy = true;
+    l.seq = ++s->launches;
+    s->batches++;
+    s->batched_requests += reqs.size();
+  }
+  return SZSEL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int szsel_server_create(szsel_server **out, szsel_ctx *ctx, void *pool, size_t pool_bytes, int lanes,
+                        size_t lane_workspace_bytes) {
+  if (!out) return SZSEL_EINVAL;
+  *out = nullptr;
+  if (lanes < 0 || lanes > 16 || (ctx && (!pool || lanes < 1))) return SZSEL_EINVAL;
+  if ((uintptr_t)pool % kGranule) return SZSEL_EINVAL;
+  szsel_server *s = new (std::nothrow) szsel_server();
+  if (!s) return SZSEL_ENOMEM;
+  s->ctx = ctx;
+  s->pool = (char *)pool;
+  s->arena.init(pool_bytes);
+  if (lane_workspace_bytes) s->lane_budget = lane_workspace_bytes;
+  s->bopt.graph = false;
+  if (ctx) {
+    s->ncu = szsel::ctx_ncu(ctx);
+    s->lanes.resize((size_t)lanes);
+    for (Lane &l : s->lanes) {
+      void *h = nullptr;
+      if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
+          hipHostMalloc(&h, sizeof(szsel_result) * kServeBatch, hipHostMallocDefault) != hipSuccess) {
+        szsel_server_destroy(s);
+        return SZSEL_EHIP;
+      }
+      l.res = (szsel_result *)h;
+    }
+  }
+  *out = s;
+  return SZSEL_OK;
+}
+
+void szsel_server_destroy(szsel_server *s) {
+  if (!s) return;
+  if (s->ctx) (void)hipDeviceSynchronize();
+  for (Lane &l : s->lanes) {
+    if (l.bs) szsel::batch_destroy(l.bs);
+    if (l.s) (void)hipStreamDestroy(l.s);
+    if (l.done) (void)hipEventDestroy(l.done);
+    if (l.res) (void)hipHostFree(l.res);
+  }
+  for (auto &kv : s->snaps)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  delete s;
+}
+
+int szsel_server_reserve(szsel_server *s, size_t bytes, void **dev_ptr, uint64_t *ticket) {
+  if (!s || !dev_ptr || !ticket || bytes == 0) return SZSEL_EINVAL;
+  if (bytes > s->arena.size) return sfail(s, SZSEL_ENOMEM, "snapshot larger than the pool");
+  size_t off = 0;
+  if (!s->arena.alloc(bytes, off)) return sfail(s, SZSEL_EBUSY, "pool full: wait for running snapshots");
+  const uint64_t t = s->next_ticket++;
+  Snapshot &sn = s->snaps[t];
+  sn.off = off;
+  sn.bytes = bytes;
+  *dev_ptr = s->pool + off;
+  *ticket = t;
+  return SZSEL_OK;
+}
+
+int szsel_server_cancel(szsel_server *s, uint64_t ticket) {
+  if (!s) return SZSEL_EINVAL;
+  auto it = s->snaps.find(ticket);
+  if (it == s->snaps.end() || it->second.submitted) return sfail(s, SZSEL_EINVAL, "no reservation to cancel");
+  s->arena.release(it->second.off, it->second.bytes);
+  s->snaps.erase(it);
+  return SZSEL_OK;
+}
+
+int szsel_server_submit(szsel_server *s, uint64_t ticket, const szsel_request *reqs, int n, szsel_result *out,
+                        void *producer_stream) {
+  if (!s || !s->ctx || n < 1 || !reqs || !out) return SZSEL_EINVAL;
+  auto it = s->snaps.find(ticket);
+  if (it == s->snaps.end() || it->second.submitted) return sfail(s, SZSEL_EINVAL, "unknown or already submitted ticket");
+  Snapshot &sn = it->second;
+  const char *lo = s->pool + sn.off, *hi = lo + sn.bytes;
+  for (int i = 0; i < n; i++) {
+    const szsel_request &q = reqs[i];
+    if (q.ndims < 1 || q.ndims > 3) return sfail(s, SZSEL_EINVAL, "request " + std::to_string(i) + ": bad ndims");
+    size_t b = q.dtype == SZSEL_F64 ? 8 : 4;
+    for (int k = 0; k < q.ndims; k++) b *= (size_t)(q.dims[k] > 0 ? q.dims[k] : 0);
+    const char *f = (const char *)q.field;
+    if (f < lo || f + b > hi)
+      return sfail(s, SZSEL_EINVAL, "request " + std::to_string(i) + ": field outside the snapshot's reservation");
+  }
+  if (producer_stream) {
+    hipError_t e = hipEventCreateWithFlags(&sn.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(sn.ready, (hipStream_t)producer_stream);
+    if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("producer event: ") + hipGetErrorString(e));
+  }
+  sn.submitted = true;
+  sn.remaining = n;
+  sn.out = out;
+  sn.t_submit = now_ms();
+  for (int i = 0; i < n; i++) s->queue.push_back(Pending{ticket, i, reqs[i]});
+  return dispatch(s);
+}
+
+int szsel_server_progress(szsel_server *s, int wait) {
+  if (!s || !s->ctx) return SZSEL_EINVAL;
+  bool busy = false;
+  for (Lane &l : s->lanes) busy = busy || l.busy;
+  int done = retire(s, wait && busy);
+  const int rc = dispatch(s);
+  if (rc != SZSEL_OK) return rc;
+  return done;
+}
+
+int szsel_server_status(szsel_server *s, uint64_t ticket, double *latency_ms) {
+  if (!s) return SZSEL_EINVAL;
+  auto it = s->snaps.find(ticket);
+  if (it == s->snaps.end()) return sfail(s, SZSEL_EINVAL, "unknown ticket");
+  if (!it->second.done) return 0;
+  if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+  s->snaps.erase(it);
+  return 1;
+}
+
+int szsel_server_stats(const szsel_server *s, uint64_t *stats) {
+  if (!s || !stats) return SZSEL_EINVAL;
+  size_t pending = s->queue.size(), busy = 0;
+  for (const Lane &l : s->lanes) busy += l.busy ? 1 : 0;
+  stats[0] = s->batches;
+  stats[1] = s->batched_requests;
+  stats[2] = s->snapshots_done;
+  stats[3] = pending;
+  stats[4] = busy;
+  stats[5] = s->arena.used;
+  stats[6] = s->arena.size;
+  stats[7] = s->arena.largest();
+  return SZSEL_OK;
+}
+
+const char *szsel_server_last_error(const szsel_server *s) { return s ? s->err.c_str() : "no server"; }
+
+}  // extern "C"

@@ -64,7 +64,10 @@ RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
 _SINGLE = ("szsel_estimate_sz", "szsel_estimate_zfp", "szsel_select", "szsel_select_fixed_eb")
 EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szsel_last_error",
                      "szsel_stride_for_rate", "szsel_set_option", "szsel_set_debug",
-                     "szsel_profile_read")
+                     "szsel_profile_read", "szsel_server_create", "szsel_server_destroy",
+                     "szsel_server_reserve", "szsel_server_cancel", "szsel_server_submit",
+                     "szsel_server_progress", "szsel_server_status", "szsel_server_stats",
+                     "szsel_server_last_error")
 
 _lib = None
 
@@ -92,6 +95,17 @@ def load_library(path: str = LIB_PATH):
     L.szsel_set_option.argtypes = [P, C.c_int, C.c_double]
     L.szsel_set_debug.argtypes = [P, C.POINTER(Debug)]
     L.szsel_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.szsel_server_create.argtypes = [C.POINTER(C.c_void_p), P, P, C.c_size_t, C.c_int, C.c_size_t]
+    L.szsel_server_destroy.argtypes = [P]
+    L.szsel_server_destroy.restype = None
+    L.szsel_server_reserve.argtypes = [P, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
+    L.szsel_server_cancel.argtypes = [P, C.c_uint64]
+    L.szsel_server_submit.argtypes = [P, C.c_uint64, C.POINTER(Request), C.c_int, C.POINTER(Result), P]
+    L.szsel_server_progress.argtypes = [P, C.c_int]
+    L.szsel_server_status.argtypes = [P, C.c_uint64, C.POINTER(C.c_double)]
+    L.szsel_server_stats.argtypes = [P, C.POINTER(C.c_uint64)]
+    L.szsel_server_last_error.argtypes = [P]
+    L.szsel_server_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -270,3 +284,94 @@ class Context:
             return out
         s.synchronize()
         return [_as_dict(out[i]) for i in range(n)]
+
+
+class Server:
+    """Continuous-batching serving engine (szsel_server_*): snapshots are
+    admitted by reserving their bytes in `pool` (a device uint8 tensor the
+    caller owns), written there by the producer, then submitted.
+
+    With ctx=None only the admission calls work (bookkeeping, no device):
+    pass pool_bytes and no pool."""
+
+    STATS = ("batches", "batched_requests", "snapshots_done", "waiting_requests", "busy_lanes",
+             "pool_reserved", "pool_bytes", "largest_free")
+
+    def __init__(self, ctx=None, pool=None, lanes: int = 4, lane_workspace_bytes: int = 0,
+                 pool_bytes: int = None):
+        self.lib = load_library()
+        self.ctx = ctx
+        self.pool = pool
+        base = pool.data_ptr() if pool is not None else 0
+        nbytes = pool.numel() * pool.element_size() if pool is not None else int(pool_bytes or 0)
+        self.base = base
+        h = C.c_void_p()
+        rc = self.lib.szsel_server_create(C.byref(h), ctx.h if ctx is not None else None,
+                                          C.c_void_p(base) if base else None, nbytes,
+                                          lanes if ctx is not None else 0, lane_workspace_bytes)
+        if rc != 0:
+            raise SzselError("szsel_server_create failed with %d" % rc)
+        self.h = h
+        self._outs = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.szsel_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self):
+        return self.lib.szsel_server_last_error(self.h).decode()
+
+    def reserve(self, nbytes: int):
+        """(offset in the pool, ticket), or None while the pool lacks room."""
+        p = C.c_void_p()
+        t = C.c_uint64()
+        rc = self.lib.szsel_server_reserve(self.h, int(nbytes), C.byref(p), C.byref(t))
+        if rc == -5:  # SZSEL_EBUSY
+            return None
+        if rc != 0:
+            raise SzselError("szsel_server_reserve failed (%d): %s" % (rc, self._err()))
+        return (p.value or 0) - self.base, t.value
+
+    def cancel(self, ticket: int):
+        rc = self.lib.szsel_server_cancel(self.h, ticket)
+        if rc != 0:
+            raise SzselError("szsel_server_cancel failed (%d): %s" % (rc, self._err()))
+
+    def submit(self, ticket: int, items, stream=None):
+        reqs = self.ctx.make_requests(items)
+        n = len(reqs)
+        out = (Result * n)()
+        self._outs[ticket] = out
+        sp = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        rc = self.lib.szsel_server_submit(self.h, ticket, reqs, n, out, sp)
+        if rc != 0:
+            raise SzselError("szsel_server_submit failed (%d): %s" % (rc, self._err()))
+
+    def progress(self, wait: bool = False) -> int:
+        rc = self.lib.szsel_server_progress(self.h, 1 if wait else 0)
+        if rc < 0:
+            raise SzselError("szsel_server_progress failed (%d): %s" % (rc, self._err()))
+        return rc
+
+    def status(self, ticket: int):
+        """None while the snapshot runs; else (results, submit-to-done ms)."""
+        lat = C.c_double()
+        rc = self.lib.szsel_server_status(self.h, ticket, C.byref(lat))
+        if rc < 0:
+            raise SzselError("szsel_server_status failed (%d): %s" % (rc, self._err()))
+        if rc == 0:
+            return None
+        out = self._outs.pop(ticket)
+        return [_as_dict(out[i]) for i in range(len(out))], lat.value
+
+    def stats(self) -> dict:
+        v = (C.c_uint64 * 8)()
+        self.lib.szsel_server_stats(self.h, v)
+        return {k: int(v[i]) for i, k in enumerate(self.STATS)}
