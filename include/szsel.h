@@ -184,8 +184,9 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   results do not depend on it.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
  *   HIP graph and replays it while the batch shape repeats.
- * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the batch
- *   schedule without autotuning (and the autotuner's starting point): SZ
+ * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the schedule
+ *   of single-request calls and of batches without autotuning (and the
+ *   autotuner's starting point): SZ
  *   workgroups per request in quarters of the CU count (1..256, default 16),
  *   smallest ZFP chunk in sampled blocks (a power of two 64..65536, default
  *   64), range workgroups per CU and request (1..64, default 2); 0 restores

@@ -733,6 +733,7 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
 template <typename T, int D>
 struct Rows {
   static constexpr int NR = 1 << (D - 1);
+  static constexpr uint32_t kAll = (2u << NR) - 1u;  // every row and x - 1 inside the field
   T v[NR][5];     // [m][x + 1], m: bit k set = displaced along slower axis k
   uint32_t keep;  // bit m: row m lies inside the field; bit NR: x - 1 does
 };
@@ -897,6 +898,53 @@ __device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t 
   }
 }
 
+// Histogram update for the 4 codes of a lane (code 0 = unpredictable, not
+// counted here).  Codes in the LDS window: when all 4 are equal (the common
+// case on smooth data) one atomic adds 4, else one atomic per code; the LDS
+// serialises lanes that hit one bin, off the vector pipeline.  Codes outside
+// the window are appended to the workgroup's overflow region, numbered by
+// one LDS atomic per wave (the wave's first such lane reserves room for all).
+__device__ inline void hist_add4(const int (&code)[4], bool active, uint32_t *s_hist, uint16_t *region,
+                                 uint32_t *s_n) {
+  bool out[4];
+  bool anyout = false;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int wi = code[k] - kHistLo;
+    out[k] = active && code[k] != 0 && (wi < 0 || wi >= kHistWin);
+    anyout = anyout || out[k];
+  }
+  if (active) {
+    const bool same = code[0] == code[1] && code[0] == code[2] && code[0] == code[3];
+    const int w0 = code[0] - kHistLo;
+    if (same && code[0] != 0 && !out[0]) {
+      atomicAdd(&s_hist[w0], 4u);
+    } else if (!same) {
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (code[k] != 0 && !out[k]) atomicAdd(&s_hist[code[k] - kHistLo], 1u);
+    }
+  }
+  if (__ballot(anyout)) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t mine = (uint32_t)out[0] + (uint32_t)out[1] + (uint32_t)out[2] + (uint32_t)out[3];
+    // exclusive prefix of the lanes' counts (Hillis-Steele)
+    uint32_t inc = mine;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d);
+      if (lane >= d) inc += o;
+    }
+    const uint32_t total = (uint32_t)__shfl(inc, kWave - 1);
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(s_n, total);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + inc - mine;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (out[k]) region[base++] = (uint16_t)code[k];
+  }
+}
+
 // One tile of the SZ side (tile blocks starting at `base`): each round the
 // 4 waves take 4 * 64 / 4^(D-1) consecutive blocks; the next round's rows
 // are loaded while the current round is processed.  Per-block squared
@@ -918,7 +966,9 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
     const bool active = j < r.nblk;
     Rows<T, D> sc = sn;
     if (rd + 1 < rounds) sn = load_rows<T, D, VEC>(r, j + kWaves * BPW, q);
-    rows_mask<T, D>(sc);
+    // only rows at the field's low faces (or past the last block) need
+    // zeroing; most waves have none
+    if (__ballot(sc.keep != Rows<T, D>::kAll)) rows_mask<T, D>(sc);
     // the 4 points' predictions and codes first (independent chains the
     // compiler can interleave), then their histogram updates
     double e2[4], ae[4];
@@ -934,14 +984,15 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
         ae[xi] = 0.0;
       }
     }
+    hist_add4(code, active, s_hist, region, s_n);
 #pragma unroll
     for (int xi = 0; xi < 4; xi++) {
-      hist_add(active && code[xi] != 0, code[xi], s_hist, region, s_n);
-      if (active) {
-        acc.a += code[xi] == 0 ? 1u : 0u;
-        acc.maxerr = fmax(acc.maxerr, ae[xi]);
-        if (r.dbg_codes) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code[xi];
-      }
+      acc.a += code[xi] == 0 && active ? 1u : 0u;
+      acc.maxerr = fmax(acc.maxerr, ae[xi]);
+    }
+    if (r.dbg_codes && active) {
+#pragma unroll
+      for (int xi = 0; xi < 4; xi++) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code[xi];
     }
     double bsse = (e2[0] + e2[1]) + (e2[2] + e2[3]);
     if constexpr (LPB > 1) bsse = group_tree_first<LPB>(bsse);

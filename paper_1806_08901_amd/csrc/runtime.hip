@@ -214,7 +214,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   if (!ctx) return SZSEL_EINVAL;
   if (!out) return fail(ctx, SZSEL_EINVAL, "out is NULL");
   ReqDesc r;
-  int rc = plan_request(ctx, op, field, dims, nd, dtype, eb, eb_mode, stride, Tune(), r);
+  int rc = plan_request(ctx, op, field, dims, nd, dtype, eb, eb_mode, stride, ctx->bopt.fixed, r);
   if (rc != SZSEL_OK) return rc;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
