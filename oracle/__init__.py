@@ -41,6 +41,7 @@ class Result(C.Structure):
         ("sz_maxerr", C.c_double), ("sz_sse", C.c_double),
         ("sz_values", C.c_uint64), ("sz_unpredictable", C.c_uint64),
         ("chosen_eb", C.c_double),
+        ("sz_huffman_bits", C.c_uint64), ("sz_huffman_bitrate", C.c_double),
     ]
 
 
@@ -71,7 +72,7 @@ def lib():
         L = C.CDLL(build())
         P, I64P, I32P = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
         L.orc_run.argtypes = [C.c_int, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
-                              C.c_double, C.POINTER(Result), C.POINTER(Dump)]
+                              C.c_double, C.c_int, C.POINTER(Result), C.POINTER(Dump)]
         L.orc_range.argtypes = [P, C.c_int64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_num_sampled_blocks.argtypes = [I64P, C.c_int, I32P]
         L.orc_num_sampled_blocks.restype = C.c_int64
@@ -101,6 +102,8 @@ def lib():
         L.orc_tree_sum.restype = C.c_double
         L.orc_entropy.argtypes = [C.POINTER(C.c_uint32), C.c_int64, C.c_uint64]
         L.orc_entropy.restype = C.c_double
+        L.orc_huffman_bits.argtypes = [C.POINTER(C.c_uint32), C.c_int64]
+        L.orc_huffman_bits.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -122,7 +125,7 @@ def result_dict(r: Result) -> dict:
 
 
 def run(op: int, field: np.ndarray, eb: float, eb_mode: int = EB_REL, stride=None,
-        sz_offset: float = 0.5, dump: bool = False):
+        sz_offset: float = 0.5, dump: bool = False, huffman: int = 0):
     """Run the estimator on a C-order numpy field.  Returns (result dict, dump dict|None)."""
     field = np.ascontiguousarray(field)
     nd = field.ndim
@@ -146,15 +149,21 @@ def run(op: int, field: np.ndarray, eb: float, eb_mode: int = EB_REL, stride=Non
         }
         dp = Dump(*[arrays[k].ctypes.data for k, _ in Dump._fields_])
     rc = lib().orc_run(op, field.ctypes.data, _ptr(dims, C.c_int64), nd, _dtype_code(field),
-                       float(eb), eb_mode, _ptr(st, C.c_int32), float(sz_offset), C.byref(out),
+                       float(eb), eb_mode, _ptr(st, C.c_int32), float(sz_offset), int(huffman), C.byref(out),
                        C.byref(dp) if dp is not None else None)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return result_dict(out), arrays
 
 
-def select(field, eb, eb_mode=EB_REL, stride=None, sz_offset=0.5, dump=False):
-    return run(OP_SELECT, field, eb, eb_mode, stride, sz_offset, dump)
+def select(field, eb, eb_mode=EB_REL, stride=None, sz_offset=0.5, dump=False, huffman=0):
+    return run(OP_SELECT, field, eb, eb_mode, stride, sz_offset, dump, huffman)
+
+
+def huffman_bits(hist) -> int:
+    """Total bits of an optimal prefix code for the symbol counts `hist`."""
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    return int(lib().orc_huffman_bits(h.ctypes.data_as(C.POINTER(C.c_uint32)), h.size))
 
 
 # ---- pieces for the pin tests ----

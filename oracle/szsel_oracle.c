@@ -435,16 +435,73 @@ double orc_entropy(const uint32_t *hist, int64_t nbins, uint64_t n) {
   return log2((double)n) - s / (double)n;
 }
 
+/* Exact cost of the entropy-coding stage that the +0.5 bits/value offset of
+ * Section 6.2 stands in for: the code histogram is Huffman coded (Section
+ * 3's Stage III), and an optimal prefix code spends sum_i h_i L_i bits, which
+ * equals the sum of the internal node weights of the Huffman tree.  The
+ * minimum is unique even though the tree is not.  Binary min-heap of 64-bit
+ * node weights. */
+static void heap_push(uint64_t *h, int64_t *n, uint64_t v) {
+  int64_t i = (*n)++;
+  h[i] = v;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h[p] <= h[i]) break;
+    uint64_t t = h[p];
+    h[p] = h[i];
+    h[i] = t;
+    i = p;
+  }
+}
+
+static uint64_t heap_pop(uint64_t *h, int64_t *n) {
+  uint64_t top = h[0];
+  h[0] = h[--(*n)];
+  int64_t i = 0;
+  for (;;) {
+    int64_t l = 2 * i + 1, r = l + 1, m = i;
+    if (l < *n && h[l] < h[m]) m = l;
+    if (r < *n && h[r] < h[m]) m = r;
+    if (m == i) break;
+    uint64_t t = h[m];
+    h[m] = h[i];
+    h[i] = t;
+    i = m;
+  }
+  return top;
+}
+
+uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins) {
+  uint64_t *h = (uint64_t *)malloc((size_t)(nbins > 0 ? nbins : 1) * sizeof(uint64_t));
+  int64_t n = 0;
+  uint64_t total = 0;
+  for (int64_t i = 0; i < nbins; i++)
+    if (hist[i]) {
+      heap_push(h, &n, hist[i]);
+      total += hist[i];
+    }
+  uint64_t cost = 0;
+  if (n == 1) cost = total; /* one symbol: 1 bit each */
+  while (n > 1) {
+    uint64_t a = heap_pop(h, &n), b = heap_pop(h, &n);
+    cost += a + b;
+    heap_push(h, &n, a + b);
+  }
+  free(h);
+  return cost;
+}
+
 /* ------------------------------------------------------------------ */
 /* The estimator (Algorithm 1)                                          */
 /* ------------------------------------------------------------------ */
 
 int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,
-            int eb_mode, const int32_t *stride, double sz_offset, orc_result *out,
+            int eb_mode, const int32_t *stride, double sz_offset, int huffman, orc_result *out,
             orc_dump *dump) {
   if (!out || !field || !dims || !stride) return -1;
   if (nd < 1 || nd > 3 || (dtype != ORC_F32 && dtype != ORC_F64)) return -1;
   if (op < ORC_OP_SZ || op > ORC_OP_FIXED_EB) return -1;
+  if (huffman < 0 || huffman > 2) return -1;
   if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != ORC_EB_ABS && eb_mode != ORC_EB_REL)) return -1;
   for (int k = 0; k < nd; k++)
     if (dims[k] < 1 || stride[k] < 1) return -1;
@@ -593,12 +650,21 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
     out->sz_psnr_model = 20.0 * log10(vr / delta) + 10.0 * log10(12.0);
     out->sz_psnr_measured =
         out->sz_mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(out->sz_mse) : INFINITY;
+    double br_sel = br; /* hist[0] counts the unpredictable points (code 0) */
+    if (huffman) {
+      const uint64_t hb = orc_huffman_bits(hist, NBINS);
+      double hbr = (double)hb / (double)nvals;
+      hbr = hbr + ((double)unpred * (double)W) / (double)nvals;
+      out->sz_huffman_bits = hb;
+      out->sz_huffman_bitrate = hbr;
+      if (huffman == 2) br_sel = hbr;
+    }
     if (dump && dump->hist) memcpy(dump->hist, hist, NBINS * sizeof(uint32_t));
     free(hist);
 
     /* lines 10-14: the lower estimated bit-rate wins; ties go to ZFP */
     if (selecting) {
-      out->choice = out->sz_bitrate < br_zfp ? 0 : 1;
+      out->choice = br_sel < br_zfp ? 0 : 1;
       out->chosen_eb = out->choice == 0 ? eb_sz : eb_abs;
       if (eb_sz > eb_abs) out->flags |= ORC_FLAG_EB_EXCEEDS;
     }

@@ -47,6 +47,9 @@ typedef struct {
   uint64_t sz_values, sz_unpredictable;
   /* selection (Algorithm 1) */
   double chosen_eb;
+  /* exact Huffman cost of the code histogram (when requested) */
+  uint64_t sz_huffman_bits;
+  double sz_huffman_bitrate;
 } orc_result;
 
 /* Optional per-sample outputs; every pointer may be NULL. */
@@ -62,10 +65,18 @@ typedef struct {
 /* Whole estimator: range, sampling, ZFP side and/or SZ side, selection.
  * op: ORC_OP_SZ (delta = 2 eb_abs), ORC_OP_ZFP, ORC_OP_SELECT (Algorithm 1),
  * ORC_OP_FIXED_EB (both sides at the same eb_abs, pick the lower bit-rate).
- * Returns 0, or -1 on invalid arguments. */
+ * huffman: 0 = no Huffman cost; 1 = also report the exact Huffman cost of
+ * the code histogram; 2 = report it and select with it as BR_sz (in place of
+ * entropy + offset).  Returns 0, or -1 on invalid arguments. */
 int orc_run(int op, const void *field, const int64_t *dims, int ndims, int dtype,
-            double eb, int eb_mode, const int32_t *stride, double sz_offset,
+            double eb, int eb_mode, const int32_t *stride, double sz_offset, int huffman,
             orc_result *out, orc_dump *dump);
+
+/* Total bits of an optimal prefix code for the symbol counts hist[0..nbins)
+ * (Huffman): the sum of the internal node weights of a tree built by
+ * repeatedly merging the two lightest nodes.  A single symbol gets 1 bit per
+ * occurrence; no symbol, 0. */
+uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins);
 
 /* ---- pieces exposed for the pin tests ---- */
 int orc_range(const void *field, int64_t n, int dtype, double *vmin, double *vmax);
