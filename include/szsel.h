@@ -73,7 +73,11 @@ enum {
   SZSEL_FLAG_ZERO_MSE = 4,    /* ZFP reproduced the samples exactly: delta = 2 eb_abs */
   SZSEL_FLAG_EB_EXCEEDS = 8,  /* the SZ bound delta/2 is larger than eb_abs */
   SZSEL_FLAG_NO_BLOCKS = 16,  /* no full 4^d block: nothing estimated, choice = SZ */
-  SZSEL_FLAG_BAD_EB = 32      /* eb_rel * value range is 0 or not finite */
+  SZSEL_FLAG_BAD_EB = 32,     /* eb_rel * value range is 0 or not finite */
+  SZSEL_FLAG_NO_HUFFMAN = 64  /* Huffman cost requested but not computed: more than
+                                 8192 codes occur 4096 times or more (never with at
+                                 most 2^25 sampled values), or the merge holds more
+                                 than 8192 distinct pending node weights at once */
 };
 
 /* Result of one request.  Bit-rates are bits per value, PSNRs in dB, MSEs in
@@ -94,6 +98,11 @@ typedef struct {
   double sz_psnr_model, sz_psnr_measured, sz_mse, sz_maxerr, sz_sse;
   uint64_t sz_values, sz_unpredictable;
   double chosen_eb;           /* error bound handed to the chosen compressor */
+  /* exact Huffman cost of the SZ code histogram (SZSEL_OPT_HUFFMAN): total
+   * bits of an optimal prefix code for the codes, and that per value plus
+   * W raw bits per unpredictable point; 0 when not requested */
+  uint64_t sz_huffman_bits;
+  double sz_huffman_bitrate;
 } szsel_result;
 
 /* One request of a batch (szsel_select_batch). */
@@ -195,10 +204,16 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   default 1; 0 restores it): the requests are dealt to that many groups
  *   (requests on one field stay together), each running on its own stream,
  *   and group g starts its range scans when group g-1's are done, so the
- *   scans of later groups overlap the sampled passes of earlier ones. */
+ *   scans of later groups overlap the sampled passes of earlier ones.
+ * SZSEL_OPT_HUFFMAN: 0 (default) no Huffman cost; 1 also computes the exact
+ *   Huffman cost of the SZ code histogram (the entropy-coding stage that the
+ *   0.5 bits/value offset of Section 6.2 stands in for) into
+ *   sz_huffman_bits / sz_huffman_bitrate; 2 computes it and selects with it
+ *   as BR_sz in place of entropy + offset.  The minimum cost is unique, so
+ *   the result does not depend on how the tree is built. */
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
-       SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8 };
+       SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* Phase timers: synchronises the recorded events and returns, per phase

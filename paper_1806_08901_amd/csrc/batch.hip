@@ -152,7 +152,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
         case kBatchZfp: c = r.op != SZSEL_OP_SZ ? (uint32_t)r.nzfp : 0u; break;
         case kBatchSz: c = r.op != SZSEL_OP_ZFP ? (uint32_t)r.nsz : 0u; break;
         case kBatchOvf: c = r.op != SZSEL_OP_ZFP ? (uint32_t)(kOvfSlices * kOvfRanges) : 0u; break;
-        default: c = r.op != SZSEL_OP_ZFP ? (uint32_t)kEntWgs : 0u; break;
+        case kBatchEnt: c = r.op != SZSEL_OP_ZFP ? (uint32_t)kEntWgs : 0u; break;
+        default: c = r.op != SZSEL_OP_ZFP && r.huff ? 1u : 0u; break;
       }
       p.first[(size_t)ps * (n + 1) + k] = acc;
       acc += c;

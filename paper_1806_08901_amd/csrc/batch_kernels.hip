@@ -135,6 +135,15 @@ __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *tab, const uin
 }
 
 template <typename T, int D>
+__global__ __launch_bounds__(kHuffThreads) void kb_huff(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+  __shared__ HuffLds S;
+  __shared__ uint32_t s_first[kMaxBatch + 1];
+  int local;
+  const ReqDesc &r = tab[batch_item(first, c0, c1, s_first, local)];
+  if (!skip_request(r.st)) huff_wg<T, D>(r, S);
+}
+
+template <typename T, int D>
 static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
   const dim3 grid(a.grid ? a.grid : a.items);
   switch (a.pass) {
@@ -156,8 +165,11 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
     case kBatchOvf:
       hipLaunchKernelGGL((kb_ovf<D>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
-    default:
+    case kBatchEnt:
       hipLaunchKernelGGL((kb_ent<T, D>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
+      break;
+    default:
+      hipLaunchKernelGGL((kb_huff<T, D>), grid, dim3(kHuffThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
   }
   return hipGetLastError();

@@ -37,6 +37,10 @@ constexpr int kMaxBatch = 1024;        // requests per batch
 constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
 enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
+constexpr int kHuffThreads = 1024;     // threads of the Huffman pass (one workgroup per request)
+constexpr int kHuffSmall = 4096;       // counts below this are tallied by value
+constexpr int kHuffBig = 8192;         // at most this many counts of kHuffSmall or more
+constexpr int kHuffQueue = 8192;       // runs of merged nodes waiting at once
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
@@ -132,6 +136,8 @@ struct ReqDesc {
   int32_t vec;     // 1: every row of 4 values starts 16-byte aligned (vector loads)
   int32_t nshare;  // batches: requests right after this one in the table that share its range scan
   int32_t nhc;     // global histogram copies in use (power of two <= kHistCopies)
+  int32_t huff;    // 0 no Huffman cost, 1 report it, 2 report and select with it
+  int32_t pad2;
   ReqState *st;
   PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;
@@ -140,6 +146,7 @@ struct ReqDesc {
   uint16_t *ovf;       // per SZ workgroup, sblk * 4^d codes that fell outside its LDS window
   uint32_t *ovf_hist;  // kOvfSlices dense 65536-bin counts of the overflow codes
   uint32_t *hist;      // kHistCopies x 65536 counts, left zeroed by the entropy pass
+  uint32_t *hfinal;    // the final 65536 counts, for the Huffman pass
   szsel_result *res;
   uint16_t *dbg_codes;
   uint32_t *dbg_zbits;

@@ -1201,6 +1201,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     }
   }
   if (bin0 == 0) h[0] = (uint32_t)unpred;  // code 0: the unpredictable points
+  if (r.huff) *(uint4 *)(r.hfinal + bin0) = make_uint4(h[0], h[1], h[2], h[3]);
   if (r.dbg_hist) {
 #pragma unroll
     for (int k = 0; k < kEntPerThread; k++) r.dbg_hist[bin0 + k] = h[k];
@@ -1255,7 +1256,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     put_u64(&res->sz_unpredictable, unpred);
     put_f64(&res->sz_psnr_model, 20.0 * log10(vr / delta) + 10.0 * log10(12.0));
     put_f64(&res->sz_psnr_measured, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
-    if (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) {
+    if ((r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB) && r.huff != 2) {
       const double br_zfp = get_f64(&res->zfp_bitrate);
       const int32_t choice = br < br_zfp ? 0 : 1;
       uint32_t flags = (uint32_t)get_u64((uint64_t *)&res->flags);
@@ -1264,6 +1265,249 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
       put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
     }
   }
+}
+
+// ===========================================================================
+// Exact Huffman cost of the code histogram (one workgroup per request)
+// ===========================================================================
+
+// The optimal prefix code's total length sum_i h_i L_i is the sum of the
+// internal node weights of a Huffman tree, and that minimum is unique, so
+// any tie-breaking gives the same cost.  The leaves are the nonzero bin
+// counts.  Counts below kHuffSmall are tallied by value (how many bins hold
+// count c), the others sorted (bitonic, in LDS).  The two-queue merge then
+// runs on runs of equal weights: the leaf runs in ascending order, and the
+// merged nodes, which are created in nondecreasing order, in a ring of runs
+// whose front and back stay in registers.  Taking the lighter front (leaves
+// on ties): a run of m >= 2 equal weights w pairs up at once into m/2 nodes
+// of weight 2w (its items stay the lightest while two remain); a single item
+// merges with the next lightest one.
+struct HuffLds {
+  uint32_t runs[kHuffSmall];  // bins per small count, then packed runs (m << 12 | w)
+  uint32_t big[kHuffBig];     // the counts >= kHuffSmall, sorted
+  uint64_t qw[kHuffQueue];    // merged-node runs: weight
+  uint32_t qm[kHuffQueue];    // and multiplicity
+  uint32_t nbig, nruns, leaves, wave[kHuffThreads / kWave];
+};
+static_assert(kHuffSmall == 4096, "small counts are packed in 12 bits");
+static_assert((kHuffQueue & (kHuffQueue - 1)) == 0, "ring size is a power of two");
+
+template <typename T, int D>
+__device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
+  constexpr int BS = 1 << (2 * D);
+  constexpr int NT = kHuffThreads;
+  constexpr int kPer = kHuffSmall / NT;
+  static_assert(kPer * NT == kHuffSmall, "each thread owns kPer small counts");
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1), wv = t / kWave;
+#pragma unroll
+  for (int k = 0; k < kPer; k++) S.runs[t * kPer + k] = 0;
+  if (t == 0) {
+    S.nbig = 0;
+    S.leaves = 0;
+  }
+  __syncthreads();
+  // tally: the k_ent pass left the final counts in hfinal
+  uint32_t leaves = 0;
+  for (int q = t; q < kBins / 4; q += NT) {
+    const uint4 v = ((const uint4 *)r.hfinal)[q];
+    const uint32_t c4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t c = c4[k];
+      if (!c) continue;
+      leaves++;
+      if (c < (uint32_t)kHuffSmall) {
+        atomicAdd(&S.runs[c], 1u);
+      } else {
+        const uint32_t i = atomicAdd(&S.nbig, 1u);
+        if (i < (uint32_t)kHuffBig) S.big[i] = c;
+      }
+    }
+  }
+  leaves = group_isum<kWave>(leaves);
+  if (lane == 0) atomicAdd(&S.leaves, leaves);
+  __syncthreads();
+  const uint32_t nbig = S.nbig;
+  const bool fits = nbig <= (uint32_t)kHuffBig;
+  if (fits) {
+    // bitonic sort of the large counts, padded with the largest value
+    uint32_t P = 1;
+    while (P < nbig) P <<= 1;
+    for (uint32_t i = nbig + t; i < P; i += NT) S.big[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = t; i < P; i += NT) {
+          const uint32_t l = i ^ j;
+          if (l > i) {
+            const uint32_t a = S.big[i], b = S.big[l];
+            if ((i & k) == 0 ? a > b : a < b) {
+              S.big[i] = b;
+              S.big[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // the small counts' runs in ascending count, packed in place: every
+    // thread reads its kPer tallies before any run is written
+    uint32_t m[kPer], occ = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+      m[k] = S.runs[t * kPer + k];
+      occ += m[k] ? 1u : 0u;
+    }
+    uint32_t inc = occ;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d);
+      if (lane >= d) inc += o;
+    }
+    if (lane == kWave - 1) S.wave[wv] = inc;
+    __syncthreads();
+    uint32_t pos = inc - occ;
+    for (int w = 0; w < wv; w++) pos += S.wave[w];
+#pragma unroll
+    for (int k = 0; k < kPer; k++)
+      if (m[k]) S.runs[pos++] = (m[k] << 12) | (uint32_t)(t * kPer + k);
+    if (t == NT - 1) S.nruns = pos;
+    __syncthreads();
+  }
+  if (t != 0) return;
+
+  // ---- the merge, on one thread ----
+  const uint32_t nruns = fits ? S.nruns : 0;
+  const uint32_t nleaf = nruns + (fits ? nbig : 0);
+  bool ok = fits;
+  uint64_t cost = 0, items = S.leaves;
+  // leaf runs: current (aw, am; am == 0 once they are used up) and the next
+  // one, loaded a run ahead
+  uint32_t ai = 0;
+  uint64_t aw = 0, am = 0, nw = 0, nm = 0;
+  auto fetch = [&]() {
+    if (ai < nruns) {
+      const uint32_t v = S.runs[ai];
+      nw = v & 0xFFFu;
+      nm = v >> 12;
+    } else if (ai < nleaf) {
+      nw = S.big[ai - nruns];
+      nm = 1;
+    } else {
+      nm = 0;
+    }
+    ai++;
+  };
+  auto next_leaf = [&]() {
+    aw = nw;
+    am = nm;
+    fetch();
+  };
+  // merged runs: qc entries from slot qh; the front (fw, fm) and, when
+  // qc >= 2, the back (bw, bm) live in registers, the ones between in LDS
+  uint64_t fw = 0, fm = 0, bw = 0, bm = 0;
+  uint32_t qh = 0, qc = 0;
+  auto push = [&](uint64_t w, uint64_t mult) {
+    if (qc == 0) {
+      fw = w;
+      fm = mult;
+      qc = 1;
+    } else if (qc == 1) {
+      if (fw == w) {
+        fm += mult;
+      } else {
+        bw = w;
+        bm = mult;
+        qc = 2;
+      }
+    } else if (bw == w) {
+      bm += mult;
+    } else if (qc == (uint32_t)kHuffQueue) {
+      ok = false;
+    } else {
+      const uint32_t slot = (qh + qc - 1) & (kHuffQueue - 1);
+      S.qw[slot] = bw;
+      S.qm[slot] = (uint32_t)bm;
+      bw = w;
+      bm = mult;
+      qc++;
+    }
+  };
+  auto pop = [&](uint64_t n) {
+    fm -= n;
+    if (fm) return;
+    qh = (qh + 1) & (kHuffQueue - 1);
+    qc--;
+    if (qc == 1) {
+      fw = bw;
+      fm = bm;
+    } else if (qc >= 2) {
+      fw = S.qw[qh];
+      fm = S.qm[qh];
+    }
+  };
+  if (ok) {
+    fetch();
+    next_leaf();
+  }
+  while (ok && items > 1) {
+    const bool leaf = am && (!qc || aw <= fw);
+    const uint64_t xw = leaf ? aw : fw, xm = leaf ? am : fm;
+    if (xm >= 2) {
+      const uint64_t k = xm >> 1;
+      cost += k * (xw << 1);
+      items -= k;
+      if (leaf) {
+        am -= k << 1;
+        if (!am) next_leaf();
+      } else {
+        pop(k << 1);
+      }
+      push(xw << 1, k);
+    } else {
+      if (leaf)
+        next_leaf();
+      else
+        pop(1);
+      const bool leaf2 = am && (!qc || aw <= fw);
+      const uint64_t yw = leaf2 ? aw : fw;
+      if (leaf2) {
+        if (!--am) next_leaf();
+      } else {
+        pop(1);
+      }
+      cost += xw + yw;
+      items--;
+      push(xw + yw, 1);
+    }
+  }
+  const uint64_t nv = (uint64_t)r.nblk * BS;
+  if (S.leaves == 1) cost = nv;  // one symbol: 1 bit each
+  ReqState *st = r.st;
+  szsel_result *res = r.res;
+  const uint64_t unpred = get_u64(&st->sz_unpred);
+  double hbr = (double)cost / (double)nv;
+  hbr = hbr + ((double)unpred * (double)Prec<T>::W) / (double)nv;
+  const uint64_t fc = get_u64((uint64_t *)&res->flags);
+  uint32_t flags = (uint32_t)fc;
+  uint32_t choice = (uint32_t)(fc >> 32);
+  if (ok) {
+    put_u64(&res->sz_huffman_bits, cost);
+    put_f64(&res->sz_huffman_bitrate, hbr);
+  } else {
+    flags |= SZSEL_FLAG_NO_HUFFMAN;
+  }
+  if (r.huff == 2 && (r.op == SZSEL_OP_SELECT || r.op == SZSEL_OP_FIXED_EB)) {
+    // select with the Huffman bit-rate (with entropy + offset when it is missing)
+    const double br = ok ? hbr : get_f64(&res->sz_bitrate);
+    const double br_zfp = get_f64(&res->zfp_bitrate);
+    const double eb_sz = get_f64(&st->eb_sz), eb_abs = get_f64(&st->eb_abs);
+    choice = br < br_zfp ? 0u : 1u;
+    if (eb_sz > eb_abs) flags |= SZSEL_FLAG_EB_EXCEEDS;
+    put_f64(&res->chosen_eb, choice == 0 ? eb_sz : eb_abs);
+  }
+  put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)choice << 32));
 }
 
 // Whole SZ pass of workgroup w (LDS window cleared on entry, flushed once at

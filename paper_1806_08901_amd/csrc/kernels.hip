@@ -4,6 +4,7 @@
 //   k_sz    : Lorenzo/quantization codes and their histogram (Section 5.1)
 //   k_ovf   : counts the codes that fell outside the SZ pass's LDS window
 //   k_ent   : entropy of the histogram, SZ bit-rate, selection (Eq. 5, Alg. 1)
+//   k_huff  : exact Huffman cost of the histogram (when asked for)
 // Passes with a cross-workgroup total end in a last-workgroup finalizer; a
 // request is a chain of launches on one stream with no host round trip.
 #include "estimator.hpp"
@@ -49,6 +50,13 @@ __global__ __launch_bounds__(kThreads) void k_ent(ReqDesc r) {
   ent_wg<T, D>(r, blockIdx.x, L);
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(kHuffThreads) void k_huff(ReqDesc r) {
+  __shared__ HuffLds S;
+  if (skip_request(r.st)) return;
+  huff_wg<T, D>(r, S);
+}
+
 static hipError_t mark(const hipEvent_t *ev, int k, hipStream_t s) {
   return ev ? hipEventRecord(ev[k], s) : hipSuccess;
 }
@@ -84,6 +92,11 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
     hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (r.huff) {
+      hipLaunchKernelGGL((k_huff<T, D>), dim3(1), dim3(kHuffThreads), 0, s, r);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   return mark(ev, 5, s);
 }
@@ -125,7 +138,7 @@ size_t request_fixed_bytes() {
   return align_up(sizeof(ReqState), 256) + align_up(sizeof(PassSync) * kPasses, 256) +
          align_up(sizeof(uint32_t) * kBins * kHistCopies, 256) + align_up(sizeof(szsel_result), 256) +
          parts_bytes(kEntWgs) + group_parts_bytes() * kPasses +
-         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
+         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256) + align_up(sizeof(uint32_t) * kBins, 256);
 }
 
 size_t request_var_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
@@ -157,6 +170,8 @@ void bind_request_workspace(ReqDesc &r, char *fixed, char *var) {
   r.ep = bind_parts(p, kEntWgs);
   for (int k = 0; k < kPasses; k++) r.grp[k] = bind_parts(p, kMaxGroups);
   r.ovf_hist = (uint32_t *)p;
+  p += align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
+  r.hfinal = (uint32_t *)p;
   p = var;
   r.rp = bind_parts(p, r.nrange);
   r.zp = bind_parts(p, r.nzfp);

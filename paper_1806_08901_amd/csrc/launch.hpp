@@ -31,7 +31,7 @@ inline size_t request_var_bytes(const ReqDesc &r) {
 
 // One launch of a batched pass over table entries [c0, c1) (see
 // batch_kernels.hip); `items` workgroups in total.
-enum { kBatchRange = 0, kBatchZfp, kBatchSz, kBatchOvf, kBatchEnt, kBatchPasses };
+enum { kBatchRange = 0, kBatchZfp, kBatchSz, kBatchOvf, kBatchEnt, kBatchHuff, kBatchPasses };
 struct BatchLaunch {
   int group, pass, dtype, nd, vec;
   const ReqDesc *tab;

@@ -19,9 +19,9 @@ F32, F64 = 0, 1
 EB_ABS, EB_REL = 0, 1
 OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
 FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
-FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
+FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB, FLAG_NO_HUFFMAN = 8, 16, 32, 64
 OPT_SZ_OFFSET, OPT_PROFILE, OPT_AUTOTUNE, OPT_BATCH_GRAPH = 1, 2, 3, 4
-OPT_SZ_WGS, OPT_ZFP_CHUNK, OPT_RANGE_WGS, OPT_BATCH_GROUPS = 5, 6, 7, 8
+OPT_SZ_WGS, OPT_ZFP_CHUNK, OPT_RANGE_WGS, OPT_BATCH_GROUPS, OPT_HUFFMAN = 5, 6, 7, 8, 9
 NBINS = 65536
 
 
@@ -44,6 +44,7 @@ class Result(C.Structure):
         ("sz_maxerr", C.c_double), ("sz_sse", C.c_double),
         ("sz_values", C.c_uint64), ("sz_unpredictable", C.c_uint64),
         ("chosen_eb", C.c_double),
+        ("sz_huffman_bits", C.c_uint64), ("sz_huffman_bitrate", C.c_double),
     ]
 
 
