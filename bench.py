@@ -433,6 +433,28 @@ def main():
         blat.append((time.perf_counter() - t) * 1e3)
     blat.sort()
 
+    # exact Huffman cost of the code histograms (an option): its pass's time
+    # on the same plain steps
+    ctx.set_option(szsel.OPT_HUFFMAN, 1)
+    huff_results = [ctx.select(field, eb, stride=stride) for eb in ebs]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_huff = t0.elapsed_time(t1) / args.steps
+    ctx.set_option(szsel.OPT_PROFILE, 1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    hprof = ctx.profile_read()
+    ctx.set_option(szsel.OPT_PROFILE, 0)
+    ctx.set_option(szsel.OPT_HUFFMAN, 0)
+    ent_huff_ms = hprof["ent"][0] / max(1, hprof["ent"][1])
+
     # latency of one synchronous select call (host wall clock)
     lat = []
     for k in range(args.latency_calls):
@@ -482,6 +504,14 @@ def main():
         "latency_ms": {"p50": round(lat[len(lat) // 2], 4),
                        "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
                        "calls": len(lat), "what": "one synchronous szsel_select on the field"},
+        "huffman": {
+            "what": "SZSEL_OPT_HUFFMAN=1: exact Huffman cost of every request's code histogram",
+            "ms_per_step": round(ms_huff, 4),
+            "extra_ms_per_request": round((ms_huff - ms_step) / len(ebs), 5),
+            "pass_ms": round(ent_huff_ms - phase_ms["ent"], 5),
+            "bitrate": [round(r["sz_huffman_bitrate"], 5) for r in huff_results],
+            "entropy_plus_offset": [round(r["sz_bitrate"], 5) for r in huff_results],
+        },
     }
 
     if not args.no_cpu_baseline:
@@ -489,12 +519,14 @@ def main():
         from tests.gpu_common import assert_matches_oracle
         host = field.cpu().numpy()
         t = time.perf_counter()
-        orc = [oracle.select(host, eb, stride=stride)[0] for eb in ebs]
+        orc = [oracle.select(host, eb, stride=stride, huffman=1)[0] for eb in ebs]
         cpu_s = time.perf_counter() - t
+        huff_keys = ("sz_huffman_bits", "sz_huffman_bitrate")
         parity = True
-        for g, o in zip(gpu_results, orc):
+        for g, h, o in zip(gpu_results, huff_results, orc):
             try:
-                assert_matches_oracle(g, o)
+                assert_matches_oracle(h, o)
+                assert all(g[k] == (0 if k in huff_keys else h[k]) for k in g)
             except AssertionError:
                 parity = False
         out["cpu_baseline"] = {

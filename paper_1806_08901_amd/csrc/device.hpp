@@ -39,8 +39,8 @@ constexpr int kMaxGroups = kMaxParts / kGroup;
 enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
 constexpr int kHuffThreads = 1024;     // threads of the Huffman pass (one workgroup per request)
 constexpr int kHuffSmall = 4096;       // counts below this are tallied by value
-constexpr int kHuffBig = 8192;         // at most this many counts of kHuffSmall or more
-constexpr int kHuffQueue = 8192;       // runs of merged nodes waiting at once
+constexpr int kHuffCap = 8192;         // runs of distinct weights held at once (and large counts)
+constexpr int kHuffMaxRounds = 256;    // bound on the merge rounds (about 2 log2(total) are needed)
 
 // Flags that stop the estimation after the range pass.
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |

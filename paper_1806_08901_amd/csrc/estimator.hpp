@@ -1272,228 +1272,348 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
 // ===========================================================================
 
 // The optimal prefix code's total length sum_i h_i L_i is the sum of the
-// internal node weights of a Huffman tree, and that minimum is unique, so
-// any tie-breaking gives the same cost.  The leaves are the nonzero bin
-// counts.  Counts below kHuffSmall are tallied by value (how many bins hold
-// count c), the others sorted (bitonic, in LDS).  The two-queue merge then
-// runs on runs of equal weights: the leaf runs in ascending order, and the
-// merged nodes, which are created in nondecreasing order, in a ring of runs
-// whose front and back stay in registers.  Taking the lighter front (leaves
-// on ties): a run of m >= 2 equal weights w pairs up at once into m/2 nodes
-// of weight 2w (its items stay the lightest while two remain); a single item
-// merges with the next lightest one.
+// internal node weights of a Huffman tree; that minimum is unique, so any
+// order of merging that a Huffman construction may take gives the same cost.
+//
+// The items (nonzero bin counts, then merged nodes) are kept as a sorted
+// list of runs of equal weight.  One round: with s the sum of the two
+// lightest items, every item of weight <= s is paired with its neighbour in
+// sorted order, all pairs at once.  That is what the one-pair-at-a-time
+// construction does too: every node formed weighs >= s, so items <= s stay
+// the lightest until they are paired up.  An odd item out stays.  Within a
+// run of m equal weights w the pairs form a run of (m - o) / 2 nodes of
+// weight 2w (o = 1 when the run's first item pairs with the previous run's
+// last); a run ending on an odd item pairs it with the next run's first.
+// The new runs, sorted by construction, are merged into the rest of the
+// list (equal weights combined).  The lightest weight at least doubles
+// every two rounds, so a total below 2^32 needs fewer than 70 rounds; the
+// list holds distinct weights whose sum is the total, so at most
+// sqrt(2 total) runs: 8192 suffice for 2^25 sampled values.
 struct HuffLds {
-  uint32_t runs[kHuffSmall];  // bins per small count, then packed runs (m << 12 | w)
-  uint32_t big[kHuffBig];     // the counts >= kHuffSmall, sorted
-  uint64_t qw[kHuffQueue];    // merged-node runs: weight
-  uint32_t qm[kHuffQueue];    // and multiplicity
-  uint32_t nbig, nruns, leaves, wave[kHuffThreads / kWave];
+  uint32_t aw[kHuffCap], am[kHuffCap];  // the list: weights (ascending, distinct), multiplicities
+  uint32_t bw[kHuffCap], bm[kHuffCap];  // a round's new runs; first the tally of small counts
+                                        // (bw) and the large counts (bm)
+  uint64_t scan[2][kHuffThreads / kWave];
+  uint32_t nbig, leaves, has_left, left_w;
 };
-static_assert(kHuffSmall == 4096, "small counts are packed in 12 bits");
-static_assert((kHuffQueue & (kHuffQueue - 1)) == 0, "ring size is a power of two");
+static_assert(kHuffCap % kHuffThreads == 0, "whole runs per thread");
+
+// Exclusive prefix of v in thread order and the workgroup total; one
+// barrier.  Consecutive calls must use different slot arrays unless a
+// barrier separates them.
+__device__ inline uint64_t huff_exscan(uint64_t v, uint64_t *slots, uint64_t &total) {
+  constexpr int NW = kHuffThreads / kWave;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  uint64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == kWave - 1) slots[w] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; q++) {
+    const uint64_t x = slots[q];
+    pre += q < w ? x : 0;
+    tot += x;
+  }
+  total = tot;
+  return pre + inc - v;
+}
+
+// First index in [lo, hi) of the ascending array a whose value is >= x.
+__device__ inline uint32_t huff_lower_bound(const uint32_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((uint64_t)a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 
 template <typename T, int D>
 __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
   constexpr int BS = 1 << (2 * D);
   constexpr int NT = kHuffThreads;
-  constexpr int kPer = kHuffSmall / NT;
-  static_assert(kPer * NT == kHuffSmall, "each thread owns kPer small counts");
+  constexpr int kPer = kHuffCap / NT;  // list runs per thread at most
+  constexpr int kSmallPer = kHuffSmall / NT;
   const int t = threadIdx.x;
-  const int lane = t & (kWave - 1), wv = t / kWave;
+  const uint64_t nv = (uint64_t)r.nblk * BS;
+  // every node weighs at most the total: 32-bit weights
+  bool ok = nv < (1ull << 32);
+  uint64_t cost = 0;  // this thread's share of the internal node weights
+
+  // ---- tally of the final counts (left in hfinal by the entropy pass) ----
+  if (ok) {
 #pragma unroll
-  for (int k = 0; k < kPer; k++) S.runs[t * kPer + k] = 0;
-  if (t == 0) {
-    S.nbig = 0;
-    S.leaves = 0;
-  }
-  __syncthreads();
-  // tally: the k_ent pass left the final counts in hfinal
-  uint32_t leaves = 0;
-  for (int q = t; q < kBins / 4; q += NT) {
-    const uint4 v = ((const uint4 *)r.hfinal)[q];
-    const uint32_t c4[4] = {v.x, v.y, v.z, v.w};
+    for (int k = 0; k < kSmallPer; k++) S.bw[t * kSmallPer + k] = 0;
+    if (t == 0) {
+      S.nbig = 0;
+      S.leaves = 0;
+    }
+    __syncthreads();
+    uint32_t leaves = 0;
+    for (int q = t; q < kBins / 4; q += NT) {
+      const uint4 v = ((const uint4 *)r.hfinal)[q];
+      const uint32_t c4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const uint32_t c = c4[k];
-      if (!c) continue;
-      leaves++;
-      if (c < (uint32_t)kHuffSmall) {
-        atomicAdd(&S.runs[c], 1u);
-      } else {
-        const uint32_t i = atomicAdd(&S.nbig, 1u);
-        if (i < (uint32_t)kHuffBig) S.big[i] = c;
+      for (int k = 0; k < 4; k++) {
+        const uint32_t c = c4[k];
+        if (!c) continue;
+        leaves++;
+        if (c < (uint32_t)kHuffSmall) {
+          atomicAdd(&S.bw[c], 1u);
+        } else {
+          const uint32_t i = atomicAdd(&S.nbig, 1u);
+          if (i < (uint32_t)kHuffCap) S.bm[i] = c;
+        }
       }
     }
+    leaves = group_isum<kWave>(leaves);
+    if ((t & (kWave - 1)) == 0) atomicAdd(&S.leaves, leaves);
+    __syncthreads();
+    ok = S.nbig <= (uint32_t)kHuffCap;
   }
-  leaves = group_isum<kWave>(leaves);
-  if (lane == 0) atomicAdd(&S.leaves, leaves);
-  __syncthreads();
-  const uint32_t nbig = S.nbig;
-  const bool fits = nbig <= (uint32_t)kHuffBig;
-  if (fits) {
-    // bitonic sort of the large counts, padded with the largest value
+
+  // ---- the initial list: runs of the small counts, then of the sorted large ones ----
+  uint32_t n = 0;
+  if (ok) {
+    const uint32_t nbig = S.nbig;
     uint32_t P = 1;
     while (P < nbig) P <<= 1;
-    for (uint32_t i = nbig + t; i < P; i += NT) S.big[i] = 0xFFFFFFFFu;
+    for (uint32_t i = nbig + t; i < P; i += NT) S.bm[i] = 0xFFFFFFFFu;
     __syncthreads();
     for (uint32_t k = 2; k <= P; k <<= 1) {
       for (uint32_t j = k >> 1; j > 0; j >>= 1) {
         for (uint32_t i = t; i < P; i += NT) {
           const uint32_t l = i ^ j;
           if (l > i) {
-            const uint32_t a = S.big[i], b = S.big[l];
-            if ((i & k) == 0 ? a > b : a < b) {
-              S.big[i] = b;
-              S.big[l] = a;
+            const uint32_t x = S.bm[i], y = S.bm[l];
+            if ((i & k) == 0 ? x > y : x < y) {
+              S.bm[i] = y;
+              S.bm[l] = x;
             }
           }
         }
         __syncthreads();
       }
     }
-    // the small counts' runs in ascending count, packed in place: every
-    // thread reads its kPer tallies before any run is written
-    uint32_t m[kPer], occ = 0;
+    uint32_t mult[kSmallPer];
+    uint32_t occ = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; k++) {
-      m[k] = S.runs[t * kPer + k];
-      occ += m[k] ? 1u : 0u;
+    for (int k = 0; k < kSmallPer; k++) {
+      mult[k] = S.bw[t * kSmallPer + k];
+      occ += mult[k] ? 1u : 0u;
     }
-    uint32_t inc = occ;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = __shfl_up(inc, d);
-      if (lane >= d) inc += o;
+    const uint32_t bper = (nbig + NT - 1) / NT, b0 = t * bper;
+    uint32_t starts = 0;
+    for (uint32_t j = 0; j < bper; j++) {
+      const uint32_t i = b0 + j;
+      if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) starts++;
     }
-    if (lane == kWave - 1) S.wave[wv] = inc;
-    __syncthreads();
-    uint32_t pos = inc - occ;
-    for (int w = 0; w < wv; w++) pos += S.wave[w];
+    uint64_t tot;
+    const uint64_t pre = huff_exscan(occ | ((uint64_t)starts << 32), S.scan[0], tot);
+    const uint32_t nsmall = (uint32_t)tot, nbruns = (uint32_t)(tot >> 32);
+    n = nsmall + nbruns;
+    ok = n <= (uint32_t)kHuffCap;
+    if (ok) {
+      uint32_t pos = (uint32_t)pre;
 #pragma unroll
-    for (int k = 0; k < kPer; k++)
-      if (m[k]) S.runs[pos++] = (m[k] << 12) | (uint32_t)(t * kPer + k);
-    if (t == NT - 1) S.nruns = pos;
+      for (int k = 0; k < kSmallPer; k++)
+        if (mult[k]) {
+          S.aw[pos] = (uint32_t)(t * kSmallPer + k);
+          S.am[pos] = mult[k];
+          pos++;
+        }
+      const uint32_t bpre = (uint32_t)(pre >> 32);
+      pos = nsmall + bpre;
+      for (uint32_t j = 0; j < bper; j++) {
+        const uint32_t i = b0 + j;
+        if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) {
+          S.aw[pos] = S.bm[i];
+          S.am[pos] = 0;
+          pos++;
+        }
+      }
+      __syncthreads();
+      // each large count adds one to its run (the last run started at or before it)
+      uint32_t c = bpre;
+      for (uint32_t j = 0; j < bper; j++) {
+        const uint32_t i = b0 + j;
+        if (i < nbig) {
+          if (i == 0 || S.bm[i] != S.bm[i - 1]) c++;
+          atomicAdd(&S.am[nsmall + c - 1], 1u);
+        }
+      }
+    }
     __syncthreads();
   }
-  if (t != 0) return;
 
-  // ---- the merge, on one thread ----
-  const uint32_t nruns = fits ? S.nruns : 0;
-  const uint32_t nleaf = nruns + (fits ? nbig : 0);
-  bool ok = fits;
-  uint64_t cost = 0, items = S.leaves;
-  // leaf runs: current (aw, am; am == 0 once they are used up) and the next
-  // one, loaded a run ahead
-  uint32_t ai = 0;
-  uint64_t aw = 0, am = 0, nw = 0, nm = 0;
-  auto fetch = [&]() {
-    if (ai < nruns) {
-      const uint32_t v = S.runs[ai];
-      nw = v & 0xFFFu;
-      nm = v >> 12;
-    } else if (ai < nleaf) {
-      nw = S.big[ai - nruns];
-      nm = 1;
-    } else {
-      nm = 0;
-    }
-    ai++;
-  };
-  auto next_leaf = [&]() {
-    aw = nw;
-    am = nm;
-    fetch();
-  };
-  // merged runs: qc entries from slot qh; the front (fw, fm) and, when
-  // qc >= 2, the back (bw, bm) live in registers, the ones between in LDS
-  uint64_t fw = 0, fm = 0, bw = 0, bm = 0;
-  uint32_t qh = 0, qc = 0;
-  auto push = [&](uint64_t w, uint64_t mult) {
-    if (qc == 0) {
-      fw = w;
-      fm = mult;
-      qc = 1;
-    } else if (qc == 1) {
-      if (fw == w) {
-        fm += mult;
-      } else {
-        bw = w;
-        bm = mult;
-        qc = 2;
-      }
-    } else if (bw == w) {
-      bm += mult;
-    } else if (qc == (uint32_t)kHuffQueue) {
+  // ---- merge rounds ----
+  int rounds = 0;
+  while (ok) {
+    const uint32_t w0 = S.aw[0], m0 = S.am[0];
+    if (n == 1 && m0 == 1) break;  // the root
+    if (++rounds > kHuffMaxRounds) {
       ok = false;
-    } else {
-      const uint32_t slot = (qh + qc - 1) & (kHuffQueue - 1);
-      S.qw[slot] = bw;
-      S.qm[slot] = (uint32_t)bm;
-      bw = w;
-      bm = mult;
-      qc++;
+      break;
     }
-  };
-  auto pop = [&](uint64_t n) {
-    fm -= n;
-    if (fm) return;
-    qh = (qh + 1) & (kHuffQueue - 1);
-    qc--;
-    if (qc == 1) {
-      fw = bw;
-      fm = bm;
-    } else if (qc >= 2) {
-      fw = S.qw[qh];
-      fm = S.qm[qh];
-    }
-  };
-  if (ok) {
-    fetch();
-    next_leaf();
-  }
-  while (ok && items > 1) {
-    const bool leaf = am && (!qc || aw <= fw);
-    const uint64_t xw = leaf ? aw : fw, xm = leaf ? am : fm;
-    if (xm >= 2) {
-      const uint64_t k = xm >> 1;
-      cost += k * (xw << 1);
-      items -= k;
-      if (leaf) {
-        am -= k << 1;
-        if (!am) next_leaf();
-      } else {
-        pop(k << 1);
+    const uint64_t sv = m0 >= 2 ? 2ull * w0 : (uint64_t)w0 + S.aw[1];
+    if (t == 0) S.has_left = 0;
+    // M = runs of weight <= s (a prefix); the band = runs <= 2 s, beyond
+    // which no new node can reach
+    const uint32_t per = (n + NT - 1) / NT, i0 = t * per;
+    uint32_t w[kPer], m[kPer];
+    uint32_t cntM = 0, msumM = 0, cntB = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const uint32_t i = i0 + j;
+      w[j] = 0;
+      m[j] = 0;
+      if ((uint32_t)j < per && i < n) {
+        w[j] = S.aw[i];
+        m[j] = S.am[i];
+        if (w[j] <= sv) {
+          cntM++;
+          msumM += m[j];
+        }
+        if (w[j] <= 2 * sv) cntB++;
       }
-      push(xw << 1, k);
-    } else {
-      if (leaf)
-        next_leaf();
-      else
-        pop(1);
-      const bool leaf2 = am && (!qc || aw <= fw);
-      const uint64_t yw = leaf2 ? aw : fw;
-      if (leaf2) {
-        if (!--am) next_leaf();
-      } else {
-        pop(1);
-      }
-      cost += xw + yw;
-      items--;
-      push(xw + yw, 1);
     }
+    uint64_t tot;
+    const uint64_t pre =
+        huff_exscan((uint64_t)msumM | ((uint64_t)cntM << 20) | ((uint64_t)cntB << 40), S.scan[0], tot);
+    const uint32_t k = (uint32_t)(tot >> 20) & 0xFFFFFu, k2 = (uint32_t)(tot >> 40);
+    // pair up M; new runs whose weight is already in the band are added to it
+    uint32_t par = (uint32_t)pre & 1u;
+    uint32_t emit = 0, ecount = 0;  // bit 2j: pair run of element j kept, bit 2j+1: cross pair kept
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const uint32_t i = i0 + j;
+      if ((uint32_t)j < per && i < k) {
+        const uint32_t e = m[j] - par;
+        const uint32_t pairs = e >> 1, odd = e & 1u;
+        if (pairs) {
+          const uint64_t x = 2ull * w[j];
+          cost += x * pairs;
+          const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
+          if (f < k2 && (uint64_t)S.aw[f] == x) {
+            atomicAdd(&S.am[f], pairs);
+          } else {
+            emit |= 1u << (2 * j);
+            ecount++;
+          }
+        }
+        if (odd && i + 1 < k) {
+          const uint64_t x = (uint64_t)w[j] + S.aw[i + 1];
+          cost += x;
+          const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
+          if (f < k2 && (uint64_t)S.aw[f] == x) {
+            atomicAdd(&S.am[f], 1u);
+          } else {
+            emit |= 2u << (2 * j);
+            ecount++;
+          }
+        } else if (odd) {
+          S.has_left = 1;  // the odd item out
+          S.left_w = w[j];
+        }
+        par = odd;
+      }
+    }
+    uint64_t atot;
+    uint32_t epos = (uint32_t)huff_exscan(ecount, S.scan[1], atot);
+    const uint32_t a = (uint32_t)atot;
+    // new list: [odd item] + merge(new runs, rest); checked before any write
+    const uint32_t has_left = S.has_left, left_w = S.left_w;
+    const bool left_sep = has_left && left_w != sv;  // an odd item of weight s joins the first new run
+    const uint32_t off = left_sep ? 1u : 0u;
+    const uint32_t rest = n - k, n2 = off + a + rest;
+    if (n2 > (uint32_t)kHuffCap) {
+      ok = false;
+      break;
+    }
+    {  // write the kept new runs, in order
+      uint32_t par2 = (uint32_t)pre & 1u;
+#pragma unroll
+      for (int j = 0; j < kPer; j++) {
+        const uint32_t i = i0 + j;
+        if ((uint32_t)j < per && i < k) {
+          const uint32_t e = m[j] - par2;
+          if (emit & (1u << (2 * j))) {
+            S.bw[epos] = 2 * w[j];
+            S.bm[epos] = e >> 1;
+            epos++;
+          }
+          if (emit & (2u << (2 * j))) {
+            S.bw[epos] = w[j] + S.aw[i + 1];
+            S.bm[epos] = 1;
+            epos++;
+          }
+          par2 = e & 1u;
+        }
+      }
+    }
+    __syncthreads();
+    // positions in the new list, read before any thread writes it
+    const uint32_t U = a + rest, uper = (U + NT - 1) / NT, u0 = t * uper;
+    uint32_t pw[kPer], pm[kPer], pp[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const uint32_t u = u0 + j;
+      pp[j] = 0xFFFFFFFFu;
+      if ((uint32_t)j < uper && u < U) {
+        if (u < a) {
+          pw[j] = S.bw[u];
+          pm[j] = S.bm[u] + ((u == 0 && has_left && !left_sep) ? 1u : 0u);
+          pp[j] = off + u + (huff_lower_bound(S.aw, k, k2, pw[j]) - k);
+        } else {
+          const uint32_t q = u - a;
+          pw[j] = S.aw[k + q];
+          pm[j] = S.am[k + q];
+          pp[j] = off + q + (k + q < k2 ? huff_lower_bound(S.bw, 0, a, pw[j]) : a);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; j++)
+      if (pp[j] != 0xFFFFFFFFu) {
+        S.aw[pp[j]] = pw[j];
+        S.am[pp[j]] = pm[j];
+      }
+    if (t == 0 && left_sep) {
+      S.aw[0] = left_w;
+      S.am[0] = 1;
+    }
+    __syncthreads();
+    n = n2;
   }
-  const uint64_t nv = (uint64_t)r.nblk * BS;
-  if (S.leaves == 1) cost = nv;  // one symbol: 1 bit each
+
+  // ---- total and result ----
+  __syncthreads();  // a round left early may still have readers of the scan slots
+  cost = group_isum<kWave>(cost);
+  if ((t & (kWave - 1)) == 0) S.scan[1][t / kWave] = cost;
+  __syncthreads();
+  if (t != 0) return;
+  uint64_t total = 0;
+#pragma unroll
+  for (int q = 0; q < NT / kWave; q++) total += S.scan[1][q];
+  if (ok && S.leaves == 1) total = nv;  // one symbol: 1 bit each
   ReqState *st = r.st;
   szsel_result *res = r.res;
   const uint64_t unpred = get_u64(&st->sz_unpred);
-  double hbr = (double)cost / (double)nv;
+  double hbr = (double)total / (double)nv;
   hbr = hbr + ((double)unpred * (double)Prec<T>::W) / (double)nv;
   const uint64_t fc = get_u64((uint64_t *)&res->flags);
   uint32_t flags = (uint32_t)fc;
   uint32_t choice = (uint32_t)(fc >> 32);
   if (ok) {
-    put_u64(&res->sz_huffman_bits, cost);
+    put_u64(&res->sz_huffman_bits, total);
     put_f64(&res->sz_huffman_bitrate, hbr);
   } else {
     flags |= SZSEL_FLAG_NO_HUFFMAN;
