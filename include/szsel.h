@@ -74,10 +74,10 @@ enum {
   SZSEL_FLAG_EB_EXCEEDS = 8,  /* the SZ bound delta/2 is larger than eb_abs */
   SZSEL_FLAG_NO_BLOCKS = 16,  /* no full 4^d block: nothing estimated, choice = SZ */
   SZSEL_FLAG_BAD_EB = 32,     /* eb_rel * value range is 0 or not finite */
-  SZSEL_FLAG_NO_HUFFMAN = 64  /* Huffman cost requested but not computed: more than
-                                 8192 codes occur 4096 times or more (never with at
-                                 most 2^25 sampled values), or the merge holds more
-                                 than 8192 distinct pending node weights at once */
+  SZSEL_FLAG_NO_HUFFMAN = 64  /* Huffman cost requested but not computed: the counts
+                                 took more than 8192 distinct values during the
+                                 construction (impossible with at most 2^25 sampled
+                                 values), or 2^32 sampled values or more */
 };
 
 /* Result of one request.  Bit-rates are bits per value, PSNRs in dB, MSEs in

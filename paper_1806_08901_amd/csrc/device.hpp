@@ -38,7 +38,7 @@ constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
 enum { kPassRange = 0, kPassZfp = 1, kPassSz = 2, kPassEnt = 3, kPasses = 4 };
 constexpr int kHuffThreads = 1024;     // threads of the Huffman pass (one workgroup per request)
-constexpr int kHuffSmall = 4096;       // counts below this are tallied by value
+constexpr int kHuffSmall = 8192;       // counts below this are tallied by value
 constexpr int kHuffCap = 8192;         // runs of distinct weights held at once (and large counts)
 constexpr int kHuffMaxRounds = 256;    // bound on the merge rounds (about 2 log2(total) are needed)
 

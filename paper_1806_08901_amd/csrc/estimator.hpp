@@ -1288,46 +1288,65 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
 // list (equal weights combined).  The lightest weight at least doubles
 // every two rounds, so a total below 2^32 needs fewer than 70 rounds; the
 // list holds distinct weights whose sum is the total, so at most
-// sqrt(2 total) runs: 8192 suffice for 2^25 sampled values.
+// sqrt(2 total) runs: 8192 suffice for 2^25 sampled values.  Once at most
+// 64 items are left, one wave merges them one pair at a time in registers.
 struct HuffLds {
   uint32_t aw[kHuffCap], am[kHuffCap];  // the list: weights (ascending, distinct), multiplicities
   uint32_t bw[kHuffCap], bm[kHuffCap];  // a round's new runs; first the tally of small counts
                                         // (bw) and the large counts (bm)
-  uint64_t scan[2][kHuffThreads / kWave];
+  uint32_t slots[2][2 * (kHuffThreads / kWave)];
+  uint64_t red[kHuffThreads / kWave];
   uint32_t nbig, leaves, has_left, left_w;
 };
-static_assert(kHuffCap % kHuffThreads == 0, "whole runs per thread");
+static_assert(kHuffCap % kHuffThreads == 0 && kHuffSmall <= kHuffCap, "Huffman pass layout");
 
-// Exclusive prefix of v in thread order and the workgroup total; one
-// barrier.  Consecutive calls must use different slot arrays unless a
-// barrier separates them.
-__device__ inline uint64_t huff_exscan(uint64_t v, uint64_t *slots, uint64_t &total) {
+// Inclusive prefix sum over the 64 lanes of a wave: shifts of 1, 2, 4, 8
+// within rows of 16 lanes (row_shr), then the row ends carried into the
+// later rows (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and
+// 3).  Lanes without a source add 0.
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
+// Exclusive prefixes (pa, pb) of a and b over the workgroup in thread
+// order, and their totals; one barrier.  Consecutive calls use different
+// slot arrays unless a barrier separates them.
+__device__ inline void huff_scan2(uint32_t a, uint32_t b, uint32_t *slots, uint32_t &pa, uint32_t &pb,
+                                  uint32_t &ta, uint32_t &tb) {
   constexpr int NW = kHuffThreads / kWave;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  uint64_t inc = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint64_t o = __shfl_up(inc, d);
-    if (lane >= d) inc += o;
+  const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+  if (lane == kWave - 1) {
+    slots[w] = ia;
+    slots[NW + w] = ib;
   }
-  if (lane == kWave - 1) slots[w] = inc;
   __syncthreads();
-  uint64_t pre = 0, tot = 0;
+  uint32_t sa = 0, sb = 0, xa = 0, xb = 0;
 #pragma unroll
   for (int q = 0; q < NW; q++) {
-    const uint64_t x = slots[q];
-    pre += q < w ? x : 0;
-    tot += x;
+    const uint32_t x = slots[q], y = slots[NW + q];
+    sa += q < w ? x : 0u;
+    sb += q < w ? y : 0u;
+    xa += x;
+    xb += y;
   }
-  total = tot;
-  return pre + inc - v;
+  ta = xa;
+  tb = xb;
+  pa = sa + ia - a;
+  pb = sb + ib - b;
 }
 
 // First index in [lo, hi) of the ascending array a whose value is >= x.
-__device__ inline uint32_t huff_lower_bound(const uint32_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
+__device__ inline uint32_t huff_lower_bound(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
-    if ((uint64_t)a[mid] < x)
+    if (a[mid] < x)
       lo = mid + 1;
     else
       hi = mid;
@@ -1335,12 +1354,201 @@ __device__ inline uint32_t huff_lower_bound(const uint32_t *a, uint32_t lo, uint
   return lo;
 }
 
+// One merge round over the list (aw, am)[0, n) holding `items` items.
+// Returns false when the new list would not fit.
+__device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint64_t &cost) {
+  constexpr int NT = kHuffThreads;
+  constexpr int kPer = kHuffCap / NT;  // list runs per thread at most
+  const int t = threadIdx.x;
+  const uint32_t w0 = S.aw[0], m0 = S.am[0];
+  // s: the two lightest items' sum (at most the total: 32 bits)
+  const uint32_t sv = m0 >= 2 ? 2u * w0 : w0 + S.aw[1];
+  const uint64_t sv2 = 2ull * sv;
+  if (t == 0) S.has_left = 0;
+  // M = the runs of weight <= s (a prefix); the band = the runs <= 2s,
+  // beyond which no new node reaches
+  const uint32_t per = (n + NT - 1) / NT, i0 = t * per;
+  uint32_t w[kPer], m[kPer];
+  uint32_t cntM = 0, msumM = 0, cntB = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t i = i0 + j;
+    w[j] = 0;
+    m[j] = 0;
+    if ((uint32_t)j < per && i < n) {
+      w[j] = S.aw[i];
+      m[j] = S.am[i];
+      if (w[j] <= sv) {
+        cntM++;
+        msumM += m[j];
+      }
+      if ((uint64_t)w[j] <= sv2) cntB++;
+    }
+  }
+  uint32_t pm, pc, tm, tc;
+  huff_scan2(msumM, cntM | (cntB << 16), S.slots[0], pm, pc, tm, tc);
+  const uint32_t k = tc & 0xFFFFu, k2 = tc >> 16;
+  // pair up M; a new run whose weight is already in the band joins that run
+  uint32_t par = pm & 1u;
+  uint32_t emit = 0, ecount = 0, made = 0;  // bit 2j: element j's run of pairs kept, bit 2j+1: its cross pair
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t i = i0 + j;
+    if ((uint32_t)j < per && i < k) {
+      const uint32_t e = m[j] - par;
+      const uint32_t pairs = e >> 1, odd = e & 1u;
+      if (pairs) {
+        const uint32_t x = 2u * w[j];
+        cost += (uint64_t)x * pairs;
+        made += pairs;
+        const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
+        if (f < k2 && S.aw[f] == x) {
+          atomicAdd(&S.am[f], pairs);
+        } else {
+          emit |= 1u << (2 * j);
+          ecount++;
+        }
+      }
+      if (odd && i + 1 < k) {
+        const uint32_t x = w[j] + S.aw[i + 1];
+        cost += x;
+        made++;
+        const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
+        if (f < k2 && S.aw[f] == x) {
+          atomicAdd(&S.am[f], 1u);
+        } else {
+          emit |= 2u << (2 * j);
+          ecount++;
+        }
+      } else if (odd) {
+        S.has_left = 1;  // the odd item out
+        S.left_w = w[j];
+      }
+      par = odd;
+    }
+  }
+  uint32_t epos, pmade, a, tmade;
+  huff_scan2(ecount, made, S.slots[1], epos, pmade, a, tmade);
+  // new list: [odd item] + merge(new runs, rest); checked before any write
+  const uint32_t has_left = S.has_left, left_w = S.left_w;
+  const bool left_sep = has_left && left_w != sv;  // an odd item of weight s joins the first new run
+  const uint32_t off = left_sep ? 1u : 0u;
+  const uint32_t rest = n - k, n2 = off + a + rest;
+  if (n2 > (uint32_t)kHuffCap) return false;
+  {
+    uint32_t par2 = pm & 1u;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const uint32_t i = i0 + j;
+      if ((uint32_t)j < per && i < k) {
+        const uint32_t e = m[j] - par2;
+        if (emit & (1u << (2 * j))) {
+          S.bw[epos] = 2u * w[j];
+          S.bm[epos] = e >> 1;
+          epos++;
+        }
+        if (emit & (2u << (2 * j))) {
+          S.bw[epos] = w[j] + S.aw[i + 1];
+          S.bm[epos] = 1;
+          epos++;
+        }
+        par2 = e & 1u;
+      }
+    }
+  }
+  __syncthreads();
+  // positions in the new list, all read before any thread writes it
+  const uint32_t U = a + rest, uper = (U + NT - 1) / NT, u0 = t * uper;
+  uint32_t pw[kPer], pq[kPer], pp[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t u = u0 + j;
+    pp[j] = 0xFFFFFFFFu;
+    pw[j] = 0;
+    pq[j] = 0;
+    if ((uint32_t)j < uper && u < U) {
+      if (u < a) {
+        pw[j] = S.bw[u];
+        pq[j] = S.bm[u] + ((u == 0 && has_left && !left_sep) ? 1u : 0u);
+        pp[j] = off + u + (huff_lower_bound(S.aw, k, k2, pw[j]) - k);
+      } else {
+        const uint32_t q = u - a;
+        pw[j] = S.aw[k + q];
+        pq[j] = S.am[k + q];
+        pp[j] = off + q + (k + q < k2 ? huff_lower_bound(S.bw, 0, a, pw[j]) : a);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kPer; j++)
+    if (pp[j] != 0xFFFFFFFFu) {
+      S.aw[pp[j]] = pw[j];
+      S.am[pp[j]] = pq[j];
+    }
+  if (t == 0 && left_sep) {
+    S.aw[0] = left_w;
+    S.am[0] = 1;
+  }
+  __syncthreads();
+  n = n2;
+  items -= tmade;
+  return true;
+}
+
+// At most 64 items (n runs) left: wave 0 places them in its lanes,
+// ascending, and merges them one pair at a time, the leaves and the nodes
+// made so far (ascending by construction) as two queues in registers.
+__device__ inline void huff_tail(HuffLds &S, uint32_t n, uint32_t items, uint64_t &cost) {
+  const int lane = threadIdx.x;
+  uint32_t w = 0, m = 0;
+  if ((uint32_t)lane < n) {
+    w = S.aw[lane];
+    m = S.am[lane];
+  }
+  const uint32_t pre = wave_incl_scan(m) - m;
+  for (uint32_t q = 0; q < m; q++) S.bw[pre + q] = w;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t leaf = (uint32_t)lane < items ? S.bw[lane] : 0xFFFFFFFFu;
+  uint32_t node = 0xFFFFFFFFu;
+  uint32_t li = 0, qh = 0, qt = 0;
+  uint64_t c = 0;
+  for (uint32_t step = 1; step < items; step++) {
+    uint32_t lw = li < items ? (uint32_t)__builtin_amdgcn_readlane((int)leaf, (int)li) : 0xFFFFFFFFu;
+    uint32_t qw = qh < qt ? (uint32_t)__builtin_amdgcn_readlane((int)node, (int)qh) : 0xFFFFFFFFu;
+    uint32_t x;
+    if (lw <= qw) {
+      x = lw;
+      li++;
+      lw = li < items ? (uint32_t)__builtin_amdgcn_readlane((int)leaf, (int)li) : 0xFFFFFFFFu;
+    } else {
+      x = qw;
+      qh++;
+      qw = qh < qt ? (uint32_t)__builtin_amdgcn_readlane((int)node, (int)qh) : 0xFFFFFFFFu;
+    }
+    uint32_t y;
+    if (lw <= qw) {
+      y = lw;
+      li++;
+    } else {
+      y = qw;
+      qh++;
+    }
+    node = (uint32_t)lane == qt ? x + y : node;
+    qt++;
+    c += (uint64_t)x + y;
+  }
+  if (lane == 0) cost += c;
+}
+
 template <typename T, int D>
 __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
   constexpr int BS = 1 << (2 * D);
   constexpr int NT = kHuffThreads;
-  constexpr int kPer = kHuffCap / NT;  // list runs per thread at most
   constexpr int kSmallPer = kHuffSmall / NT;
+  constexpr int kLoads = kBins / 4 / NT;
   const int t = threadIdx.x;
   const uint64_t nv = (uint64_t)r.nblk * BS;
   // every node weighs at most the total: 32-bit weights
@@ -1356,10 +1564,13 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
       S.leaves = 0;
     }
     __syncthreads();
+    uint4 v[kLoads];
+#pragma unroll
+    for (int q = 0; q < kLoads; q++) v[q] = ((const uint4 *)r.hfinal)[t + q * NT];
     uint32_t leaves = 0;
-    for (int q = t; q < kBins / 4; q += NT) {
-      const uint4 v = ((const uint4 *)r.hfinal)[q];
-      const uint32_t c4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < kLoads; q++) {
+      const uint32_t c4[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const uint32_t c = c4[k];
@@ -1415,13 +1626,12 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
       const uint32_t i = b0 + j;
       if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) starts++;
     }
-    uint64_t tot;
-    const uint64_t pre = huff_exscan(occ | ((uint64_t)starts << 32), S.scan[0], tot);
-    const uint32_t nsmall = (uint32_t)tot, nbruns = (uint32_t)(tot >> 32);
+    uint32_t po, ps, nsmall, nbruns;
+    huff_scan2(occ, starts, S.slots[0], po, ps, nsmall, nbruns);
     n = nsmall + nbruns;
     ok = n <= (uint32_t)kHuffCap;
     if (ok) {
-      uint32_t pos = (uint32_t)pre;
+      uint32_t pos = po;
 #pragma unroll
       for (int k = 0; k < kSmallPer; k++)
         if (mult[k]) {
@@ -1429,8 +1639,7 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
           S.am[pos] = mult[k];
           pos++;
         }
-      const uint32_t bpre = (uint32_t)(pre >> 32);
-      pos = nsmall + bpre;
+      pos = nsmall + ps;
       for (uint32_t j = 0; j < bper; j++) {
         const uint32_t i = b0 + j;
         if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) {
@@ -1441,7 +1650,7 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
       }
       __syncthreads();
       // each large count adds one to its run (the last run started at or before it)
-      uint32_t c = bpre;
+      uint32_t c = ps;
       for (uint32_t j = 0; j < bper; j++) {
         const uint32_t i = b0 + j;
         if (i < nbig) {
@@ -1453,156 +1662,25 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
     __syncthreads();
   }
 
-  // ---- merge rounds ----
-  int rounds = 0;
-  while (ok) {
-    const uint32_t w0 = S.aw[0], m0 = S.am[0];
-    if (n == 1 && m0 == 1) break;  // the root
-    if (++rounds > kHuffMaxRounds) {
-      ok = false;
-      break;
+  // ---- merge rounds, then the last items one pair at a time ----
+  if (ok) {
+    uint32_t items = S.leaves;
+    int rounds = 0;
+    while (ok && items > (uint32_t)kWave) {
+      ok = huff_round(S, n, items, cost) && ++rounds <= kHuffMaxRounds;
     }
-    const uint64_t sv = m0 >= 2 ? 2ull * w0 : (uint64_t)w0 + S.aw[1];
-    if (t == 0) S.has_left = 0;
-    // M = runs of weight <= s (a prefix); the band = runs <= 2 s, beyond
-    // which no new node can reach
-    const uint32_t per = (n + NT - 1) / NT, i0 = t * per;
-    uint32_t w[kPer], m[kPer];
-    uint32_t cntM = 0, msumM = 0, cntB = 0;
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      const uint32_t i = i0 + j;
-      w[j] = 0;
-      m[j] = 0;
-      if ((uint32_t)j < per && i < n) {
-        w[j] = S.aw[i];
-        m[j] = S.am[i];
-        if (w[j] <= sv) {
-          cntM++;
-          msumM += m[j];
-        }
-        if (w[j] <= 2 * sv) cntB++;
-      }
-    }
-    uint64_t tot;
-    const uint64_t pre =
-        huff_exscan((uint64_t)msumM | ((uint64_t)cntM << 20) | ((uint64_t)cntB << 40), S.scan[0], tot);
-    const uint32_t k = (uint32_t)(tot >> 20) & 0xFFFFFu, k2 = (uint32_t)(tot >> 40);
-    // pair up M; new runs whose weight is already in the band are added to it
-    uint32_t par = (uint32_t)pre & 1u;
-    uint32_t emit = 0, ecount = 0;  // bit 2j: pair run of element j kept, bit 2j+1: cross pair kept
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      const uint32_t i = i0 + j;
-      if ((uint32_t)j < per && i < k) {
-        const uint32_t e = m[j] - par;
-        const uint32_t pairs = e >> 1, odd = e & 1u;
-        if (pairs) {
-          const uint64_t x = 2ull * w[j];
-          cost += x * pairs;
-          const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
-          if (f < k2 && (uint64_t)S.aw[f] == x) {
-            atomicAdd(&S.am[f], pairs);
-          } else {
-            emit |= 1u << (2 * j);
-            ecount++;
-          }
-        }
-        if (odd && i + 1 < k) {
-          const uint64_t x = (uint64_t)w[j] + S.aw[i + 1];
-          cost += x;
-          const uint32_t f = huff_lower_bound(S.aw, k, k2, x);
-          if (f < k2 && (uint64_t)S.aw[f] == x) {
-            atomicAdd(&S.am[f], 1u);
-          } else {
-            emit |= 2u << (2 * j);
-            ecount++;
-          }
-        } else if (odd) {
-          S.has_left = 1;  // the odd item out
-          S.left_w = w[j];
-        }
-        par = odd;
-      }
-    }
-    uint64_t atot;
-    uint32_t epos = (uint32_t)huff_exscan(ecount, S.scan[1], atot);
-    const uint32_t a = (uint32_t)atot;
-    // new list: [odd item] + merge(new runs, rest); checked before any write
-    const uint32_t has_left = S.has_left, left_w = S.left_w;
-    const bool left_sep = has_left && left_w != sv;  // an odd item of weight s joins the first new run
-    const uint32_t off = left_sep ? 1u : 0u;
-    const uint32_t rest = n - k, n2 = off + a + rest;
-    if (n2 > (uint32_t)kHuffCap) {
-      ok = false;
-      break;
-    }
-    {  // write the kept new runs, in order
-      uint32_t par2 = (uint32_t)pre & 1u;
-#pragma unroll
-      for (int j = 0; j < kPer; j++) {
-        const uint32_t i = i0 + j;
-        if ((uint32_t)j < per && i < k) {
-          const uint32_t e = m[j] - par2;
-          if (emit & (1u << (2 * j))) {
-            S.bw[epos] = 2 * w[j];
-            S.bm[epos] = e >> 1;
-            epos++;
-          }
-          if (emit & (2u << (2 * j))) {
-            S.bw[epos] = w[j] + S.aw[i + 1];
-            S.bm[epos] = 1;
-            epos++;
-          }
-          par2 = e & 1u;
-        }
-      }
-    }
-    __syncthreads();
-    // positions in the new list, read before any thread writes it
-    const uint32_t U = a + rest, uper = (U + NT - 1) / NT, u0 = t * uper;
-    uint32_t pw[kPer], pm[kPer], pp[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      const uint32_t u = u0 + j;
-      pp[j] = 0xFFFFFFFFu;
-      if ((uint32_t)j < uper && u < U) {
-        if (u < a) {
-          pw[j] = S.bw[u];
-          pm[j] = S.bm[u] + ((u == 0 && has_left && !left_sep) ? 1u : 0u);
-          pp[j] = off + u + (huff_lower_bound(S.aw, k, k2, pw[j]) - k);
-        } else {
-          const uint32_t q = u - a;
-          pw[j] = S.aw[k + q];
-          pm[j] = S.am[k + q];
-          pp[j] = off + q + (k + q < k2 ? huff_lower_bound(S.bw, 0, a, pw[j]) : a);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPer; j++)
-      if (pp[j] != 0xFFFFFFFFu) {
-        S.aw[pp[j]] = pw[j];
-        S.am[pp[j]] = pm[j];
-      }
-    if (t == 0 && left_sep) {
-      S.aw[0] = left_w;
-      S.am[0] = 1;
-    }
-    __syncthreads();
-    n = n2;
+    if (ok && t < kWave) huff_tail(S, n, items, cost);
   }
 
   // ---- total and result ----
-  __syncthreads();  // a round left early may still have readers of the scan slots
+  __syncthreads();
   cost = group_isum<kWave>(cost);
-  if ((t & (kWave - 1)) == 0) S.scan[1][t / kWave] = cost;
+  if ((t & (kWave - 1)) == 0) S.red[t / kWave] = cost;
   __syncthreads();
   if (t != 0) return;
   uint64_t total = 0;
 #pragma unroll
-  for (int q = 0; q < NT / kWave; q++) total += S.scan[1][q];
+  for (int q = 0; q < NT / kWave; q++) total += S.red[q];
   if (ok && S.leaves == 1) total = nv;  // one symbol: 1 bit each
   ReqState *st = r.st;
   szsel_result *res = r.res;

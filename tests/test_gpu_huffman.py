@@ -98,26 +98,27 @@ def test_constant_field_reports_no_cost(ctx):
 
 
 def test_many_large_counts_are_sorted(ctx):
-    """16.7 M sampled values of noise: about 2000 codes occur 4096 times or
+    """16.7 M sampled values of noise: about 1000 codes occur 8192 times or
     more, so the sorted list of large counts is exercised."""
     g = torch.Generator().manual_seed(88)
     x = torch.rand(4096, 4096, generator=g)
-    gpu = _with_huffman(ctx, 1, lambda: ctx.run(oracle.OP_SZ, x.cuda(), 3e-4, oracle.EB_ABS, (1, 1)))
-    orc, dump = oracle.run(oracle.OP_SZ, x.numpy(), 3e-4, oracle.EB_ABS, (1, 1), huffman=1, dump=True)
-    assert (dump["hist"] >= 4096).sum() > 1000
+    gpu = _with_huffman(ctx, 1, lambda: ctx.run(oracle.OP_SZ, x.cuda(), 5e-4, oracle.EB_ABS, (1, 1)))
+    orc, dump = oracle.run(oracle.OP_SZ, x.numpy(), 5e-4, oracle.EB_ABS, (1, 1), huffman=1, dump=True)
+    assert (dump["hist"] >= 8192).sum() > 500
     assert_matches_oracle(gpu, orc, "noise 4096^2")
 
 
-def test_too_many_large_counts_fall_back(ctx):
-    """105 M sampled values of noise with bins of 2 eb: some 12,000 codes
-    occur more than 4096 times each, so the cost is not computed, the flag
-    says so, and the selection falls back to entropy + offset."""
+def test_too_many_distinct_counts_fall_back(ctx):
+    """105 M sampled values of noise with bins of 2 eb: the counts take some
+    9000 distinct values, more than the pass holds, so the cost is not
+    computed, the flag says so, and the selection falls back to entropy +
+    offset."""
     from paper_1806_08901_amd import szsel
     g = torch.Generator(device="cuda").manual_seed(89)
     x = torch.rand(10240, 10240, generator=g, device="cuda")
-    plain = ctx.run(oracle.OP_FIXED_EB, x, 6e-5, oracle.EB_ABS, (1, 1))
+    plain = ctx.run(oracle.OP_FIXED_EB, x, 1e-4, oracle.EB_ABS, (1, 1))
     for mode in (1, 2):
-        got = _with_huffman(ctx, mode, lambda: ctx.run(oracle.OP_FIXED_EB, x, 6e-5, oracle.EB_ABS, (1, 1)))
+        got = _with_huffman(ctx, mode, lambda: ctx.run(oracle.OP_FIXED_EB, x, 1e-4, oracle.EB_ABS, (1, 1)))
         assert got["flags"] == plain["flags"] | szsel.FLAG_NO_HUFFMAN
         assert got["sz_huffman_bits"] == 0
         assert {k: v for k, v in got.items() if k != "flags"} == {k: v for k, v in plain.items() if k != "flags"}
