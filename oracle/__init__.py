@@ -23,6 +23,7 @@ EB_ABS, EB_REL = 0, 1
 F32, F64 = 0, 1
 FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
 FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB = 8, 16, 32
+FLAG_EC_SAMPLED = 128
 NBINS = 65536
 
 
@@ -42,6 +43,7 @@ class Result(C.Structure):
         ("sz_values", C.c_uint64), ("sz_unpredictable", C.c_uint64),
         ("chosen_eb", C.c_double),
         ("sz_huffman_bits", C.c_uint64), ("sz_huffman_bitrate", C.c_double),
+        ("zfp_ec_points", C.c_uint64), ("zfp_ec_nsb2", C.c_uint64),
     ]
 
 
@@ -49,6 +51,7 @@ class Dump(C.Structure):
     _fields_ = [
         ("codes", C.c_void_p), ("zfp_bits", C.c_void_p), ("zfp_sse", C.c_void_p),
         ("zfp_emax", C.c_void_p), ("sz_sse", C.c_void_p), ("hist", C.c_void_p),
+        ("ec_nsb2", C.c_void_p), ("ec_err", C.c_void_p),
     ]
 
 
@@ -72,7 +75,15 @@ def lib():
         L = C.CDLL(build())
         P, I64P, I32P = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
         L.orc_run.argtypes = [C.c_int, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
-                              C.c_double, C.c_int, C.POINTER(Result), C.POINTER(Dump)]
+                              C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(Result), C.POINTER(Dump)]
+        L.orc_ec_gain.argtypes = [C.c_int, C.c_int]
+        L.orc_ec_gain.restype = C.c_double
+        L.orc_ec_default_points.argtypes = [C.c_int]
+        L.orc_ec_positions.argtypes = [C.c_int, C.c_int, I32P]
+        L.orc_zfp_block_ec.argtypes = [C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int,
+                                       C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]
         L.orc_range.argtypes = [P, C.c_int64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_num_sampled_blocks.argtypes = [I64P, C.c_int, I32P]
         L.orc_num_sampled_blocks.restype = C.c_int64
@@ -125,8 +136,14 @@ def result_dict(r: Result) -> dict:
 
 
 def run(op: int, field: np.ndarray, eb: float, eb_mode: int = EB_REL, stride=None,
-        sz_offset: float = 0.5, dump: bool = False, huffman: int = 0):
-    """Run the estimator on a C-order numpy field.  Returns (result dict, dump dict|None)."""
+        sz_offset: float = 0.5, dump: bool = False, huffman: int = 0, ec_points: int = 0,
+        ec_weight: int = 0):
+    """Run the estimator on a C-order numpy field.  Returns (result dict, dump dict|None).
+
+    ec_points: 0 = exact ZFP estimate; 1 = the paper's point sub-sampling
+    (3/9/16 points per 1/2/3-D block); r >= 2 = r points per block.
+    ec_weight: 1 = weight each sub-sampled squared error by its coefficient's
+    data-domain gain under the inverse transform."""
     field = np.ascontiguousarray(field)
     nd = field.ndim
     dims = np.array(field.shape, dtype=np.int64)
@@ -146,18 +163,62 @@ def run(op: int, field: np.ndarray, eb: float, eb_mode: int = EB_REL, stride=Non
             "zfp_emax": np.zeros(nblk, np.int32),
             "sz_sse": np.zeros(nblk, np.float64),
             "hist": np.zeros(NBINS, np.uint32),
+            "ec_nsb2": np.zeros(nblk, np.uint32),
+            "ec_err": np.zeros(nblk * ec_slots(nd, ec_points), np.float64),
         }
         dp = Dump(*[arrays[k].ctypes.data for k, _ in Dump._fields_])
     rc = lib().orc_run(op, field.ctypes.data, _ptr(dims, C.c_int64), nd, _dtype_code(field),
-                       float(eb), eb_mode, _ptr(st, C.c_int32), float(sz_offset), int(huffman), C.byref(out),
+                       float(eb), eb_mode, _ptr(st, C.c_int32), float(sz_offset), int(huffman),
+                       int(ec_points), int(ec_weight), C.byref(out),
                        C.byref(dp) if dp is not None else None)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return result_dict(out), arrays
 
 
-def select(field, eb, eb_mode=EB_REL, stride=None, sz_offset=0.5, dump=False, huffman=0):
-    return run(OP_SELECT, field, eb, eb_mode, stride, sz_offset, dump, huffman)
+def select(field, eb, eb_mode=EB_REL, stride=None, sz_offset=0.5, dump=False, huffman=0, ec_points=0,
+           ec_weight=0):
+    return run(OP_SELECT, field, eb, eb_mode, stride, sz_offset, dump, huffman, ec_points, ec_weight)
+
+
+def ec_points_per_block(nd: int, ec_points: int) -> int:
+    """Sub-sampled points per block for an ec_points argument (0: none)."""
+    return int(lib().orc_ec_default_points(nd)) if ec_points == 1 else int(ec_points)
+
+
+def ec_slots(nd: int, ec_points: int) -> int:
+    """Dump slots per block: the points rounded up to a power of two (1 when off)."""
+    r = ec_points_per_block(nd, ec_points)
+    R = 1
+    while R < r:
+        R *= 2
+    return R
+
+
+def ec_positions(size: int, r: int):
+    pos = np.zeros(r, np.int32)
+    lib().orc_ec_positions(size, r, pos.ctypes.data_as(C.POINTER(C.c_int32)))
+    return pos
+
+
+def zfp_block_ec(x, nd: int, dtype: int, minexp: int, r: int):
+    """(twice the interpolated significant bits, significant bits of the r
+    points, scaled errors in R slots, their gains, emax) of one block."""
+    xb = np.ascontiguousarray(x, dtype=np.float64)
+    R = 1
+    while R < r:
+        R *= 2
+    err = np.zeros(R, np.float64)
+    gain = np.zeros(R, np.float64)
+    twice, pts, emax = C.c_uint64(), C.c_uint64(), C.c_int32()
+    lib().orc_zfp_block_ec(xb.ctypes.data_as(C.POINTER(C.c_double)), nd, dtype, minexp, r,
+                           C.byref(twice), C.byref(pts), err.ctypes.data_as(C.POINTER(C.c_double)),
+                           gain.ctypes.data_as(C.POINTER(C.c_double)), C.byref(emax))
+    return int(twice.value), int(pts.value), err, gain, int(emax.value)
+
+
+def ec_gain(i: int, nd: int) -> float:
+    return float(lib().orc_ec_gain(i, nd))
 
 
 def huffman_bits(hist) -> int:

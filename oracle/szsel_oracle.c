@@ -376,6 +376,87 @@ uint32_t orc_zfp_block(const double *x, int nd, int dtype, int minexp, double *x
 }
 
 /* ------------------------------------------------------------------ */
+/* ZFP side by point sub-sampling (Sections 5.2.1, 5.2.2)              */
+/* ------------------------------------------------------------------ */
+
+int orc_ec_default_points(int nd) { return nd == 1 ? 3 : (nd == 2 ? 9 : 16); }
+
+/* k-th of r positions: round(k (size - 1) / (r - 1)), halves rounded up. */
+void orc_ec_positions(int size, int r, int32_t *pos) {
+  for (int k = 0; k < r; k++)
+    pos[k] = (int32_t)((2L * k * (size - 1) + (r - 1)) / (2L * (r - 1)));
+}
+
+/* The paper's estimate for one block: transform the block as ZFP does, take
+ * r coefficients spread over the coding order, count each one's significant
+ * bits within the coded planes (its top set bit down to the last coded
+ * plane), fill the other positions by linear interpolation between the
+ * neighbouring samples and sum; and take each sampled coefficient's
+ * truncation error (the value of the digits below the last coded plane),
+ * scaled by the block's exponent to the data's units.
+ * The interpolated sum over a gap between samples at positions a < b with
+ * counts va, vb is (b - a - 1)(va + vb)/2, so twice the block's total is an
+ * integer. */
+/* Squared norm of the data-domain image of a unit coefficient with
+ * frequency f along one axis: the columns of the inverse of ZFP's transform
+ * matrix (1/16)[[4,4,4,4],[5,1,-1,-5],[-4,4,4,-4],[-2,6,-6,2]] are
+ * (1/4)(4,4,4,4), (1/4)(6,2,-2,-6), (1/4)(-4,4,4,-4), (1/4)(-1,5,-5,1). */
+static const double kInvColNorm2[4] = {4.0, 5.0, 4.0, 3.25};
+
+double orc_ec_gain(int i, int nd) {
+  double g = 1.0;
+  for (int a = 0; a < nd; a++) g *= kInvColNorm2[(i >> (2 * a)) & 3];
+  return g;
+}
+
+void orc_zfp_block_ec(const double *x, int nd, int dtype, int minexp, int r, uint64_t *nsb2,
+                      uint64_t *nsb_pts, double *err, double *gain, int32_t *emax_out) {
+  const int W = dtype == ORC_F32 ? 32 : 64;
+  const int P = W - 2;
+  const int size = 1 << (2 * nd);
+  int R = 1;
+  while (R < r) R *= 2;
+  int32_t perm[64], pos[64];
+  orc_reorder_table(nd, perm);
+  orc_ec_positions(size, r, pos);
+  for (int k = 0; k < R; k++) {
+    err[k] = 0.0;
+    gain[k] = k < r ? orc_ec_gain(perm[pos[k]], nd) : 1.0;
+  }
+  *nsb2 = 0;
+  *nsb_pts = 0;
+  double m = 0.0;
+  for (int i = 0; i < size; i++)
+    if (fabs(x[i]) > m) m = fabs(x[i]);
+  if (m == 0.0) { /* every coefficient is 0: no bits, no error */
+    *emax_out = INT32_MIN;
+    return;
+  }
+  const int emax = orc_frexp_exponent(m);
+  *emax_out = emax;
+  const int prec = orc_precision(emax, minexp, nd, W);
+  int64_t c[64];
+  for (int i = 0; i < size; i++) c[i] = (int64_t)trunc(ldexp(x[i], P - emax));
+  orc_fwd_xform(c, nd, W);
+  const int kmin = W - prec;
+  const uint64_t keep = kmin >= W ? 0ull : (low_bits(W) & ~((1ull << kmin) - 1ull));
+  uint64_t v[64];
+  for (int k = 0; k < r; k++) {
+    const int64_t coef = c[perm[pos[k]]];
+    const uint64_t u = orc_to_negabinary(coef, W);
+    const int ms = msb64(u);
+    v[k] = ms >= kmin ? (uint64_t)(ms - kmin + 1) : 0;
+    *nsb_pts += v[k];
+    const int64_t kept = orc_from_negabinary(u & keep, W);
+    err[k] = ldexp((double)sub(coef, kept, W), emax - P);
+  }
+  uint64_t twice = 0;
+  for (int k = 0; k < r; k++) twice += 2 * v[k];
+  for (int k = 0; k + 1 < r; k++) twice += (uint64_t)(pos[k + 1] - pos[k] - 1) * (v[k] + v[k + 1]);
+  *nsb2 = twice;
+}
+
+/* ------------------------------------------------------------------ */
 /* SZ side (prediction-based transform, Section 4.1; linear-scaling     */
 /* quantization, Section 5.1)                                           */
 /* ------------------------------------------------------------------ */
@@ -496,11 +577,13 @@ uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins) {
 /* ------------------------------------------------------------------ */
 
 int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,
-            int eb_mode, const int32_t *stride, double sz_offset, int huffman, orc_result *out,
-            orc_dump *dump) {
+            int eb_mode, const int32_t *stride, double sz_offset, int huffman, int ec_points,
+            int ec_weight, orc_result *out, orc_dump *dump) {
   if (!out || !field || !dims || !stride) return -1;
   if (nd < 1 || nd > 3 || (dtype != ORC_F32 && dtype != ORC_F64)) return -1;
   if (op < ORC_OP_SZ || op > ORC_OP_FIXED_EB) return -1;
+  if (ec_points < 0 || ec_points > (1 << (2 * nd))) return -1;
+  const int ec_r = ec_points == 1 ? orc_ec_default_points(nd) : ec_points;
   if (huffman < 0 || huffman > 2) return -1;
   if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != ORC_EB_ABS && eb_mode != ORC_EB_REL)) return -1;
   for (int k = 0; k < nd; k++)
@@ -551,7 +634,51 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
 
   /* lines 5-6: ZFP bit-rate and PSNR on the sampled blocks */
   double br_zfp = 0.0, mse_zfp = 0.0;
-  if (op != ORC_OP_SZ) {
+  if (op != ORC_OP_SZ && ec_r) {
+    /* lines 4-6 as the paper states them: point sub-sampling of the
+     * sampled blocks, interpolated mean significant-bit count, MSE of the
+     * sub-sampled points' transform-domain errors */
+    int R = 1;
+    while (R < ec_r) R *= 2;
+    double *e2 = (double *)malloc((size_t)nblk * R * sizeof(double));
+    uint64_t twice_total = 0, pts_total = 0;
+    double maxerr = 0.0, err[64], gain[64];
+    for (int64_t j = 0; j < nblk; j++) {
+      orc_sampled_block_origin(dims, nd, stride, j, origin);
+      for (int i = 0; i < size; i++)
+        x[i] = load(field, dtype, block_point_index(dims, nd, origin, i, pt));
+      uint64_t twice, pts;
+      int32_t emax;
+      orc_zfp_block_ec(x, nd, dtype, minexp, ec_r, &twice, &pts, err, gain, &emax);
+      twice_total += twice;
+      pts_total += pts;
+      for (int k = 0; k < R; k++) {
+        e2[j * R + k] = ec_weight ? (err[k] * err[k]) * gain[k] : err[k] * err[k];
+        if (fabs(err[k]) > maxerr) maxerr = fabs(err[k]);
+        if (dump && dump->ec_err) dump->ec_err[j * R + k] = err[k];
+      }
+      if (dump && dump->ec_nsb2) dump->ec_nsb2[j] = (uint32_t)twice;
+      if (dump && dump->zfp_emax) dump->zfp_emax[j] = emax;
+    }
+    const int64_t npts = nblk * ec_r;
+    const double sse = orc_tree_sum(e2, nblk * R);
+    free(e2);
+    mse_zfp = sse / (double)npts;
+    br_zfp = (double)twice_total / (double)(2 * nvals);
+    out->flags |= ORC_FLAG_EC_SAMPLED;
+    out->zfp_sse = sse;
+    out->zfp_mse = mse_zfp;
+    out->zfp_bits = 0;
+    out->zfp_values = (uint64_t)nvals;
+    out->zfp_blocks = (uint64_t)nblk;
+    out->zfp_nsb_total = pts_total;
+    out->zfp_nsb_mean = br_zfp;
+    out->zfp_bitrate = br_zfp;
+    out->zfp_maxerr = maxerr;
+    out->zfp_psnr = mse_zfp > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse_zfp) : INFINITY;
+    out->zfp_ec_points = (uint64_t)npts;
+    out->zfp_ec_nsb2 = twice_total;
+  } else if (op != ORC_OP_SZ) {
     uint64_t bits_total = 0, nsb_total = 0;
     double maxerr = 0.0;
     for (int64_t j = 0; j < nblk; j++) {

@@ -30,7 +30,8 @@ enum { ORC_EB_ABS = 0, ORC_EB_REL = 1 };
 enum { ORC_OP_SZ = 0, ORC_OP_ZFP = 1, ORC_OP_SELECT = 2, ORC_OP_FIXED_EB = 3 };
 enum {
   ORC_FLAG_CONSTANT = 1, ORC_FLAG_NONFINITE = 2, ORC_FLAG_ZERO_MSE = 4,
-  ORC_FLAG_EB_EXCEEDS = 8, ORC_FLAG_NO_BLOCKS = 16, ORC_FLAG_BAD_EB = 32
+  ORC_FLAG_EB_EXCEEDS = 8, ORC_FLAG_NO_BLOCKS = 16, ORC_FLAG_BAD_EB = 32,
+  ORC_FLAG_EC_SAMPLED = 128
 };
 
 typedef struct {
@@ -50,6 +51,10 @@ typedef struct {
   /* exact Huffman cost of the code histogram (when requested) */
   uint64_t sz_huffman_bits;
   double sz_huffman_bitrate;
+  /* point sub-sampling of the ZFP side (when requested): sub-sampled points,
+   * and twice the interpolated significant-bit total over all values of the
+   * sampled blocks (an integer) */
+  uint64_t zfp_ec_points, zfp_ec_nsb2;
 } orc_result;
 
 /* Optional per-sample outputs; every pointer may be NULL. */
@@ -60,6 +65,9 @@ typedef struct {
   int32_t *zfp_emax;   /* block exponent (frexp convention), INT32_MIN for an empty block */
   double *sz_sse;      /* SZ squared error of each sampled block */
   uint32_t *hist;      /* 65536 code counts */
+  uint32_t *ec_nsb2;   /* sub-sampling: twice the interpolated significant bits of each block */
+  double *ec_err;      /* sub-sampling: R slots per block (R = r rounded up to a power of two),
+                          the scaled transform-domain error of each sampled point, 0 in the pads */
 } orc_dump;
 
 /* Whole estimator: range, sampling, ZFP side and/or SZ side, selection.
@@ -67,10 +75,35 @@ typedef struct {
  * ORC_OP_FIXED_EB (both sides at the same eb_abs, pick the lower bit-rate).
  * huffman: 0 = no Huffman cost; 1 = also report the exact Huffman cost of
  * the code histogram; 2 = report it and select with it as BR_sz (in place of
- * entropy + offset).  Returns 0, or -1 on invalid arguments. */
+ * entropy + offset).
+ * ec_points: 0 = the exact ZFP estimate (coder bit count, decoded error);
+ * otherwise the paper's point sub-sampling of Section 5.2 with ec_points
+ * points per block (1 = the paper's 3, 9 or 16 for 1, 2 or 3 D; at most
+ * 4^d): BR_zfp is the interpolated mean significant-bit count and MSE_zfp
+ * the mean squared transform-domain truncation error of the sub-sampled
+ * points.  ec_weight: 0 = those errors as the paper states them (its
+ * Theorem 1 assumes a norm-preserving transform); 1 = each squared error
+ * times the squared norm of its coefficient's data-domain image under ZFP's
+ * inverse transform.  Returns 0, or -1 on invalid arguments. */
 int orc_run(int op, const void *field, const int64_t *dims, int ndims, int dtype,
             double eb, int eb_mode, const int32_t *stride, double sz_offset, int huffman,
-            orc_result *out, orc_dump *dump);
+            int ec_points, int ec_weight, orc_result *out, orc_dump *dump);
+
+/* Squared norm of the data-domain image of unit coefficient i (in-block
+ * index) under ZFP's inverse transform: the product over the axes of
+ * 4, 5, 4, 13/4 for frequencies 0..3. */
+double orc_ec_gain(int i, int ndims);
+
+/* The paper's sub-sample size for a rank (3, 9, 16) and the coding-order
+ * positions of r points spread evenly over a block of `size` values. */
+int orc_ec_default_points(int ndims);
+void orc_ec_positions(int size, int r, int32_t *pos);
+/* Sub-sampled estimate of one block: twice the interpolated significant-bit
+ * total (nsb2), the significant bits of the r points (nsb_pts), and their
+ * scaled truncation errors in err[0..R) (R = r rounded up to a power of two,
+ * zeros past r) with their coefficients' gains (orc_ec_gain; 1 past r). */
+void orc_zfp_block_ec(const double *x, int ndims, int dtype, int minexp, int r, uint64_t *nsb2,
+                      uint64_t *nsb_pts, double *err, double *gain, int32_t *emax_out);
 
 /* Total bits of an optimal prefix code for the symbol counts hist[0..nbins)
  * (Huffman): the sum of the internal node weights of a tree built by
