@@ -74,10 +74,12 @@ enum {
   SZSEL_FLAG_EB_EXCEEDS = 8,  /* the SZ bound delta/2 is larger than eb_abs */
   SZSEL_FLAG_NO_BLOCKS = 16,  /* no full 4^d block: nothing estimated, choice = SZ */
   SZSEL_FLAG_BAD_EB = 32,     /* eb_rel * value range is 0 or not finite */
-  SZSEL_FLAG_NO_HUFFMAN = 64  /* Huffman cost requested but not computed: the counts
+  SZSEL_FLAG_NO_HUFFMAN = 64, /* Huffman cost requested but not computed: the counts
                                  took more than 8192 distinct values during the
                                  construction (impossible with at most 2^25 sampled
                                  values), or 2^32 sampled values or more */
+  SZSEL_FLAG_EC_SAMPLED = 128 /* the ZFP side is the point sub-sampling estimate
+                                 (SZSEL_OPT_EC_SAMPLING) */
 };
 
 /* Result of one request.  Bit-rates are bits per value, PSNRs in dB, MSEs in
@@ -103,6 +105,10 @@ typedef struct {
    * W raw bits per unpredictable point; 0 when not requested */
   uint64_t sz_huffman_bits;
   double sz_huffman_bitrate;
+  /* ZFP point sub-sampling (SZSEL_OPT_EC_SAMPLING): points sub-sampled, and
+   * twice the interpolated significant-bit total of all values of the
+   * sampled blocks (an integer); 0 otherwise */
+  uint64_t zfp_ec_points, zfp_ec_nsb2;
 } szsel_result;
 
 /* One request of a batch (szsel_select_batch). */
@@ -210,10 +216,25 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   0.5 bits/value offset of Section 6.2 stands in for) into
  *   sz_huffman_bits / sz_huffman_bitrate; 2 computes it and selects with it
  *   as BR_sz in place of entropy + offset.  The minimum cost is unique, so
- *   the result does not depend on how the tree is built. */
+ *   the result does not depend on how the tree is built.
+ * SZSEL_OPT_EC_SAMPLING: 0 (default) the exact ZFP estimate (coder bit count
+ *   of every sampled block, error after decoding); 1 the paper's cheaper
+ *   estimate (Section 5.2.1-5.2.2, Algorithm 1 lines 4-6): 3, 9 or 16
+ *   coefficients per 1-, 2- or 3-D block, spread evenly over the coding
+ *   order (position round(k (4^d - 1)/(r - 1))); BR_zfp = the mean
+ *   significant-bit count with the other positions interpolated linearly;
+ *   MSE_zfp = the mean squared truncation error of the sampled coefficients
+ *   scaled by 2^(emax - P); 2 as 1 with each squared error weighted by the
+ *   squared norm of its coefficient's data-domain image under ZFP's inverse
+ *   transform (products of 4, 5, 4, 13/4 per axis), which the paper's
+ *   norm-preservation argument leaves out.  zfp_bits is then 0, zfp_nsb_total
+ *   counts the sampled points only, zfp_bitrate = zfp_nsb_mean =
+ *   zfp_ec_nsb2 / (2 zfp_values), zfp_mse = zfp_sse / zfp_ec_points, and the
+ *   flag SZSEL_FLAG_EC_SAMPLED is set. */
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
-       SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9 };
+       SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9,
+       SZSEL_OPT_EC_SAMPLING = 10 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* Phase timers: synchronises the recorded events and returns, per phase

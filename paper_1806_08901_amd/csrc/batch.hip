@@ -171,7 +171,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
         if (tg[a] != tg[b]) return false;
         const ReqDesc &x = p.tab[a], &y = p.tab[b];
         if (ps == kBatchRange) return x.dtype == y.dtype;
-        return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec;
+        return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec && (x.ec != 0) == (y.ec != 0);
       };
       while (e < n && same_class(k, e)) e++;
       BatchLaunch L;
@@ -180,6 +180,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       L.dtype = p.tab[k].dtype;
       L.nd = p.tab[k].nd;
       L.vec = p.tab[k].vec;
+      L.ec = p.tab[k].ec != 0;
       L.tab = nullptr;
       L.first = nullptr;
       L.c0 = k;
@@ -208,7 +209,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
   for (uint32_t v : p.first) p.sig.push_back(v);
   for (const BatchLaunch &L : p.launches)
     p.sig.push_back(((uint64_t)L.group << 59) | ((uint64_t)L.pass << 56) | ((uint64_t)L.dtype << 52) | ((uint64_t)L.nd << 48) |
-                    ((uint64_t)L.vec << 47) | ((uint64_t)L.grid << 24) | ((uint64_t)L.c0 << 12) | (uint64_t)L.c1);
+                    ((uint64_t)L.vec << 47) | ((uint64_t)L.ec << 46) | ((uint64_t)L.grid << 24) |
+                    ((uint64_t)L.c0 << 12) | (uint64_t)L.c1);
   for (size_t v : p.voff) p.sig.push_back(v);
   return SZSEL_OK;
 }

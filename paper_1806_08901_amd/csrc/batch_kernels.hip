@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *tab, const u
   range_wg<T>(tab[i], local, L);
 }
 
-template <typename T, int D, bool VEC>
+template <typename T, int D, bool VEC, bool EC>
 __global__ __launch_bounds__(kWave, 2) void kb_zfp(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kWave, 2) void kb_zfp(const ReqDesc *tab, const uin
   const int i = batch_item(first, c0, c1, s_first, local);
   const ReqDesc &r = tab[i];
   if (skip_request(r.st)) return;
-  zfp_wg<T, D, VEC>(r, local, L);
+  zfp_wg<T, D, VEC, EC>(r, local, L);
 }
 
 template <typename T, int D, bool VEC>
@@ -151,10 +151,16 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
       hipLaunchKernelGGL((kb_range<T>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
     case kBatchZfp:
-      if (a.vec)
-        hipLaunchKernelGGL((kb_zfp<T, D, true>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
-      else
-        hipLaunchKernelGGL((kb_zfp<T, D, false>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
+      if (a.ec) {
+        if (a.vec)
+          hipLaunchKernelGGL((kb_zfp<T, D, true, true>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
+        else
+          hipLaunchKernelGGL((kb_zfp<T, D, false, true>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
+      } else if (a.vec) {
+        hipLaunchKernelGGL((kb_zfp<T, D, true, false>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
+      } else {
+        hipLaunchKernelGGL((kb_zfp<T, D, false, false>), grid, dim3(kWave), 0, s, a.tab, a.first, a.c0, a.c1);
+      }
       break;
     case kBatchSz:
       if (a.vec)

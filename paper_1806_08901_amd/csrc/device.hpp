@@ -137,7 +137,7 @@ struct ReqDesc {
   int32_t nshare;  // batches: requests right after this one in the table that share its range scan
   int32_t nhc;     // global histogram copies in use (power of two <= kHistCopies)
   int32_t huff;    // 0 no Huffman cost, 1 report it, 2 report and select with it
-  int32_t pad2;
+  int32_t ec;      // ZFP side: 0 exact, 1 point sub-sampling, 2 sub-sampling with gain weights
   ReqState *st;
   PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;

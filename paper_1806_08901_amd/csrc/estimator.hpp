@@ -444,7 +444,92 @@ struct ZfpLane {
   int emax;
 };
 
-template <typename T, int D, bool VEC>
+// Point sub-sampling of the ZFP side (Sections 5.2.1, 5.2.2): kPts of the
+// 4^D coefficients at coding positions round(k (4^D - 1) / (kPts - 1)),
+// halves up, and for each the squared norm of its data-domain image under
+// the inverse transform (per axis 4, 5, 4, 13/4 for frequencies 0..3: the
+// column norms of the inverse of (1/16)[[4,4,4,4],[5,1,-1,-5],[-4,4,4,-4],
+// [-2,6,-6,2]]).
+template <int D> struct EcTable {
+  static constexpr int kSize = 1 << (2 * D);
+  static constexpr int kPts = D == 1 ? 3 : (D == 2 ? 9 : 16);
+  static constexpr int kSlots = D == 1 ? 4 : 16;  // kPts rounded up to a power of two
+  int pos[kPts];      // coding positions sampled
+  int coef[kPts];     // in-block coefficient coded there
+  double gain[kPts];  // its squared data-domain norm
+  constexpr EcTable() : pos(), coef(), gain() {
+    const double g1[4] = {4.0, 5.0, 4.0, 3.25};
+    for (int k = 0; k < kPts; k++) {
+      pos[k] = (2 * k * (kSize - 1) + (kPts - 1)) / (2 * (kPts - 1));
+      coef[k] = Order<D>::table.perm[pos[k]];
+      double g = 1.0;
+      for (int a = 0; a < D; a++) g *= g1[(coef[k] >> (2 * a)) & 3];
+      gain[k] = g;
+    }
+  }
+};
+template <int D> struct Ec {
+  static constexpr EcTable<D> table{};
+};
+
+// The sub-sampled estimate of one block from its negabinary coefficients:
+// significant bits of each sampled coefficient within the coded planes, the
+// other positions filled by linear interpolation (a gap of g positions
+// between counts va and vb adds g (va + vb) / 2, so twice the block's total
+// is an integer: `bits`), and each sampled coefficient's truncation error
+// (the value of its digits below the last coded plane) scaled by
+// 2^(emax - P), squared, optionally weighted by its gain, and summed by the
+// pair tree over kSlots slots (zeros past kPts).
+template <typename T, int D>
+__device__ inline ZfpLane zfp_block_ec(const typename Prec<T>::I *c, int prec, int emax, bool empty,
+                                       bool weighted) {
+  using Q = Prec<T>;
+  using U = typename Q::U;
+  using I = typename Q::I;
+  using E = Ec<D>;
+  constexpr int NP = EcTable<D>::kPts, R = EcTable<D>::kSlots;
+  constexpr int W = Q::W;
+  const int kmin = W - prec;
+  const U keep = kmin >= W ? U(0) : (~U(0) << kmin);
+  uint32_t v[NP];
+  double sq[R];
+  double mx = 0.0;
+  uint32_t pts = 0;
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const U u = (U)c[E::table.coef[k]];
+    const int m = u ? W - clz_u(u) : 0;
+    v[k] = m > kmin ? (uint32_t)(m - kmin) : 0u;
+    pts += v[k];
+    const I e = (I)((((U)(u & ~keep)) ^ Q::NB) - Q::NB);
+    const double es = ldexp((double)e, emax - Q::P);
+    mx = fmax(mx, fabs(es));
+    double s2 = es * es;
+    if (weighted) s2 = s2 * E::table.gain[k];
+    sq[k] = s2;
+  }
+#pragma unroll
+  for (int k = NP; k < R; k++) sq[k] = 0.0;
+#pragma unroll
+  for (int w = R; w > 1; w >>= 1) {
+#pragma unroll
+    for (int k = 0; k < w / 2; k++) sq[k] = sq[2 * k] + sq[2 * k + 1];
+  }
+  uint32_t twice = 0;
+#pragma unroll
+  for (int k = 0; k < NP; k++) twice += 2u * v[k];
+#pragma unroll
+  for (int k = 0; k + 1 < NP; k++) twice += (uint32_t)(E::table.pos[k + 1] - E::table.pos[k] - 1) * (v[k] + v[k + 1]);
+  ZfpLane out;
+  out.emax = empty ? INT32_MIN : emax;
+  out.bits = twice;
+  out.nsb = pts;
+  out.sse = sq[0];
+  out.maxerr = mx;
+  return out;
+}
+
+template <typename T, int D, bool VEC, bool EC>
 __device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int32_t *minexp_p) {
   using Q = Prec<T>;
   using U = typename Q::U;
@@ -480,6 +565,7 @@ __device__ inline ZfpLane zfp_block_lane(const ReqDesc &r, int64_t j, const int3
   fwd_xform<D>(c);
 #pragma unroll
   for (int i = 0; i < BS; i++) c[i] = (I)(((U)c[i] + Q::NB) ^ Q::NB);
+  if constexpr (EC) return zfp_block_ec<T, D>(c, prec, emax, empty, r.ec == 2);
 
   // Group-testing embedded coding of planes W-1 .. kmin, counted without
   // running the coder.  With msb_k the highest set bit of the coefficient
@@ -634,7 +720,10 @@ __device__ inline void wg_acc_store(TileLds &L, const LaneAcc &acc, const Parts 
 
 // ZFP totals, PSNR_zfp and (for Algorithm 1) the SZ bin width delta whose
 // uniform-error PSNR equals PSNR_zfp (Eq. 10 inverted: delta = sqrt(12 MSE)).
-template <typename T, int D>
+// With EC the totals are the sub-sampled ones: `bits` is twice the
+// interpolated significant-bit total, `nsb` the sampled points' bits, `sse`
+// over the sampled points.
+template <typename T, int D, bool EC>
 __device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
   const double sse = tot.s, maxerr = tot.m;
   const uint64_t bits = tot.a, nsb = tot.b;
@@ -642,17 +731,32 @@ __device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
     constexpr int BS = 1 << (2 * D);
     ReqState *st = r.st;
     szsel_result *res = r.res;
-    const double nv = (double)(r.nblk * BS);
-    const double mse = sse / nv;
+    const uint64_t nvals = (uint64_t)(r.nblk * BS);
+    const double nv = (double)nvals;
     const double vr = get_f64(&st->vr);
+    double mse;
+    if constexpr (EC) {
+      const uint64_t npts = (uint64_t)r.nblk * EcTable<D>::kPts;
+      mse = sse / (double)npts;
+      const double br = (double)bits / (double)(2 * nvals);
+      put_u64(&res->zfp_bits, 0);
+      put_u64(&res->zfp_ec_points, npts);
+      put_u64(&res->zfp_ec_nsb2, bits);
+      put_f64(&res->zfp_nsb_mean, br);
+      put_f64(&res->zfp_bitrate, br);
+      const uint64_t fc = get_u64((uint64_t *)&res->flags);
+      put_u64((uint64_t *)&res->flags, fc | SZSEL_FLAG_EC_SAMPLED);
+    } else {
+      mse = sse / nv;
+      put_u64(&res->zfp_bits, bits);
+      put_f64(&res->zfp_nsb_mean, (double)nsb / nv);
+      put_f64(&res->zfp_bitrate, (double)bits / nv);
+    }
     put_f64(&res->zfp_sse, sse);
     put_f64(&res->zfp_mse, mse);
-    put_u64(&res->zfp_bits, bits);
-    put_u64(&res->zfp_values, (uint64_t)(r.nblk * BS));
+    put_u64(&res->zfp_values, nvals);
     put_u64(&res->zfp_blocks, (uint64_t)r.nblk);
     put_u64(&res->zfp_nsb_total, nsb);
-    put_f64(&res->zfp_nsb_mean, (double)nsb / nv);
-    put_f64(&res->zfp_bitrate, (double)bits / nv);
     put_f64(&res->zfp_maxerr, maxerr);
     put_f64(&res->zfp_psnr, mse > 0.0 ? 20.0 * log10(vr) - 10.0 * log10(mse) : INFINITY);
     if (r.op == SZSEL_OP_SELECT) {
@@ -675,7 +779,7 @@ __device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
 // sampled blocks of its aligned chunk, one block per lane; the round sums
 // (wave butterfly) are folded with the binary counter.  Returns true in the
 // workgroup that ran the finalizer.
-template <typename T, int D, bool VEC>
+template <typename T, int D, bool VEC, bool EC>
 __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
   const int lane = threadIdx.x;
   const int rounds = r.zblk / kWave;
@@ -690,7 +794,7 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
     }
     const int64_t j = base + lane;
     const bool active = j < r.nblk;
-    const ZfpLane z = zfp_block_lane<T, D, VEC>(r, j, &r.st->minexp);
+    const ZfpLane z = zfp_block_lane<T, D, VEC, EC>(r, j, &r.st->minexp);
     double s = 0.0;
     if (active) {
       bits += z.bits;
@@ -715,7 +819,7 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
   }
   Part tot;
   if (!pass_complete<false>(r.zp, r.grp[kPassZfp], r.sync + kPassZfp, w, r.nzfp, L, tot)) return false;
-  zfp_finalize<T, D>(r, tot);
+  zfp_finalize<T, D, EC>(r, tot);
   return true;
 }
 

@@ -21,11 +21,12 @@ __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
 // Two waves per SIMD (at most 256 registers each) so that every wave of a
 // request's ZFP pass is resident at once.
 // VEC: rows of 4 values start 16-byte aligned and are read as vectors.
-template <typename T, int D, bool VEC>
+// EC: the paper's point sub-sampling estimate instead of the exact one.
+template <typename T, int D, bool VEC, bool EC>
 __global__ __launch_bounds__(kWave, 2) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
-  zfp_wg<T, D, VEC>(r, blockIdx.x, L);
+  zfp_wg<T, D, VEC, EC>(r, blockIdx.x, L);
 }
 
 template <typename T, int D, bool VEC>
@@ -65,10 +66,16 @@ template <typename T, int D>
 static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t *ev) {
   hipError_t e = hipSuccess;
   if (r.op != SZSEL_OP_SZ) {
-    if (r.vec)
-      hipLaunchKernelGGL((k_zfp<T, D, true>), dim3(r.nzfp), dim3(kWave), 0, s, r);
-    else
-      hipLaunchKernelGGL((k_zfp<T, D, false>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    if (r.ec) {
+      if (r.vec)
+        hipLaunchKernelGGL((k_zfp<T, D, true, true>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+      else
+        hipLaunchKernelGGL((k_zfp<T, D, false, true>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    } else if (r.vec) {
+      hipLaunchKernelGGL((k_zfp<T, D, true, false>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    } else {
+      hipLaunchKernelGGL((k_zfp<T, D, false, false>), dim3(r.nzfp), dim3(kWave), 0, s, r);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

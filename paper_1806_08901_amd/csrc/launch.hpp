@@ -33,7 +33,7 @@ inline size_t request_var_bytes(const ReqDesc &r) {
 // batch_kernels.hip); `items` workgroups in total.
 enum { kBatchRange = 0, kBatchZfp, kBatchSz, kBatchOvf, kBatchEnt, kBatchHuff, kBatchPasses };
 struct BatchLaunch {
-  int group, pass, dtype, nd, vec;
+  int group, pass, dtype, nd, vec, ec;
   const ReqDesc *tab;
   const uint32_t *first;
   int c0, c1;

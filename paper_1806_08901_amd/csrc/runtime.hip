@@ -41,6 +41,7 @@ struct szsel_ctx {
   int next = 0;
   double sz_offset = 0.5;
   int huffman = 0;
+  int ec = 0;
   szsel_debug dbg{};
   bool dbg_armed = false;
   std::string err;
@@ -97,6 +98,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   r.eb = eb;
   r.sz_offset = ctx->sz_offset;
   r.huff = ctx->huffman;
+  r.ec = ctx->ec;
   int64_t n = 1;
   uint64_t nblk = 1;
   for (int k = 0; k < nd; k++) {
@@ -424,6 +426,11 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
   if (option == SZSEL_OPT_HUFFMAN) {
     if (value != 0.0 && value != 1.0 && value != 2.0) return fail(c, SZSEL_EINVAL, "Huffman option: 0, 1 or 2");
     c->huffman = (int)value;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_EC_SAMPLING) {
+    if (value != 0.0 && value != 1.0 && value != 2.0) return fail(c, SZSEL_EINVAL, "EC sampling option: 0, 1 or 2");
+    c->ec = (int)value;
     return SZSEL_OK;
   }
   if (option == SZSEL_OPT_AUTOTUNE) {

@@ -13,7 +13,7 @@ EXACT_KEYS = [
     "zfp_bitrate", "zfp_nsb_mean", "zfp_maxerr",
     "sz_delta", "sz_inv_delta", "sz_eb", "sz_sse", "sz_mse", "sz_maxerr",
     "sz_values", "sz_unpredictable", "chosen_eb",
-    "sz_huffman_bits", "sz_huffman_bitrate",
+    "sz_huffman_bits", "sz_huffman_bitrate", "zfp_ec_points", "zfp_ec_nsb2",
 ]
 # Results that go through log2 / log10 (device and host math libraries may
 # differ in the last bits): 1e-9 relative.

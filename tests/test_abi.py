@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_result_layout_matches_header():
     # 2 x u32, 4 doubles, 2 x i32, 6 doubles, 4 u64, 10 doubles, 2 u64, 1 double
-    assert ctypes.sizeof(szsel.Result) == 8 + 32 + 8 + 48 + 32 + 80 + 16 + 8 + 16
+    assert ctypes.sizeof(szsel.Result) == 8 + 32 + 8 + 48 + 32 + 80 + 16 + 8 + 16 + 16
     assert ctypes.sizeof(szsel.Request) == 8 + 24 + 8 + 8 + 8 + 12 + 4
 
 
