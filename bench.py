@@ -455,6 +455,40 @@ def main():
     ctx.set_option(szsel.OPT_HUFFMAN, 0)
     ent_huff_ms = hprof["ent"][0] / max(1, hprof["ent"][1])
 
+    # the paper's point sub-sampling of the ZFP side (an option): its ZFP
+    # pass time and how far its estimates land from the exact ones
+    ec = {}
+    for mode in (1, 2):
+        ctx.set_option(szsel.OPT_EC_SAMPLING, mode)
+        ec_results = [ctx.select(field, eb, stride=stride) for eb in ebs]
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.steps):
+            step()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_ec = t0.elapsed_time(t1) / args.steps
+        ctx.set_option(szsel.OPT_PROFILE, 1)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        eprof = ctx.profile_read()
+        ctx.set_option(szsel.OPT_PROFILE, 0)
+        ctx.set_option(szsel.OPT_EC_SAMPLING, 0)
+        ec["plain" if mode == 1 else "gain_weighted"] = {
+            "ms_per_step": round(ms_ec, 4),
+            "zfp_pass_ms": round(eprof["zfp"][0] / max(1, eprof["zfp"][1]), 5),
+            "bitrate_zfp": [round(r["zfp_bitrate"], 4) for r in ec_results],
+            "psnr_zfp": [round(r["zfp_psnr"], 3) for r in ec_results],
+            "choices": [r["choice"] for r in ec_results],
+        }
+    ec["exact"] = {"zfp_pass_ms": round(phase_ms["zfp"], 5),
+                   "bitrate_zfp": [round(r["zfp_bitrate"], 4) for r in gpu_results],
+                   "psnr_zfp": [round(r["zfp_psnr"], 3) for r in gpu_results],
+                   "choices": [r["choice"] for r in gpu_results]}
+
     # latency of one synchronous select call (host wall clock)
     lat = []
     for k in range(args.latency_calls):
@@ -512,6 +546,9 @@ def main():
             "bitrate": [round(r["sz_huffman_bitrate"], 5) for r in huff_results],
             "entropy_plus_offset": [round(r["sz_bitrate"], 5) for r in huff_results],
         },
+        "ec_sampling": dict(ec, what="SZSEL_OPT_EC_SAMPLING 1 (the paper's 3/9/16-point sub-sampling, "
+                                     "transform-domain MSE) and 2 (MSE weighted by the inverse "
+                                     "transform's column norms), against the exact estimate"),
     }
 
     if not args.no_cpu_baseline:
