@@ -47,6 +47,14 @@ class Result(C.Structure):
     ]
 
 
+class Step4(C.Structure):
+    _fields_ = [
+        ("bits", C.c_uint64), ("values", C.c_uint64), ("blocks", C.c_uint64),
+        ("bitrate", C.c_double), ("sse", C.c_double), ("mse", C.c_double), ("psnr", C.c_double),
+        ("maxerr", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double),
+    ]
+
+
 class Dump(C.Structure):
     _fields_ = [
         ("codes", C.c_void_p), ("zfp_bits", C.c_void_p), ("zfp_sse", C.c_void_p),
@@ -76,6 +84,10 @@ def lib():
         P, I64P, I32P = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)
         L.orc_run.argtypes = [C.c_int, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
                               C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(Result), C.POINTER(Dump)]
+        L.orc_zfp_compress.argtypes = [P, I64P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_uint8),
+                                       C.c_int64, C.POINTER(C.c_double), C.POINTER(Step4)]
+        L.orc_zfp_num_blocks.argtypes = [I64P, C.c_int]
+        L.orc_zfp_num_blocks.restype = C.c_int64
         L.orc_ec_gain.argtypes = [C.c_int, C.c_int]
         L.orc_ec_gain.restype = C.c_double
         L.orc_ec_default_points.argtypes = [C.c_int]
@@ -338,3 +350,35 @@ def entropy(hist, n=None) -> float:
     if n is None:
         n = int(h.sum())
     return lib().orc_entropy(_ptr(h, C.c_uint32), len(h), n)
+
+
+def zfp_compress(field: np.ndarray, eb_abs: float):
+    """Step 4, ZFP: (result dict, stream as little-endian uint64 words,
+    decompressed field as float64)."""
+    field = np.ascontiguousarray(field)
+    dims = np.array(field.shape, dtype=np.int64)
+    out = Step4()
+    L = lib()
+    rc = L.orc_zfp_compress(field.ctypes.data, _ptr(dims, C.c_int64), field.ndim, _dtype_code(field),
+                            float(eb_abs), None, 0, None, C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    nbits = int(out.bits)
+    bits = np.zeros(max(nbits, 1), np.uint8)
+    dec = np.zeros(field.size, np.float64)
+    rc = L.orc_zfp_compress(field.ctypes.data, _ptr(dims, C.c_int64), field.ndim, _dtype_code(field),
+                            float(eb_abs), _ptr(bits, C.c_uint8), nbits, _ptr(dec, C.c_double),
+                            C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle compression failed (%d)" % rc)
+    nwords = (nbits + 63) // 64
+    packed = np.zeros(nwords * 8, np.uint8)
+    pb = np.packbits(bits[:nbits], bitorder="little")
+    packed[:pb.size] = pb
+    res = {name: getattr(out, name) for name, _ in Step4._fields_}
+    return res, packed.view("<u8"), dec.reshape(field.shape)
+
+
+def zfp_num_blocks(shape) -> int:
+    d = np.array(shape, np.int64)
+    return int(lib().orc_zfp_num_blocks(_ptr(d, C.c_int64), len(shape)))

@@ -799,3 +799,191 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
   free(err2);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Step 4 (Algorithm 1 lines 11-13): ZFP compression of the whole      */
+/* field at eb_abs, and its decompression                               */
+/* ------------------------------------------------------------------ */
+
+/* Stream: the bits in order, bit i in bit (i mod 64) of 64-bit word i/64
+ * (here one byte per bit).  Blocks in row-major block order over
+ * ceil(n_k / 4) blocks per axis; a block's positions past the field's
+ * upper faces repeat the field's last value along that axis.  A block:
+ * one bit (0: coded as zero, when all values are 0 or no plane is kept;
+ * 1: coded), then E bits of emax + 2^(E-1) - 1 (lowest bit first; emax
+ * is at least 2 - 2^(E-1), ZFP's smallest normal exponent), then the
+ * group-testing code of planes W-1 .. W-prec. */
+
+static void put_bits(uint8_t *bits, int64_t cap, int64_t *pos, uint64_t v, int n) {
+  for (int b = 0; b < n; b++) {
+    if (bits && *pos < cap) bits[*pos] = (uint8_t)((v >> b) & 1u);
+    (*pos)++;
+  }
+}
+
+static int get_bit(const uint8_t *bits, int64_t nbits, int64_t *pos) {
+  int b = *pos < nbits ? bits[*pos] : 0;
+  (*pos)++;
+  return b;
+}
+
+/* Gathers block (row-major block index jb) with edge repetition. */
+static void gather_block(const void *field, const int64_t *dims, int nd, int dtype, int64_t jb,
+                         double *x, int64_t *lin, int *valid) {
+  int64_t nb[3], bo[3];
+  for (int k = 0; k < nd; k++) nb[k] = (dims[k] + 3) / 4;
+  int64_t rem = jb;
+  for (int k = nd - 1; k >= 0; k--) {
+    bo[k] = 4 * (rem % nb[k]);
+    rem /= nb[k];
+  }
+  const int size = 1 << (2 * nd);
+  for (int i = 0; i < size; i++) {
+    int64_t l = 0;
+    int ok = 1;
+    for (int k = 0; k < nd; k++) {
+      int off = (i >> (2 * (nd - 1 - k))) & 3;
+      int64_t p = bo[k] + off;
+      if (p >= dims[k]) {
+        p = dims[k] - 1;
+        ok = 0;
+      }
+      l = l * dims[k] + p;
+    }
+    x[i] = load(field, dtype, l);
+    lin[i] = l;
+    valid[i] = ok;
+  }
+}
+
+int64_t orc_zfp_num_blocks(const int64_t *dims, int nd) {
+  int64_t n = 1;
+  for (int k = 0; k < nd; k++) n *= (dims[k] + 3) / 4;
+  return n;
+}
+
+/* Encodes one gathered block; returns the number of bits. */
+static int64_t zfp_encode_block(const double *x, int nd, int dtype, int minexp, uint8_t *bits,
+                                int64_t cap, int64_t pos0) {
+  const int W = dtype == ORC_F32 ? 32 : 64;
+  const int P = W - 2;
+  const int E = dtype == ORC_F32 ? 8 : 11;
+  const int bias = (1 << (E - 1)) - 1;
+  const int size = 1 << (2 * nd);
+  int64_t pos = pos0;
+  double m = 0.0;
+  for (int i = 0; i < size; i++)
+    if (fabs(x[i]) > m) m = fabs(x[i]);
+  int emax = m > 0.0 ? orc_frexp_exponent(m) : 0;
+  if (emax < 1 - bias) emax = 1 - bias;
+  const int prec = m > 0.0 ? orc_precision(emax, minexp, nd, W) : 0;
+  if (prec == 0) {
+    put_bits(bits, cap, &pos, 0, 1);
+    return pos - pos0;
+  }
+  put_bits(bits, cap, &pos, 1, 1);
+  put_bits(bits, cap, &pos, (uint64_t)(emax + bias), E);
+  int64_t c[64];
+  for (int i = 0; i < size; i++) c[i] = (int64_t)trunc(ldexp(x[i], P - emax));
+  orc_fwd_xform(c, nd, W);
+  int32_t perm[64];
+  orc_reorder_table(nd, perm);
+  uint64_t u[64];
+  for (int r = 0; r < size; r++) u[r] = orc_to_negabinary(c[perm[r]], W);
+  int64_t nb = orc_encode_planes(u, size, W, prec, bits ? bits + pos : NULL,
+                                 bits ? (cap > pos ? cap - pos : 0) : 0);
+  return pos + nb - pos0;
+}
+
+/* Decodes one block from the stream at *pos (advanced past it). */
+static void zfp_decode_block(const uint8_t *bits, int64_t nbits, int64_t *pos, int nd, int dtype,
+                             int minexp, double *xhat) {
+  const int W = dtype == ORC_F32 ? 32 : 64;
+  const int P = W - 2;
+  const int E = dtype == ORC_F32 ? 8 : 11;
+  const int bias = (1 << (E - 1)) - 1;
+  const int size = 1 << (2 * nd);
+  for (int i = 0; i < size; i++) xhat[i] = 0.0;
+  if (!get_bit(bits, nbits, pos)) return;
+  uint64_t e = 0;
+  for (int b = 0; b < E; b++) e |= (uint64_t)get_bit(bits, nbits, pos) << b;
+  const int emax = (int)e - bias;
+  const int prec = orc_precision(emax, minexp, nd, W);
+  uint64_t u[64] = {0};
+  int n = 0;
+  for (int k = W - 1; k >= W - prec; k--) {
+    const uint64_t one = 1ull << k;
+    for (int i = 0; i < n; i++)
+      if (get_bit(bits, nbits, pos)) u[i] |= one;
+    int p = n;
+    while (p < size) {
+      if (!get_bit(bits, nbits, pos)) break; /* no further value gains this plane */
+      while (p < size - 1 && !get_bit(bits, nbits, pos)) p++;
+      u[p] |= one; /* read as 1, or implied at the last position */
+      p++;
+      n = p;
+    }
+  }
+  int32_t perm[64];
+  orc_reorder_table(nd, perm);
+  int64_t d[64];
+  for (int r = 0; r < size; r++) d[perm[r]] = orc_from_negabinary(u[r], W);
+  orc_inv_xform(d, nd, W);
+  for (int i = 0; i < size; i++) xhat[i] = to_dtype(ldexp((double)d[i], emax - P), dtype);
+}
+
+int orc_zfp_compress(const void *field, const int64_t *dims, int nd, int dtype, double eb_abs,
+                     uint8_t *bits, int64_t cap, double *decoded, orc_step4 *out) {
+  if (!field || !dims || !out || nd < 1 || nd > 3) return -1;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return -1;
+  if (!(eb_abs > 0.0) || !isfinite(eb_abs)) return -1;
+  for (int k = 0; k < nd; k++)
+    if (dims[k] < 1) return -1;
+  memset(out, 0, sizeof(*out));
+  const int64_t N = prod(dims, nd);
+  double vmin, vmax;
+  if (orc_range(field, N, dtype, &vmin, &vmax)) return -1;
+  const int minexp = orc_floor_log2(eb_abs);
+  const int size = 1 << (2 * nd);
+  const int64_t nblocks = orc_zfp_num_blocks(dims, nd);
+  double *e2 = (double *)calloc((size_t)nblocks * size, sizeof(double));
+  double x[64], xh[64];
+  int64_t lin[64];
+  int valid[64];
+  int64_t pos = 0;
+  double maxerr = 0.0;
+  for (int64_t jb = 0; jb < nblocks; jb++) {
+    gather_block(field, dims, nd, dtype, jb, x, lin, valid);
+    const int64_t start = pos;
+    pos += zfp_encode_block(x, nd, dtype, minexp, bits, cap, pos);
+    if (bits && pos <= cap) { /* decode from the stream itself */
+      int64_t rp = start;
+      zfp_decode_block(bits, pos, &rp, nd, dtype, minexp, xh);
+      if (rp != pos) {
+        free(e2);
+        return -2; /* the decoder read a different number of bits */
+      }
+      for (int i = 0; i < size; i++)
+        if (valid[i]) {
+          const double e = x[i] - xh[i];
+          e2[jb * size + i] = e * e;
+          if (fabs(e) > maxerr) maxerr = fabs(e);
+          if (decoded) decoded[lin[i]] = xh[i];
+        }
+    }
+  }
+  out->bits = (uint64_t)pos;
+  out->values = (uint64_t)N;
+  out->blocks = (uint64_t)nblocks;
+  out->bitrate = (double)pos / (double)N;
+  out->vr = vmax - vmin;
+  out->eb_abs = eb_abs;
+  if (bits && pos <= cap) {
+    out->sse = orc_tree_sum(e2, nblocks * size);
+    out->mse = out->sse / (double)N;
+    out->maxerr = maxerr;
+    out->psnr = out->mse > 0.0 ? 20.0 * log10(out->vr) - 10.0 * log10(out->mse) : INFINITY;
+  }
+  free(e2);
+  return 0;
+}

@@ -111,6 +111,23 @@ void orc_zfp_block_ec(const double *x, int ndims, int dtype, int minexp, int r, 
  * occurrence; no symbol, 0. */
 uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins);
 
+/* Step 4 (Algorithm 1 lines 11-13): compressing the whole field. */
+typedef struct {
+  uint64_t bits, values, blocks;
+  double bitrate, sse, mse, psnr, maxerr, vr, eb_abs;
+} orc_step4;
+
+/* ZFP fixed-accuracy compression of every block of the field at eb_abs
+ * (partial blocks repeat the last value along each axis), one byte per
+ * stream bit into bits[0..cap) (NULL: count only), then each block decoded
+ * from the stream; decoded (N values, may be NULL) receives the
+ * decompressed field.  SSE: pair tree over the blocks' 4^d slots (zeros at
+ * padded positions).  Returns 0, -1 on bad arguments, -2 if a block does
+ * not decode to the bits it was coded in. */
+int orc_zfp_compress(const void *field, const int64_t *dims, int ndims, int dtype, double eb_abs,
+                     uint8_t *bits, int64_t cap, double *decoded, orc_step4 *out);
+int64_t orc_zfp_num_blocks(const int64_t *dims, int ndims);
+
 /* ---- pieces exposed for the pin tests ---- */
 int orc_range(const void *field, int64_t n, int dtype, double *vmin, double *vmax);
 int64_t orc_num_sampled_blocks(const int64_t *dims, int ndims, const int32_t *stride);
