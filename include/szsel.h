@@ -237,6 +237,44 @@ enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_EC_SAMPLING = 10 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
+/* ---------------------------------------------------------------------
+ * Step 4 (Algorithm 1 lines 11-13): compressing the whole field with the
+ * chosen compressor, for the true bit-rate and PSNR behind an estimate.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  uint64_t bits;              /* compressed size in bits */
+  uint64_t values, blocks;    /* values of the field, 4^d blocks coded */
+  double bitrate;             /* bits / values */
+  double sse, mse, psnr, maxerr;  /* decompressed field against the input; PSNR with VR below */
+  double vr, eb_abs;          /* value range of the field, the bound used */
+} szsel_compressed;
+
+/* Bytes of stream buffer szsel_zfp_compress needs for a field (a bound on
+ * the stream plus two spare words); 0 for invalid arguments. */
+size_t szsel_zfp_stream_bytes(const int64_t *dims, int ndims, int dtype);
+
+/* ZFP fixed-accuracy compression at eb_abs of every 4^d block of the field
+ * (Section 4.2 transform, Section 5.2 embedded coding; the same blocks the
+ * estimator samples, padded at the upper faces by repeating the last value
+ * along each axis), and its decompression.  Stream format: bit i is bit
+ * (i mod 64) of 64-bit word i/64; blocks in row-major block order; a block
+ * is one 0 bit (all zero or no plane kept), or a 1, E = 8/11 bits of
+ * emax + 2^(E-1) - 1 (lowest first; emax at least the smallest normal
+ * exponent) and the group-testing code of planes W-1 .. W-prec, prec =
+ * emax - floor(log2 eb_abs) + 2(d+1) clamped to [0, W].  On whole blocks the
+ * stream holds exactly the bits the estimator counts at stride 1.
+ *   field        device pointer, C order, dims[0..ndims) slowest first
+ *   stream_buf   device buffer (8-byte aligned) of stream_bytes >=
+ *                szsel_zfp_stream_bytes(); receives the stream
+ *   decoded      device buffer of the field's size and dtype for the
+ *                decompressed field, or NULL
+ *   out          host; filled when the call returns (the call waits for the
+ *                work it queued on `stream`)
+ * Returns SZSEL_OK or a negative code (szsel_last_error). */
+int szsel_zfp_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims, int dtype,
+                       double eb_abs, void *stream_buf, size_t stream_bytes, void *decoded,
+                       szsel_compressed *out, void *stream);
+
 /* Phase timers: synchronises the recorded events and returns, per phase
  * (0 = range pass, 1 = ZFP pass, 2 = SZ pass, 3 = overflow count, 4 =
  * entropy and selection), the summed GPU milliseconds in ms[5] and the

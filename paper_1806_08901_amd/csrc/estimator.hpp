@@ -435,6 +435,10 @@ __device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s
     return bfp_int<T>(x, emax);
 }
 
+// Occupancy of the ZFP kernels: waves per SIMD (one block per lane).
+template <typename T, int D>
+constexpr int kZfpWavesPerSimd = (sizeof(T) == 8 && D == 3) ? 1 : 2;
+
 // Results of one block: coder bits (headers included), significant bits,
 // data-domain squared error (adjacent-pair tree in in-block order), largest
 // absolute error, block exponent (INT32_MIN for an all-zero block).

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "compress.hpp"
 #include "launch.hpp"
 #include "szsel.h"
 
@@ -42,6 +43,8 @@ struct szsel_ctx {
   double sz_offset = 0.5;
   int huffman = 0;
   int ec = 0;
+  char *zc_ws = nullptr;  // Step 4 workspace (grown on demand)
+  size_t zc_ws_bytes = 0;
   szsel_debug dbg{};
   bool dbg_armed = false;
   std::string err;
@@ -331,6 +334,7 @@ void szsel_destroy(szsel_ctx *c) {
     if (c->slots[k].done) (void)hipEventDestroy(c->slots[k].done);
   }
   for (int k = 0; k < kBatchSlots; k++) batch_destroy(c->batch[k]);
+  if (c->zc_ws) (void)hipFree(c->zc_ws);
   for (auto &ev : c->prof_events)
     if (ev) (void)hipEventDestroy(ev);
   delete c;
@@ -509,3 +513,117 @@ int szsel_set_debug(szsel_ctx *c, const szsel_debug *d) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Step 4 (Algorithm 1 lines 11-13): ZFP compression of the whole field
+// ---------------------------------------------------------------------------
+
+static int64_t zc_num_blocks(const int64_t *dims, int nd) {
+  int64_t nb = 1;
+  for (int k = 0; k < nd; k++) nb *= (dims[k] + 3) / 4;
+  return nb;
+}
+
+size_t szsel_zfp_stream_bytes(const int64_t *dims, int ndims, int dtype) {
+  if (!dims || ndims < 1 || ndims > 3 || (dtype != SZSEL_F32 && dtype != SZSEL_F64)) return 0;
+  for (int k = 0; k < ndims; k++)
+    if (dims[k] < 1) return 0;
+  return szsel::zc_stream_words(zc_num_blocks(dims, ndims), ndims, dtype) * 8;
+}
+
+static uint64_t unordered_bits(uint64_t b) { return (b >> 63) ? (b & ~(1ull << 63)) : ~b; }
+static double bits_double(uint64_t b) {
+  double v;
+  std::memcpy(&v, &b, sizeof(v));
+  return v;
+}
+
+int szsel_zfp_compress(szsel_ctx *c, const void *field, const int64_t *dims, int ndims, int dtype,
+                       double eb_abs, void *stream_buf, size_t stream_bytes, void *decoded,
+                       szsel_compressed *out, void *stream) {
+  if (!c) return SZSEL_EINVAL;
+  if (!field || !dims || !stream_buf || !out) return fail(c, SZSEL_EINVAL, "null argument");
+  if (ndims < 1 || ndims > 3) return fail(c, SZSEL_EINVAL, "ndims must be 1, 2 or 3");
+  if (dtype != SZSEL_F32 && dtype != SZSEL_F64) return fail(c, SZSEL_EINVAL, "dtype must be SZSEL_F32 or SZSEL_F64");
+  if (!(eb_abs > 0.0) || !std::isfinite(eb_abs)) return fail(c, SZSEL_EINVAL, "eb_abs must be > 0 and finite");
+  int64_t n = 1;
+  for (int k = 0; k < ndims; k++) {
+    if (dims[k] < 1) return fail(c, SZSEL_EINVAL, "every extent must be >= 1");
+    if (n > INT64_MAX / dims[k]) return fail(c, SZSEL_EINVAL, "field too large");
+    n *= dims[k];
+  }
+  const size_t esz = dtype == SZSEL_F32 ? 4 : 8;
+  if ((uintptr_t)field % esz || (decoded && (uintptr_t)decoded % esz))
+    return fail(c, SZSEL_EINVAL, "field and decoded must be aligned to their element size");
+  if ((uintptr_t)stream_buf % 8) return fail(c, SZSEL_EINVAL, "stream buffer must be 8-byte aligned");
+  const size_t need = szsel_zfp_stream_bytes(dims, ndims, dtype);
+  if (stream_bytes < need) return fail(c, SZSEL_EINVAL, "stream buffer smaller than szsel_zfp_stream_bytes()");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nblocks = zc_num_blocks(dims, ndims);
+  if (nblocks > (int64_t)INT32_MAX * 64) return fail(c, SZSEL_EINVAL, "too many blocks");
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t red_half = szsel::zc_red_half(nblocks), nchunks = szsel::zc_chunks(nblocks);
+  const size_t b_counts = al(4 * (size_t)nblocks), b_offsets = al(8 * (size_t)nblocks), b_sse = al(8 * (size_t)nblocks);
+  const size_t b_chunk = al(8 * nchunks), b_red = al(16 * red_half), b_res = al(sizeof(szsel::ZcResult));
+  const size_t total = b_counts + b_offsets + b_sse + b_chunk + b_red + b_res;
+  if (total > c->zc_ws_bytes) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    if (c->zc_ws) (void)hipFree(c->zc_ws);
+    c->zc_ws = nullptr;
+    c->zc_ws_bytes = 0;
+    e = hipMalloc((void **)&c->zc_ws, total);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (compression workspace)");
+    c->zc_ws_bytes = total;
+  }
+  char *p = c->zc_ws;
+  szsel::ZcArgs a{};
+  a.field = field;
+  for (int k = 0; k < ndims; k++) {
+    a.dims[k] = dims[k];
+    a.nb[k] = (dims[k] + 3) / 4;
+  }
+  a.nd = ndims;
+  a.dtype = dtype;
+  {
+    int e2;
+    (void)std::frexp(eb_abs, &e2);
+    a.minexp = e2 - 1;  // floor(log2(eb_abs))
+  }
+  a.nblocks = nblocks;
+  a.counts = (uint32_t *)p;
+  p += b_counts;
+  a.offsets = (uint64_t *)p;
+  p += b_offsets;
+  a.bsse = (double *)p;
+  p += b_sse;
+  a.chunk = (uint64_t *)p;
+  p += b_chunk;
+  a.red = (double *)p;
+  a.red_half = (int64_t)red_half;
+  p += b_red;
+  a.res = (szsel::ZcResult *)p;
+  a.stream = (uint64_t *)stream_buf;
+  a.stream_words = (int64_t)(need / 8);
+  a.decoded = decoded;
+  hipError_t e = szsel::zc_launch(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "ZFP compression launch");
+  szsel::ZcResult h{};
+  e = hipMemcpyAsync(&h, a.res, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "ZFP compression");
+  std::memset(out, 0, sizeof(*out));
+  out->bits = h.bits;
+  out->values = (uint64_t)n;
+  out->blocks = (uint64_t)nblocks;
+  out->bitrate = (double)h.bits / (double)n;
+  out->sse = h.sse;
+  out->mse = h.sse / (double)n;
+  out->maxerr = bits_double(unordered_bits(h.maxerr_bits));
+  const double vmin = bits_double(unordered_bits(h.vmin_bits)), vmax = bits_double(unordered_bits(h.vmax_bits));
+  out->vr = vmax - vmin;
+  out->eb_abs = eb_abs;
+  out->psnr = out->mse > 0.0 ? 20.0 * std::log10(out->vr) - 10.0 * std::log10(out->mse) : INFINITY;
+  return SZSEL_OK;
+}

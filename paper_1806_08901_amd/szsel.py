@@ -64,6 +64,12 @@ class Debug(C.Structure):
                 ("zfp_emax", C.c_void_p), ("sz_sse", C.c_void_p), ("hist", C.c_void_p)]
 
 
+class Compressed(C.Structure):
+    _fields_ = [("bits", C.c_uint64), ("values", C.c_uint64), ("blocks", C.c_uint64),
+                ("bitrate", C.c_double), ("sse", C.c_double), ("mse", C.c_double), ("psnr", C.c_double),
+                ("maxerr", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double)]
+
+
 RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
 _SINGLE = ("szsel_estimate_sz", "szsel_estimate_zfp", "szsel_select", "szsel_select_fixed_eb")
 EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szsel_last_error",
@@ -71,7 +77,7 @@ EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szs
                      "szsel_profile_read", "szsel_server_create", "szsel_server_destroy",
                      "szsel_server_reserve", "szsel_server_cancel", "szsel_server_submit",
                      "szsel_server_progress", "szsel_server_status", "szsel_server_stats",
-                     "szsel_server_last_error")
+                     "szsel_server_last_error", "szsel_zfp_stream_bytes", "szsel_zfp_compress")
 
 _lib = None
 
@@ -110,6 +116,10 @@ def load_library(path: str = LIB_PATH):
     L.szsel_server_stats.argtypes = [P, C.POINTER(C.c_uint64)]
     L.szsel_server_last_error.argtypes = [P]
     L.szsel_server_last_error.restype = C.c_char_p
+    L.szsel_zfp_stream_bytes.argtypes = [I64P, C.c_int, C.c_int]
+    L.szsel_zfp_stream_bytes.restype = C.c_size_t
+    L.szsel_zfp_compress.argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, P, C.c_size_t, P,
+                                     C.POINTER(Compressed), P]
     _lib = L
     return L
 
@@ -241,6 +251,30 @@ class Context:
 
     def select_fixed_eb(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
         return self.run(OP_FIXED_EB, field, eb, eb_mode, stride, stream)
+
+    # -- Step 4: compression of the whole field -----------------------------
+    def zfp_compress(self, field: torch.Tensor, eb_abs: float, decoded: bool = True, stream=None):
+        """ZFP fixed-accuracy compression of the whole field at eb_abs.
+        Returns (result dict, stream words as an int64 device tensor of
+        ceil(bits / 64) words, decompressed field or None)."""
+        if not field.is_cuda or not field.is_contiguous():
+            raise SzselError("field must be a contiguous device tensor")
+        nd = field.dim()
+        dims = (C.c_int64 * nd)(*field.shape)
+        nbytes = self.lib.szsel_zfp_stream_bytes(dims, nd, _dtype_code(field))
+        if nbytes == 0:
+            raise SzselError("szsel_zfp_stream_bytes rejected the shape")
+        buf = torch.empty(nbytes // 8, dtype=torch.int64, device=field.device)
+        dec = torch.empty_like(field) if decoded else None
+        out = Compressed()
+        s, sp = self._stream(stream)
+        self._check(self.lib.szsel_zfp_compress(self.h, C.c_void_p(field.data_ptr()), dims, nd,
+                                                _dtype_code(field), float(eb_abs),
+                                                C.c_void_p(buf.data_ptr()), nbytes,
+                                                C.c_void_p(dec.data_ptr()) if dec is not None else None,
+                                                C.byref(out), sp), "szsel_zfp_compress")
+        res = {name: getattr(out, name) for name, _ in Compressed._fields_}
+        return res, buf[: (res["bits"] + 63) // 64], dec
 
     # -- batches -----------------------------------------------------------
     def make_requests(self, items):
