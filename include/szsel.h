@@ -247,6 +247,12 @@ typedef struct {
   double bitrate;             /* bits / values */
   double sse, mse, psnr, maxerr;  /* decompressed field against the input; PSNR with VR below */
   double vr, eb_abs;          /* value range of the field, the bound used */
+  /* SZ only: values stored raw (escapes), distinct code symbols, bits of the
+   * optimal prefix code of the symbols, their entropy in bits per value */
+  uint64_t unpredictable, symbols, code_bits;
+  double code_entropy;
+  uint32_t flags;             /* SZSEL_FLAG_NO_HUFFMAN: code_bits not computed */
+  int32_t pad;
 } szsel_compressed;
 
 /* Bytes of stream buffer szsel_zfp_compress needs for a field (a bound on
@@ -274,6 +280,27 @@ size_t szsel_zfp_stream_bytes(const int64_t *dims, int ndims, int dtype);
 int szsel_zfp_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims, int dtype,
                        double eb_abs, void *stream_buf, size_t stream_bytes, void *decoded,
                        szsel_compressed *out, void *stream);
+
+/* SZ compression at eb_abs of the whole field: Lorenzo prediction
+ * (Section 4.3) from the decompressed values and linear-scaling
+ * quantization (Section 5.1) with bins of 2 eb_abs, made parallel by
+ * quantizing first: q = the nearest integer to x / (2 eb_abs) (halves away
+ * from zero, 1/(2 eb_abs) one IEEE division; 0 when that is 2^50 or more),
+ * so the decompressed neighbours are q 2 eb_abs exactly and the prediction
+ * is the integer Lorenzo sum of their q (0 outside the field); code =
+ * q - prediction.  A value is an escape, stored in W bits, when |code| >=
+ * 32768 or q 2 eb_abs in the field's precision misses it by more than
+ * eb_abs; its symbol is 0, otherwise code + 32768.  Decompressed value:
+ * q 2 eb_abs, or the stored value.  bits = optimal prefix-code bits of the
+ * symbols + W per escape + 32 per distinct symbol (the code table); when
+ * the optimal code cannot be computed (SZSEL_FLAG_NO_HUFFMAN), bits is 0 and
+ * bitrate uses the symbols' entropy instead.  The squared errors are summed
+ * by the pair tree in field order.
+ *   symbols  device buffer of N uint16 for the symbols, or NULL
+ *   decoded  device buffer of the field's size and dtype, or NULL
+ * The call waits for the work it queued on `stream`. */
+int szsel_sz_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims, int dtype,
+                      double eb_abs, void *symbols, void *decoded, szsel_compressed *out, void *stream);
 
 /* Phase timers: synchronises the recorded events and returns, per phase
  * (0 = range pass, 1 = ZFP pass, 2 = SZ pass, 3 = overflow count, 4 =

@@ -52,6 +52,8 @@ class Step4(C.Structure):
         ("bits", C.c_uint64), ("values", C.c_uint64), ("blocks", C.c_uint64),
         ("bitrate", C.c_double), ("sse", C.c_double), ("mse", C.c_double), ("psnr", C.c_double),
         ("maxerr", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double),
+        ("unpredictable", C.c_uint64), ("symbols", C.c_uint64), ("code_bits", C.c_uint64),
+        ("code_entropy", C.c_double),
     ]
 
 
@@ -86,6 +88,8 @@ def lib():
                               C.c_double, C.c_int, C.c_int, C.c_int, C.POINTER(Result), C.POINTER(Dump)]
         L.orc_zfp_compress.argtypes = [P, I64P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_uint8),
                                        C.c_int64, C.POINTER(C.c_double), C.POINTER(Step4)]
+        L.orc_sz_compress.argtypes = [P, I64P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_uint32),
+                                      C.POINTER(C.c_uint16), C.POINTER(C.c_double), C.POINTER(Step4)]
         L.orc_zfp_num_blocks.argtypes = [I64P, C.c_int]
         L.orc_zfp_num_blocks.restype = C.c_int64
         L.orc_ec_gain.argtypes = [C.c_int, C.c_int]
@@ -382,3 +386,21 @@ def zfp_compress(field: np.ndarray, eb_abs: float):
 def zfp_num_blocks(shape) -> int:
     d = np.array(shape, np.int64)
     return int(lib().orc_zfp_num_blocks(_ptr(d, C.c_int64), len(shape)))
+
+
+def sz_compress(field: np.ndarray, eb_abs: float):
+    """Step 4, SZ: (result dict, 65536 symbol counts, symbol of every value,
+    decompressed field as float64)."""
+    field = np.ascontiguousarray(field)
+    dims = np.array(field.shape, dtype=np.int64)
+    out = Step4()
+    hist = np.zeros(NBINS, np.uint32)
+    syms = np.zeros(field.size, np.uint16)
+    dec = np.zeros(field.size, np.float64)
+    rc = lib().orc_sz_compress(field.ctypes.data, _ptr(dims, C.c_int64), field.ndim, _dtype_code(field),
+                               float(eb_abs), _ptr(hist, C.c_uint32), _ptr(syms, C.c_uint16),
+                               _ptr(dec, C.c_double), C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    res = {name: getattr(out, name) for name, _ in Step4._fields_}
+    return res, hist, syms.reshape(field.shape), dec.reshape(field.shape)

@@ -987,3 +987,102 @@ int orc_zfp_compress(const void *field, const int64_t *dims, int nd, int dtype, 
   free(e2);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Step 4, SZ: compression of the whole field (quantize first, then    */
+/* Lorenzo on the integers)                                            */
+/* ------------------------------------------------------------------ */
+
+static int64_t prequant(double x, double inv) {
+  const double t = fabs(x) * inv + 0.5;
+  if (!(t < 1125899906842624.0)) return 0; /* 2^50 */
+  const int64_t q = (int64_t)floor(t);
+  return x < 0.0 ? -q : q;
+}
+
+int orc_sz_compress(const void *field, const int64_t *dims, int nd, int dtype, double eb_abs,
+                    uint32_t *hist_out, uint16_t *symbols, double *decoded, orc_step4 *out) {
+  if (!field || !dims || !out || nd < 1 || nd > 3) return -1;
+  if (dtype != ORC_F32 && dtype != ORC_F64) return -1;
+  if (!(eb_abs > 0.0) || !isfinite(eb_abs)) return -1;
+  for (int k = 0; k < nd; k++)
+    if (dims[k] < 1) return -1;
+  memset(out, 0, sizeof(*out));
+  const int W = dtype == ORC_F32 ? 32 : 64;
+  const int64_t N = prod(dims, nd);
+  double vmin, vmax;
+  if (orc_range(field, N, dtype, &vmin, &vmax)) return -1;
+  const double delta = 2.0 * eb_abs;
+  const double inv = 1.0 / delta;
+  int64_t *q = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+  for (int64_t i = 0; i < N; i++) q[i] = prequant(load(field, dtype, i), inv);
+  uint32_t *hist = (uint32_t *)calloc(NBINS, sizeof(uint32_t));
+  double *e2 = (double *)malloc((size_t)N * sizeof(double));
+  uint64_t esc = 0;
+  double maxerr = 0.0;
+  int64_t p[3] = {0, 0, 0};
+  for (int64_t i = 0; i < N; i++) {
+    /* coordinates of point i */
+    int64_t rem = i;
+    for (int k = nd - 1; k >= 0; k--) {
+      p[k] = rem % dims[k];
+      rem /= dims[k];
+    }
+    /* Lorenzo on the integers: the sum over the nonempty subsets S of the
+     * axes of (-1)^(|S|+1) q[p - e_S], 0 outside */
+    int64_t pred = 0;
+    for (int S = 1; S < (1 << nd); S++) {
+      int card = 0, inside = 1;
+      int64_t lin = 0;
+      for (int k = 0; k < nd; k++) {
+        int64_t c = p[k];
+        if (S & (1 << k)) {
+          c -= 1;
+          card++;
+        }
+        if (c < 0) inside = 0;
+        lin = lin * dims[k] + c;
+      }
+      if (!inside) continue;
+      pred = (card & 1) ? pred + q[lin] : pred - q[lin];
+    }
+    const double x = load(field, dtype, i);
+    const int64_t code = q[i] - pred;
+    const double recon = to_dtype((double)q[i] * delta, dtype);
+    int sym = 0;
+    double xh = x;
+    if (code > -RADIUS && code < RADIUS && fabs(x - recon) <= eb_abs) {
+      sym = (int)code + RADIUS;
+      xh = recon;
+    } else {
+      esc++;
+    }
+    hist[sym]++;
+    if (symbols) symbols[i] = (uint16_t)sym;
+    const double e = x - xh;
+    e2[i] = e * e;
+    if (fabs(e) > maxerr) maxerr = fabs(e);
+    if (decoded) decoded[i] = xh;
+  }
+  uint64_t nsym = 0;
+  for (int b = 0; b < NBINS; b++) nsym += hist[b] ? 1 : 0;
+  const uint64_t code_bits = orc_huffman_bits(hist, NBINS);
+  out->code_bits = code_bits;
+  out->code_entropy = orc_entropy(hist, NBINS, (uint64_t)N);
+  out->symbols = nsym;
+  out->unpredictable = esc;
+  out->bits = code_bits + (uint64_t)W * esc + 32ull * nsym;
+  out->values = (uint64_t)N;
+  out->bitrate = (double)out->bits / (double)N;
+  out->sse = orc_tree_sum(e2, N);
+  out->mse = out->sse / (double)N;
+  out->maxerr = maxerr;
+  out->vr = vmax - vmin;
+  out->eb_abs = eb_abs;
+  out->psnr = out->mse > 0.0 ? 20.0 * log10(out->vr) - 10.0 * log10(out->mse) : INFINITY;
+  if (hist_out) memcpy(hist_out, hist, NBINS * sizeof(uint32_t));
+  free(q);
+  free(hist);
+  free(e2);
+  return 0;
+}

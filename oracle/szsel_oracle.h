@@ -115,6 +115,10 @@ uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins);
 typedef struct {
   uint64_t bits, values, blocks;
   double bitrate, sse, mse, psnr, maxerr, vr, eb_abs;
+  /* SZ only: values stored raw, distinct code symbols, bits of the optimal
+   * prefix code of the symbols */
+  uint64_t unpredictable, symbols, code_bits;
+  double code_entropy;
 } orc_step4;
 
 /* ZFP fixed-accuracy compression of every block of the field at eb_abs
@@ -127,6 +131,22 @@ typedef struct {
 int orc_zfp_compress(const void *field, const int64_t *dims, int ndims, int dtype, double eb_abs,
                      uint8_t *bits, int64_t cap, double *decoded, orc_step4 *out);
 int64_t orc_zfp_num_blocks(const int64_t *dims, int ndims);
+
+/* SZ compression of the whole field at eb_abs with Lorenzo prediction from
+ * decompressed values, made parallel by quantizing first: q = the nearest
+ * multiple of 2 eb_abs in units (round half away from zero, 1/(2 eb_abs)
+ * one IEEE division; 0 when |x| / (2 eb_abs) >= 2^50), code = q - L(q) with
+ * L the Lorenzo predictor (Section 4.3 terms, integers, 0 outside the
+ * field); symbol code + 32768, or 0 (escape, value stored in W bits) when
+ * |code| >= 32768 or q 2 eb_abs rounded to the field's precision misses
+ * eb_abs.  Decompressed value: q 2 eb_abs (rounded), or the stored value.
+ * Size: optimal prefix-code bits of the symbols + W per escape + 32 per
+ * distinct symbol (the code table).  SSE: pair tree in field order.
+ * hist (65536, may be NULL) receives the symbol counts, symbols (N, may be
+ * NULL) the symbol of every value, decoded (N, may be NULL) the
+ * decompressed field. */
+int orc_sz_compress(const void *field, const int64_t *dims, int ndims, int dtype, double eb_abs,
+                    uint32_t *hist, uint16_t *symbols, double *decoded, orc_step4 *out);
 
 /* ---- pieces exposed for the pin tests ---- */
 int orc_range(const void *field, int64_t n, int dtype, double *vmin, double *vmax);

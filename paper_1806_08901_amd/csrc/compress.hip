@@ -471,4 +471,248 @@ hipError_t zc_launch(const ZcArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ===========================================================================
+// Step 4 for SZ: Lorenzo prediction from decompressed values, made parallel
+// by quantizing first (every value to the nearest multiple of 2 eb in
+// units, q; the decompressed neighbours are then q 2 eb exactly, so the
+// prediction from them is the integer Lorenzo sum of their q).  The code
+// q - L(q) is a symbol when it is below 32768 in magnitude and q 2 eb, in
+// the field's precision, is within eb of the value; otherwise the value is
+// stored raw (symbol 0, the escape).  Size: the optimal prefix code of the
+// symbols (the Huffman pass), W bits per escape, and 32 bits per distinct
+// symbol for the code table.
+// ===========================================================================
+namespace {
+
+constexpr int kSz4Threads = 256;
+constexpr int kSz4Rounds = 256;                 // rounds of 256 consecutive points
+constexpr int64_t kSz4Chunk = (int64_t)kSz4Threads * kSz4Rounds;  // points per workgroup
+constexpr int kSz4Win = 16384;                  // LDS window of symbols around code 0
+constexpr int kSz4WinLo = 32768 - kSz4Win / 2;
+
+__device__ inline int64_t sz4_prequant(double x, double inv) {
+  const double t = fabs(x) * inv + 0.5;
+  if (!(t < 1125899906842624.0)) return 0;  // 2^50
+  const int64_t q = (int64_t)floor(t);
+  return x < 0.0 ? -q : q;
+}
+
+template <typename T, int D>
+__device__ inline int64_t sz4_q_at(const SzArgs &a, const int64_t (&p)[3], int S) {
+  // q of the neighbour p - e_S (0 outside the field)
+  int64_t lin = 0;
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    const int64_t c = p[k] - ((S >> k) & 1);
+    if (c < 0) return 0;
+    lin = lin * a.dims[k] + c;
+  }
+  return sz4_prequant((double)((const T *)a.field)[lin], a.inv);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kSz4Threads) void k_sz4(SzArgs a) {
+  __shared__ uint32_t win[kSz4Win];
+  __shared__ double stk[2][kSz4Threads / kWave];
+  __shared__ double lstk[8];
+  for (int k = threadIdx.x; k < kSz4Win; k += kSz4Threads) win[k] = 0;
+  __syncthreads();
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kSz4Chunk;
+  uint32_t *gh = a.hist + (size_t)(blockIdx.x % kSzCopies) * kBins;
+  uint32_t esc = 0;
+  double maxerr = 0.0, vmin = INFINITY, vmax = -INFINITY;
+  double acc = 0.0;  // binary counter over the rounds (thread 0)
+  for (int r = 0; r < kSz4Rounds; r++) {
+    const int64_t i = base + (int64_t)r * kSz4Threads + t;
+    double e2 = 0.0;
+    if (i < a.n) {
+      int64_t p[3];
+      int64_t rem = i;
+#pragma unroll
+      for (int k = D - 1; k >= 0; k--) {
+        p[k] = rem % a.dims[k];
+        rem /= a.dims[k];
+      }
+      const T xv = ((const T *)a.field)[i];
+      const double x = (double)xv;
+      const int64_t q = sz4_prequant(x, a.inv);
+      int64_t pred = 0;
+#pragma unroll
+      for (int S = 1; S < (1 << D); S++) {
+        const int card = __builtin_popcount(S);
+        const int64_t v = sz4_q_at<T, D>(a, p, S);
+        pred = (card & 1) ? pred + v : pred - v;
+      }
+      const int64_t code = q - pred;
+      const T recon = (T)((double)q * a.delta);
+      int sym = 0;
+      T xh = xv;
+      if (code > -32768 && code < 32768 && fabs(x - (double)recon) <= a.eb) {
+        sym = (int)code + 32768;
+        xh = recon;
+      }
+      if (sym == 0) {
+        esc++;
+      } else {
+        const int wi = sym - kSz4WinLo;
+        if (wi >= 0 && wi < kSz4Win)
+          atomicAdd(&win[wi], 1u);
+        else
+          atomicAdd(&gh[sym], 1u);
+      }
+      const double e = x - (double)xh;
+      e2 = e * e;
+      maxerr = fmax(maxerr, fabs(e));
+      vmin = fmin(vmin, x);
+      vmax = fmax(vmax, x);
+      if (a.decoded) ((T *)a.decoded)[i] = xh;
+      if (a.symbols) a.symbols[i] = (uint16_t)sym;
+    }
+    // the round's 256 squared errors as an aligned pair tree, folded into
+    // the chunk's subtree by a binary counter over the rounds
+    e2 = group_tree_sum<kWave>(e2);
+    if (lane == 0) stk[r & 1][w] = e2;
+    __syncthreads();
+    if (t == 0) {
+      double v = (stk[r & 1][0] + stk[r & 1][1]) + (stk[r & 1][2] + stk[r & 1][3]);
+      for (int l = 0; l < 8; l++) {
+        if ((r >> l) & 1) {
+          v = lstk[l] + v;
+        } else {
+          lstk[l] = v;
+          break;
+        }
+      }
+      if (r == kSz4Rounds - 1) acc = v;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kSz4Win; k += kSz4Threads)
+    if (win[k]) atomicAdd(&gh[kSz4WinLo + k], win[k]);
+  esc = group_isum<kWave>(esc);
+  maxerr = group_max<kWave>(maxerr);
+  vmin = group_min<kWave>(vmin);
+  vmax = group_max<kWave>(vmax);
+  if (lane == 0) {
+    atomicAdd((unsigned long long *)&a.res->escapes, (unsigned long long)esc);
+    atomicMax((unsigned long long *)&a.res->maxerr_bits, (unsigned long long)ordered_bits(maxerr));
+    atomicMin((unsigned long long *)&a.res->vmin_bits, (unsigned long long)ordered_bits(vmin));
+    atomicMax((unsigned long long *)&a.res->vmax_bits, (unsigned long long)ordered_bits(vmax));
+  }
+  if (t == 0) a.chunk_sse[blockIdx.x] = acc;
+}
+
+// Final counts: the copies summed, the escapes in bin 0.
+__global__ void k_sz4_combine(SzArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kBins) return;
+  uint32_t h = 0;
+#pragma unroll
+  for (int c = 0; c < kSzCopies; c++) h += a.hist[(size_t)c * kBins + b];
+  a.hfinal[b] = b == 0 ? (uint32_t)a.res->escapes : h;
+}
+
+// Optimal code bits and sum h log2 h of the final counts (one workgroup).
+__global__ __launch_bounds__(kHuffThreads) void k_sz4_huff(SzArgs a) {
+  __shared__ HuffLds S;
+  __shared__ double wsum[kHuffThreads / kWave];
+  __shared__ uint32_t wsym[kHuffThreads / kWave];
+  // sum of h log2 h: the pair tree over the 65,536 bins (64 per thread)
+  constexpr int kPer = kBins / kHuffThreads;
+  const int t = threadIdx.x;
+  double stkv[8];
+  double v = 0.0;
+  uint32_t nsym = 0;
+  for (int k = 0; k < kPer; k++) {
+    const uint32_t h = a.hfinal[t * kPer + k];
+    nsym += h ? 1u : 0u;
+    const double hd = (double)h;
+    double x = h ? hd * log2(hd) : 0.0;
+    for (int l = 0; l < 6; l++) {
+      if ((k >> l) & 1) {
+        x = stkv[l] + x;
+      } else {
+        stkv[l] = x;
+        break;
+      }
+    }
+    if (k == kPer - 1) v = x;
+  }
+  v = group_tree_sum<kWave>(v);
+  nsym = group_isum<kWave>(nsym);
+  if ((t & (kWave - 1)) == 0) {
+    wsum[t / kWave] = v;
+    wsym[t / kWave] = nsym;
+  }
+  __syncthreads();
+  uint64_t total;
+  const bool ok = huff_cost(a.hfinal, (uint64_t)a.n, S, total);
+  if (t == 0) {
+    double w16[kHuffThreads / kWave];
+    for (int q = 0; q < kHuffThreads / kWave; q++) w16[q] = wsum[q];
+    for (int m = kHuffThreads / kWave; m > 1; m >>= 1)
+      for (int q = 0; q < m / 2; q++) w16[q] = w16[2 * q] + w16[2 * q + 1];
+    a.res->hsum = w16[0];
+    a.res->code_bits = ok ? total : 0;
+    a.res->huff_ok = ok ? 1 : 0;
+    uint64_t syms = 0;
+    for (int q = 0; q < kHuffThreads / kWave; q++) syms += wsym[q];
+    a.res->symbols = syms;
+  }
+}
+
+template <typename T, int D>
+hipError_t sz4_typed(const SzArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_sz4<T, D>), dim3((unsigned)a.nchunks), dim3(kSz4Threads), 0, s, a);
+  hipLaunchKernelGGL(k_sz4_combine, dim3(kBins / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sz4_huff, dim3(1), dim3(kHuffThreads), 0, s, a);
+  const double *in = a.chunk_sse;
+  int64_t n = a.nchunks;
+  double *bufs[2] = {a.red, a.red + a.red_half};
+  int k = 0;
+  do {
+    const int64_t m = (n + kRedChunk - 1) / kRedChunk;
+    hipLaunchKernelGGL(k_tree_level, dim3((unsigned)m), dim3(kRedThreads), 0, s, in, n, bufs[k]);
+    in = bufs[k];
+    k ^= 1;
+    n = m;
+  } while (n > 1);
+  return hipMemcpyAsync(&a.res->sse, in, sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace
+
+size_t sz4_chunks(int64_t n) { return (size_t)((n + kSz4Chunk - 1) / kSz4Chunk); }
+
+hipError_t sz4_launch(const SzArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, (uint64_t *)a.hist,
+                     (int64_t)((size_t)kSzCopies * kBins / 2), (uint64_t)0);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)a.res,
+                     (int64_t)(sizeof(SzResult) / 8), (uint64_t)0);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, (uint64_t *)&a.res->maxerr_bits, (int64_t)1,
+                     (uint64_t)0x8000000000000000ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, (uint64_t *)&a.res->vmin_bits, (int64_t)1,
+                     (uint64_t)0xFFF0000000000000ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, (uint64_t *)&a.res->vmax_bits, (int64_t)1,
+                     (uint64_t)0x000FFFFFFFFFFFFFull);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.dtype == SZSEL_F32) {
+    switch (a.nd) {
+      case 1: e = sz4_typed<float, 1>(a, s); break;
+      case 2: e = sz4_typed<float, 2>(a, s); break;
+      default: e = sz4_typed<float, 3>(a, s); break;
+    }
+  } else {
+    switch (a.nd) {
+      case 1: e = sz4_typed<double, 1>(a, s); break;
+      case 2: e = sz4_typed<double, 2>(a, s); break;
+      default: e = sz4_typed<double, 3>(a, s); break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
 }  // namespace szsel

@@ -42,4 +42,32 @@ size_t zc_chunks(int64_t nblocks);
 
 hipError_t zc_launch(const ZcArgs &a, hipStream_t s);
 
+// SZ compression of the whole field (quantize first, Lorenzo on the
+// integers; see compress.hip).
+constexpr int kSzCopies = 16;  // global histogram copies
+struct SzResult {
+  uint64_t escapes, code_bits, symbols, huff_ok;
+  uint64_t maxerr_bits, vmin_bits, vmax_bits;
+  double sse, hsum;  // hsum: sum of h log2 h over the symbol counts
+};
+
+struct SzArgs {
+  const void *field;
+  int64_t dims[3];
+  int nd, dtype;
+  int64_t n;
+  double delta, inv, eb;
+  uint32_t *hist;      // kSzCopies x 65536 counts (zeroed here)
+  uint32_t *hfinal;    // the 65536 symbol counts
+  double *chunk_sse;   // squared-error sum of each chunk of points
+  int64_t nchunks;
+  double *red;
+  int64_t red_half;
+  void *decoded;       // decompressed field, or nullptr
+  uint16_t *symbols;   // symbol of every point, or nullptr
+  SzResult *res;
+};
+size_t sz4_chunks(int64_t n);
+hipError_t sz4_launch(const SzArgs &a, hipStream_t s);
+
 }  // namespace szsel

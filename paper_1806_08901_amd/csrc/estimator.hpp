@@ -1651,14 +1651,15 @@ __device__ inline void huff_tail(HuffLds &S, uint32_t n, uint32_t items, uint64_
   if (lane == 0) cost += c;
 }
 
-template <typename T, int D>
-__device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
-  constexpr int BS = 1 << (2 * D);
+// Optimal prefix-code bits of the 65,536 counts hist (which sum to nv),
+// by the whole workgroup; valid on thread 0, which returns true when it was
+// computed (false: more distinct weights than the pass holds, or nv >=
+// 2^32).  S.leaves holds the number of nonzero counts afterwards.
+__device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, uint64_t &total_out) {
   constexpr int NT = kHuffThreads;
   constexpr int kSmallPer = kHuffSmall / NT;
   constexpr int kLoads = kBins / 4 / NT;
   const int t = threadIdx.x;
-  const uint64_t nv = (uint64_t)r.nblk * BS;
   // every node weighs at most the total: 32-bit weights
   bool ok = nv < (1ull << 32);
   uint64_t cost = 0;  // this thread's share of the internal node weights
@@ -1674,7 +1675,7 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
     __syncthreads();
     uint4 v[kLoads];
 #pragma unroll
-    for (int q = 0; q < kLoads; q++) v[q] = ((const uint4 *)r.hfinal)[t + q * NT];
+    for (int q = 0; q < kLoads; q++) v[q] = ((const uint4 *)hist)[t + q * NT];
     uint32_t leaves = 0;
 #pragma unroll
     for (int q = 0; q < kLoads; q++) {
@@ -1780,16 +1781,26 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
     if (ok && t < kWave) huff_tail(S, n, items, cost);
   }
 
-  // ---- total and result ----
-  __syncthreads();
+  // ---- total ----
+  __syncthreads();  // a round left early may still have readers of the scan slots
   cost = group_isum<kWave>(cost);
   if ((t & (kWave - 1)) == 0) S.red[t / kWave] = cost;
   __syncthreads();
-  if (t != 0) return;
   uint64_t total = 0;
 #pragma unroll
   for (int q = 0; q < NT / kWave; q++) total += S.red[q];
   if (ok && S.leaves == 1) total = nv;  // one symbol: 1 bit each
+  total_out = total;
+  return ok;
+}
+
+template <typename T, int D>
+__device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
+  constexpr int BS = 1 << (2 * D);
+  const uint64_t nv = (uint64_t)r.nblk * BS;
+  uint64_t total;
+  const bool ok = huff_cost(r.hfinal, nv, S, total);
+  if (threadIdx.x != 0) return;
   ReqState *st = r.st;
   szsel_result *res = r.res;
   const uint64_t unpred = get_u64(&st->sz_unpred);

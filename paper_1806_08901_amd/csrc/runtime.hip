@@ -627,3 +627,94 @@ int szsel_zfp_compress(szsel_ctx *c, const void *field, const int64_t *dims, int
   out->psnr = out->mse > 0.0 ? 20.0 * std::log10(out->vr) - 10.0 * std::log10(out->mse) : INFINITY;
   return SZSEL_OK;
 }
+
+int szsel_sz_compress(szsel_ctx *c, const void *field, const int64_t *dims, int ndims, int dtype,
+                      double eb_abs, void *symbols, void *decoded, szsel_compressed *out, void *stream) {
+  if (!c) return SZSEL_EINVAL;
+  if (!field || !dims || !out) return fail(c, SZSEL_EINVAL, "null argument");
+  if (ndims < 1 || ndims > 3) return fail(c, SZSEL_EINVAL, "ndims must be 1, 2 or 3");
+  if (dtype != SZSEL_F32 && dtype != SZSEL_F64) return fail(c, SZSEL_EINVAL, "dtype must be SZSEL_F32 or SZSEL_F64");
+  if (!(eb_abs > 0.0) || !std::isfinite(eb_abs)) return fail(c, SZSEL_EINVAL, "eb_abs must be > 0 and finite");
+  int64_t n = 1;
+  for (int k = 0; k < ndims; k++) {
+    if (dims[k] < 1) return fail(c, SZSEL_EINVAL, "every extent must be >= 1");
+    if (n > INT64_MAX / dims[k]) return fail(c, SZSEL_EINVAL, "field too large");
+    n *= dims[k];
+  }
+  const size_t esz = dtype == SZSEL_F32 ? 4 : 8;
+  if ((uintptr_t)field % esz || (decoded && (uintptr_t)decoded % esz) || ((uintptr_t)symbols % 2))
+    return fail(c, SZSEL_EINVAL, "buffers must be aligned to their element size");
+  const double delta = 2.0 * eb_abs;
+  if (!std::isfinite(delta)) return fail(c, SZSEL_EINVAL, "2 eb_abs overflows");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nchunks = szsel::sz4_chunks(n);
+  if (nchunks > (size_t)INT32_MAX) return fail(c, SZSEL_EINVAL, "field too large");
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t red_half = szsel::zc_red_half((int64_t)nchunks);
+  const size_t b_hist = al(sizeof(uint32_t) * (size_t)szsel::kSzCopies * 65536), b_hfinal = al(sizeof(uint32_t) * 65536);
+  const size_t b_chunk = al(8 * nchunks), b_red = al(16 * red_half), b_res = al(sizeof(szsel::SzResult));
+  const size_t total = b_hist + b_hfinal + b_chunk + b_red + b_res;
+  if (total > c->zc_ws_bytes) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    if (c->zc_ws) (void)hipFree(c->zc_ws);
+    c->zc_ws = nullptr;
+    c->zc_ws_bytes = 0;
+    e = hipMalloc((void **)&c->zc_ws, total);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (compression workspace)");
+    c->zc_ws_bytes = total;
+  }
+  char *p = c->zc_ws;
+  szsel::SzArgs a{};
+  a.field = field;
+  for (int k = 0; k < ndims; k++) a.dims[k] = dims[k];
+  a.nd = ndims;
+  a.dtype = dtype;
+  a.n = n;
+  a.delta = delta;
+  a.inv = 1.0 / delta;
+  a.eb = eb_abs;
+  a.hist = (uint32_t *)p;
+  p += b_hist;
+  a.hfinal = (uint32_t *)p;
+  p += b_hfinal;
+  a.chunk_sse = (double *)p;
+  a.nchunks = (int64_t)nchunks;
+  p += b_chunk;
+  a.red = (double *)p;
+  a.red_half = (int64_t)red_half;
+  p += b_red;
+  a.res = (szsel::SzResult *)p;
+  a.decoded = decoded;
+  a.symbols = (uint16_t *)symbols;
+  hipError_t e = szsel::sz4_launch(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "SZ compression launch");
+  szsel::SzResult h{};
+  e = hipMemcpyAsync(&h, a.res, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "SZ compression");
+  const int W = dtype == SZSEL_F32 ? 32 : 64;
+  std::memset(out, 0, sizeof(*out));
+  out->values = (uint64_t)n;
+  out->unpredictable = h.escapes;
+  out->symbols = h.symbols;
+  out->code_bits = h.code_bits;
+  out->code_entropy = std::log2((double)n) - h.hsum / (double)n;
+  const uint64_t side = (uint64_t)W * h.escapes + 32ull * h.symbols;
+  if (h.huff_ok) {
+    out->bits = h.code_bits + side;
+    out->bitrate = (double)out->bits / (double)n;
+  } else {
+    out->flags |= SZSEL_FLAG_NO_HUFFMAN;
+    out->bitrate = out->code_entropy + (double)side / (double)n;
+  }
+  out->sse = h.sse;
+  out->mse = h.sse / (double)n;
+  out->maxerr = bits_double(unordered_bits(h.maxerr_bits));
+  const double vmin = bits_double(unordered_bits(h.vmin_bits)), vmax = bits_double(unordered_bits(h.vmax_bits));
+  out->vr = vmax - vmin;
+  out->eb_abs = eb_abs;
+  out->psnr = out->mse > 0.0 ? 20.0 * std::log10(out->vr) - 10.0 * std::log10(out->mse) : INFINITY;
+  return SZSEL_OK;
+}

@@ -67,7 +67,9 @@ class Debug(C.Structure):
 class Compressed(C.Structure):
     _fields_ = [("bits", C.c_uint64), ("values", C.c_uint64), ("blocks", C.c_uint64),
                 ("bitrate", C.c_double), ("sse", C.c_double), ("mse", C.c_double), ("psnr", C.c_double),
-                ("maxerr", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double)]
+                ("maxerr", C.c_double), ("vr", C.c_double), ("eb_abs", C.c_double),
+                ("unpredictable", C.c_uint64), ("symbols", C.c_uint64), ("code_bits", C.c_uint64),
+                ("code_entropy", C.c_double), ("flags", C.c_uint32), ("pad", C.c_int32)]
 
 
 RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
@@ -77,7 +79,8 @@ EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szs
                      "szsel_profile_read", "szsel_server_create", "szsel_server_destroy",
                      "szsel_server_reserve", "szsel_server_cancel", "szsel_server_submit",
                      "szsel_server_progress", "szsel_server_status", "szsel_server_stats",
-                     "szsel_server_last_error", "szsel_zfp_stream_bytes", "szsel_zfp_compress")
+                     "szsel_server_last_error", "szsel_zfp_stream_bytes", "szsel_zfp_compress",
+                     "szsel_sz_compress")
 
 _lib = None
 
@@ -120,6 +123,8 @@ def load_library(path: str = LIB_PATH):
     L.szsel_zfp_stream_bytes.restype = C.c_size_t
     L.szsel_zfp_compress.argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, P, C.c_size_t, P,
                                      C.POINTER(Compressed), P]
+    L.szsel_sz_compress.argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, P, P,
+                                    C.POINTER(Compressed), P]
     _lib = L
     return L
 
@@ -273,8 +278,29 @@ class Context:
                                                 C.c_void_p(buf.data_ptr()), nbytes,
                                                 C.c_void_p(dec.data_ptr()) if dec is not None else None,
                                                 C.byref(out), sp), "szsel_zfp_compress")
-        res = {name: getattr(out, name) for name, _ in Compressed._fields_}
+        res = {name: getattr(out, name) for name, _ in Compressed._fields_ if name != "pad"}
         return res, buf[: (res["bits"] + 63) // 64], dec
+
+    def sz_compress(self, field: torch.Tensor, eb_abs: float, decoded: bool = True, symbols: bool = False,
+                    stream=None):
+        """SZ compression of the whole field at eb_abs (quantize first, then
+        the integer Lorenzo predictor).  Returns (result dict, symbols as an
+        int16 device tensor or None, decompressed field or None)."""
+        if not field.is_cuda or not field.is_contiguous():
+            raise SzselError("field must be a contiguous device tensor")
+        nd = field.dim()
+        dims = (C.c_int64 * nd)(*field.shape)
+        dec = torch.empty_like(field) if decoded else None
+        sym = torch.empty(field.shape, dtype=torch.int16, device=field.device) if symbols else None
+        out = Compressed()
+        s, sp = self._stream(stream)
+        self._check(self.lib.szsel_sz_compress(self.h, C.c_void_p(field.data_ptr()), dims, nd,
+                                               _dtype_code(field), float(eb_abs),
+                                               C.c_void_p(sym.data_ptr()) if sym is not None else None,
+                                               C.c_void_p(dec.data_ptr()) if dec is not None else None,
+                                               C.byref(out), sp), "szsel_sz_compress")
+        res = {name: getattr(out, name) for name, _ in Compressed._fields_ if name != "pad"}
+        return res, sym, dec
 
     # -- batches -----------------------------------------------------------
     def make_requests(self, items):

@@ -98,3 +98,47 @@ def test_argument_errors(ctx):
         ctx.zfp_compress(x, 0.0)
     with pytest.raises(szsel.SzselError, match="eb_abs"):
         ctx.zfp_compress(x, float("inf"))
+
+
+# ---------------------------------------------------------------- SZ side
+
+SZ_EXACT = ("bits", "values", "sse", "mse", "maxerr", "vr", "eb_abs", "unpredictable", "symbols",
+            "code_bits", "bitrate", "psnr")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("eb", [1e-2, 1e-4, 1e-6])
+def test_sz_compression_matches_oracle(ctx, case, eb):
+    label, make = case
+    x = make()
+    host = x.numpy()
+    eb_abs = eb * float(host.max() - host.min())
+    _note("step4 sz", label, eb)
+    gpu, syms, dec = ctx.sz_compress(x.cuda(), eb_abs, symbols=True)
+    orc, hist, osyms, odec = oracle.sz_compress(host, eb_abs)
+    assert gpu["flags"] == 0
+    for k in SZ_EXACT:
+        assert gpu[k] == orc[k], "%s: gpu %r oracle %r" % (k, gpu[k], orc[k])
+    assert abs(gpu["code_entropy"] - orc["code_entropy"]) <= 1e-9 * max(1.0, orc["code_entropy"])
+    assert np.array_equal(syms.cpu().numpy().view(np.uint16), osyms)
+    assert np.array_equal(dec.cpu().numpy().astype(np.float64), odec)
+    assert gpu["maxerr"] <= eb_abs
+
+
+def test_sz_full_size_field(ctx):
+    """The 512^3 benchmark field: the round trip within the bound, the size
+    made of its parts, and a 16^3 corner's symbols and values against the
+    oracle on that corner (the corner's predictions only look backwards)."""
+    field = synth.workload_turb512(device="cuda")
+    vr = float(field.max() - field.min())
+    for eb in (1e-2, 1e-4, 1e-6):
+        gpu, syms, dec = ctx.sz_compress(field, eb * vr, symbols=True)
+        _note("turb512 sz step4 eb", eb, gpu["bitrate"], gpu["psnr"], gpu["flags"])
+        assert gpu["maxerr"] <= eb * vr
+        assert (dec.double() - field.double()).abs().max().item() == gpu["maxerr"]
+        if not gpu["flags"]:
+            assert gpu["bits"] == gpu["code_bits"] + 32 * gpu["unpredictable"] + 32 * gpu["symbols"]
+        sub = field[:16, :16, :16].contiguous().cpu().numpy()
+        _, _, osyms, odec = oracle.sz_compress(sub, eb * vr)
+        assert np.array_equal(syms[:16, :16, :16].cpu().numpy().view(np.uint16), osyms)
+        assert np.array_equal(dec[:16, :16, :16].cpu().numpy().astype(np.float64), odec)

@@ -129,3 +129,72 @@ def test_independent_decoder_reads_the_stream(shape, dtype):
     eb_abs = 3e-4
     r, words, dec = oracle.zfp_compress(x, eb_abs)
     assert np.array_equal(_decode_stream(words, shape, dtype, eb_abs), dec)
+
+
+# ---------------------------------------------------------------- SZ side
+
+
+def _sz_decode(symbols, raw, shape, eb_abs, dtype):
+    """Sequential decoder written from the format: each value's q is its
+    symbol - 32768 plus the integer Lorenzo sum of the decoded neighbours'
+    q (0 outside); an escape's value is stored raw and its q recomputed."""
+    nd = len(shape)
+    delta = 2.0 * eb_abs
+    inv = 1.0 / delta
+    q = np.zeros(shape, np.int64)
+    out = np.zeros(shape, np.float64)
+    for idx in np.ndindex(*shape):
+        pred = 0
+        for S in range(1, 1 << nd):
+            nb = tuple(i - ((S >> k) & 1) for k, i in enumerate(idx))
+            if min(nb) < 0:
+                continue
+            pred += int(q[nb]) if bin(S).count("1") % 2 else -int(q[nb])
+        s = int(symbols[idx])
+        if s == 0:
+            x = float(raw[idx])
+            t = abs(x) * inv + 0.5
+            qq = int(math.floor(t)) if t < 2.0 ** 50 else 0
+            q[idx] = -qq if x < 0 else qq
+            out[idx] = x
+        else:
+            q[idx] = s - 32768 + pred
+            out[idx] = float(dtype(float(q[idx]) * delta))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("eb", [1e-2, 1e-4, 1e-6])
+def test_sz_round_trip_and_size(case, eb):
+    x = _fields()[case]
+    eb_abs = eb * float(x.max() - x.min())
+    r, hist, syms, dec = oracle.sz_compress(x, eb_abs)
+    assert r["maxerr"] <= eb_abs
+    assert int(hist.sum()) == x.size and int(hist[0]) == r["unpredictable"]
+    assert r["symbols"] == int((hist > 0).sum())
+    assert r["code_bits"] == oracle.huffman_bits(hist)
+    W = 32 if x.dtype == np.float32 else 64
+    assert r["bits"] == r["code_bits"] + W * r["unpredictable"] + 32 * r["symbols"]
+    assert abs(r["code_entropy"] - oracle.entropy(hist, x.size)) <= 1e-12 * max(1.0, r["code_entropy"])
+    esc = syms == 0
+    assert np.array_equal(dec[esc], x[esc].astype(np.float64))
+
+
+@pytest.mark.parametrize("shape,dtype", [((37,), np.float32), ((9, 11), np.float64), ((5, 6, 7), np.float32)])
+def test_sz_independent_decoder(shape, dtype):
+    x = synth.spectral(shape, slope=-2.0, seed=79).numpy().astype(dtype)
+    for eb in (1e-2, 1e-5):
+        eb_abs = eb * float(x.max() - x.min())
+        r, hist, syms, dec = oracle.sz_compress(x, eb_abs)
+        assert np.array_equal(_sz_decode(syms, x, shape, eb_abs, dtype), dec)
+
+
+def test_sz_bilinear_field_predicts_exactly():
+    """Values on the quantization grid that are bilinear in the indices:
+    the 2-D Lorenzo predictor is exact away from the first row and column."""
+    eb = 0.5
+    i, j = np.meshgrid(np.arange(30), np.arange(40), indexing="ij")
+    x = (2 * eb * (3 * i + 5 * j + 7)).astype(np.float64)
+    r, hist, syms, dec = oracle.sz_compress(x, eb)
+    assert np.all(syms[1:, 1:] == 32768)
+    assert r["sse"] == 0.0 and r["unpredictable"] == 0
