@@ -40,10 +40,11 @@ def parse():
     ap.add_argument("--latency-calls", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
-    ap.add_argument("--workload", default="turb512", choices=["turb512", "atm79", "mix3d", "serve"],
+    ap.add_argument("--workload", default="turb512", choices=["turb512", "atm79", "mix3d", "serve", "accuracy"],
                     help="turb512: one 512^3 field, 5 bounds (default); atm79: 79 fields of "
                          "1800x3600; mix3d: 43 uneven 3-D fields (FP32 and FP64); serve: a Poisson "
-                         "stream of snapshots through the serving engine")
+                         "stream of snapshots through the serving engine; accuracy: the "
+                         "selection against whole-field compression (Step 4)")
     ap.add_argument("--serve-rate", type=float, default=20.0,
                     help="snapshots per second (0: all at once, the engine's capacity)")
     ap.add_argument("--serve-snapshots", type=int, default=1000)
@@ -215,6 +216,79 @@ def field_batch(args, torch, synth, szsel):
     print(json.dumps(out), flush=True)
 
 
+def accuracy(args, torch, synth, szsel):
+    """Algorithm 1 against Step 4: for every field and bound, the estimator's
+    choice against the compressor that really needs fewer bits (SZ at the
+    bound the selection hands it, ZFP at eb_abs, both over the whole field),
+    and the estimates' errors; also the compressors' throughput."""
+    dev = torch.device("cuda:0")
+    cases = [("turb512", synth.workload_turb512(device=dev), (5, 4, 1))]
+    for k, sp in enumerate(synth.workload_atm_specs()[:10]):
+        cases.append(("atm%d" % k, synth.make_field(sp, device=dev), (20, 1)))
+    for k, sp in enumerate(synth.workload_mix3d_specs()[::7]):
+        cases.append(("mix%d" % k, synth.make_field(sp, device=dev), (5, 4, 1)))
+    torch.cuda.synchronize()
+    ctx = szsel.Context(0)
+    rows = []
+    t_sz = t_zfp = 0.0
+    nbytes_c = 0
+    huff_ok = 0
+    for name, f, st in cases:
+        for eb in synth.EB_SWEEP:
+            ctx.set_option(szsel.OPT_HUFFMAN, 2)
+            est_h = ctx.select(f, eb, stride=st)
+            ctx.set_option(szsel.OPT_HUFFMAN, 0)
+            est = ctx.select(f, eb, stride=st)
+            if est["flags"] & 0x13:  # constant / non-finite / no blocks: nothing to compare
+                continue
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sz, _, _ = ctx.sz_compress(f, est["sz_eb"], decoded=False)
+            t1 = time.perf_counter()
+            zf, _, _ = ctx.zfp_compress(f, est["eb_abs"], decoded=False)
+            t2 = time.perf_counter()
+            t_sz += t1 - t0
+            t_zfp += t2 - t1
+            nbytes_c += f.numel() * f.element_size()
+            truth = 0 if sz["bitrate"] < zf["bitrate"] else 1
+            huff_ok += 1 if est_h["choice"] == truth else 0
+            chosen = sz["bitrate"] if est["choice"] == 0 else zf["bitrate"]
+            best = min(sz["bitrate"], zf["bitrate"])
+            rows.append({
+                "field": name, "eb_rel": eb, "choice": est["choice"], "best": truth,
+                "br_sz": [round(est["sz_bitrate"], 4), round(sz["bitrate"], 4)],
+                "br_zfp": [round(est["zfp_bitrate"], 4), round(zf["bitrate"], 4)],
+                "psnr_sz": [round(est["sz_psnr_model"], 3), round(sz["psnr"], 3)],
+                "psnr_zfp": [round(est["zfp_psnr"], 3), round(zf["psnr"], 3)],
+                "loss_pct": round(100.0 * (chosen / best - 1.0), 3) if best > 0 else 0.0,
+            })
+    ok = sum(1 for r in rows if r["choice"] == r["best"])
+
+    def rel(a):
+        return abs(a[0] - a[1]) / a[1] if a[1] else 0.0
+
+    out = {
+        "metric": "selection accuracy of Algorithm 1 against Step 4 (whole-field compression)",
+        "value": round(ok / max(1, len(rows)), 4), "unit": "fraction", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+        "config": {"workload": "accuracy: turb512, 10 atm fields, 7 mix3d fields x 5 bounds",
+                   "cases": len(rows)},
+        "mean_bitrate_loss_pct": round(sum(r["loss_pct"] for r in rows) / max(1, len(rows)), 4),
+        "accuracy_selecting_with_huffman_cost": round(huff_ok / max(1, len(rows)), 4),
+        "estimate_error": {
+            "br_sz_mean_rel": round(sum(rel(r["br_sz"]) for r in rows) / max(1, len(rows)), 4),
+            "br_zfp_mean_rel": round(sum(rel(r["br_zfp"]) for r in rows) / max(1, len(rows)), 4),
+            "psnr_sz_mean_abs_db": round(sum(abs(r["psnr_sz"][0] - r["psnr_sz"][1]) for r in rows) / max(1, len(rows)), 4),
+            "psnr_zfp_mean_abs_db": round(sum(abs(r["psnr_zfp"][0] - r["psnr_zfp"][1]) for r in rows) / max(1, len(rows)), 4),
+        },
+        "compress_GBps": {"sz": round(nbytes_c / t_sz / 1e9, 2), "zfp": round(nbytes_c / t_zfp / 1e9, 2),
+                          "what": "host wall clock around each synchronous call, whole fields"},
+        "rows": rows,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def serve(args, torch, synth, szsel):
     """Poisson arrivals of snapshots (5-40 fields each, shapes 64^3, 512^3
     and 1800x3600 FP32, eb_rel uniform in [1e-6, 1e-2]) through the serving
@@ -343,6 +417,9 @@ def main():
 
     if args.workload == "serve":
         serve(args, torch, synth, szsel)
+        return
+    if args.workload == "accuracy":
+        accuracy(args, torch, synth, szsel)
         return
     if args.workload != "turb512":
         field_batch(args, torch, synth, szsel)
