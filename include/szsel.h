@@ -251,7 +251,9 @@ typedef struct {
    * optimal prefix code of the symbols, their entropy in bits per value */
   uint64_t unpredictable, symbols, code_bits;
   double code_entropy;
-  uint32_t flags;             /* SZSEL_FLAG_NO_HUFFMAN: code_bits not computed */
+  uint32_t flags;             /* SZSEL_FLAG_NO_HUFFMAN: code_bits not computed;
+                                 SZSEL_FLAG_NONFINITE: the field holds NaN or Inf
+                                 (the stream and totals are then meaningless) */
   int32_t pad;
 } szsel_compressed;
 

@@ -68,6 +68,7 @@ __device__ inline bool zc_coefficients(const T (&x)[1 << (2 * D)], int minexp, i
   constexpr int BS = 1 << (2 * D);
   constexpr int W = Q::W;
   constexpr int kMinExp = 2 - (1 << (Q::E - 1));
+  constexpr int kMaxExp = 1 << (Q::E - 1);  // largest finite exponent (NaN / Inf blocks are clamped)
   U mmax = 0;
 #pragma unroll
   for (int i = 0; i < BS; i++) {
@@ -80,7 +81,7 @@ __device__ inline bool zc_coefficients(const T (&x)[1 << (2 * D)], int minexp, i
     return false;
   }
   emax = frexp_exponent_bits<T>(mmax);
-  emax = emax < kMinExp ? kMinExp : emax;
+  emax = emax < kMinExp ? kMinExp : (emax > kMaxExp ? kMaxExp : emax);
   prec = emax - minexp + 2 * (D + 1);
   prec = prec < 0 ? 0 : (prec > W ? W : prec);
   if (prec == 0) return false;
@@ -216,7 +217,7 @@ struct BitReader {
 // pair-tree sum of its squared errors (zeros at padded positions).
 template <typename T, int D>
 __device__ inline double zc_decode_block(const ZcArgs &a, int64_t jb, double &maxerr, double &vmin,
-                                         double &vmax) {
+                                         double &vmax, bool &bad) {
   using Q = Prec<T>;
   using U = typename Q::U;
   using I = typename Q::I;
@@ -284,6 +285,7 @@ __device__ inline double zc_decode_block(const ZcArgs &a, int64_t jb, double &ma
       maxerr = fmax(maxerr, fabs(e));
       vmin = fmin(vmin, (double)x[i]);
       vmax = fmax(vmax, (double)x[i]);
+      bad = bad || !isfinite((double)x[i]);
       if (a.decoded) ((T *)a.decoded)[lin] = xh[i];
     }
   }
@@ -306,11 +308,14 @@ template <typename T, int D>
 __global__ __launch_bounds__(kZcThreads, 1) void k_zc_decode(ZcArgs a) {
   const int64_t jb = (int64_t)blockIdx.x * kZcThreads + threadIdx.x;
   double maxerr = 0.0, vmin = INFINITY, vmax = -INFINITY;
-  if (jb < a.nblocks) a.bsse[jb] = zc_decode_block<T, D>(a, jb, maxerr, vmin, vmax);
+  bool bad = false;
+  if (jb < a.nblocks) a.bsse[jb] = zc_decode_block<T, D>(a, jb, maxerr, vmin, vmax, bad);
   maxerr = group_max<kWave>(maxerr);
   vmin = group_min<kWave>(vmin);
   vmax = group_max<kWave>(vmax);
+  const bool any_bad = __ballot(bad) != 0;
   if (threadIdx.x == 0) {
+    if (any_bad) atomicOr((unsigned long long *)&a.res->nonfinite, 1ull);
     atomicMax((unsigned long long *)&a.res->maxerr_bits, (unsigned long long)ordered_bits(maxerr));
     atomicMin((unsigned long long *)&a.res->vmin_bits, (unsigned long long)ordered_bits(vmin));
     atomicMax((unsigned long long *)&a.res->vmax_bits, (unsigned long long)ordered_bits(vmax));
@@ -452,6 +457,7 @@ hipError_t zc_launch(const ZcArgs &a, hipStream_t s) {
                      (uint64_t)0xFFF0000000000000ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, (uint64_t *)&a.res->vmax_bits, (int64_t)1,
                      (uint64_t)0x000FFFFFFFFFFFFFull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, (uint64_t *)&a.res->nonfinite, (int64_t)1, (uint64_t)0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.dtype == SZSEL_F32) {
@@ -522,6 +528,7 @@ __global__ __launch_bounds__(kSz4Threads) void k_sz4(SzArgs a) {
   uint32_t *gh = a.hist + (size_t)(blockIdx.x % kSzCopies) * kBins;
   uint32_t esc = 0;
   double maxerr = 0.0, vmin = INFINITY, vmax = -INFINITY;
+  bool bad = false;
   double acc = 0.0;  // binary counter over the rounds (thread 0)
   for (int r = 0; r < kSz4Rounds; r++) {
     const int64_t i = base + (int64_t)r * kSz4Threads + t;
@@ -566,6 +573,7 @@ __global__ __launch_bounds__(kSz4Threads) void k_sz4(SzArgs a) {
       maxerr = fmax(maxerr, fabs(e));
       vmin = fmin(vmin, x);
       vmax = fmax(vmax, x);
+      bad = bad || !isfinite(x);
       if (a.decoded) ((T *)a.decoded)[i] = xh;
       if (a.symbols) a.symbols[i] = (uint16_t)sym;
     }
@@ -594,7 +602,9 @@ __global__ __launch_bounds__(kSz4Threads) void k_sz4(SzArgs a) {
   maxerr = group_max<kWave>(maxerr);
   vmin = group_min<kWave>(vmin);
   vmax = group_max<kWave>(vmax);
+  const bool any_bad = __ballot(bad) != 0;
   if (lane == 0) {
+    if (any_bad) atomicOr((unsigned long long *)&a.res->nonfinite, 1ull);
     atomicAdd((unsigned long long *)&a.res->escapes, (unsigned long long)esc);
     atomicMax((unsigned long long *)&a.res->maxerr_bits, (unsigned long long)ordered_bits(maxerr));
     atomicMin((unsigned long long *)&a.res->vmin_bits, (unsigned long long)ordered_bits(vmin));

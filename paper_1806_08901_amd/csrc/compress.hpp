@@ -13,6 +13,7 @@ struct ZcResult {
   uint64_t bits;         // stream length
   uint64_t maxerr_bits;  // largest absolute error, order-preserving bits
   uint64_t vmin_bits, vmax_bits;
+  uint64_t nonfinite;    // nonzero when the field holds NaN or Inf
   double sse;
 };
 
@@ -48,7 +49,8 @@ constexpr int kSzCopies = 16;  // global histogram copies
 struct SzResult {
   uint64_t escapes, code_bits, symbols, huff_ok;
   uint64_t maxerr_bits, vmin_bits, vmax_bits;
-  double sse, hsum;  // hsum: sum of h log2 h over the symbol counts
+  uint64_t nonfinite;  // nonzero when the field holds NaN or Inf
+  double sse, hsum;    // hsum: sum of h log2 h over the symbol counts
 };
 
 struct SzArgs {

@@ -625,6 +625,7 @@ int szsel_zfp_compress(szsel_ctx *c, const void *field, const int64_t *dims, int
   out->vr = vmax - vmin;
   out->eb_abs = eb_abs;
   out->psnr = out->mse > 0.0 ? 20.0 * std::log10(out->vr) - 10.0 * std::log10(out->mse) : INFINITY;
+  if (h.nonfinite) out->flags |= SZSEL_FLAG_NONFINITE;
   return SZSEL_OK;
 }
 
@@ -716,5 +717,6 @@ int szsel_sz_compress(szsel_ctx *c, const void *field, const int64_t *dims, int 
   out->vr = vmax - vmin;
   out->eb_abs = eb_abs;
   out->psnr = out->mse > 0.0 ? 20.0 * std::log10(out->vr) - 10.0 * std::log10(out->mse) : INFINITY;
+  if (h.nonfinite) out->flags |= SZSEL_FLAG_NONFINITE;
   return SZSEL_OK;
 }

@@ -142,3 +142,13 @@ def test_sz_full_size_field(ctx):
         _, _, osyms, odec = oracle.sz_compress(sub, eb * vr)
         assert np.array_equal(syms[:16, :16, :16].cpu().numpy().view(np.uint16), osyms)
         assert np.array_equal(dec[:16, :16, :16].cpu().numpy().astype(np.float64), odec)
+
+
+def test_non_finite_fields_are_flagged(ctx):
+    from paper_1806_08901_amd import szsel
+    x = synth.spectral((24, 20), seed=91)
+    x[3, 7] = float("nan")
+    x[10, 2] = float("inf")
+    for fn in (ctx.zfp_compress, ctx.sz_compress):
+        res, _, _ = fn(x.cuda(), 1e-3, decoded=False)
+        assert res["flags"] & szsel.FLAG_NONFINITE
