@@ -198,7 +198,8 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   shape and keep the fastest; 0 (default) uses the fixed schedule.  The
  *   results do not depend on it.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
- *   HIP graph and replays it while the batch shape repeats.
+ *   HIP graph and replays it while the batch shape repeats (schedules with
+ *   more than two request groups are launched without a graph).
  * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the schedule
  *   of single-request calls and of batches without autotuning (and the
  *   autotuner's starting point): SZ

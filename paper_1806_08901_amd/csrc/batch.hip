@@ -40,6 +40,7 @@ namespace {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 constexpr int kMaxGroupsPerBatch = 8;
+constexpr int kMaxCapturedGroups = 2;  // larger group counts are launched without a graph
 
 struct Plan {
   std::vector<ReqDesc> tab;             // table order
@@ -550,7 +551,10 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
   int rc = make_plan(ctx, ncu, reqs, n, tu, p, msg);
   if (rc != SZSEL_OK) return rc;
   if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
-  if (opt.graph) {
+  // A captured graph forking into more than two request-group streams
+  // crashed the host process inside the runtime on this ROCm; such
+  // schedules run uncaptured (the path the autotuner times).
+  if (opt.graph && p.groups <= kMaxCapturedGroups) {
     if (!bs->exec || bs->sig != p.sig) {
       if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
       if (bs->graph) (void)hipGraphDestroy(bs->graph);

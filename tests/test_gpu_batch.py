@@ -124,6 +124,21 @@ def test_autotune_and_no_graph_give_the_same_results(ctx):
     assert eager == ref
 
 
+def test_request_group_schedules_equal_single_calls(ctx):
+    """Fixed schedules with 2, 4 and 8 request groups (two groups replay a
+    captured graph, more run uncaptured) give the single calls' results."""
+    from paper_1806_08901_amd import szsel
+    items = _items(_fields(), ebs=(1e-3, 1e-5))
+    singles = _singles(ctx, items)
+    try:
+        for g in (2, 4, 8):
+            ctx.set_option(szsel.OPT_BATCH_GROUPS, g)
+            for rep in range(2):
+                assert ctx.select_batch(items) == singles, "groups %d rep %d" % (g, rep)
+    finally:
+        ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
+
+
 def test_batches_in_flight_on_two_streams(ctx):
     a_items = _items(_fields()[:3], ebs=(1e-3,))
     b_items = _items(_fields()[3:6], ebs=(1e-4,))
