@@ -89,6 +89,7 @@ struct alignas(64) ReqState {
   int32_t minexp;
   uint32_t flags;
   uint32_t ovf_slices;       // slices the overflow pass counts them in (set by the SZ finalizer)
+  uint64_t code_chunks;      // bit c: some code fell in bins [1024 c, 1024 c + 1024)
 };
 
 // Completion counters of one pass.  Atomics on one address (one 128-byte

@@ -263,6 +263,7 @@ __device__ inline void range_finalize_one(const ReqDesc &r, double lo, double hi
   put_f64(&res->eb_abs, eb_abs);
   put_u64((uint64_t *)&res->flags, (uint64_t)flags | ((uint64_t)(uint32_t)choice << 32));
   put_u64((uint64_t *)&res->minexp, (uint64_t)(uint32_t)minexp);
+  put_u64(&st->code_chunks, 0);
   put_f64(&st->vmin, lo);
   put_f64(&st->vmax, hi);
   put_f64(&st->vr, vr);
@@ -682,7 +683,8 @@ __device__ inline double tile_sse(const TileLds &L, int tile) {
 struct LaneAcc {
   uint32_t a, b;
   double maxerr;
-  __device__ LaneAcc() : a(0u), b(0u), maxerr(0.0) {}
+  uint64_t chunks;  // SZ: the entropy pass's 1024-bin chunks this lane's codes fell in
+  __device__ LaneAcc() : a(0u), b(0u), maxerr(0.0), chunks(0) {}
 };
 
 __device__ inline void wg_acc_reset(TileLds &L) {
@@ -1097,6 +1099,7 @@ __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double 
     for (int xi = 0; xi < 4; xi++) {
       acc.a += code[xi] == 0 && active ? 1u : 0u;
       acc.maxerr = fmax(acc.maxerr, ae[xi]);
+      acc.chunks |= 1ull << (code[xi] >> 10);
     }
     if (r.dbg_codes && active) {
 #pragma unroll
@@ -1283,13 +1286,17 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   const int nhc = r.nhc;
   static_assert(kEntPerThread == 4, "four bins per thread, one 16-byte vector");
   const int bin0 = c * kEntChunk + t * kEntPerThread;
+  static_assert(kEntChunk == 1024 && kEntWgs == 64, "one code-chunk bit per entropy workgroup");
+  // a chunk no code fell in holds zeros everywhere (its copies were never
+  // written, its h log2 h subtree is 0): nothing to read or clear
+  const bool live = c == 0 || ((get_u64(&r.st->code_chunks) >> c) & 1u);
   // the SZ workgroups' counts, spread over nhc copies so that no bin takes
   // more than about 128 workgroups' atomics; every copy's four bins are one
   // 16-byte load, all issued before any is used
   uint4 hc[kHistCopies];
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++)
-    hc[q] = q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
+    hc[q] = live && q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
   uint32_t h[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++) {
@@ -1298,7 +1305,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     h[2] += hc[q].z;
     h[3] += hc[q].w;
   }
-  {  // add the overflow pass's counts
+  if (live) {  // add the overflow pass's counts
 #pragma unroll 8
     for (int p = 0; p < S; p++) {
       const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
@@ -1856,6 +1863,13 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   hist_hand_over(s_hist, r.hist + (size_t)(w & (r.nhc - 1)) * kBins, region, &s_n,
                  (uint32_t)(nb * BS), L);
   __syncthreads();
+  // the chunks the codes fell in, for the entropy pass to skip empty ones:
+  // one OR per wave, only when it adds a bit (most waves add none)
+  uint64_t ch = acc.chunks;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) ch |= __shfl_xor(ch, d);
+  if ((threadIdx.x & (kWave - 1)) == 0 && (ch & ~get_u64(&r.st->code_chunks)))
+    __hip_atomic_fetch_or(&r.st->code_chunks, ch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
   wg_acc_store(L, acc, r.sp, w);
   Part tot;
