@@ -35,6 +35,34 @@ def test_result_layout_matches_header():
     assert ctypes.sizeof(szsel.Request) == 8 + 24 + 8 + 8 + 8 + 12 + 4
 
 
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every field offset of the binding's structures equals the one a C
+    compiler gives for include/szsel.h."""
+    import os
+    import subprocess
+    structs = {"szsel_result": szsel.Result, "szsel_request": szsel.Request,
+               "szsel_compressed": szsel.Compressed, "szsel_debug": szsel.Debug}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "szsel.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
 @pytest.mark.parametrize("shape,rate,want", [
     ((512, 512, 512), 0.05, (5, 4, 1)),
     ((1800, 3600), 0.05, (20, 1)),
@@ -66,3 +94,30 @@ def test_no_gpu_means_loud_failure():
         pytest.skip("a GPU is present")
     with pytest.raises(szsel.SzselError):
         szsel.Context(0)
+
+
+def test_oracle_struct_layouts_match_the_c_compiler(tmp_path):
+    """The oracle's ctypes structures against its C header."""
+    import os
+    import subprocess
+    import oracle
+    structs = {"orc_result": oracle.Result, "orc_dump": oracle.Dump, "orc_step4": oracle.Step4}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "szsel_oracle.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "olayout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "olayout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
