@@ -492,6 +492,10 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     const int sz_opts[] = {2, 4, 8, 16, 32};
     const int zfp_opts[] = {64, 128, 256};
     const int range_opts[] = {1, 2, 4};
+    // two sweeps of the coordinates: the best group count depends on how
+    // fast the sampled passes became with the other knobs
+    for (int sweep = 0; sweep < 2; sweep++) {
+    const Tune before = cur;
     for (int v : group_opts) {
       if (rc != SZSEL_OK || v == cur.groups || v > n) continue;
       Tune c = cur;
@@ -535,6 +539,8 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
         best_ms = ms;
         cur = c;
       }
+    }
+    if (std::memcmp(&before, &cur, sizeof(Tune)) == 0) break;  // nothing moved
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
