@@ -203,10 +203,13 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the schedule
  *   of single-request calls and of batches without autotuning (and the
  *   autotuner's starting point): SZ
- *   workgroups per request in quarters of the CU count (1..256, default 16),
+ *   workgroups in quarters of the CU count (1..256, default 16),
  *   smallest ZFP chunk in sampled blocks (a power of two 64..65536, default
- *   64), range workgroups per CU and request (1..64, default 2); 0 restores
- *   the default.  Results do not depend on them.
+ *   64), range workgroups per CU (1..64, default 2); 0 restores the
+ *   default.  The SZ and range counts are those of a single request, and
+ *   of a whole batch, dealt to its requests in proportion to their sampled
+ *   blocks and to the bytes of their fields.  Results do not depend on
+ *   them.
  * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
  *   default 1; 0 restores it): the requests are dealt to that many groups
  *   (requests on one field stay together), each running on its own stream,

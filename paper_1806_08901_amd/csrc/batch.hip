@@ -75,6 +75,41 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       return rc;
     }
   }
+  // Workgroup counts: the schedule's SZ and range counts are the batch's,
+  // dealt to the requests in proportion to their sampled blocks and to the
+  // bytes of their fields (a field scanned once for all its requests counts
+  // once), so that the small fields of a large batch get a few long-running
+  // workgroups instead of many whose time goes to their set-up, the SZ LDS
+  // histogram's clearing and hand-over and the completion counters
+  if (n > 1) {
+    double sz_blocks = 0.0, scan_bytes = 0.0;
+    for (int i = 0; i < n; i++) {
+      if (d[i].op != SZSEL_OP_ZFP) sz_blocks += (double)d[i].nblk;
+      bool first_on_field = true;
+      for (int j = 0; j < i && first_on_field; j++) first_on_field = !same_field(d[i], d[j]);
+      if (first_on_field) scan_bytes += (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0);
+    }
+    const double sz_want = std::max(1.0, (double)tu.sz_wgs_q * (double)ncu / 4.0);
+    const double range_want = std::max(1.0, (double)tu.range_wgs_per_cu * (double)ncu);
+    auto share = [](double want, double part, double whole) {
+      return (int)std::max(1.0, std::min(1e9, std::round(want * part / whole)));
+    };
+    for (int i = 0; i < n; i++) {
+      const szsel_request &q = reqs[i];
+      int32_t st[3];
+      for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
+      Tune t = tu;
+      if (d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sz_blocks > 0.0)
+        t.sz_target = share(sz_want, (double)d[i].nblk, sz_blocks);
+      if (scan_bytes > 0.0)
+        t.range_target = share(range_want, (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0), scan_bytes);
+      const int rc = plan_request(ctx, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, t, d[i]);
+      if (rc != SZSEL_OK) {
+        msg = "request " + std::to_string(i) + ": ";
+        return rc;
+      }
+    }
+  }
   // request groups: requests on one field stay together (they share the
   // scan); fields are dealt to the groups largest first, each to the group
   // with the least estimated work (range bytes plus 8 bytes per sampled value)
@@ -270,6 +305,8 @@ struct BatchState {
   size_t meta_cap = 0;
   char *stage = nullptr;  // pinned staging copy of meta
   size_t stage_cap = 0;
+  std::vector<char> staged;  // what the staging buffer holds
+  bool dirty = false;        // staging rewritten since the last upload to meta
   hipEvent_t done = nullptr;
   bool used = false;
   hipStream_t cap = nullptr;  // private capture stream
@@ -322,8 +359,17 @@ Tuner &tuner() {
   return t;
 }
 
+// Waits until the state's last batch (and with it every copy from its
+// staging buffer and every read of its workspace) is finished.
+hipError_t batch_wait(BatchState *bs) {
+  return bs->used ? hipEventSynchronize(bs->done) : hipSuccess;
+}
+
 // Makes the state's buffers large enough for plan p, binds every table
-// entry to its workspace and result, and writes the staging copy.
+// entry to its workspace and result, and rewrites the staging copy when
+// the table or the prefix counts differ from what it holds (after the
+// state's last batch is finished; an unchanged plan waits for nothing, so
+// the host can queue the next batch while one runs).
 hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
   const size_t n = p.tab.size();
   const size_t fixed = request_fixed_bytes();
@@ -336,11 +382,18 @@ hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
     return hipErrorOutOfMemory;
   }
   hipError_t e = hipSuccess;
-  if (fixed * n > bs->fixed_cap) e = dev_grow(bs->fixed, bs->fixed_cap, fixed * n, true);
+  if (fixed * n > bs->fixed_cap || p.var > bs->var_cap || sizeof(szsel_result) * n > bs->res_cap ||
+      meta > bs->meta_cap || meta > bs->stage_cap)
+    e = batch_wait(bs);
+  if (e == hipSuccess && fixed * n > bs->fixed_cap) e = dev_grow(bs->fixed, bs->fixed_cap, fixed * n, true);
   if (e == hipSuccess) e = dev_grow(bs->var, bs->var_cap, p.var, false);
   if (e == hipSuccess) e = dev_grow(bs->res, bs->res_cap, sizeof(szsel_result) * n, false);
-  if (e == hipSuccess) e = dev_grow(bs->meta, bs->meta_cap, meta, false);
+  if (e == hipSuccess && meta > bs->meta_cap) {
+    bs->staged.clear();  // a new device table holds nothing yet
+    e = dev_grow(bs->meta, bs->meta_cap, meta, false);
+  }
   if (e == hipSuccess && meta > bs->stage_cap) {
+    bs->staged.clear();
     if (bs->stage) (void)hipHostFree(bs->stage);
     bs->stage = nullptr;
     bs->stage_cap = 0;
@@ -367,8 +420,19 @@ hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
     L.tab = dtab;
     L.first = dfirst + (size_t)L.pass * (n + 1);
   }
-  std::memcpy(bs->stage, p.tab.data(), sizeof(ReqDesc) * n);
-  std::memcpy(bs->stage + tab_bytes, p.first.data(), sizeof(uint32_t) * p.first.size());
+  std::vector<char> img(meta, 0);
+  std::memcpy(img.data(), p.tab.data(), sizeof(ReqDesc) * n);
+  std::memcpy(img.data() + tab_bytes, p.first.data(), sizeof(uint32_t) * p.first.size());
+  if (img != bs->staged) {
+    e = batch_wait(bs);
+    if (e != hipSuccess) {
+      msg = std::string("batch: ") + hipGetErrorString(e);
+      return e;
+    }
+    std::memcpy(bs->stage, img.data(), meta);
+    bs->staged.swap(img);
+    bs->dirty = true;
+  }
   // buffer addresses are part of what a captured graph depends on
   p.sig.push_back((uint64_t)(uintptr_t)bs->fixed);
   p.sig.push_back((uint64_t)(uintptr_t)bs->var);
@@ -378,15 +442,22 @@ hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
   return hipSuccess;
 }
 
-// Upload of the table and every launch of plan p, on stream s.  With G
+// Upload of the staged table and prefix counts when they changed, on
+// stream s (ahead of the launches that read them; not part of a graph).
+hipError_t upload_meta(BatchState *bs, hipStream_t s) {
+  if (!bs->dirty) return hipSuccess;
+  const hipError_t e = hipMemcpyAsync(bs->meta, bs->stage, bs->staged.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) bs->dirty = false;
+  return e;
+}
+
+// Every launch of plan p, on stream s.  With G
 // request groups, group g runs on its own stream (s for group 0) and
 // starts its range scans when group g-1's are done, so that the scans run
 // one group at a time at full bandwidth while the earlier groups' sampled
 // passes (latency- and issue-bound) overlap them; s waits for every group.
 hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s) {
-  const size_t n = p.tab.size();
-  const size_t meta = align_up(sizeof(ReqDesc) * n, 256) + sizeof(uint32_t) * p.first.size();
-  hipError_t e = hipMemcpyAsync(bs->meta, bs->stage, meta, hipMemcpyHostToDevice, s);
+  hipError_t e = hipSuccess;
   const int G = p.groups;
   hipStream_t st[kMaxGroupsPerBatch];
   st[0] = s;
@@ -431,14 +502,12 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     }
   }
   hipError_t e = hipSuccess;
-  // the previous use of this state (its staging buffer, workspace and
-  // results) must be finished before they are rewritten
-  if (bs->used) {
-    e = hipEventSynchronize(bs->done);
-    if (e != hipSuccess) {
-      msg = std::string("batch: ") + hipGetErrorString(e);
-      return SZSEL_EHIP;
-    }
+  // the host waits for the state's previous batch only where it rewrites
+  // what that batch may still read (bind_plan, graph re-capture); on the
+  // device, this batch follows the previous one also across streams
+  if (bs->used && (e = hipStreamWaitEvent(s, bs->done, 0)) != hipSuccess) {
+    msg = std::string("batch: ") + hipGetErrorString(e);
+    return SZSEL_EHIP;
   }
   // knobs: the tuned ones for this batch shape, else the defaults
   const std::vector<uint64_t> key = shape_key(reqs, n);
@@ -468,7 +537,8 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       int rc = make_plan(ctx, ncu, reqs, n, c, p, msg);
       if (rc != SZSEL_OK) return rc;
       if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
-      hipError_t q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
+      hipError_t q = upload_meta(bs, s);
+      if (q == hipSuccess) q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
       ms = 1e30f;
       for (int rep = 0; rep < 3 && q == hipSuccess; rep++) {  // best of 3
         float one = 0.f;
@@ -489,9 +559,9 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     float best_ms = 0.f;
     int rc = time_of(cur, best_ms);
     const int group_opts[] = {1, 2, 4, 8};
-    const int sz_opts[] = {2, 4, 8, 16, 32};
+    const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {64, 128, 256};
-    const int range_opts[] = {1, 2, 4};
+    const int range_opts[] = {1, 2, 4, 8, 16};
     // two sweeps of the coordinates: the best group count depends on how
     // fast the sampled passes became with the other knobs
     for (int sweep = 0; sweep < 2; sweep++) {
@@ -557,11 +627,19 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
   int rc = make_plan(ctx, ncu, reqs, n, tu, p, msg);
   if (rc != SZSEL_OK) return rc;
   if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
+  if ((e = upload_meta(bs, s)) != hipSuccess) {
+    msg = std::string("batch upload: ") + hipGetErrorString(e);
+    return SZSEL_EHIP;
+  }
   // A captured graph forking into more than two request-group streams
   // crashed the host process inside the runtime on this ROCm; such
   // schedules run uncaptured (the path the autotuner times).
   if (opt.graph && p.groups <= kMaxCapturedGroups) {
     if (!bs->exec || bs->sig != p.sig) {
+      if ((e = batch_wait(bs)) != hipSuccess) {  // the old graph may still run
+        msg = std::string("batch: ") + hipGetErrorString(e);
+        return SZSEL_EHIP;
+      }
       if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
       if (bs->graph) (void)hipGraphDestroy(bs->graph);
       bs->exec = nullptr;

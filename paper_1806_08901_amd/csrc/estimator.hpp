@@ -1144,10 +1144,13 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
   constexpr int kPer = kHistWin / kThreads;  // 16 bins per thread
   __shared__ uint32_t s_distinct, s_wave[kWaves];
   const int t = threadIdx.x;
+  // a thread's 16 bins are visited starting at a lane-dependent one, so
+  // that one read of the wave touches distinct LDS banks
+  const int skew = t >> 2;
   uint32_t nz = 0, sum = 0;
 #pragma unroll
   for (int k = 0; k < kPer; k++) {
-    const uint32_t v = s_hist[t * kPer + k];
+    const uint32_t v = s_hist[t * kPer + ((k + skew) & (kPer - 1))];
     nz += v ? 1u : 0u;
     sum += v;
   }
@@ -1172,7 +1175,7 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
   uint32_t base = *s_n + inc - sum;
   for (int q = 0; q < wv; q++) base += s_wave[q];
   for (int k = 0; k < kPer; k++) {
-    const int b = t * kPer + k;
+    const int b = t * kPer + ((k + skew) & (kPer - 1));
     const uint32_t v = s_hist[b];
     for (uint32_t c = 0; c < v; c++) region[base + c] = (uint16_t)(kHistLo + b);
     base += v;

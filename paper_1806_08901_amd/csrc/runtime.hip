@@ -165,8 +165,9 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
   // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; by
   // default 4 workgroups per CU, all of them resident at once
-  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)),
-                                std::max<uint64_t>(1, (uint64_t)tu.sz_wgs_q * (uint64_t)ctx->ncu / 4), kMaxParts);
+  const uint64_t sz_target = tu.sz_target > 0 ? (uint64_t)tu.sz_target
+                                               : std::max<uint64_t>(1, (uint64_t)tu.sz_wgs_q * (uint64_t)ctx->ncu / 4);
+  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)), sz_target, kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
@@ -182,7 +183,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // range_wgs_per_cu workgroups per CU, at least 8 vectors per thread
   const int64_t vn = 16 / (int64_t)esz;
   const int64_t quantum = (int64_t)kThreads * vn;
-  const int64_t rw = (int64_t)tu.range_wgs_per_cu * ctx->ncu;
+  const int64_t rw = tu.range_target > 0 ? (int64_t)tu.range_target : (int64_t)tu.range_wgs_per_cu * ctx->ncu;
   int64_t chunk = (n + rw - 1) / rw;
   chunk = std::max<int64_t>(chunk, 8 * quantum);
   chunk = (chunk + quantum - 1) / quantum * quantum;
