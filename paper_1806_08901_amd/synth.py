@@ -83,17 +83,21 @@ def spectral(shape, slope=-5.0 / 3.0, kmax=64.0, noise=0.01, seed=0, device="cpu
 
 def spiky_constant(shape, frac=1e-3, seed=0, device="cpu", dtype=torch.float32) -> torch.Tensor:
     """A constant c ~ U(-1, 1) plus N(0, 1) spikes at a fraction ``frac`` of
-    the points (the mostly-constant fields of the 2-D batch)."""
-    g = _gen(seed, device)
-    c = 2.0 * torch.rand((), generator=g, device=device, dtype=torch.float64) - 1.0
+    the points (the mostly-constant fields of the 2-D batch).
+
+    Built on the CPU for every device: a spike position drawn twice is
+    written twice, and only the CPU's in-order writes make the field the
+    same on every run."""
+    g = _gen(seed, "cpu")
+    c = 2.0 * torch.rand((), generator=g, dtype=torch.float64) - 1.0
     n = 1
     for s in shape:
         n *= s
-    f = torch.full((n,), float(c), device=device, dtype=torch.float64)
+    f = torch.full((n,), float(c), dtype=torch.float64)
     k = max(1, int(round(frac * n)))
-    idx = torch.randint(0, n, (k,), generator=g, device=device)
-    f[idx] += torch.randn(k, generator=g, device=device, dtype=torch.float64)
-    return f.view(*shape).to(dtype).contiguous()
+    idx = torch.randint(0, n, (k,), generator=g)
+    f[idx] += torch.randn(k, generator=g, dtype=torch.float64)
+    return f.view(*shape).to(dtype).contiguous().to(device)
 
 
 # ---------------------------------------------------------------------------
