@@ -202,14 +202,17 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   more than two request groups are launched without a graph).
  * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the schedule
  *   of single-request calls and of batches without autotuning (and the
- *   autotuner's starting point): SZ
- *   workgroups in quarters of the CU count (1..256, default 16),
- *   smallest ZFP chunk in sampled blocks (a power of two 64..65536, default
- *   64), range workgroups per CU (1..64, default 2); 0 restores the
- *   default.  The SZ and range counts are those of a single request, and
- *   of a whole batch, dealt to its requests in proportion to their sampled
- *   blocks and to the bytes of their fields.  Results do not depend on
- *   them.
+ *   autotuner's starting point): SZ workgroups in quarters of the CU
+ *   count (1..256, default 16), smallest ZFP chunk in sampled blocks (a
+ *   power of two 64..65536, default 64), range workgroups per CU (1..64,
+ *   default 2); 0 restores the default.  Results do not depend on them.
+ * SZSEL_OPT_BATCH_SHARE: how a batch applies the SZ and range counts above
+ *   (0..2, default 0): 0 gives them to every request; 1 makes the SZ count
+ *   the whole batch's, dealt to its requests in proportion to their sampled
+ *   blocks; 2 does that and deals the range count of the batch in
+ *   proportion to the bytes of the fields (a field scanned once for all its
+ *   requests counts once).  Many small fields favour 1 or 2, mixes of large
+ *   and small ones 0; the autotuner tries all three.
  * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
  *   default 1; 0 restores it): the requests are dealt to that many groups
  *   (requests on one field stay together), each running on its own stream,
@@ -238,7 +241,7 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
        SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9,
-       SZSEL_OPT_EC_SAMPLING = 10 };
+       SZSEL_OPT_EC_SAMPLING = 10, SZSEL_OPT_BATCH_SHARE = 11 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* ---------------------------------------------------------------------

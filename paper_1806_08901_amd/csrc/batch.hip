@@ -75,13 +75,14 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       return rc;
     }
   }
-  // Workgroup counts: the schedule's SZ and range counts are the batch's,
-  // dealt to the requests in proportion to their sampled blocks and to the
-  // bytes of their fields (a field scanned once for all its requests counts
-  // once), so that the small fields of a large batch get a few long-running
+  // Workgroup counts (tu.share >= 1): the schedule's SZ count is the
+  // batch's, dealt to the requests in proportion to their sampled blocks,
+  // and (tu.share == 2) its range count too, in proportion to the bytes of
+  // their fields (a field scanned once for all its requests counts once),
+  // so that the small fields of a large batch get a few long-running
   // workgroups instead of many whose time goes to their set-up, the SZ LDS
   // histogram's clearing and hand-over and the completion counters
-  if (n > 1) {
+  if (n > 1 && tu.share > 0) {
     double sz_blocks = 0.0, scan_bytes = 0.0;
     for (int i = 0; i < n; i++) {
       if (d[i].op != SZSEL_OP_ZFP) sz_blocks += (double)d[i].nblk;
@@ -101,7 +102,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       Tune t = tu;
       if (d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sz_blocks > 0.0)
         t.sz_target = share(sz_want, (double)d[i].nblk, sz_blocks);
-      if (scan_bytes > 0.0)
+      if (tu.share >= 2 && scan_bytes > 0.0)
         t.range_target = share(range_want, (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0), scan_bytes);
       const int rc = plan_request(ctx, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, t, d[i]);
       if (rc != SZSEL_OK) {
@@ -558,6 +559,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     Tune cur = opt.fixed;
     float best_ms = 0.f;
     int rc = time_of(cur, best_ms);
+    const int share_opts[] = {0, 1, 2};
     const int group_opts[] = {1, 2, 4, 8};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {64, 128, 256};
@@ -566,6 +568,17 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     // fast the sampled passes became with the other knobs
     for (int sweep = 0; sweep < 2; sweep++) {
     const Tune before = cur;
+    for (int v : share_opts) {
+      if (rc != SZSEL_OK || v == cur.share) continue;
+      Tune c = cur;
+      c.share = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
     for (int v : group_opts) {
       if (rc != SZSEL_OK || v == cur.groups || v > n) continue;
       Tune c = cur;

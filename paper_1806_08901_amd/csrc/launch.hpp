@@ -51,6 +51,8 @@ struct Tune {
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
   int range_wgs_per_cu = 2;  // range workgroups per CU for one request
   int groups = 1;            // batches: request groups pipelined on parallel streams
+  int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
+                             // count is the batch's, 2 = both are the batch's
   // set by the batch planner for one request from the batch's counts above
   // (never tuned or cached): nonzero = SZ workgroups, range workgroups aimed at
   int sz_target = 0;

@@ -139,6 +139,26 @@ def test_request_group_schedules_equal_single_calls(ctx):
         ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
 
 
+def test_workgroup_share_modes_equal_single_calls(ctx):
+    """Fixed schedules that deal the SZ count, or the SZ and range counts,
+    over the batch give the single calls' results; a mode outside 0..2 is
+    rejected."""
+    from paper_1806_08901_amd import szsel
+    items = _items(_fields(), ebs=(1e-3, 1e-5))
+    singles = _singles(ctx, items)
+    try:
+        for mode in (1, 2, 0):
+            ctx.set_option(szsel.OPT_BATCH_SHARE, mode)
+            for groups in (1, 2):
+                ctx.set_option(szsel.OPT_BATCH_GROUPS, groups)
+                assert ctx.select_batch(items) == singles, "share %d groups %d" % (mode, groups)
+        with pytest.raises(szsel.SzselError):
+            ctx.set_option(szsel.OPT_BATCH_SHARE, 3)
+    finally:
+        ctx.set_option(szsel.OPT_BATCH_SHARE, 0)
+        ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
+
+
 def test_batches_in_flight_on_two_streams(ctx):
     a_items = _items(_fields()[:3], ebs=(1e-3,))
     b_items = _items(_fields()[3:6], ebs=(1e-4,))
