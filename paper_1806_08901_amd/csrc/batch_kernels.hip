@@ -65,17 +65,16 @@ __global__ __launch_bounds__(kThreads) void kb_sz(const ReqDesc *tab, const uint
   sz_wg<T, D, VEC>(r, local, L, s_hist);
 }
 
-// The overflow and entropy passes have many small items, most of which
-// (requests without overflow codes) end at once: a grid of a few
-// workgroups per CU loops over them instead of one workgroup per item.  The
-// overflow pass first keeps only the items that have work: every
-// workgroup reads the slice counts of the launch's requests (set by their
-// SZ finalizers) and numbers the kOvfRanges x S items of each by a scan.
-template <int D>
-__global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
-  __shared__ uint32_t s_cnt[kOvfBins];
-  __shared__ uint32_t s_pre[kMaxBatch + 1];
-  __shared__ uint32_t s_wave[kWaves];
+// The overflow and entropy passes have many small items, and how many a
+// request has is known only on the device (overflow slices, chunks with
+// codes): a grid of a few workgroups per CU first numbers the items of the
+// launch's requests (every workgroup reads the counts and scans them) and
+// then loops over them.  Requests without items in this pass (first[i + 1]
+// == first[i]) and skipped requests count 0.  s_pre[i] is request c0 + i's
+// first item, s_pre[c1 - c0] the total.
+template <typename F>
+__device__ inline uint32_t batch_device_items(const ReqDesc *tab, const uint32_t *first, int c0, int c1,
+                                              uint32_t *s_pre, uint32_t *s_wave, F count) {
   const int n = c1 - c0, t = threadIdx.x;
   constexpr int kPer = (kMaxBatch + kThreads - 1) / kThreads;  // requests per thread
   uint32_t cnt[kPer], sum = 0;
@@ -84,8 +83,8 @@ __global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uin
     const int i = t * kPer + k;
     cnt[k] = 0;
     if (i < n && first[c0 + i + 1] != first[c0 + i]) {
-      const ReqState *st = tab[c0 + i].st;
-      if (!skip_request(st)) cnt[k] = get_u32(&st->ovf_slices) * (uint32_t)kOvfRanges;
+      const ReqDesc &r = tab[c0 + i];
+      if (!skip_request(r.st)) cnt[k] = count(r);
     }
     sum += cnt[k];
   }
@@ -108,28 +107,51 @@ __global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uin
   }
   if (t == kThreads - 1 && n == kMaxBatch) s_pre[n] = base;
   __syncthreads();
-  const uint32_t items = s_pre[n];
+  return s_pre[n];
+}
+
+// The request (index from c0) whose items hold item g: the last one whose
+// first item is <= g.
+__device__ inline int batch_owner(const uint32_t *s_pre, int n, uint32_t g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_pre[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+  __shared__ uint32_t s_cnt[kOvfBins];
+  __shared__ uint32_t s_pre[kMaxBatch + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  const uint32_t items = batch_device_items(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
+    return get_u32(&r.st->ovf_slices) * (uint32_t)kOvfRanges;
+  });
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
-    int lo = 0, hi = n - 1;  // last request whose first item is <= g
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_pre[mid] <= g) lo = mid; else hi = mid - 1;
-    }
+    const int lo = batch_owner(s_pre, c1 - c0, g);
     ovf_wg<D>(tab[c0 + lo], (int)(g - s_pre[lo]), s_cnt);
     __syncthreads();
   }
 }
 
+// Items: the chunks the entropy pass works on (ent_chunks), in bit order.
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
-  __shared__ uint32_t s_first[kMaxBatch + 1];
-  batch_stage(first, c0, c1, s_first);
-  const uint32_t items = s_first[c1 - c0] - s_first[0];
+  __shared__ uint32_t s_pre[kMaxBatch + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  const uint32_t items = batch_device_items(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
+    return (uint32_t)__popcll(ent_chunks(r));
+  });
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
-    int local;
-    const ReqDesc &r = tab[batch_find(s_first, c0, c1, g, local)];
-    if (!skip_request(r.st)) ent_wg<T, D>(r, local, L);
+    const int lo = batch_owner(s_pre, c1 - c0, g);
+    const ReqDesc &r = tab[c0 + lo];
+    const uint64_t chunks = ent_chunks(r);
+    uint64_t m = chunks;
+    for (uint32_t k = g - s_pre[lo]; k > 0; k--) m &= m - 1;  // drop the lower chunks
+    ent_wg<T, D>(r, __ffsll((long long)m) - 1, chunks, L);
     __syncthreads();
   }
 }

@@ -1272,16 +1272,26 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   for (int b = threadIdx.x; b < kOvfBins; b += kThreads) out[b] = s_cnt[b];
 }
 
-// Entropy pass, workgroup c of 64: the adjacent-pair subtree of h log2 h
-// over bins [1024c, 1024c+1024) (4 consecutive bins per thread), clearing
-// the bins for the next request.
-// The completion tree folds the 256 subtrees and its last workgroup
-// finishes the request:
+// Chunks of 1,024 bins the entropy pass works on: those some code fell in
+// (chunk 0 always: it holds the unpredictable count), or all 64 when the
+// final counts are wanted (Huffman cost, debug dump), since the others'
+// final counts must then be written as zeros.
+__device__ inline uint64_t ent_chunks(const ReqDesc &r) {
+  return (r.huff || r.dbg_hist) ? ~0ull : (get_u64(&r.st->code_chunks) | 1ull);
+}
+
+// Entropy pass, chunk c (one of `chunks`): the adjacent-pair subtree of
+// h log2 h over bins [1024c, 1024c+1024) (4 consecutive bins per thread),
+// clearing the bins for the next request.  The chunks' workgroups count on
+// one counter; the last one folds the 64 chunk subtrees (0 for a chunk
+// without codes, whose h log2 h terms are all 0) by the wave butterfly, the
+// same tree as the completion of the other passes, and finishes the
+// request:
 // entropy (Eq. 5 with P_i = h_i/n), SZ bit-rate (entropy + offset + W escape
 // bits per unpredictable point, Section 6.2), both PSNRs and the selection
 // of Algorithm 1 (lower bit-rate wins, ties go to ZFP).
 template <typename T, int D>
-__device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
+__device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds &L) {
   constexpr int BS = 1 << (2 * D);
   const int t = threadIdx.x;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
@@ -1290,16 +1300,13 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
   static_assert(kEntPerThread == 4, "four bins per thread, one 16-byte vector");
   const int bin0 = c * kEntChunk + t * kEntPerThread;
   static_assert(kEntChunk == 1024 && kEntWgs == 64, "one code-chunk bit per entropy workgroup");
-  // a chunk no code fell in holds zeros everywhere (its copies were never
-  // written, its h log2 h subtree is 0): nothing to read or clear
-  const bool live = c == 0 || ((get_u64(&r.st->code_chunks) >> c) & 1u);
   // the SZ workgroups' counts, spread over nhc copies so that no bin takes
   // more than about 128 workgroups' atomics; every copy's four bins are one
   // 16-byte load, all issued before any is used
   uint4 hc[kHistCopies];
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++)
-    hc[q] = live && q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
+    hc[q] = q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
   uint32_t h[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++) {
@@ -1308,15 +1315,14 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     h[2] += hc[q].z;
     h[3] += hc[q].w;
   }
-  if (live) {  // add the overflow pass's counts
+  // the overflow pass's counts
 #pragma unroll 8
-    for (int p = 0; p < S; p++) {
-      const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
-      h[0] += o.x;
-      h[1] += o.y;
-      h[2] += o.z;
-      h[3] += o.w;
-    }
+  for (int p = 0; p < S; p++) {
+    const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
+    h[0] += o.x;
+    h[1] += o.y;
+    h[2] += o.z;
+    h[3] += o.w;
   }
   if (bin0 == 0) h[0] = (uint32_t)unpred;  // code 0: the unpredictable points
   if (r.huff) *(uint4 *)(r.hfinal + bin0) = make_uint4(h[0], h[1], h[2], h[3]);
@@ -1346,8 +1352,18 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, TileLds &L) {
     pc.s = (L.red[0] + L.red[1]) + (L.red[2] + L.red[3]);
     part_store(r.ep, c, pc);
   }
+  wait_memory();
+  __syncthreads();
+  if (t == 0) {
+    PassSync *sy = r.sync + kPassEnt;
+    const uint32_t old = __hip_atomic_fetch_add(&sy->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    L.last = old == (uint32_t)__popcll(chunks) - 1u;
+    if (L.last) put_u32(&sy->top.v, 0);
+  }
+  __syncthreads();
+  if (!L.last) return;
   Part tot;
-  if (!pass_complete<false>(r.ep, r.grp[kPassEnt], r.sync + kPassEnt, c, kEntWgs, L, tot)) return;
+  if (t < kWave) tot = part_wave<false>(((chunks >> t) & 1u) ? part_load(r.ep, t) : part_identity<false>());
   if (t == 0) {
     const double s = tot.s;
     ReqState *st = r.st;

@@ -50,7 +50,8 @@ template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_ent(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
-  ent_wg<T, D>(r, blockIdx.x, L);
+  const uint64_t chunks = ent_chunks(r);
+  if ((chunks >> blockIdx.x) & 1u) ent_wg<T, D>(r, blockIdx.x, chunks, L);
 }
 
 template <typename T, int D>
