@@ -28,13 +28,17 @@ __device__ inline int batch_find(const uint32_t *s_first, int c0, int c1, uint32
 }
 
 // One work item per workgroup.
+// Both are the same in every thread; saying so keeps the request's fields
+// in scalar registers (one copy per wave, not per lane).
 __device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t *s_first, int &local) {
   batch_stage(first, c0, c1, s_first);
-  return batch_find(s_first, c0, c1, blockIdx.x, local);
+  const int i = batch_find(s_first, c0, c1, blockIdx.x, local);
+  local = __builtin_amdgcn_readfirstlane(local);
+  return __builtin_amdgcn_readfirstlane(i);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
   int local;
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *tab, const u
 }
 
 template <typename T, int D, bool VEC, bool EC>
-__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void kb_zfp(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void kb_zfp(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
   int local;
@@ -54,7 +58,7 @@ __global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void kb_zfp(const 
 }
 
 template <typename T, int D, bool VEC>
-__global__ __launch_bounds__(kThreads) void kb_sz(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kThreads) void kb_sz(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_hist[kHistWin];
   __shared__ uint32_t s_first[kMaxBatch + 1];
@@ -118,11 +122,11 @@ __device__ inline int batch_owner(const uint32_t *s_pre, int n, uint32_t g) {
     const int mid = (lo + hi + 1) >> 1;
     if (s_pre[mid] <= g) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);  // the same in every thread
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ uint32_t s_cnt[kOvfBins];
   __shared__ uint32_t s_pre[kMaxBatch + 1];
   __shared__ uint32_t s_wave[kWaves];
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *tab, const uin
 
 // Items: the chunks the entropy pass works on (ent_chunks), in bit order.
 template <typename T, int D>
-__global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_pre[kMaxBatch + 1];
   __shared__ uint32_t s_wave[kWaves];
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *tab, const uin
 }
 
 template <typename T, int D>
-__global__ __launch_bounds__(kHuffThreads) void kb_huff(const ReqDesc *tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kHuffThreads) void kb_huff(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ HuffLds S;
   __shared__ uint32_t s_first[kMaxBatch + 1];
   int local;
