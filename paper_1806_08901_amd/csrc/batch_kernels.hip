@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void kb_zfp(const 
 }
 
 template <typename T, int D, bool VEC>
-__global__ __launch_bounds__(kThreads) void kb_sz(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kThreads, (kSzWavesPerSimd<T, D>)) void kb_sz(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_hist[kHistWin];
   __shared__ uint32_t s_first[kMaxBatch + 1];

@@ -436,6 +436,11 @@ __device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s
     return bfp_int<T>(x, emax);
 }
 
+// Occupancy of the SZ kernels: waves per SIMD (the register budget that
+// keeps their state out of scratch memory; binary64 3-D would spill at 5).
+template <typename T, int D>
+constexpr int kSzWavesPerSimd = (sizeof(T) == 8 && D == 3) ? 4 : 5;
+
 // Occupancy of the ZFP kernels: waves per SIMD (one block per lane).
 template <typename T, int D>
 constexpr int kZfpWavesPerSimd = (sizeof(T) == 8 && D == 3) ? 1 : 2;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void k_zfp(ReqDesc
 }
 
 template <typename T, int D, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_sz(ReqDesc r) {
+__global__ __launch_bounds__(kThreads, (kSzWavesPerSimd<T, D>)) void k_sz(ReqDesc r) {
   __shared__ TileLds L;
   __shared__ uint32_t s_hist[kHistWin];
   if (skip_request(r.st)) return;
