@@ -98,11 +98,12 @@ def copy_calibration(torch):
 
 
 def source_digest():
-    """Digest of the kernel sources, to tell whether recorded counters still
-    describe the current kernels."""
+    """Digest of the kernel sources and of the planning that sets their
+    launch shapes, to tell whether recorded counters still describe the
+    current kernels."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("device.hpp", "estimator.hpp", "kernels.hip"):
+    for name in ("device.hpp", "estimator.hpp", "kernels.hip", "launch.hpp", "runtime.hip"):
         with open(os.path.join(ROOT, "paper_1806_08901_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -47,9 +47,9 @@ hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 // they only move the balance between parallelism and per-workgroup
 // overheads, which the batch autotuner measures.
 struct Tune {
-  int sz_wgs_q = 16;         // SZ workgroups per request, in quarters of the CU count
+  int sz_wgs_q = 8;          // SZ workgroups per request, in quarters of the CU count
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
-  int range_wgs_per_cu = 2;  // range workgroups per CU for one request
+  int range_wgs_per_cu = 1;  // range workgroups per CU for one request
   int groups = 1;            // batches: request groups pipelined on parallel streams
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
                              // count is the batch's, 2 = both are the batch's

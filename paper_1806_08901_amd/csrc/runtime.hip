@@ -164,7 +164,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   };
   const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
   // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; by
-  // default 4 workgroups per CU, all of them resident at once
+  // default 2 workgroups per CU, all of them resident at once
   const uint64_t sz_target = tu.sz_target > 0 ? (uint64_t)tu.sz_target
                                                : std::max<uint64_t>(1, (uint64_t)tu.sz_wgs_q * (uint64_t)ctx->ncu / 4);
   const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)), sz_target, kMaxParts);
