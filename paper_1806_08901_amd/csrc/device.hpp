@@ -145,7 +145,8 @@ struct ReqDesc {
   Parts ep;        // entropy pass: one h log2 h subtree per 256-bin chunk (sse slot)
   Parts grp[kPasses];  // per pass, the partials of its completion groups
   uint16_t *ovf;       // per SZ workgroup, sblk * 4^d codes that fell outside its LDS window
-  uint32_t *ovf_hist;  // kOvfSlices dense 65536-bin counts of the overflow codes
+  uint32_t *ovf_hist;  // 65536-bin counts of the overflow codes (added to by the overflow
+                       // pass, read and cleared by the entropy pass)
   uint32_t *hist;      // kHistCopies x 65536 counts, left zeroed by the entropy pass
   uint32_t *hfinal;    // the final 65536 counts, for the Huffman pass
   szsel_result *res;

@@ -1212,8 +1212,10 @@ __device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
 
 // Overflow pass, workgroup (p, q) of kOvfSlices x kOvfRanges: for p below
 // the request's slice count S, counts, in LDS, the overflow codes of SZ
-// workgroups [p n/S, (p+1) n/S) that lie in code range q, and writes the
-// dense counts of that range to slice p's counts (no atomics).  The occupied 16-byte vectors (8 codes) of the
+// workgroups [p n/S, (p+1) n/S) that lie in code range q, and adds the
+// nonzero ones to the request's overflow counts (one global atomic per
+// nonzero bin; the entropy pass reads and clears them).  The occupied
+// 16-byte vectors (8 codes) of the
 // slice's regions are numbered through an LDS prefix sum of the regions'
 // vector counts, so the work follows the number of overflow codes; 4
 // vectors are in flight per thread.
@@ -1273,8 +1275,11 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
     for (int u = 0; u < 4; u++) count(v[u], valid[u]);
   }
   __syncthreads();
-  uint32_t *out = r.ovf_hist + (size_t)p * kBins + lo;
-  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) out[b] = s_cnt[b];
+  uint32_t *out = r.ovf_hist + lo;
+  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) {
+    const uint32_t v = s_cnt[b];
+    if (v) atomicAdd(&out[b], v);
+  }
 }
 
 // Chunks of 1,024 bins the entropy pass works on: those some code fell in
@@ -1321,14 +1326,11 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
     h[3] += hc[q].w;
   }
   // the overflow pass's counts
-#pragma unroll 8
-  for (int p = 0; p < S; p++) {
-    const uint4 o = *(const uint4 *)(r.ovf_hist + (size_t)p * kBins + bin0);
-    h[0] += o.x;
-    h[1] += o.y;
-    h[2] += o.z;
-    h[3] += o.w;
-  }
+  const uint4 o = S > 0 ? *(const uint4 *)(r.ovf_hist + bin0) : make_uint4(0, 0, 0, 0);
+  h[0] += o.x;
+  h[1] += o.y;
+  h[2] += o.z;
+  h[3] += o.w;
   if (bin0 == 0) h[0] = (uint32_t)unpred;  // code 0: the unpredictable points
   if (r.huff) *(uint4 *)(r.hfinal + bin0) = make_uint4(h[0], h[1], h[2], h[3]);
   if (r.dbg_hist) {
@@ -1339,6 +1341,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
   for (int q = 0; q < kHistCopies; q++)
     if (q < nhc && (hc[q].x | hc[q].y | hc[q].z | hc[q].w))
       *(uint4 *)(r.hist + (size_t)q * kBins + bin0) = make_uint4(0, 0, 0, 0);
+  if (o.x | o.y | o.z | o.w) *(uint4 *)(r.ovf_hist + bin0) = make_uint4(0, 0, 0, 0);
   double hv[kEntPerThread];
 #pragma unroll
   for (int k = 0; k < kEntPerThread; k++) {

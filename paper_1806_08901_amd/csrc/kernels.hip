@@ -148,7 +148,7 @@ size_t request_fixed_bytes() {
   return align_up(sizeof(ReqState), 256) + align_up(sizeof(PassSync) * kPasses, 256) +
          align_up(sizeof(uint32_t) * kBins * kHistCopies, 256) + align_up(sizeof(szsel_result), 256) +
          parts_bytes(kEntWgs) + group_parts_bytes() * kPasses +
-         align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256) + align_up(sizeof(uint32_t) * kBins, 256);
+         align_up(sizeof(uint32_t) * kBins, 256) + align_up(sizeof(uint32_t) * kBins, 256);
 }
 
 size_t request_var_bytes(int nrange, int nzfp, int nsz, int64_t ovf_cap) {
@@ -180,7 +180,7 @@ void bind_request_workspace(ReqDesc &r, char *fixed, char *var) {
   r.ep = bind_parts(p, kEntWgs);
   for (int k = 0; k < kPasses; k++) r.grp[k] = bind_parts(p, kMaxGroups);
   r.ovf_hist = (uint32_t *)p;
-  p += align_up(sizeof(uint32_t) * kBins * kOvfSlices, 256);
+  p += align_up(sizeof(uint32_t) * kBins, 256);
   r.hfinal = (uint32_t *)p;
   p = var;
   r.rp = bind_parts(p, r.nrange);
