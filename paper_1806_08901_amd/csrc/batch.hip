@@ -541,7 +541,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       hipError_t q = upload_meta(bs, s);
       if (q == hipSuccess) q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
       ms = 1e30f;
-      for (int rep = 0; rep < 3 && q == hipSuccess; rep++) {  // best of 3
+      for (int rep = 0; rep < 5 && q == hipSuccess; rep++) {  // best of 5
         float one = 0.f;
         q = hipEventRecord(t0, s);
         if (q == hipSuccess) q = enqueue_plan(bs, p, s);
