@@ -194,9 +194,10 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  * SZSEL_OPT_PROFILE: nonzero records HIP events between the passes of every
  *   single-request call (read with szsel_profile_read).
  * SZSEL_OPT_AUTOTUNE: nonzero lets szsel_select_batch time a few launch
- *   shapes (workgroups per request and pass) the first time it sees a batch
- *   shape and keep the fastest; 0 (default) uses the fixed schedule.  The
- *   results do not depend on it.
+ *   shapes (workgroups per request and pass, request groups, how the counts
+ *   are shared, overflow codes per slice of the overflow pass) the first
+ *   time it sees a batch shape and keep the fastest; 0 (default) uses the
+ *   fixed schedule.  The results do not depend on it.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
  *   HIP graph and replays it while the batch shape repeats (schedules with
  *   more than two request groups are launched without a graph).

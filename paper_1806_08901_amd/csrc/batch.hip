@@ -564,6 +564,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {64, 128, 256};
     const int range_opts[] = {1, 2, 4, 8, 16};
+    const int ovf_opts[] = {kOvfPerSlice, 2 * kOvfPerSlice, 4 * kOvfPerSlice};
     // two sweeps of the coordinates: the best group count depends on how
     // fast the sampled passes became with the other knobs
     for (int sweep = 0; sweep < 2; sweep++) {
@@ -616,6 +617,17 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       if (rc != SZSEL_OK || v == cur.range_wgs_per_cu) continue;
       Tune c = cur;
       c.range_wgs_per_cu = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    for (int v : ovf_opts) {
+      if (rc != SZSEL_OK || v == cur.ovf_slice) continue;
+      Tune c = cur;
+      c.ovf_slice = v;
       float ms = 0.f;
       rc = time_of(c, ms);
       if (rc == SZSEL_OK && ms < best_ms) {

@@ -32,7 +32,7 @@ constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workg
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
 constexpr int kHistCopies = 16;        // most global histogram copies (SZ workgroup w adds to copy w mod nhc)
-constexpr int kOvfPerSlice = 65536;    // overflow codes per slice of the overflow count
+constexpr int kOvfPerSlice = 65536;    // overflow codes per slice of the overflow count (default)
 constexpr int kMaxBatch = 1024;        // requests per batch
 constexpr int kGroup = 64;             // workgroups per completion group
 constexpr int kMaxGroups = kMaxParts / kGroup;
@@ -139,6 +139,8 @@ struct ReqDesc {
   int32_t nhc;     // global histogram copies in use (power of two <= kHistCopies)
   int32_t huff;    // 0 no Huffman cost, 1 report it, 2 report and select with it
   int32_t ec;      // ZFP side: 0 exact, 1 point sub-sampling, 2 sub-sampling with gain weights
+  int32_t ovf_per_slice;  // overflow codes per slice of the overflow pass (>= 1)
+  int32_t pad0;
   ReqState *st;
   PassSync *sync;  // kPasses completion trees
   Parts rp, zp, sp;

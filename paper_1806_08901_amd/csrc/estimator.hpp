@@ -1196,9 +1196,10 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
 // workgroups' subtrees, maximum error, unpredictable count.
 __device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
   if (threadIdx.x == 0) {
-    // slices of the overflow count: about kOvfPerSlice codes each, and few
-    // enough SZ workgroups per slice for the overflow pass's LDS tables
-    const uint64_t want = (tot.b + kOvfPerSlice - 1) / kOvfPerSlice;
+    // slices of the overflow count: about r.ovf_per_slice codes each, and
+    // few enough SZ workgroups per slice for the overflow pass's LDS tables
+    const uint64_t per = (uint64_t)r.ovf_per_slice;
+    const uint64_t want = (tot.b + per - 1) / per;
     const uint64_t least = ((uint64_t)r.nsz + kOvfMaxRegions - 1) / kOvfMaxRegions;
     uint64_t sl = want > least ? want : least;
     sl = sl < 1 ? 1 : (sl > (uint64_t)kOvfSlices ? (uint64_t)kOvfSlices : sl);

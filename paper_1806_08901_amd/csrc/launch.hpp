@@ -51,6 +51,7 @@ struct Tune {
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
   int range_wgs_per_cu = 1;  // range workgroups per CU for one request
   int groups = 1;            // batches: request groups pipelined on parallel streams
+  int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
                              // count is the batch's, 2 = both are the batch's
   // set by the batch planner for one request from the batch's counts above

@@ -102,6 +102,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   r.sz_offset = ctx->sz_offset;
   r.huff = ctx->huffman;
   r.ec = ctx->ec;
+  r.ovf_per_slice = tu.ovf_slice > 0 ? tu.ovf_slice : kOvfPerSlice;
   int64_t n = 1;
   uint64_t nblk = 1;
   for (int k = 0; k < nd; k++) {
