@@ -41,6 +41,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 constexpr int kMaxGroupsPerBatch = 8;
 constexpr int kMaxCapturedGroups = 2;  // larger group counts are launched without a graph
+constexpr int kGraphCache = 8;         // captured graphs kept per batch state
 
 struct Plan {
   std::vector<ReqDesc> tab;             // table order
@@ -315,9 +316,15 @@ struct BatchState {
   hipEvent_t fork = nullptr;
   hipEvent_t scanned[kMaxGroupsPerBatch] = {};    // group g's range scans are done
   hipEvent_t finished[kMaxGroupsPerBatch] = {};   // group g's last pass is done
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::vector<uint64_t> sig;  // launch shape of the captured graph
+  struct Graph {
+    std::vector<uint64_t> key;  // launch shape, result destination
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<Graph> graphs;  // captured graphs, the least recently used replaced
+  uint64_t clock = 0;
+  std::vector<const void *> outs;  // result destinations of the last calls
   std::vector<uint64_t> last_key;  // last batch shape, and its knobs
   Tune last_tune;
   bool last_auto = false;
@@ -331,8 +338,10 @@ size_t batch_state_bytes(const BatchState *bs) {
 void batch_destroy(BatchState *bs) {
   if (!bs) return;
   (void)hipDeviceSynchronize();
-  if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
-  if (bs->graph) (void)hipGraphDestroy(bs->graph);
+  for (BatchState::Graph &g : bs->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   if (bs->cap) (void)hipStreamDestroy(bs->cap);
   for (hipStream_t q : bs->side)
     if (q) (void)hipStreamDestroy(q);
@@ -656,39 +665,72 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     msg = std::string("batch upload: ") + hipGetErrorString(e);
     return SZSEL_EHIP;
   }
+  const size_t res_bytes = sizeof(szsel_result) * (size_t)n;
+  bool copied = false;
   // A captured graph forking into more than two request-group streams
   // crashed the host process inside the runtime on this ROCm; such
   // schedules run uncaptured (the path the autotuner times).
   if (opt.graph && p.groups <= kMaxCapturedGroups) {
-    if (!bs->exec || bs->sig != p.sig) {
-      if ((e = batch_wait(bs)) != hipSuccess) {  // the old graph may still run
-        msg = std::string("batch: ") + hipGetErrorString(e);
-        return SZSEL_EHIP;
+    // the results' copy is part of the graph when `out` came back from one
+    // of the last calls (a caller rotating a few result buffers) and the
+    // device can reach it (pinned host or device memory): a copy queued
+    // after a graph starts several microseconds after it ends, one inside it
+    // right away.  Such graphs are kept per destination; a destination seen
+    // once gets the graph without the copy, so fresh buffers every call do
+    // not capture every call.
+    const bool again = std::find(bs->outs.begin(), bs->outs.end(), (const void *)out) != bs->outs.end();
+    if (!again) {
+      if (bs->outs.size() >= (size_t)kGraphCache - 1) bs->outs.erase(bs->outs.begin());
+      bs->outs.push_back(out);
+    }
+    hipPointerAttribute_t at;
+    const bool reach = again && hipPointerGetAttributes(&at, out) == hipSuccess &&
+                       (at.type == hipMemoryTypeHost || at.type == hipMemoryTypeDevice);
+    if (again && !reach) (void)hipGetLastError();  // unregistered host memory: not an error here
+    std::vector<uint64_t> key = p.sig;
+    key.push_back(reach ? (uint64_t)(uintptr_t)out : 0u);
+    key.push_back((uint64_t)n);
+    BatchState::Graph *g = nullptr;
+    for (BatchState::Graph &c : bs->graphs)
+      if (c.key == key) g = &c;
+    if (!g) {
+      if (bs->graphs.size() >= (size_t)kGraphCache) {
+        if ((e = batch_wait(bs)) != hipSuccess) {  // the graph replaced may still run
+          msg = std::string("batch: ") + hipGetErrorString(e);
+          return SZSEL_EHIP;
+        }
+        auto lru = std::min_element(bs->graphs.begin(), bs->graphs.end(),
+                                    [](const BatchState::Graph &a, const BatchState::Graph &b) { return a.used < b.used; });
+        if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+        if (lru->graph) (void)hipGraphDestroy(lru->graph);
+        bs->graphs.erase(lru);
       }
-      if (bs->exec) (void)hipGraphExecDestroy(bs->exec);
-      if (bs->graph) (void)hipGraphDestroy(bs->graph);
-      bs->exec = nullptr;
-      bs->graph = nullptr;
-      bs->sig.clear();
+      BatchState::Graph c;
       e = hipStreamBeginCapture(bs->cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         hipError_t e2 = enqueue_plan(bs, p, bs->cap);
-        e = hipStreamEndCapture(bs->cap, &bs->graph);
+        if (e2 == hipSuccess && reach) e2 = hipMemcpyAsync(out, bs->res, res_bytes, hipMemcpyDefault, bs->cap);
+        e = hipStreamEndCapture(bs->cap, &c.graph);
         if (e == hipSuccess) e = e2;
       }
-      if (e == hipSuccess) e = hipGraphInstantiate(&bs->exec, bs->graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0);
       if (e != hipSuccess) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        if (c.graph) (void)hipGraphDestroy(c.graph);
         msg = std::string("batch graph capture: ") + hipGetErrorString(e);
         return SZSEL_EHIP;
       }
-      bs->sig = p.sig;
+      c.key = std::move(key);
+      bs->graphs.push_back(std::move(c));
+      g = &bs->graphs.back();
     }
-    e = hipGraphLaunch(bs->exec, s);
+    g->used = ++bs->clock;
+    e = hipGraphLaunch(g->exec, s);
+    copied = reach;
   } else {
     e = enqueue_plan(bs, p, s);
   }
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out, bs->res, sizeof(szsel_result) * (size_t)n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && !copied) e = hipMemcpyAsync(out, bs->res, res_bytes, hipMemcpyDefault, s);
   if (e == hipSuccess) e = hipEventRecord(bs->done, s);
   if (e != hipSuccess) {
     msg = std::string("batch launch: ") + hipGetErrorString(e);

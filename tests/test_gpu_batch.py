@@ -139,6 +139,30 @@ def test_request_group_schedules_equal_single_calls(ctx):
         ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
 
 
+def test_rotating_result_buffers(ctx):
+    """Three result buffers used in turn over seven calls with no host
+    synchronisation (from the second round on, each destination's graph
+    holds the results' copy), the field changed on the stream before every
+    call: each call's buffer holds that call's results."""
+    from paper_1806_08901_amd.szsel import _as_dict
+    f = synth.spectral((48, 40, 36), seed=76).cuda()
+    items_of = lambda a: [(a, eb, oracle.EB_REL, (1, 2, 1), oracle.OP_SELECT) for eb in (1e-2, 1e-4, 1e-6)]
+    items = items_of(f)
+    reqs = ctx.make_requests(items)
+    bufs = [ctx.result_buffer(len(items)) for _ in range(3)]
+    snaps, got = [], []
+    for k in range(7):
+        f.mul_(0.75).add_(0.05 * k)
+        snaps.append(f.clone())
+        ctx.select_batch(None, reqs=reqs, sync=False, out=bufs[k % 3])
+        if k % 3 == 2 or k == 6:  # read the round's buffers once the stream is there
+            torch.cuda.synchronize()
+            for j in range(k - k % 3, k + 1):
+                got.append([_as_dict(bufs[j % 3][i]) for i in range(len(items))])
+    for k in range(7):
+        assert got[k] == _singles(ctx, items_of(snaps[k])), "call %d" % k
+
+
 def test_workgroup_share_modes_equal_single_calls(ctx):
     """Fixed schedules that deal the SZ count, or the SZ and range counts,
     over the batch give the single calls' results; a mode outside 0..2 is
