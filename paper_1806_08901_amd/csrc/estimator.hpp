@@ -437,9 +437,9 @@ __device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s
 }
 
 // Occupancy of the SZ kernels: waves per SIMD (the register budget that
-// keeps their state out of scratch memory; binary64 3-D would spill at 5).
+// keeps their state out of scratch memory; one more wave would spill).
 template <typename T, int D>
-constexpr int kSzWavesPerSimd = (sizeof(T) == 8 && D == 3) ? 4 : 5;
+constexpr int kSzWavesPerSimd = D == 3 ? (sizeof(T) == 8 ? 4 : 5) : (sizeof(T) == 8 ? 5 : 6);
 
 // Occupancy of the ZFP kernels: waves per SIMD (one block per lane).
 template <typename T, int D>
