@@ -397,8 +397,13 @@ __global__ __launch_bounds__(kRedThreads) void k_tree_level(const double *in, in
   const double a0 = i < n ? in[i] : 0.0, a1 = i + 1 < n ? in[i + 1] : 0.0;
   s[threadIdx.x] = a0 + a1;
   __syncthreads();
+  // each level reads all its pairs before any is overwritten: the slots a
+  // level writes are read by other waves in the same level
   for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] = s[2 * threadIdx.x] + s[2 * threadIdx.x + 1];
+    double v = 0.0;
+    if ((int)threadIdx.x < w) v = s[2 * threadIdx.x] + s[2 * threadIdx.x + 1];
+    __syncthreads();
+    if ((int)threadIdx.x < w) s[threadIdx.x] = v;
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = s[0];
