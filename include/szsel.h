@@ -192,7 +192,8 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  * SZSEL_OPT_SZ_OFFSET: bits per value added to the SZ entropy estimate
  *   (Section 6.2 sets it to 0.5; default 0.5).
  * SZSEL_OPT_PROFILE: nonzero records HIP events between the passes of every
- *   single-request call (read with szsel_profile_read).
+ *   single-request call and around every launch of a batch (batches then
+ *   launch without a graph); read with szsel_profile_read.
  * SZSEL_OPT_AUTOTUNE: nonzero lets szsel_select_batch time a few launch
  *   shapes (workgroups per request and pass, request groups, how the counts
  *   are shared, overflow codes per slice of the overflow pass) the first
@@ -314,9 +315,15 @@ int szsel_sz_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, in
 
 /* Phase timers: synchronises the recorded events and returns, per phase
  * (0 = range pass, 1 = ZFP pass, 2 = SZ pass, 3 = overflow count, 4 =
- * entropy and selection), the summed GPU milliseconds in ms[5] and the
- * number of timed calls in calls[5]; then clears them. */
+ * entropy and selection, with the Huffman pass when it runs), the summed GPU
+ * milliseconds in ms[5] and the number of timed calls (single requests) or
+ * launches (batches: one launch per pass and request class) in calls[5];
+ * then clears them. */
 int szsel_profile_read(szsel_ctx *ctx, double *ms, uint64_t *calls);
+
+/* The same split by field dtype: entry 2 * phase + dtype (SZSEL_F32 = 0,
+ * SZSEL_F64 = 1) of ms[10] and calls[10]; clears the timers too. */
+int szsel_profile_read_split(szsel_ctx *ctx, double *ms, uint64_t *calls);
 
 /* Arms per-sample dumps for the next single-request call (NULL disarms). */
 int szsel_set_debug(szsel_ctx *ctx, const szsel_debug *dump);

@@ -466,7 +466,27 @@ hipError_t upload_meta(BatchState *bs, hipStream_t s) {
 // starts its range scans when group g-1's are done, so that the scans run
 // one group at a time at full bandwidth while the earlier groups' sampled
 // passes (latency- and issue-bound) overlap them; s waits for every group.
-hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s) {
+// One launch, with the timer's event pair around it when profiling.
+hipError_t timed_launch(const BatchLaunch &L, hipStream_t s, LaunchTimer *lt) {
+  if (!lt) return launch_batch_pass(L, s);
+  const size_t k = lt->used;
+  hipError_t e = hipSuccess;
+  while (e == hipSuccess && lt->ev.size() < 2 * (k + 1)) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreate(&ev);
+    if (e == hipSuccess) lt->ev.push_back(ev);
+  }
+  if (e != hipSuccess) return e;
+  if (lt->tag.size() < k + 1) lt->tag.resize(k + 1);
+  lt->tag[k] = 2 * L.pass + L.dtype;
+  e = hipEventRecord(lt->ev[2 * k], s);
+  if (e == hipSuccess) e = launch_batch_pass(L, s);
+  if (e == hipSuccess) e = hipEventRecord(lt->ev[2 * k + 1], s);
+  if (e == hipSuccess) lt->used = k + 1;
+  return e;
+}
+
+hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTimer *lt = nullptr) {
   hipError_t e = hipSuccess;
   const int G = p.groups;
   hipStream_t st[kMaxGroupsPerBatch];
@@ -477,10 +497,10 @@ hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s) {
   for (int g = 0; g < G && e == hipSuccess; g++) {
     if (g > 0) e = hipStreamWaitEvent(st[g], bs->scanned[g - 1], 0);
     for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
-      if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = launch_batch_pass(p.launches[k], st[g]);
+      if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = timed_launch(p.launches[k], st[g], lt);
     if (G > 1 && e == hipSuccess) e = hipEventRecord(bs->scanned[g], st[g]);
     for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
-      if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = launch_batch_pass(p.launches[k], st[g]);
+      if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = timed_launch(p.launches[k], st[g], lt);
     if (G > 1 && g > 0 && e == hipSuccess) e = hipEventRecord(bs->finished[g], st[g]);
   }
   for (int g = 1; g < G && e == hipSuccess; g++) e = hipStreamWaitEvent(s, bs->finished[g], 0);
@@ -670,7 +690,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
   // A captured graph forking into more than two request-group streams
   // crashed the host process inside the runtime on this ROCm; such
   // schedules run uncaptured (the path the autotuner times).
-  if (opt.graph && p.groups <= kMaxCapturedGroups) {
+  if (opt.graph && !opt.timer && p.groups <= kMaxCapturedGroups) {
     // the results' copy is part of the graph when `out` came back from one
     // of the last calls (a caller rotating a few result buffers) and the
     // device can reach it (pinned host or device memory): a copy queued
@@ -728,7 +748,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     e = hipGraphLaunch(g->exec, s);
     copied = reach;
   } else {
-    e = enqueue_plan(bs, p, s);
+    e = enqueue_plan(bs, p, s, opt.timer);
   }
   if (e == hipSuccess && !copied) e = hipMemcpyAsync(out, bs->res, res_bytes, hipMemcpyDefault, s);
   if (e == hipSuccess) e = hipEventRecord(bs->done, s);

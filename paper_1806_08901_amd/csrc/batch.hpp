@@ -15,10 +15,20 @@ namespace szsel {
 
 struct BatchState;
 
+// Phase timer of batched launches: an event pair around every launch,
+// tagged 2 * pass + dtype (pass numbering of BatchLaunch, dtype SZSEL_F32 /
+// SZSEL_F64).  Events are created on demand and reused after a drain.
+struct LaunchTimer {
+  std::vector<hipEvent_t> ev;  // 2 per recorded launch
+  std::vector<int> tag;
+  size_t used = 0;             // launches recorded since the last drain
+};
+
 struct BatchOptions {
   bool autotune = false;  // time launch-shape candidates per batch shape, keep the fastest
   bool graph = true;      // capture the launches as a HIP graph and replay it
   Tune fixed;             // the schedule used without autotuning
+  LaunchTimer *timer = nullptr;  // non-NULL: time every launch (eager launches, no graph)
 };
 
 // Plans and runs the n requests on stream s and copies the results to

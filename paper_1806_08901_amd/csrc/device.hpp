@@ -237,36 +237,6 @@ template <typename I> __device__ inline I wsub(I a, I b) {
   return (I)((U)a - (U)b);
 }
 
-// Forward 4-point lift; equals (1/16)[[4,4,4,4],[5,1,-1,-5],[-4,4,4,-4],[-2,6,-6,2]]
-// on multiples of 16.  Returns output number `which`.
-template <typename I>
-__device__ inline I fwd_lift_pick(I x0, I x1, I x2, I x3, int which) {
-  const I s03 = wadd(x0, x3) >> 1, d03 = wsub(x0, s03);
-  const I s12 = wadd(x1, x2) >> 1, d12 = wsub(x1, s12);
-  const I y0 = wadd(s03, s12) >> 1;
-  const I y2 = wsub(s12, y0);
-  const I dm = wadd(d03, d12) >> 1;
-  const I dd = wsub(d03, dm);
-  const I y3 = wsub(dm >> 1, dd);
-  const I y1 = wsub(dm, y3 >> 1);
-  return which == 0 ? y0 : which == 1 ? y1 : which == 2 ? y2 : y3;
-}
-
-// Inverse lift (undoes each forward step in reverse order).
-template <typename I>
-__device__ inline I inv_lift_pick(I y0, I y1, I y2, I y3, int which) {
-  const I dm = wadd(y1, y3 >> 1);
-  const I dd = wsub(dm >> 1, y3);
-  const I d03 = wadd(dm, dd), d12 = wsub(dm, dd);
-  const I s12 = wadd(y0, y2), s03 = wsub(y0, y2);
-  switch (which) {
-    case 0: return wadd(s03, d03);
-    case 1: return wadd(s12, d12);
-    case 2: return wsub(s12, d12);
-    default: return wsub(s03, d03);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Coefficient order: rank of each coefficient under the key (total sequency,
 // sum of squared frequencies, slowest-axis frequency, ..., fastest).
@@ -332,22 +302,13 @@ __device__ inline V group_isum(V v) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes and
-// the gfx950 permlane swaps across rows.  Lane maps (checked on the device):
-// quad_perm picks within each aligned group of 4 lanes, row_shl:s reads lane
-// i+s of the same row (own value past the row's end), row_ror:s reads lane
-// (i-s) mod 16, row_mirror reads 15-i, row_half_mirror reads 7-i within each
-// half row; permlane16/32 swaps exchange lanes i and i^16 / i^32.
+// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes.
+// Lane maps (checked on the device): quad_perm picks within each aligned
+// group of 4 lanes, row_shl:s reads lane i+s of the same row.
 // ---------------------------------------------------------------------------
-constexpr int kDppQuad1032 = 0xB1;   // quad_perm [1,0,3,2]: lane ^ 1
-constexpr int kDppQuad2301 = 0x4E;   // quad_perm [2,3,0,1]: lane ^ 2
-constexpr int kDppQuad3210 = 0x1B;   // quad_perm [3,2,1,0]: lane ^ 3
 constexpr int kDppQuad1233 = 0xF9;   // quad_perm [1,2,3,3]: shift down 1 in a quad
 constexpr int kDppQuad2323 = 0xEE;   // quad_perm [2,3,2,3]: shift down 2 in a quad
 constexpr int kDppRowShl1 = 0x101, kDppRowShl2 = 0x102, kDppRowShl4 = 0x104, kDppRowShl8 = 0x108;
-constexpr int kDppRowRor8 = 0x128;
-constexpr int kDppRowMirror = 0x140;
-constexpr int kDppRowHalfMirror = 0x141;
 
 // Lanes whose source lies outside the row read 0 (bound_ctrl); every use
 // below either never reads such lanes or is neutral to 0.
@@ -360,91 +321,8 @@ __device__ inline uint64_t dpp(uint64_t v) {
   return (uint64_t)dpp<CTRL>((uint32_t)v) | ((uint64_t)dpp<CTRL>((uint32_t)(v >> 32)) << 32);
 }
 template <int CTRL>
-__device__ inline int32_t dpp(int32_t v) { return (int32_t)dpp<CTRL>((uint32_t)v); }
-template <int CTRL>
-__device__ inline int64_t dpp(int64_t v) { return (int64_t)dpp<CTRL>((uint64_t)v); }
-template <int CTRL>
 __device__ inline double dpp(double v) {
   return __longlong_as_double((long long)dpp<CTRL>((uint64_t)__double_as_longlong(v)));
-}
-
-__device__ inline uint32_t xor16(uint32_t v) {
-  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  return (threadIdx.x & 16) ? p[0] : p[1];
-}
-__device__ inline uint32_t xor32(uint32_t v) {
-  const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return (threadIdx.x & 32) ? p[0] : p[1];
-}
-__device__ inline uint64_t xor16(uint64_t v) {
-  return (uint64_t)xor16((uint32_t)v) | ((uint64_t)xor16((uint32_t)(v >> 32)) << 32);
-}
-__device__ inline uint64_t xor32(uint64_t v) {
-  return (uint64_t)xor32((uint32_t)v) | ((uint64_t)xor32((uint32_t)(v >> 32)) << 32);
-}
-__device__ inline int32_t xor16(int32_t v) { return (int32_t)xor16((uint32_t)v); }
-__device__ inline int32_t xor32(int32_t v) { return (int32_t)xor32((uint32_t)v); }
-__device__ inline int64_t xor16(int64_t v) { return (int64_t)xor16((uint64_t)v); }
-__device__ inline int64_t xor32(int64_t v) { return (int64_t)xor32((uint64_t)v); }
-
-// Value held by the lane whose coordinate along `AXIS` of the 4^d block
-// (lane = 16 z + 4 y + x) is c ^ X, for X in {1, 2, 3}.
-template <int AXIS, int X, typename V>
-__device__ inline V axis_xchg(V v) {
-  if constexpr (AXIS == 0) {
-    return dpp<X == 1 ? kDppQuad1032 : (X == 2 ? kDppQuad2301 : kDppQuad3210)>(v);
-  } else if constexpr (AXIS == 1) {
-    if constexpr (X == 1) return dpp<kDppQuad3210>(dpp<kDppRowHalfMirror>(v));
-    else if constexpr (X == 2) return dpp<kDppRowRor8>(v);
-    else return dpp<kDppQuad3210>(dpp<kDppRowMirror>(v));
-  } else {
-    if constexpr (X == 1) return xor16(v);
-    else if constexpr (X == 2) return xor32(v);
-    else return xor16(xor32(v));
-  }
-}
-
-// Maximum over each aligned group of W lanes, in every lane of the group.
-template <int W, typename V>
-__device__ inline V group_allmax(V v) {
-  V o = dpp<kDppQuad1032>(v); v = o > v ? o : v;
-  o = dpp<kDppQuad2301>(v); v = o > v ? o : v;
-  if constexpr (W >= 16) {
-    o = dpp<kDppRowHalfMirror>(v); v = o > v ? o : v;
-    o = dpp<kDppRowMirror>(v); v = o > v ? o : v;
-  }
-  if constexpr (W == 64) {
-    o = xor16(v); v = o > v ? o : v;
-    o = xor32(v); v = o > v ? o : v;
-  }
-  return v;
-}
-
-// Suffix maximum within each aligned group of W lanes: lane i gets the
-// maximum over lanes i .. end of its group.  Values must be >= 0 (lanes past
-// the end of a row read 0).
-template <int W>
-__device__ inline int group_suffix_max(int v) {
-  if constexpr (W == 4) {
-    v = max(v, dpp<kDppQuad1233>(v));
-    v = max(v, dpp<kDppQuad2323>(v));
-    return v;
-  } else {
-    v = max(v, dpp<kDppRowShl1>(v));
-    v = max(v, dpp<kDppRowShl2>(v));
-    v = max(v, dpp<kDppRowShl4>(v));
-    v = max(v, dpp<kDppRowShl8>(v));
-    if constexpr (W == 64) {
-      // add the maxima of the later rows (their first lanes hold them now)
-      const int r1 = __builtin_amdgcn_readlane(v, 16);
-      const int r2 = __builtin_amdgcn_readlane(v, 32);
-      const int r3 = __builtin_amdgcn_readlane(v, 48);
-      const int row = (threadIdx.x >> 4) & 3;
-      const int later = row == 0 ? max(r1, max(r2, r3)) : (row == 1 ? max(r2, r3) : (row == 2 ? r3 : 0));
-      v = max(v, later);
-    }
-    return v;
-  }
 }
 
 // Adjacent-pair tree over each aligned group of W lanes (the association of

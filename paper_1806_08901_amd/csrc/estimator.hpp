@@ -1,5 +1,5 @@
 // The estimator's device work, shared by the per-request kernels and the
-// persistent batch kernel:
+// batched kernels:
 //   * range pass: min/max/non-finite over all N values, one contiguous chunk
 //     per workgroup (Algorithm 1, line 2);
 //   * ZFP pass: every sampled block through block-floating-point, transform,

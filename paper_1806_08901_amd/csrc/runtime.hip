@@ -55,9 +55,11 @@ struct szsel_ctx {
   // phase timers
   bool prof = false;
   std::vector<hipEvent_t> prof_events;  // kPhases + 1 per recorded call
+  std::vector<int> prof_dtype;          // dtype of each recorded call
   size_t prof_used = 0;                 // events in use
-  double prof_ms[kPhases] = {};
-  uint64_t prof_calls[kPhases] = {};
+  LaunchTimer batch_timer;              // batched launches
+  double prof_ms[kPhases][2] = {};      // per phase and dtype
+  uint64_t prof_calls[kPhases][2] = {};
 };
 
 namespace {
@@ -204,17 +206,31 @@ constexpr size_t kProfEvents = kEv * 1024;
 int profile_drain(szsel_ctx *c) {
   for (size_t k = 0; k + kEv <= c->prof_used; k += kEv) {
     hipEvent_t *ev = &c->prof_events[k];
+    const int dt = c->prof_dtype[k / kEv];
     hipError_t e = hipEventSynchronize(ev[kPhases]);
     if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
     for (int ph = 0; ph < kPhases; ph++) {
       float ms = 0.f;
       e = hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
       if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
-      c->prof_ms[ph] += ms;
-      c->prof_calls[ph] += 1;
+      c->prof_ms[ph][dt] += ms;
+      c->prof_calls[ph][dt] += 1;
     }
   }
   c->prof_used = 0;
+  // batched launches: one event pair per launch; the Huffman pass counts
+  // with the entropy pass, as in single calls
+  LaunchTimer &lt = c->batch_timer;
+  for (size_t k = 0; k < lt.used; k++) {
+    hipError_t e = hipEventSynchronize(lt.ev[2 * k + 1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, lt.ev[2 * k], lt.ev[2 * k + 1]);
+    if (e != hipSuccess) return hip_fail(c, e, "batch phase timer");
+    const int ph = std::min(lt.tag[k] / 2, kPhases - 1), dt = lt.tag[k] & 1;
+    c->prof_ms[ph][dt] += ms;
+    c->prof_calls[ph][dt] += 1;
+  }
+  lt.used = 0;
   return SZSEL_OK;
 }
 
@@ -275,6 +291,7 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
       if (rc2 != SZSEL_OK) return rc2;
     }
     ev = &ctx->prof_events[ctx->prof_used];
+    ctx->prof_dtype[ctx->prof_used / kEv] = dtype;
     ctx->prof_used += kEv;
   }
   e = launch_request(r, s, ev);
@@ -339,6 +356,8 @@ void szsel_destroy(szsel_ctx *c) {
   if (c->zc_ws) (void)hipFree(c->zc_ws);
   for (auto &ev : c->prof_events)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto &ev : c->batch_timer.ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete c;
 }
 
@@ -378,7 +397,9 @@ int szsel_select_batch(szsel_ctx *c, const szsel_request *reqs, int n, szsel_res
   const size_t budget = c->budget > others ? c->budget - others : 0;
   std::string msg;
   c->err.clear();
-  const int rc = batch_run(c, c->ncu, c->batch[k], budget, reqs, n, out, (hipStream_t)stream, c->bopt, msg);
+  BatchOptions opt = c->bopt;
+  opt.timer = c->prof ? &c->batch_timer : nullptr;
+  const int rc = batch_run(c, c->ncu, c->batch[k], budget, reqs, n, out, (hipStream_t)stream, opt, msg);
   c->batch_bytes[k] = batch_state_bytes(c->batch[k]);
   if (rc != SZSEL_OK) return fail(c, rc, msg + c->err);
   c->err.clear();
@@ -481,6 +502,7 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
     if (on && c->prof_events.empty()) {
       (void)hipSetDevice(c->device);
       c->prof_events.resize(kProfEvents, nullptr);
+      c->prof_dtype.resize(kProfEvents / kEv, 0);
       for (auto &ev : c->prof_events) {
         hipError_t e = hipEventCreate(&ev);
         if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
@@ -498,14 +520,28 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
 
 int szsel_profile_read(szsel_ctx *c, double *ms, uint64_t *calls) {
   if (!c || !ms || !calls) return SZSEL_EINVAL;
-  int rc = profile_drain(c);
+  double m[2 * kPhases];
+  uint64_t n[2 * kPhases];
+  const int rc = szsel_profile_read_split(c, m, n);
   if (rc != SZSEL_OK) return rc;
   for (int k = 0; k < kPhases; k++) {
-    ms[k] = c->prof_ms[k];
-    calls[k] = c->prof_calls[k];
-    c->prof_ms[k] = 0.0;
-    c->prof_calls[k] = 0;
+    ms[k] = m[2 * k] + m[2 * k + 1];
+    calls[k] = n[2 * k] + n[2 * k + 1];
   }
+  return SZSEL_OK;
+}
+
+int szsel_profile_read_split(szsel_ctx *c, double *ms, uint64_t *calls) {
+  if (!c || !ms || !calls) return SZSEL_EINVAL;
+  int rc = profile_drain(c);
+  if (rc != SZSEL_OK) return rc;
+  for (int k = 0; k < kPhases; k++)
+    for (int d = 0; d < 2; d++) {
+      ms[2 * k + d] = c->prof_ms[k][d];
+      calls[2 * k + d] = c->prof_calls[k][d];
+      c->prof_ms[k][d] = 0.0;
+      c->prof_calls[k][d] = 0;
+    }
   return SZSEL_OK;
 }
 

@@ -76,7 +76,7 @@ RESULT_KEYS = [name for name, _ in Result._fields_ if name != "pad0"]
 _SINGLE = ("szsel_estimate_sz", "szsel_estimate_zfp", "szsel_select", "szsel_select_fixed_eb")
 EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szsel_last_error",
                      "szsel_stride_for_rate", "szsel_set_option", "szsel_set_debug",
-                     "szsel_profile_read", "szsel_server_create", "szsel_server_destroy",
+                     "szsel_profile_read", "szsel_profile_read_split", "szsel_server_create", "szsel_server_destroy",
                      "szsel_server_reserve", "szsel_server_cancel", "szsel_server_submit",
                      "szsel_server_progress", "szsel_server_status", "szsel_server_stats",
                      "szsel_server_last_error", "szsel_zfp_stream_bytes", "szsel_zfp_compress",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     L.szsel_set_option.argtypes = [P, C.c_int, C.c_double]
     L.szsel_set_debug.argtypes = [P, C.POINTER(Debug)]
     L.szsel_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.szsel_profile_read_split.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     L.szsel_server_create.argtypes = [C.POINTER(C.c_void_p), P, P, C.c_size_t, C.c_int, C.c_size_t]
     L.szsel_server_destroy.argtypes = [P]
     L.szsel_server_destroy.restype = None
@@ -216,6 +217,14 @@ class Context:
         n = (C.c_uint64 * 5)()
         self._check(self.lib.szsel_profile_read(self.h, ms, n), "szsel_profile_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(self.PHASES)}
+
+    def profile_read_split(self):
+        """As profile_read, split by field dtype: {("range", "f32"): (ms, n), ...}."""
+        ms = (C.c_double * 10)()
+        n = (C.c_uint64 * 10)()
+        self._check(self.lib.szsel_profile_read_split(self.h, ms, n), "szsel_profile_read_split")
+        return {(k, dt): (ms[2 * i + d], n[2 * i + d]) for i, k in enumerate(self.PHASES)
+                for d, dt in enumerate(("f32", "f64"))}
 
     def set_debug(self, dbg: dict | None):
         """Arms per-sample dumps for the next single call.  ``dbg`` maps the
