@@ -78,8 +78,10 @@ enum {
                                  took more than 8192 distinct values during the
                                  construction (impossible with at most 2^25 sampled
                                  values), or 2^32 sampled values or more */
-  SZSEL_FLAG_EC_SAMPLED = 128 /* the ZFP side is the point sub-sampling estimate
-                                 (SZSEL_OPT_EC_SAMPLING) */
+  SZSEL_FLAG_EC_SAMPLED = 128, /* the ZFP side is the point sub-sampling estimate
+                                  (SZSEL_OPT_EC_SAMPLING) */
+  SZSEL_FLAG_FAILED = 256     /* serving only: nothing estimated, the request could not
+                                 be run (szsel_server_last_error says why); choice = -1 */
 };
 
 /* Result of one request.  Bit-rates are bits per value, PSNRs in dB, MSEs in
@@ -340,11 +342,20 @@ int szsel_set_debug(szsel_ctx *ctx, const szsel_debug *dump);
  * the snapshot's fields into the reservation, then submits its requests
  * (every field must lie inside the reservation; producer_stream, if not
  * NULL, is the stream the producer wrote on, and the estimation waits for
- * it).  Submitted requests wait in one FIFO; each of `lanes` lanes (a stream
- * with its own batch workspace of at most lane_workspace_bytes, 0 = 4 GiB)
- * takes up to 64 waiting requests, from any number of snapshots, as one
- * batch whenever it is free, so work that arrives while other work runs
- * starts on the next free lane and overlaps it.  szsel_server_progress
+ * it).  szsel_server_submit checks every request as the single-request
+ * calls do and rejects the whole snapshot synchronously when one is
+ * invalid (SZSEL_EINVAL / SZSEL_EDTYPE; nothing is queued, the reservation
+ * stays and can be cancelled) or needs more workspace than one lane has
+ * (SZSEL_ENOMEM).  Submitted requests wait in one FIFO; each of `lanes`
+ * lanes (a stream with its own batch workspace of at most
+ * lane_workspace_bytes, 0 = 4 GiB) takes up to 64 waiting requests, from any
+ * number of snapshots and as many as its workspace holds, as one batch
+ * whenever it is free, so work that arrives while other work runs starts on
+ * the next free lane and overlaps it.  A batch that fails to launch is put
+ * back in the queue and retried in halves; a request that fails alone
+ * completes with SZSEL_FLAG_FAILED (for tests, the environment variable
+ * SZSEL_SERVER_FAIL_BATCHES = k, read at creation, makes the server's first
+ * k batches fail before they launch).  szsel_server_progress
  * retires finished lanes (writing results to each snapshot's `out`, which
  * must stay valid until the snapshot completes), releases completed
  * snapshots' reservations and dispatches waiting requests; with wait != 0

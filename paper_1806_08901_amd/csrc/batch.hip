@@ -31,10 +31,6 @@ struct szsel_ctx;
 
 namespace szsel {
 
-int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
-                 int dtype, double eb, int eb_mode, const int32_t *stride, const Tune &tu,
-                 ReqDesc &r);
-
 namespace {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -331,6 +327,11 @@ struct BatchState {
   bool have_last = false;
 };
 
+size_t batch_request_bytes(const ReqDesc &r) {
+  return request_fixed_bytes() + align_up(request_var_bytes(r), 256) + sizeof(szsel_result) + sizeof(ReqDesc) +
+         sizeof(uint32_t) * kBatchPasses + 512;
+}
+
 size_t batch_state_bytes(const BatchState *bs) {
   return bs ? bs->fixed_cap + bs->var_cap + bs->res_cap + bs->meta_cap : 0;
 }
@@ -385,13 +386,32 @@ hipError_t bind_plan(BatchState *bs, Plan &p, size_t budget, std::string &msg) {
   const size_t fixed = request_fixed_bytes();
   const size_t tab_bytes = align_up(sizeof(ReqDesc) * n, 256);
   const size_t meta = tab_bytes + sizeof(uint32_t) * p.first.size();
-  const size_t total = std::max(bs->fixed_cap, fixed * n) + std::max(bs->var_cap, p.var) +
-                       std::max(bs->res_cap, sizeof(szsel_result) * n) + std::max(bs->meta_cap, meta);
-  if (total > budget) {
-    msg = "batch workspace of " + std::to_string(total) + " bytes exceeds the context's budget";
+  const size_t need = fixed * n + p.var + sizeof(szsel_result) * n + meta;
+  if (need > budget) {
+    msg = "batch workspace of " + std::to_string(need) + " bytes exceeds the budget of " + std::to_string(budget);
     return hipErrorOutOfMemory;
   }
   hipError_t e = hipSuccess;
+  const size_t total = std::max(bs->fixed_cap, fixed * n) + std::max(bs->var_cap, p.var) +
+                       std::max(bs->res_cap, sizeof(szsel_result) * n) + std::max(bs->meta_cap, meta);
+  if (total > budget) {
+    // buffers grown by earlier batches of another shape: release them all
+    // (and the graphs that point into them) and allocate what this one needs
+    e = batch_wait(bs);
+    if (e != hipSuccess) {
+      msg = std::string("batch: ") + hipGetErrorString(e);
+      return e;
+    }
+    for (BatchState::Graph &g : bs->graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    bs->graphs.clear();
+    for (char **b : {&bs->fixed, &bs->var, &bs->res, &bs->meta})
+      if (*b) (void)hipFree(*b), *b = nullptr;
+    bs->fixed_cap = bs->var_cap = bs->res_cap = bs->meta_cap = 0;
+    bs->staged.clear();
+  }
   if (fixed * n > bs->fixed_cap || p.var > bs->var_cap || sizeof(szsel_result) * n > bs->res_cap ||
       meta > bs->meta_cap || meta > bs->stage_cap)
     e = batch_wait(bs);

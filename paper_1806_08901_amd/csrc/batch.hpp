@@ -43,6 +43,21 @@ void batch_destroy(BatchState *bs);
 // CU count of the context's device.
 int ctx_ncu(const szsel_ctx *ctx);
 
+// The argument checks of one request (no device, no context): SZSEL_OK or a
+// negative code with the reason in `why`.
+int check_request(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,
+                  int eb_mode, const int32_t *stride, std::string &why);
+
+// Plans one request (checks it, then sets its launch shape from `tu`);
+// errors go to the context's last error.
+int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd, int dtype,
+                 double eb, int eb_mode, const int32_t *stride, const Tune &tu, ReqDesc &r);
+
+// Device bytes a batch state needs per request of plan r (its share of
+// the fixed and variable workspace, result, table entry and prefix counts;
+// what batch_run checks against its budget, rounded up).
+size_t batch_request_bytes(const ReqDesc &r);
+
 // Device bytes held by a batch state (0 for NULL).
 size_t batch_state_bytes(const BatchState *bs);
 

@@ -79,21 +79,48 @@ namespace szsel {
 
 int ctx_ncu(const szsel_ctx *ctx) { return ctx ? ctx->ncu : 256; }
 
+int check_request(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,
+                  int eb_mode, const int32_t *stride, std::string &why) {
+  auto bad = [&](int code, const char *m) {
+    why = m;
+    return code;
+  };
+  if (!field) return bad(SZSEL_EINVAL, "field is NULL");
+  if (!dims) return bad(SZSEL_EINVAL, "dims is NULL");
+  if (nd < 1 || nd > 3) return bad(SZSEL_EINVAL, "ndims must be 1, 2 or 3");
+  if (dtype != SZSEL_F32 && dtype != SZSEL_F64) return bad(SZSEL_EDTYPE, "dtype must be SZSEL_F32 or SZSEL_F64");
+  if (op < SZSEL_OP_SZ || op > SZSEL_OP_FIXED_EB) return bad(SZSEL_EINVAL, "bad op");
+  if (!(eb > 0.0) || !std::isfinite(eb)) return bad(SZSEL_EINVAL, "eb must be > 0 and finite");
+  if (eb_mode != SZSEL_EB_ABS && eb_mode != SZSEL_EB_REL)
+    return bad(SZSEL_EINVAL, "eb_mode must be SZSEL_EB_ABS or SZSEL_EB_REL");
+  const size_t esz = dtype == SZSEL_F32 ? 4 : 8;
+  if ((uintptr_t)field % esz) return bad(SZSEL_EINVAL, "field is not aligned to its element size");
+  int64_t n = 1;
+  uint64_t nblk = 1;
+  for (int k = 0; k < nd; k++) {
+    if (dims[k] < 1) return bad(SZSEL_EINVAL, "every extent must be >= 1");
+    const int32_t st = stride ? stride[k] : 1;
+    if (st < 1) return bad(SZSEL_EINVAL, "every stride must be >= 1");
+    if (n > INT64_MAX / dims[k]) return bad(SZSEL_EINVAL, "field too large");
+    n *= dims[k];
+    const int64_t ns = (dims[k] / 4 + st - 1) / st;
+    if (ns > 0xFFFFFFFFll) return bad(SZSEL_EINVAL, "too many blocks along an axis");
+    nblk *= (uint64_t)ns;
+    if (nblk > 0xFFFFFFFFull) return bad(SZSEL_EINVAL, "more than 2^32 sampled blocks; use a larger stride");
+  }
+  return SZSEL_OK;
+}
+
 int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, int nd,
                  int dtype, double eb, int eb_mode, const int32_t *stride, const Tune &tu,
                  ReqDesc &r) {
   if (!ctx) return SZSEL_EINVAL;
-  if (!field) return fail(ctx, SZSEL_EINVAL, "field is NULL");
-  if (!dims) return fail(ctx, SZSEL_EINVAL, "dims is NULL");
-  if (nd < 1 || nd > 3) return fail(ctx, SZSEL_EINVAL, "ndims must be 1, 2 or 3");
-  if (dtype != SZSEL_F32 && dtype != SZSEL_F64)
-    return fail(ctx, SZSEL_EDTYPE, "dtype must be SZSEL_F32 or SZSEL_F64");
-  if (op < SZSEL_OP_SZ || op > SZSEL_OP_FIXED_EB) return fail(ctx, SZSEL_EINVAL, "bad op");
-  if (!(eb > 0.0) || !std::isfinite(eb)) return fail(ctx, SZSEL_EINVAL, "eb must be > 0 and finite");
-  if (eb_mode != SZSEL_EB_ABS && eb_mode != SZSEL_EB_REL)
-    return fail(ctx, SZSEL_EINVAL, "eb_mode must be SZSEL_EB_ABS or SZSEL_EB_REL");
+  {
+    std::string why;
+    const int rc = check_request(op, field, dims, nd, dtype, eb, eb_mode, stride, why);
+    if (rc != SZSEL_OK) return fail(ctx, rc, why);
+  }
   const size_t esz = dtype == SZSEL_F32 ? 4 : 8;
-  if ((uintptr_t)field % esz) return fail(ctx, SZSEL_EINVAL, "field is not aligned to its element size");
   std::memset(&r, 0, sizeof(r));
   r.field = field;
   r.nd = nd;
@@ -107,17 +134,13 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   r.ovf_per_slice = tu.ovf_slice > 0 ? tu.ovf_slice : kOvfPerSlice;
   int64_t n = 1;
   uint64_t nblk = 1;
-  for (int k = 0; k < nd; k++) {
-    if (dims[k] < 1) return fail(ctx, SZSEL_EINVAL, "every extent must be >= 1");
+  for (int k = 0; k < nd; k++) {  // (the bounds were checked above)
     const int32_t s = stride ? stride[k] : 1;
-    if (s < 1) return fail(ctx, SZSEL_EINVAL, "every stride must be >= 1");
-    if (n > INT64_MAX / dims[k]) return fail(ctx, SZSEL_EINVAL, "field too large");
     n *= dims[k];
     r.dims[k] = dims[k];
     r.stride[k] = s;
     const int64_t nb = dims[k] / 4;
     const int64_t ns = (nb + s - 1) / s;
-    if (ns > 0xFFFFFFFFll) return fail(ctx, SZSEL_EINVAL, "too many blocks along an axis");
     r.nsel[k] = (uint32_t)ns;
     // multiply-shift constants for dividing block indices by nsel[k]
     // (Granlund and Montgomery, PLDI 1994): l = ceil(log2 d),
@@ -131,7 +154,6 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
       r.dsh[k] = (uint32_t)(l < 1 ? l : 1) | ((uint32_t)(l > 1 ? l - 1 : 0) << 8);
     }
     nblk *= (uint64_t)ns;
-    if (nblk > 0xFFFFFFFFull) return fail(ctx, SZSEL_EINVAL, "more than 2^32 sampled blocks; use a larger stride");
   }
   r.n = n;
   r.nblk = (int64_t)nblk;
@@ -244,10 +266,10 @@ int run_single(szsel_ctx *ctx, int op, const void *field, const int64_t *dims, i
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  Slot &sl = ctx->slots[ctx->next];
-  ctx->next = (ctx->next + 1) % kSlots;
   const size_t fixed = request_fixed_bytes();
   const size_t need = fixed + request_var_bytes(r);
+  Slot &sl = ctx->slots[ctx->next];
+  ctx->next = (ctx->next + 1) % kSlots;
   if (need > sl.bytes) {  // grow the slot (waits for the device)
     if (ctx->used_bytes - sl.bytes + need > ctx->budget)
       return fail(ctx, SZSEL_ENOMEM, "request workspace exceeds the context's budget");

@@ -11,11 +11,19 @@
 // them.  A snapshot completes when all of its requests have; its pool range
 // is then released, which may admit the next snapshot.
 //
+// Requests are checked when they are submitted (the planner's argument
+// checks, and that one request fits a lane's workspace), and a lane batch
+// never holds more requests than its workspace budget takes.  A batch that
+// still fails to launch is put back in the queue and retried in halves; a
+// single request that fails alone completes with SZSEL_FLAG_FAILED, so that
+// no snapshot waits forever and every pool range is released.
+//
 // Single-threaded: every call comes from the same host thread.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -100,6 +108,7 @@ struct Pending {
   uint64_t ticket;
   int index;  // request index within its snapshot
   szsel_request req;
+  size_t bytes;  // lane workspace it needs
 };
 
 struct Lane {
@@ -126,8 +135,9 @@ struct szsel_server {
   std::string err;
   szsel::BatchOptions bopt;  // eager launches: served batches rarely repeat a shape
   size_t lane_budget = (size_t)4 << 30;
+  int fail_batches = 0;  // test hook: the next this many lane batches fail before launching
   // statistics
-  uint64_t batches = 0, batched_requests = 0, snapshots_done = 0, launches = 0;
+  uint64_t batches = 0, batched_requests = 0, snapshots_done = 0, launches = 0, failed_requests = 0;
 };
 
 namespace {
@@ -135,6 +145,19 @@ namespace {
 int sfail(szsel_server *s, int code, const std::string &m) {
   s->err = m;
   return code;
+}
+
+// One request of snapshot `sn` has its result: completes the snapshot
+// (releasing its pool range) when it was the last.  Returns 1 then.
+int finish_one(szsel_server *s, Snapshot &sn, double t) {
+  if (--sn.remaining) return 0;
+  sn.done = true;
+  sn.t_done = t;
+  s->arena.release(sn.off, sn.bytes);
+  if (sn.ready) (void)hipEventDestroy(sn.ready);
+  sn.ready = nullptr;
+  s->snapshots_done++;
+  return 1;
 }
 
 // Retires finished lanes: distributes their results, completes snapshots
@@ -156,15 +179,7 @@ int retire(szsel_server *s, bool wait_one) {
       if (it == s->snaps.end()) continue;
       Snapshot &sn = it->second;
       sn.out[l.parts[k].second] = l.res[k];
-      if (--sn.remaining == 0) {
-        sn.done = true;
-        sn.t_done = t;
-        s->arena.release(sn.off, sn.bytes);
-        if (sn.ready) (void)hipEventDestroy(sn.ready);
-        sn.ready = nullptr;
-        s->snapshots_done++;
-        completed++;
-      }
+      completed += finish_one(s, sn, t);
     }
     l.parts.clear();
     l.busy = false;
@@ -172,36 +187,72 @@ int retire(szsel_server *s, bool wait_one) {
   return completed;
 }
 
-// Packs waiting requests onto free lanes.
+// Packs waiting requests onto free lanes: up to kServeBatch of them, and no
+// more than the lane's workspace budget takes.  A batch that fails to
+// launch goes back to the front of the queue and is retried in halves; a
+// request that fails alone gets a result with SZSEL_FLAG_FAILED.
 int dispatch(szsel_server *s) {
+  int cap = kServeBatch;
   for (Lane &l : s->lanes) {
-    if (s->queue.empty()) break;
-    if (l.busy) continue;
-    std::vector<szsel_request> reqs;
-    l.parts.clear();
-    std::vector<hipEvent_t> waits;
-    while (!s->queue.empty() && (int)reqs.size() < kServeBatch) {
-      Pending &p = s->queue.front();
-      Snapshot &sn = s->snaps[p.ticket];
-      if (sn.ready && (waits.empty() || waits.back() != sn.ready)) waits.push_back(sn.ready);
-      reqs.push_back(p.req);
-      l.parts.emplace_back(p.ticket, p.index);
-      s->queue.pop_front();
+    while (!l.busy && !s->queue.empty()) {
+      std::vector<szsel_request> reqs;
+      std::vector<Pending> taken;
+      std::vector<hipEvent_t> waits;
+      size_t bytes = 0;
+      while (!s->queue.empty() && (int)reqs.size() < cap) {
+        Pending &p = s->queue.front();
+        if (!reqs.empty() && bytes + p.bytes > s->lane_budget) break;
+        bytes += p.bytes;
+        Snapshot &sn = s->snaps[p.ticket];
+        if (sn.ready && (waits.empty() || waits.back() != sn.ready)) waits.push_back(sn.ready);
+        reqs.push_back(p.req);
+        taken.push_back(p);
+        s->queue.pop_front();
+      }
+      hipError_t e = hipSuccess;
+      for (hipEvent_t ev : waits)
+        if (e == hipSuccess) e = hipStreamWaitEvent(l.s, ev, 0);
+      std::string msg;
+      int rc = SZSEL_OK;
+      if (e != hipSuccess) {
+        rc = SZSEL_EHIP;
+        msg = std::string("lane wait: ") + hipGetErrorString(e);
+      } else if (s->fail_batches > 0) {
+        s->fail_batches--;
+        rc = SZSEL_EHIP;
+        msg = "failure injected by SZSEL_SERVER_FAIL_BATCHES";
+      } else {
+        rc = szsel::batch_run(s->ctx, s->ncu, l.bs, s->lane_budget, reqs.data(), (int)reqs.size(), l.res, l.s,
+                              s->bopt, msg);
+      }
+      if (rc == SZSEL_OK) {
+        e = hipEventRecord(l.done, l.s);
+        if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        l.parts.clear();
+        for (const Pending &p : taken) l.parts.emplace_back(p.ticket, p.index);
+        l.busy = true;
+        l.seq = ++s->launches;
+        s->batches++;
+        s->batched_requests += reqs.size();
+        break;
+      }
+      s->err = "batch of " + std::to_string(reqs.size()) + " requests failed: " + msg;
+      if (taken.size() > 1) {  // back to the front, in order; retry in halves
+        for (size_t k = taken.size(); k-- > 0;) s->queue.push_front(taken[k]);
+        cap = std::max<int>(1, (int)taken.size() / 2);
+        continue;
+      }
+      auto it = s->snaps.find(taken[0].ticket);
+      if (it != s->snaps.end()) {
+        szsel_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.flags = SZSEL_FLAG_FAILED;
+        r.choice = -1;
+        it->second.out[taken[0].index] = r;
+        s->failed_requests++;
+        finish_one(s, it->second, now_ms());
+      }
     }
-    hipError_t e = hipSuccess;
-    for (hipEvent_t ev : waits)
-      if (e == hipSuccess) e = hipStreamWaitEvent(l.s, ev, 0);
-    if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("lane wait: ") + hipGetErrorString(e));
-    std::string msg;
-    const int rc = szsel::batch_run(s->ctx, s->ncu, l.bs, s->lane_budget, reqs.data(), (int)reqs.size(), l.res,
-                                    l.s, s->bopt, msg);
-    if (rc != SZSEL_OK) return sfail(s, rc, "batch: " + msg);
-    e = hipEventRecord(l.done, l.s);
-    if (e != hipSuccess) return sfail(s, SZSEL_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
-    l.busy = true;
-    l.seq = ++s->launches;
-    s->batches++;
-    s->batched_requests += reqs.size();
   }
   return SZSEL_OK;
 }
@@ -223,6 +274,7 @@ int szsel_server_create(szsel_server **out, szsel_ctx *ctx, void *pool, size_t p
   s->arena.init(pool_bytes);
   if (lane_workspace_bytes) s->lane_budget = lane_workspace_bytes;
   s->bopt.graph = false;
+  if (const char *v = std::getenv("SZSEL_SERVER_FAIL_BATCHES")) s->fail_batches = std::max(0, std::atoi(v));
   if (ctx) {
     s->ncu = szsel::ctx_ncu(ctx);
     s->lanes.resize((size_t)lanes);
@@ -285,14 +337,26 @@ int szsel_server_submit(szsel_server *s, uint64_t ticket, const szsel_request *r
   if (it == s->snaps.end() || it->second.submitted) return sfail(s, SZSEL_EINVAL, "unknown or already submitted ticket");
   Snapshot &sn = it->second;
   const char *lo = s->pool + sn.off, *hi = lo + sn.bytes;
+  std::vector<size_t> need((size_t)n);
   for (int i = 0; i < n; i++) {
     const szsel_request &q = reqs[i];
-    if (q.ndims < 1 || q.ndims > 3) return sfail(s, SZSEL_EINVAL, "request " + std::to_string(i) + ": bad ndims");
+    const std::string who = "request " + std::to_string(i) + ": ";
+    int32_t st[3] = {1, 1, 1};
+    for (int k = 0; k < 3; k++) st[k] = q.stride[k] ? q.stride[k] : 1;
+    std::string why;
+    int rc = szsel::check_request(q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, why);
+    if (rc != SZSEL_OK) return sfail(s, rc, who + why);
     size_t b = q.dtype == SZSEL_F64 ? 8 : 4;
-    for (int k = 0; k < q.ndims; k++) b *= (size_t)(q.dims[k] > 0 ? q.dims[k] : 0);
+    for (int k = 0; k < q.ndims; k++) b *= (size_t)q.dims[k];
     const char *f = (const char *)q.field;
-    if (f < lo || f + b > hi)
-      return sfail(s, SZSEL_EINVAL, "request " + std::to_string(i) + ": field outside the snapshot's reservation");
+    if (f < lo || f + b > hi) return sfail(s, SZSEL_EINVAL, who + "field outside the snapshot's reservation");
+    szsel::ReqDesc r;
+    rc = szsel::plan_request(s->ctx, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, s->bopt.fixed, r);
+    if (rc != SZSEL_OK) return sfail(s, rc, who + szsel_last_error(s->ctx));
+    need[(size_t)i] = szsel::batch_request_bytes(r);
+    if (need[(size_t)i] > s->lane_budget)
+      return sfail(s, SZSEL_ENOMEM, who + "needs " + std::to_string(need[(size_t)i]) +
+                                        " bytes of lane workspace, more than the lane budget");
   }
   if (producer_stream) {
     hipError_t e = hipEventCreateWithFlags(&sn.ready, hipEventDisableTiming);
@@ -303,7 +367,7 @@ int szsel_server_submit(szsel_server *s, uint64_t ticket, const szsel_request *r
   sn.remaining = n;
   sn.out = out;
   sn.t_submit = now_ms();
-  for (int i = 0; i < n; i++) s->queue.push_back(Pending{ticket, i, reqs[i]});
+  for (int i = 0; i < n; i++) s->queue.push_back(Pending{ticket, i, reqs[i], need[(size_t)i]});
   return dispatch(s);
 }
 

@@ -20,7 +20,7 @@ EB_ABS, EB_REL = 0, 1
 OP_SZ, OP_ZFP, OP_SELECT, OP_FIXED_EB = 0, 1, 2, 3
 FLAG_CONSTANT, FLAG_NONFINITE, FLAG_ZERO_MSE = 1, 2, 4
 FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB, FLAG_NO_HUFFMAN = 8, 16, 32, 64
-FLAG_EC_SAMPLED = 128
+FLAG_EC_SAMPLED, FLAG_FAILED = 128, 256
 OPT_SZ_OFFSET, OPT_PROFILE, OPT_AUTOTUNE, OPT_BATCH_GRAPH = 1, 2, 3, 4
 OPT_SZ_WGS, OPT_ZFP_CHUNK, OPT_RANGE_WGS, OPT_BATCH_GROUPS, OPT_HUFFMAN = 5, 6, 7, 8, 9
 OPT_EC_SAMPLING, OPT_BATCH_SHARE = 10, 11

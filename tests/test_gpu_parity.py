@@ -194,3 +194,41 @@ def test_turb512_full_size(ctx, turb512, eb):
     orc, _ = oracle.select(turb512.cpu().numpy(), eb, stride=stride)
     assert_matches_oracle(gpu, orc, "turb512 eb %g" % eb)
     assert not is_tie(orc)
+
+
+@pytest.mark.parametrize("eb", [1e-5, 1e-6])
+def test_turb512_full_dump_tight_bounds(ctx, turb512, eb):
+    """512^3 at the tight bounds, where the histogram is widest and the
+    overflow pass counts most codes: every code, the 65,536-bin histogram
+    and every per-block ZFP and SZ value against the oracle."""
+    _note("turb512 dump eb", eb)
+    stride = (5, 4, 1)
+    nblk = oracle.num_sampled_blocks((512, 512, 512), stride)
+    bufs = debug_buffers(torch, nblk, 3)
+    ctx.set_debug(bufs)
+    gpu = ctx.select(turb512, eb, stride=stride)
+    gd = debug_to_numpy(bufs, nblk, 3)
+    orc, od = oracle.select(turb512.cpu().numpy(), eb, stride=stride, dump=True)
+    assert_matches_oracle(gpu, orc, "turb512 dump eb %g" % eb)
+    _compare_dumps(gd, od, oracle.OP_SELECT, orc)
+    assert int((od["hist"] > 0).sum()) > 4096  # wider than the SZ pass's LDS window
+
+
+@pytest.mark.parametrize("dtype,offset,want", [(torch.float32, 0.5, 6.25), (torch.float64, 0.25, 10.0)])
+def test_sz_bitrate_hand_fixture(ctx, dtype, offset, want):
+    """The 16-value field whose codes are known by construction (8 x 0, 4 x 1,
+    2 x 2 and 2 escapes at delta = 1): entropy 1.75 bits, bit-rate by hand."""
+    from paper_1806_08901_amd import szsel
+    steps = [0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 40000, 40000, 0, 0, 0, 0]
+    x = torch.tensor(steps, dtype=torch.float64).cumsum(0).to(dtype).cuda()
+    ctx.set_option(szsel.OPT_SZ_OFFSET, offset)
+    ctx.set_option(szsel.OPT_HUFFMAN, 1)
+    try:
+        r = ctx.estimate_sz(x, 0.5, oracle.EB_ABS, (1,))
+    finally:
+        ctx.set_option(szsel.OPT_SZ_OFFSET, 0.5)
+        ctx.set_option(szsel.OPT_HUFFMAN, 0)
+    W = 32 if dtype == torch.float32 else 64
+    assert r["sz_unpredictable"] == 2 and r["sz_entropy"] == 1.75
+    assert r["sz_bitrate"] == want
+    assert r["sz_huffman_bits"] == 28 and r["sz_huffman_bitrate"] == 1.75 + 2 * W / 16

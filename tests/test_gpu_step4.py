@@ -138,6 +138,14 @@ def test_sz_full_size_field(ctx):
         assert (dec.double() - field.double()).abs().max().item() == gpu["maxerr"]
         if not gpu["flags"]:
             assert gpu["bits"] == gpu["code_bits"] + 32 * gpu["unpredictable"] + 32 * gpu["symbols"]
+        # whole-field SSE: the adjacent-pair tree of the squared errors in
+        # field order (2^27 values, no padding), on the host
+        v = (dec.double() - field.double()).cpu().numpy().reshape(-1)
+        v = v * v
+        while v.size > 1:
+            v = v[0::2] + v[1::2]
+        assert float(v[0]) == gpu["sse"]
+        del v
         sub = field[:16, :16, :16].contiguous().cpu().numpy()
         _, _, osyms, odec = oracle.sz_compress(sub, eb * vr)
         assert np.array_equal(syms[:16, :16, :16].cpu().numpy().view(np.uint16), osyms)
