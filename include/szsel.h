@@ -169,6 +169,28 @@ int szsel_select_fixed_eb(szsel_ctx *ctx, const void *field, const int64_t *dims
                           int dtype, double eb, int eb_mode, const int32_t *stride,
                           szsel_result *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * request and the same result as szsel_select, bit for bit, with the
+ * request's workspace in a static device array of
+ * SZSEL_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (looked up and zeroed by szsel_create).  The call
+ * enqueues kernels and the result's copy on `stream` and allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine; no event either).
+ * `out` should be pinned host memory where the call is captured.
+ * A request whose workspace would exceed the array (about 4.6 MB plus 2
+ * bytes per sampled value) returns SZSEL_ENOMEM with the sizes in
+ * szsel_last_error(); argument errors are those of szsel_select.
+ * Every call on one GPU, from any context, uses that GPU's one array, which
+ * keeps the last call's contents (the kernels leave what must start at zero
+ * cleared): calls that may overlap on the device (on different streams, or
+ * from different threads, without ordering between them) race and give
+ * wrong results.  Issue them on one stream or synchronise between them. */
+#define SZSEL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int szsel_select_noalloc(szsel_ctx *ctx, const void *field, const int64_t *dims, int ndims,
+                         int dtype, double eb, int eb_mode, const int32_t *stride,
+                         szsel_result *out, void *stream);
+
 /* n <= 1024 requests of any shape, dtype, bound and op together: one launch
  * per pass covers every request (grouped by dtype, rank and alignment),
  * captured as a HIP graph and replayed while the batch shape repeats.

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libszsel.so")
-SOURCES = ["kernels.hip", "batch_kernels.hip", "batch.hip", "server.hip", "compress.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "batch_kernels.hip", "batch.hip", "server.hip", "compress.hip", "noalloc.hip", "runtime.hip"]
 ARCH = os.environ.get("SZSEL_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

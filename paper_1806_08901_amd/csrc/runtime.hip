@@ -13,6 +13,7 @@
 #include "batch.hpp"
 #include "compress.hpp"
 #include "launch.hpp"
+#include "noalloc.hpp"
 #include "szsel.h"
 
 using namespace szsel;
@@ -357,7 +358,10 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
       return SZSEL_EHIP;
     }
   }
-  e = hipDeviceSynchronize();
+  // the allocation-free entry point's workspace on this device (once per
+  // device and process)
+  e = noalloc_setup(hip_device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     szsel_destroy(c);
     return SZSEL_EHIP;
@@ -401,6 +405,40 @@ int szsel_select(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, 
 int szsel_select_fixed_eb(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb,
                           int m, const int32_t *s, szsel_result *o, void *st) {
   return run_single(c, SZSEL_OP_FIXED_EB, f, d, nd, dt, eb, m, s, o, st);
+}
+
+int szsel_select_noalloc(szsel_ctx *c, const void *f, const int64_t *d, int nd, int dt, double eb,
+                         int m, const int32_t *s, szsel_result *o, void *st) {
+  // szsel_select with the request's workspace in the device's static array:
+  // no allocation, no event, no profiling; ordering between calls is the
+  // caller's (they share the array)
+  if (!c) return SZSEL_EINVAL;
+  if (!o) return fail(c, SZSEL_EINVAL, "out is NULL");
+  ReqDesc r;
+  int rc = plan_request(c, SZSEL_OP_SELECT, f, d, nd, dt, eb, m, s, c->bopt.fixed, r);
+  if (rc != SZSEL_OK) return rc;
+  char *ws = noalloc_scratch(c->device);
+  if (!ws) return fail(c, SZSEL_EHIP, "the allocation-free workspace is not set up on this device");
+  const size_t fixed = request_fixed_bytes();
+  const size_t need = fixed + request_var_bytes(r);
+  if (need > kNoallocScratchBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "request needs %zu bytes of workspace; szsel_select_noalloc has %zu "
+                  "(use a larger stride, or szsel_select)",
+                  need, kNoallocScratchBytes);
+    return fail(c, SZSEL_ENOMEM, msg);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const hipStream_t hs = (hipStream_t)st;
+  bind_request_workspace(r, ws, ws + fixed);
+  e = launch_request(r, hs, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  e = hipMemcpyAsync(o, r.res, sizeof(szsel_result), hipMemcpyDeviceToHost, hs);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync(result)");
+  c->err.clear();
+  return SZSEL_OK;
 }
 
 int szsel_select_batch(szsel_ctx *c, const szsel_request *reqs, int n, szsel_result *out,

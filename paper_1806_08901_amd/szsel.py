@@ -80,7 +80,7 @@ EXPORTS = _SINGLE + ("szsel_create", "szsel_destroy", "szsel_select_batch", "szs
                      "szsel_server_reserve", "szsel_server_cancel", "szsel_server_submit",
                      "szsel_server_progress", "szsel_server_status", "szsel_server_stats",
                      "szsel_server_last_error", "szsel_zfp_stream_bytes", "szsel_zfp_compress",
-                     "szsel_sz_compress")
+                     "szsel_sz_compress", "szsel_select_noalloc")
 
 _lib = None
 
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     for name in _SINGLE:
         getattr(L, name).argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
                                      C.POINTER(Result), P]
+    L.szsel_select_noalloc.argtypes = [P, P, I64P, C.c_int, C.c_int, C.c_double, C.c_int, I32P,
+                                       C.POINTER(Result), P]
     L.szsel_select_batch.argtypes = [P, C.POINTER(Request), C.c_int, C.POINTER(Result), P]
     L.szsel_last_error.argtypes = [P]
     L.szsel_last_error.restype = C.c_char_p
@@ -265,6 +267,26 @@ class Context:
 
     def select_fixed_eb(self, field, eb, eb_mode=EB_REL, stride=None, stream=None):
         return self.run(OP_FIXED_EB, field, eb, eb_mode, stride, stream)
+
+    def select_noalloc(self, field: torch.Tensor, eb: float, eb_mode: int = EB_REL, stride=None,
+                       stream=None, sync: bool = True):
+        """szsel_select_noalloc: Algorithm 1 with the workspace in the
+        library's static device array (allocates nothing; calls that may
+        overlap on the device race)."""
+        if not field.is_cuda or not field.is_contiguous():
+            raise SzselError("field must be a contiguous device tensor")
+        nd = field.dim()
+        dims = (C.c_int64 * nd)(*field.shape)
+        st = None if stride is None else (C.c_int32 * nd)(*stride)
+        out = self._results(1)
+        s, sp = self._stream(stream)
+        self._check(self.lib.szsel_select_noalloc(self.h, C.c_void_p(field.data_ptr()), dims, nd,
+                                                  _dtype_code(field), float(eb), eb_mode, st, out, sp),
+                    "szsel_select_noalloc")
+        if not sync:
+            return out
+        s.synchronize()
+        return _as_dict(out[0])
 
     # -- Step 4: compression of the whole field -----------------------------
     def zfp_compress(self, field: torch.Tensor, eb_abs: float, decoded: bool = True, stream=None):
