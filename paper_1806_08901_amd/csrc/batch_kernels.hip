@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__
 }
 
 template <typename T, int D, bool VEC, bool EC>
-__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void kb_zfp(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D, EC>)) void kb_zfp(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
   int local;

@@ -308,6 +308,9 @@ __device__ inline V group_isum(V v) {
 // ---------------------------------------------------------------------------
 constexpr int kDppQuad1233 = 0xF9;   // quad_perm [1,2,3,3]: shift down 1 in a quad
 constexpr int kDppQuad2323 = 0xEE;   // quad_perm [2,3,2,3]: shift down 2 in a quad
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]: lane q reads lane q ^ 1
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]: lane q reads lane q ^ 2
+constexpr int kDppQuadBcast3 = 0xFF; // quad_perm [3,3,3,3]: every lane reads the quad's last
 constexpr int kDppRowShl1 = 0x101, kDppRowShl2 = 0x102, kDppRowShl4 = 0x104, kDppRowShl8 = 0x108;
 
 // Lanes whose source lies outside the row read 0 (bound_ctrl); every use

@@ -441,9 +441,11 @@ __device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s
 template <typename T, int D>
 constexpr int kSzWavesPerSimd = D == 3 ? (sizeof(T) == 8 ? 4 : 5) : (sizeof(T) == 8 ? 5 : 6);
 
-// Occupancy of the ZFP kernels: waves per SIMD (one block per lane).
-template <typename T, int D>
-constexpr int kZfpWavesPerSimd = (sizeof(T) == 8 && D == 3) ? 1 : 2;
+// Occupancy of the ZFP kernels: waves per SIMD (one block per lane; 3-D
+// blocks of the exact estimate: one block per quad of lanes).
+template <typename T, int D, bool EC>
+constexpr int kZfpWavesPerSimd = (D == 3 && !EC) ? (sizeof(T) == 8 ? 4 : 5)
+                                                 : ((sizeof(T) == 8 && D == 3) ? 1 : 2);
 
 // Results of one block: coder bits (headers included), significant bits,
 // data-domain squared error (adjacent-pair tree in in-block order), largest
@@ -786,12 +788,314 @@ __device__ inline void zfp_finalize(const ReqDesc &r, const Part &tot) {
   }
 }
 
+// ===========================================================================
+// ZFP side for 3-D blocks, four lanes per block
+// ===========================================================================
+// A 3-D block's 64 values and coefficients spread over a quad of lanes, 16
+// per lane, so that a binary64 block (64 64-bit coefficients) fits in a
+// quarter of the registers it needs in one lane.  Two layouts:
+//   row layout:    lane q of the quad holds the rows (z, y = q), z = 0..3;
+//   column layout: lane q holds the values (z, y, x = q), z, y = 0..3.
+// The x lifts run in row layout and the y and z lifts in column layout; a
+// 4 x 4 transpose within the quad (two DPP exchange stages) switches between
+// them.  The coder count needs the coefficients in coding order: every lane
+// writes the bit lengths of its 16 coefficients to LDS at their coding
+// positions, and lane q scans positions 16q .. 16q + 15, starting from the
+// largest bit length after them (a suffix maximum over the quad).
+
+// Coding positions of lane q's coefficients in column layout, coefficient
+// t = 4 z + y at index 16 z + 4 y + q, one byte each, four to a word.
+struct QuadPositions {
+  uint32_t w[4][4];  // [q][t / 4]
+  constexpr QuadPositions() : w() {
+    for (int q = 0; q < 4; q++)
+      for (int t = 0; t < 16; t++)
+        w[q][t >> 2] |= (uint32_t)Order<3>::table.inv[16 * (t >> 2) + 4 * (t & 3) + q] << (8 * (t & 3));
+  }
+};
+struct QuadPos {
+  static constexpr QuadPositions table{};
+};
+
+constexpr int kQuadBlocks = kWave / 4;  // blocks per wave and round
+constexpr int kQuadLds = 80;            // LDS bytes per block (64 used; the padding spreads banks)
+
+// Value of lane q ^ 1 (XOR1) or q ^ 2 of the quad.
+template <int CTRL, typename V>
+__device__ inline V quad_get(V v) {
+  if constexpr (std::is_same<V, double>::value) {
+    return dpp<CTRL>(v);
+  } else {
+    using UV = typename std::conditional<sizeof(V) == 8, uint64_t, uint32_t>::type;
+    return (V)dpp<CTRL>((UV)v);
+  }
+}
+
+// 4 x 4 transpose within the quad: lane q's a[k] becomes lane k's a[q].
+// Stage one exchanges with lane q ^ 2 the elements whose bit 1 differs
+// from q's, stage two with lane q ^ 1 those whose bit 0 differs.
+template <typename V>
+__device__ inline void quad_transpose(V (&a)[4], int q) {
+  const bool h = (q & 2) != 0, l = (q & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    const V got = quad_get<kDppQuadXor2>(h ? a[k] : a[k + 2]);
+    a[k] = h ? got : a[k];
+    a[k + 2] = h ? a[k + 2] : got;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k += 2) {
+    const V got = quad_get<kDppQuadXor1>(l ? a[k] : a[k + 1]);
+    a[k] = l ? got : a[k];
+    a[k + 1] = l ? a[k + 1] : got;
+  }
+}
+
+// Sum over the quad, in every lane of it: (v0 + v1) + (v2 + v3), the
+// adjacent-pair association (the two orders of a sum are the same).
+template <typename V>
+__device__ inline V quad_sum(V v) {
+  v = v + quad_get<kDppQuadXor1>(v);
+  return v + quad_get<kDppQuadXor2>(v);
+}
+
+template <typename V>
+__device__ inline V quad_max(V v) {
+  V o = quad_get<kDppQuadXor1>(v);
+  v = o > v ? o : v;
+  o = quad_get<kDppQuadXor2>(v);
+  return o > v ? o : v;
+}
+
+// Row (z, y) of block j, 4 values from `p` (the row's first element).
+template <typename T, bool VEC>
+__device__ inline void load_row4(const T *p, T (&x)[4]) {
+  if constexpr (VEC) {
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = *(const f32x4 *)p;
+      x[0] = v[0];
+      x[1] = v[1];
+      x[2] = v[2];
+      x[3] = v[3];
+    } else {
+      const f64x2 a = *(const f64x2 *)p, b = *(const f64x2 *)(p + 2);
+      x[0] = a[0];
+      x[1] = a[1];
+      x[2] = b[0];
+      x[3] = b[1];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; e++) x[e] = p[e];
+  }
+}
+
+// The exact ZFP estimate of 3-D block j by quad lane q (same results as
+// zfp_block_lane<T, 3, VEC, false>, in every lane of the quad).  `pos` are
+// the lane's coding positions (QuadPositions), `sb` the block's LDS bytes.
+template <typename T, bool VEC>
+__device__ inline ZfpLane zfp_block_quad(const ReqDesc &r, int64_t j, int q, const int32_t *minexp_p,
+                                         const uint32_t (&pos)[4], uint8_t *sb) {
+  using Q = Prec<T>;
+  using U = typename Q::U;
+  using I = typename Q::I;
+  constexpr int W = Q::W;
+  // row layout: x[z][.] = row (z, y = q)
+  T x[4][4];
+  {
+    int64_t o[3];
+    const T *p = (const T *)r.field + block_base<3>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+    const int64_t sz = r.dims[1] * r.dims[2], sy = r.dims[2];
+#pragma unroll
+    for (int z = 0; z < 4; z++) load_row4<T, VEC>(p + z * sz + q * sy, x[z]);
+  }
+  const int minexp = get_i32(minexp_p);  // read while the rows are in flight
+
+  // block-floating-point: common exponent of the largest magnitude
+  U mmax = 0;
+#pragma unroll
+  for (int z = 0; z < 4; z++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const U m = Q::bits(x[z][e]) & ~(U(1) << (W - 1));
+      mmax = m > mmax ? m : mmax;
+    }
+  mmax = quad_max(mmax);
+  const bool empty = mmax == 0;
+  const int emax = empty ? 0 : frexp_exponent_bits<T>(mmax);
+  int prec = emax - minexp + 8;  // 2 (d + 1), d = 3
+  prec = empty ? 0 : (prec < 0 ? 0 : (prec > W ? W : prec));
+  const int sh = Q::P - emax;
+  const float s1 = pow2f(sh < 127 ? sh : 127), s2 = pow2f(sh < 127 ? 0 : sh - 127);
+  I c[4][4];
+#pragma unroll
+  for (int z = 0; z < 4; z++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) c[z][e] = bfp_value<T>(x[z][e], emax, s1, s2);
+
+  // forward transform, fastest axis first: x in row layout, then y and z
+  // in column layout (c[z][y] = coefficient (z, y, x = q)); negabinary
+#pragma unroll
+  for (int z = 0; z < 4; z++) fwd_lift4(c[z][0], c[z][1], c[z][2], c[z][3]);
+#pragma unroll
+  for (int z = 0; z < 4; z++) quad_transpose(c[z], q);
+#pragma unroll
+  for (int z = 0; z < 4; z++) fwd_lift4(c[z][0], c[z][1], c[z][2], c[z][3]);
+#pragma unroll
+  for (int y = 0; y < 4; y++) fwd_lift4(c[0][y], c[1][y], c[2][y], c[3][y]);
+#pragma unroll
+  for (int z = 0; z < 4; z++)
+#pragma unroll
+    for (int y = 0; y < 4; y++) c[z][y] = (I)(((U)c[z][y] + Q::NB) ^ Q::NB);
+
+  // bit lengths in coding order through LDS; lane q takes positions
+  // 16q .. 16q + 15 (see zfp_block_lane for the count itself)
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    const U u = (U)c[t >> 2][t & 3];
+    const int m = u ? W - clz_u(u) : 0;
+    sb[(pos[t >> 2] >> (8 * (t & 3))) & 0xffu] = (uint8_t)m;
+  }
+  __syncthreads();
+  const uint4 mv = *(const uint4 *)(sb + 16 * q);
+  __syncthreads();
+  const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+  int lmax = 0;
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    const int m = (int)((mw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+    lmax = m > lmax ? m : lmax;
+  }
+  // largest bit length at the positions after the lane's 16.  Every lane
+  // evaluates each cross-lane read (a lane left out of one would hand its
+  // readers 0), and only then does lane 3 take 0.
+  int after = max(lmax, (int)dpp<kDppQuad1233>((uint32_t)lmax));
+  after = max(after, (int)dpp<kDppQuad2323>((uint32_t)after));
+  const int later = (int)dpp<kDppQuad1233>((uint32_t)after);
+  after = q == 3 ? 0 : later;
+  const int kmin = W - prec;
+  int run = after > kmin ? after : kmin;
+  uint32_t verb = 0, found = 0, sig = 0;
+#pragma unroll
+  for (int t = 15; t >= 0; t--) {
+    const int m = (int)((mw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+    const int mc = m > kmin ? m : kmin;
+    found += (mc > kmin && mc >= run) ? 1u : 0u;
+    run = mc > run ? mc : run;
+    verb += (uint32_t)(run - kmin);
+    sig += (uint32_t)(mc - kmin);
+  }
+  verb = quad_sum(verb);
+  found = quad_sum(found);
+  sig = quad_sum(sig);
+  const int m_last = (int)dpp<kDppQuadBcast3>((mw[3] >> 24) & 0xffu);  // position 63
+  ZfpLane out;
+  out.emax = empty ? INT32_MIN : emax;
+  out.bits = prec == 0 ? 1u
+                       : (uint32_t)(1 + Q::E + W - (m_last > kmin ? m_last : kmin) -
+                                    (m_last > kmin ? 1 : 0)) + verb + found;
+  out.nsb = prec == 0 ? 0u : sig;
+
+  // decode at the cut-off: drop planes below kmin, invert every step
+  const U keep = kmin >= W ? U(0) : (~U(0) << kmin);
+#pragma unroll
+  for (int z = 0; z < 4; z++)
+#pragma unroll
+    for (int y = 0; y < 4; y++) c[z][y] = (I)((((U)c[z][y] & keep) ^ Q::NB) - Q::NB);
+#pragma unroll
+  for (int y = 0; y < 4; y++) inv_lift4(c[0][y], c[1][y], c[2][y], c[3][y]);
+#pragma unroll
+  for (int z = 0; z < 4; z++) inv_lift4(c[z][0], c[z][1], c[z][2], c[z][3]);
+#pragma unroll
+  for (int z = 0; z < 4; z++) quad_transpose(c[z], q);
+#pragma unroll
+  for (int z = 0; z < 4; z++) inv_lift4(c[z][0], c[z][1], c[z][2], c[z][3]);
+
+  // data-domain error: the adjacent-pair tree in in-block row-major order
+  // is, per z, the rows' pair trees (in the lane), then rows y = 0..3
+  // across the quad, then the four z planes
+  double plane[4];
+  double maxerr = 0.0;
+#pragma unroll
+  for (int z = 0; z < 4; z++) {
+    double e2[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      T xh = (T)ldexp((double)c[z][e], emax - Q::P);
+      if (prec == 0) xh = (T)0;
+      const double d = (double)x[z][e] - (double)xh;
+      maxerr = fmax(maxerr, fabs(d));
+      e2[e] = d * d;
+    }
+    plane[z] = quad_sum((e2[0] + e2[1]) + (e2[2] + e2[3]));
+  }
+  out.sse = (plane[0] + plane[1]) + (plane[2] + plane[3]);
+  out.maxerr = quad_max(maxerr);
+  return out;
+}
+
+// Whole ZFP pass of workgroup w (one wave) for 3-D blocks: rounds of 16
+// consecutive sampled blocks of its aligned chunk, one block per quad; the
+// round sums (wave butterfly over the quads' first lanes, zero elsewhere)
+// are folded with the binary counter as in zfp_wg.
+template <typename T, bool VEC>
+__device__ inline bool zfp_wg_quad(const ReqDesc &r, int w, TileLds &L) {
+  __shared__ __align__(16) uint8_t s_msb[kQuadBlocks * kQuadLds];
+  const int lane = threadIdx.x, q = lane & 3, b = lane >> 2;
+  uint32_t pos[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    pos[k] = q == 0 ? QuadPos::table.w[0][k]
+                    : (q == 1 ? QuadPos::table.w[1][k] : (q == 2 ? QuadPos::table.w[2][k] : QuadPos::table.w[3][k]));
+  uint8_t *sb = s_msb + b * kQuadLds;
+  const int rounds = r.zblk / kQuadBlocks;
+  uint32_t bits = 0, nsb = 0;
+  double maxerr = 0.0;
+  wg_acc_reset(L);
+  for (int k = 0; k < rounds; k++) {
+    const int64_t base = (int64_t)w * r.zblk + (int64_t)k * kQuadBlocks;
+    if (base >= r.nblk) {
+      wg_acc_push(L, 0.0);
+      continue;
+    }
+    const int64_t j = base + b;
+    const bool active = j < r.nblk;
+    const ZfpLane z = zfp_block_quad<T, VEC>(r, j, q, &r.st->minexp, pos, sb);
+    double s = 0.0;
+    if (active && q == 0) {
+      bits += z.bits;
+      nsb += z.nsb;
+      maxerr = fmax(maxerr, z.maxerr);
+      s = z.sse;
+      if (r.dbg_zbits) r.dbg_zbits[j] = z.bits;
+      if (r.dbg_zsse) r.dbg_zsse[j] = z.sse;
+      if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
+    }
+    wg_acc_push(L, group_tree_sum<kWave>(s));
+  }
+  Part v;
+  v.s = 0.0;
+  v.m = maxerr;
+  v.a = bits;
+  v.b = nsb;
+  v = part_wave<false>(v);
+  if (lane == 0) {
+    v.s = L.stk[0];
+    part_store(r.zp, w, v);
+  }
+  Part tot;
+  if (!pass_complete<false>(r.zp, r.grp[kPassZfp], r.sync + kPassZfp, w, r.nzfp, L, tot)) return false;
+  zfp_finalize<T, 3, false>(r, tot);
+  return true;
+}
+
 // Whole ZFP pass of workgroup w (one wave): rounds of 64 consecutive
 // sampled blocks of its aligned chunk, one block per lane; the round sums
 // (wave butterfly) are folded with the binary counter.  Returns true in the
 // workgroup that ran the finalizer.
 template <typename T, int D, bool VEC, bool EC>
 __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
+  if constexpr (D == 3 && !EC) return zfp_wg_quad<T, VEC>(r, w, L);
   const int lane = threadIdx.x;
   const int rounds = r.zblk / kWave;
   uint32_t bits = 0, nsb = 0;

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kThreads) void k_range(ReqDesc r) {
 // VEC: rows of 4 values start 16-byte aligned and are read as vectors.
 // EC: the paper's point sub-sampling estimate instead of the exact one.
 template <typename T, int D, bool VEC, bool EC>
-__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D>)) void k_zfp(ReqDesc r) {
+__global__ __launch_bounds__(kWave, (kZfpWavesPerSimd<T, D, EC>)) void k_zfp(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
   zfp_wg<T, D, VEC, EC>(r, blockIdx.x, L);
