@@ -139,7 +139,7 @@ typedef struct {
 
 /* Creates a context on HIP device `hip_device`.  workspace_budget_bytes caps
  * the device memory the context may allocate (0 = 16 GiB; a request needs
- * about 21 MB plus 2 bytes per sampled value).  Returns SZSEL_OK and *ctx,
+ * about 4.8 MB plus 2 bytes per sampled value).  Returns SZSEL_OK and *ctx,
  * or a negative code. */
 int szsel_create(szsel_ctx **ctx, int hip_device, size_t workspace_budget_bytes);
 
@@ -178,7 +178,7 @@ int szsel_select_fixed_eb(szsel_ctx *ctx, const void *field, const int64_t *dims
  * enqueues kernels and the result's copy on `stream` and allocates nothing
  * (no hipMalloc, hipFree or allocating library routine; no event either).
  * `out` should be pinned host memory where the call is captured.
- * A request whose workspace would exceed the array (about 4.6 MB plus 2
+ * A request whose workspace would exceed the array (about 4.8 MB plus 2
  * bytes per sampled value) returns SZSEL_ENOMEM with the sizes in
  * szsel_last_error(); argument errors are those of szsel_select.
  * Every call on one GPU, from any context, uses that GPU's one array, which
@@ -222,7 +222,14 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   shapes (workgroups per request and pass, request groups, how the counts
  *   are shared, overflow codes per slice of the overflow pass) the first
  *   time it sees a batch shape and keep the fastest; 0 (default) uses the
- *   fixed schedule.  The results do not depend on it.
+ *   fixed schedule.  The results do not depend on it.  The schedules are
+ *   kept per device architecture and batch shape (request count, and per
+ *   request dtype, rank, op, extents, strides, 16-byte alignment and which
+ *   earlier request shares its field) for the process; when the
+ *   environment variable SZSEL_TUNE_CACHE names a file, they are also read
+ *   from it on first use and every newly tuned one is appended to it (one
+ *   JSON object per line; lines written by another build of the library
+ *   are ignored), so that later processes skip the tuning.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
  *   HIP graph and replays it while the batch shape repeats (schedules with
  *   more than two request groups are launched without a graph).

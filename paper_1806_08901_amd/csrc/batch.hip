@@ -20,9 +20,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
+#include <sstream>
 
 #include "batch.hpp"
 #include "launch.hpp"
@@ -362,12 +366,115 @@ void batch_destroy(BatchState *bs) {
 
 namespace {
 
+// Tuned schedules per (device architecture, batch shape), shared by the
+// process's contexts.  With SZSEL_TUNE_CACHE naming a file, the schedules
+// of earlier processes are read from it on first use, and every newly
+// tuned one is appended, one JSON object per line:
+//   {"build":"...","arch":"gfx950...","key":[...],"tune":{"sz_wgs_q":8,...}}
+// Lines of another build of the library (the schedule's best value depends
+// on the kernels) or that do not parse are skipped.
+constexpr const char *kTuneBuild = __DATE__ " " __TIME__;
+
 struct Tuner {
-  std::map<std::vector<uint64_t>, Tune> best;
+  std::map<std::pair<std::string, std::vector<uint64_t>>, Tune> best;
+  std::mutex mu;
+  bool loaded = false;
+  std::string path;
 };
 Tuner &tuner() {
   static Tuner t;
   return t;
+}
+
+// The knobs of a schedule as (JSON name, member) pairs.
+template <typename F>
+void tune_fields(Tune &t, F f) {
+  f("sz_wgs_q", t.sz_wgs_q);
+  f("zfp_chunk", t.zfp_chunk);
+  f("range_wgs_per_cu", t.range_wgs_per_cu);
+  f("groups", t.groups);
+  f("ovf_slice", t.ovf_slice);
+  f("share", t.share);
+}
+
+// The string value of "name" in one line of the cache, or false.
+bool json_str(const std::string &line, const char *name, std::string &out) {
+  const std::string pat = std::string("\"") + name + "\":\"";
+  const size_t a = line.find(pat);
+  if (a == std::string::npos) return false;
+  const size_t b = line.find('"', a + pat.size());
+  if (b == std::string::npos) return false;
+  out = line.substr(a + pat.size(), b - a - pat.size());
+  return true;
+}
+
+// Parses one cache line; false if it is not a complete entry.
+bool parse_tune_line(const std::string &line, std::string &build, std::string &arch,
+                     std::vector<uint64_t> &key, Tune &t) {
+  if (!json_str(line, "build", build) || !json_str(line, "arch", arch)) return false;
+  const size_t k0 = line.find("\"key\":[");
+  if (k0 == std::string::npos) return false;
+  const char *p = line.c_str() + k0 + 7;
+  key.clear();
+  while (*p && *p != ']') {
+    char *end = nullptr;
+    const unsigned long long v = std::strtoull(p, &end, 10);
+    if (end == p) return false;
+    key.push_back((uint64_t)v);
+    p = end;
+    if (*p == ',') p++;
+  }
+  if (*p != ']' || key.empty()) return false;
+  bool ok = true;
+  tune_fields(t, [&](const char *name, int &v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t a = line.find(pat);
+    if (a == std::string::npos) {
+      ok = false;
+      return;
+    }
+    char *end = nullptr;
+    const long x = std::strtol(line.c_str() + a + pat.size(), &end, 10);
+    if (end == line.c_str() + a + pat.size() || x < 0 || x > (1l << 30)) ok = false;
+    v = (int)x;
+  });
+  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_per_cu >= 1 &&
+         t.ovf_slice >= 1 && t.share <= 2;
+}
+
+// Reads the cache file once per process (the tuner's lock held).
+void tune_cache_load(Tuner &T) {
+  if (T.loaded) return;
+  T.loaded = true;
+  const char *env = std::getenv("SZSEL_TUNE_CACHE");
+  if (!env || !*env) return;
+  T.path = env;
+  std::ifstream in(T.path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::string build, arch;
+    std::vector<uint64_t> key;
+    Tune t;
+    if (parse_tune_line(line, build, arch, key, t) && build == kTuneBuild)
+      T.best[std::make_pair(arch, key)] = t;
+  }
+}
+
+// Appends one tuned schedule to the cache file (the tuner's lock held).
+void tune_cache_append(Tuner &T, const std::string &arch, const std::vector<uint64_t> &key, Tune t) {
+  if (T.path.empty()) return;
+  std::ostringstream o;
+  o << "{\"build\":\"" << kTuneBuild << "\",\"arch\":\"" << arch << "\",\"key\":[";
+  for (size_t i = 0; i < key.size(); i++) o << (i ? "," : "") << key[i];
+  o << "],\"tune\":{";
+  bool first = true;
+  tune_fields(t, [&](const char *name, int &v) {
+    o << (first ? "" : ",") << "\"" << name << "\":" << v;
+    first = false;
+  });
+  o << "}}\n";
+  std::ofstream out(T.path, std::ios::app);
+  out << o.str();
 }
 
 // Waits until the state's last batch (and with it every copy from its
@@ -568,8 +675,11 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     tu = bs->last_tune;
     tuned = true;
   } else if (opt.autotune) {
-    auto it = tuner().best.find(key);
-    if (it != tuner().best.end()) {
+    Tuner &T = tuner();
+    std::lock_guard<std::mutex> lock(T.mu);
+    tune_cache_load(T);
+    auto it = T.best.find(std::make_pair(std::string(ctx_arch(ctx)), key));
+    if (it != T.best.end()) {
       tu = it->second;
       tuned = true;
     }
@@ -689,7 +799,12 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (rc != SZSEL_OK) return rc;
-    tuner().best[key] = cur;
+    {
+      Tuner &T = tuner();
+      std::lock_guard<std::mutex> lock(T.mu);
+      T.best[std::make_pair(std::string(ctx_arch(ctx)), key)] = cur;
+      tune_cache_append(T, ctx_arch(ctx), key, cur);
+    }
     tu = cur;
   }
   bs->last_key = key;

@@ -43,6 +43,9 @@ void batch_destroy(BatchState *bs);
 // CU count of the context's device.
 int ctx_ncu(const szsel_ctx *ctx);
 
+// Architecture name of the context's device (gcnArchName).
+const char *ctx_arch(const szsel_ctx *ctx);
+
 // The argument checks of one request (no device, no context): SZSEL_OK or a
 // negative code with the reason in `why`.
 int check_request(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,

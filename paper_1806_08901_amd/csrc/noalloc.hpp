@@ -8,7 +8,7 @@
 namespace szsel {
 
 // Size of the array (the largest workspace one allocation-free request may
-// use: about 4.6 MB of fixed workspace plus 2 bytes per sampled value).
+// use: about 4.8 MB of fixed workspace plus 2 bytes per sampled value).
 constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
 
 // Looks up the device address of the array on `device` (which must be the

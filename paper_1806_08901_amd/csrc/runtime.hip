@@ -37,6 +37,7 @@ struct Slot {
 struct szsel_ctx {
   int device = 0;
   int ncu = 256;
+  std::string arch;  // gcnArchName of the device
   size_t budget = 0;
   size_t used_bytes = 0;
   Slot slots[kSlots];
@@ -79,6 +80,8 @@ int hip_fail(szsel_ctx *c, hipError_t e, const char *what) {
 namespace szsel {
 
 int ctx_ncu(const szsel_ctx *ctx) { return ctx ? ctx->ncu : 256; }
+
+const char *ctx_arch(const szsel_ctx *ctx) { return ctx ? ctx->arch.c_str() : ""; }
 
 int check_request(int op, const void *field, const int64_t *dims, int nd, int dtype, double eb,
                   int eb_mode, const int32_t *stride, std::string &why) {
@@ -350,6 +353,10 @@ int szsel_create(szsel_ctx **out, int hip_device, size_t budget) {
     return SZSEL_EHIP;
   }
   c->ncu = ncu > 0 ? ncu : 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->arch = prop.gcnArchName;
+  }
   // slots are allocated on first use and grow with the requests they serve
   for (int k = 0; k < kSlots; k++) {
     e = hipEventCreateWithFlags(&c->slots[k].done, hipEventDisableTiming);
