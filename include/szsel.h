@@ -231,8 +231,7 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   JSON object per line; lines written by another build of the library
  *   are ignored), so that later processes skip the tuning.
  * SZSEL_OPT_BATCH_GRAPH: nonzero (default) captures a batch's launches as a
- *   HIP graph and replays it while the batch shape repeats (schedules with
- *   more than two request groups are launched without a graph).
+ *   HIP graph and replays it while the batch shape repeats.
  * SZSEL_OPT_SZ_WGS, SZSEL_OPT_ZFP_CHUNK, SZSEL_OPT_RANGE_WGS: the schedule
  *   of single-request calls and of batches without autotuning (and the
  *   autotuner's starting point): SZ workgroups in quarters of the CU
@@ -248,9 +247,14 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   and small ones 0; the autotuner tries all three.
  * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
  *   default 1; 0 restores it): the requests are dealt to that many groups
- *   (requests on one field stay together), each running on its own stream,
- *   and group g starts its range scans when group g-1's are done, so the
- *   scans of later groups overlap the sampled passes of earlier ones.
+ *   (requests on one field stay together); the groups' range scans run one
+ *   after another on a side stream and group g's sampled passes start when
+ *   its scans are done, so the scans of later groups overlap the sampled
+ *   passes of earlier ones.
+ * SZSEL_OPT_RANGE_GRID: workgroups of a batch's range-scan launch (0 =
+ *   default, one per scan chunk; k = 1..64: k per CU, each looping over
+ *   the launch's chunks, which leaves the other wave slots of every CU to
+ *   the sampled passes that run beside the scans).
  * SZSEL_OPT_HUFFMAN: 0 (default) no Huffman cost; 1 also computes the exact
  *   Huffman cost of the SZ code histogram (the entropy-coding stage that the
  *   0.5 bits/value offset of Section 6.2 stands in for) into
@@ -274,7 +278,7 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
        SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9,
-       SZSEL_OPT_EC_SAMPLING = 10, SZSEL_OPT_BATCH_SHARE = 11 };
+       SZSEL_OPT_EC_SAMPLING = 10, SZSEL_OPT_BATCH_SHARE = 11, SZSEL_OPT_RANGE_GRID = 12 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* ---------------------------------------------------------------------

@@ -40,7 +40,6 @@ namespace {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 constexpr int kMaxGroupsPerBatch = 8;
-constexpr int kMaxCapturedGroups = 2;  // larger group counts are launched without a graph
 constexpr int kGraphCache = 8;         // captured graphs kept per batch state
 
 struct Plan {
@@ -225,6 +224,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       L.c1 = e;
       L.items = f[e] - f[k];
       L.grid = L.items;
+      if (ps == kBatchRange && tu.range_grid > 0)
+        L.grid = std::min<uint32_t>(L.items, (uint32_t)tu.range_grid * (uint32_t)ncu);
       if (ps == kBatchOvf) L.grid = std::min<uint32_t>(L.items, 2u * (uint32_t)ncu);
       if (ps == kBatchEnt) L.grid = std::min<uint32_t>(L.items, 8u * (uint32_t)ncu);
       if (L.items) p.launches.push_back(L);
@@ -312,10 +313,9 @@ struct BatchState {
   hipEvent_t done = nullptr;
   bool used = false;
   hipStream_t cap = nullptr;  // private capture stream
-  hipStream_t side[kMaxGroupsPerBatch - 1] = {};  // streams of request groups 1..
+  hipStream_t scan = nullptr;  // side stream of the range scans (request groups)
   hipEvent_t fork = nullptr;
   hipEvent_t scanned[kMaxGroupsPerBatch] = {};    // group g's range scans are done
-  hipEvent_t finished[kMaxGroupsPerBatch] = {};   // group g's last pass is done
   struct Graph {
     std::vector<uint64_t> key;  // launch shape, result destination
     hipGraph_t graph = nullptr;
@@ -348,12 +348,10 @@ void batch_destroy(BatchState *bs) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (bs->cap) (void)hipStreamDestroy(bs->cap);
-  for (hipStream_t q : bs->side)
-    if (q) (void)hipStreamDestroy(q);
+  if (bs->scan) (void)hipStreamDestroy(bs->scan);
   if (bs->fork) (void)hipEventDestroy(bs->fork);
   for (int g = 0; g < kMaxGroupsPerBatch; g++) {
     if (bs->scanned[g]) (void)hipEventDestroy(bs->scanned[g]);
-    if (bs->finished[g]) (void)hipEventDestroy(bs->finished[g]);
   }
   if (bs->fixed) (void)hipFree(bs->fixed);
   if (bs->var) (void)hipFree(bs->var);
@@ -392,6 +390,7 @@ void tune_fields(Tune &t, F f) {
   f("sz_wgs_q", t.sz_wgs_q);
   f("zfp_chunk", t.zfp_chunk);
   f("range_wgs_per_cu", t.range_wgs_per_cu);
+  f("range_grid", t.range_grid);
   f("groups", t.groups);
   f("ovf_slice", t.ovf_slice);
   f("share", t.share);
@@ -438,7 +437,7 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     if (end == line.c_str() + a + pat.size() || x < 0 || x > (1l << 30)) ok = false;
     v = (int)x;
   });
-  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_per_cu >= 1 &&
+  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_per_cu >= 1 && t.range_grid >= 0 &&
          t.ovf_slice >= 1 && t.share <= 2;
 }
 
@@ -588,11 +587,6 @@ hipError_t upload_meta(BatchState *bs, hipStream_t s) {
   return e;
 }
 
-// Every launch of plan p, on stream s.  With G
-// request groups, group g runs on its own stream (s for group 0) and
-// starts its range scans when group g-1's are done, so that the scans run
-// one group at a time at full bandwidth while the earlier groups' sampled
-// passes (latency- and issue-bound) overlap them; s waits for every group.
 // One launch, with the timer's event pair around it when profiling.
 hipError_t timed_launch(const BatchLaunch &L, hipStream_t s, LaunchTimer *lt) {
   if (!lt) return launch_batch_pass(L, s);
@@ -613,24 +607,33 @@ hipError_t timed_launch(const BatchLaunch &L, hipStream_t s, LaunchTimer *lt) {
   return e;
 }
 
+// Every launch of plan p, on stream s.  With G > 1 request groups the
+// range scans of all groups run back to back on one side stream, each
+// group's followed by an event, and the sampled passes of group g run on s
+// once group g's scans are done: the scans of later groups overlap the
+// sampled passes of earlier ones, and a graph captured from this forks into
+// two streams whatever G is.  s waits for the side stream's last scan (its
+// own waits already do) before the results are read.
 hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTimer *lt = nullptr) {
   hipError_t e = hipSuccess;
   const int G = p.groups;
-  hipStream_t st[kMaxGroupsPerBatch];
-  st[0] = s;
-  for (int g = 1; g < G; g++) st[g] = bs->side[g - 1];
-  if (G > 1 && e == hipSuccess) e = hipEventRecord(bs->fork, s);
-  for (int g = 1; g < G && e == hipSuccess; g++) e = hipStreamWaitEvent(st[g], bs->fork, 0);
-  for (int g = 0; g < G && e == hipSuccess; g++) {
-    if (g > 0) e = hipStreamWaitEvent(st[g], bs->scanned[g - 1], 0);
-    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
-      if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = timed_launch(p.launches[k], st[g], lt);
-    if (G > 1 && e == hipSuccess) e = hipEventRecord(bs->scanned[g], st[g]);
-    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
-      if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = timed_launch(p.launches[k], st[g], lt);
-    if (G > 1 && g > 0 && e == hipSuccess) e = hipEventRecord(bs->finished[g], st[g]);
+  if (G == 1) {
+    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
+    return e;
   }
-  for (int g = 1; g < G && e == hipSuccess; g++) e = hipStreamWaitEvent(s, bs->finished[g], 0);
+  hipStream_t scan = bs->scan;
+  e = hipEventRecord(bs->fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(scan, bs->fork, 0);
+  for (int g = 0; g < G && e == hipSuccess; g++) {
+    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
+      if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = timed_launch(p.launches[k], scan, lt);
+    if (e == hipSuccess) e = hipEventRecord(bs->scanned[g], scan);
+  }
+  for (int g = 0; g < G && e == hipSuccess; g++) {
+    e = hipStreamWaitEvent(s, bs->scanned[g], 0);
+    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
+      if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = timed_launch(p.launches[k], s, lt);
+  }
   return e;
 }
 
@@ -646,13 +649,10 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     bs = new BatchState();
     bool ok = hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&bs->fork, hipEventDisableTiming) == hipSuccess &&
-              hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) == hipSuccess;
-    for (int g = 0; g < kMaxGroupsPerBatch && ok; g++) {
-      ok = hipEventCreateWithFlags(&bs->scanned[g], hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&bs->finished[g], hipEventDisableTiming) == hipSuccess;
-      if (ok && g + 1 < kMaxGroupsPerBatch)
-        ok = hipStreamCreateWithFlags(&bs->side[g], hipStreamNonBlocking) == hipSuccess;
-    }
+              hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&bs->scan, hipStreamNonBlocking) == hipSuccess;
+    for (int g = 0; g < kMaxGroupsPerBatch && ok; g++)
+      ok = hipEventCreateWithFlags(&bs->scanned[g], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
       msg = "batch state: event or stream creation failed";
       return SZSEL_EHIP;
@@ -723,6 +723,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {64, 128, 256};
     const int range_opts[] = {1, 2, 4, 8, 16};
+    const int grid_opts[] = {0, 1, 2, 4};
     const int ovf_opts[] = {kOvfPerSlice, 2 * kOvfPerSlice, 4 * kOvfPerSlice};
     // two sweeps of the coordinates: the best group count depends on how
     // fast the sampled passes became with the other knobs
@@ -783,6 +784,17 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
         cur = c;
       }
     }
+    for (int v : grid_opts) {
+      if (rc != SZSEL_OK || v == cur.range_grid) continue;
+      Tune c = cur;
+      c.range_grid = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
     for (int v : ovf_opts) {
       if (rc != SZSEL_OK || v == cur.ovf_slice) continue;
       Tune c = cur;
@@ -822,10 +834,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
   }
   const size_t res_bytes = sizeof(szsel_result) * (size_t)n;
   bool copied = false;
-  // A captured graph forking into more than two request-group streams
-  // crashed the host process inside the runtime on this ROCm; such
-  // schedules run uncaptured (the path the autotuner times).
-  if (opt.graph && !opt.timer && p.groups <= kMaxCapturedGroups) {
+  if (opt.graph && !opt.timer) {
     // the results' copy is part of the graph when `out` came back from one
     // of the last calls (a caller rotating a few result buffers) and the
     // device can reach it (pinned host or device memory): a copy queued

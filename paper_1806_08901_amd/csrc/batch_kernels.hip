@@ -37,13 +37,22 @@ __device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t
   return __builtin_amdgcn_readfirstlane(i);
 }
 
+// Range chunks: one per workgroup, or (a grid smaller than the chunk count)
+// every workgroup loops over chunks blockIdx.x, + gridDim.x, ... in table
+// order, so that a few resident workgroups per CU scan the whole launch.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
-  int local;
-  const int i = batch_item(first, c0, c1, s_first, local);
-  range_wg<T>(tab[i], local, L);
+  batch_stage(first, c0, c1, s_first);
+  const uint32_t items = s_first[c1 - c0] - s_first[0];
+  for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
+    int local;
+    const int i = __builtin_amdgcn_readfirstlane(batch_find(s_first, c0, c1, g, local));
+    local = __builtin_amdgcn_readfirstlane(local);
+    range_wg<T>(tab[i], local, L);
+    __syncthreads();
+  }
 }
 
 template <typename T, int D, bool VEC, bool EC>

@@ -50,6 +50,9 @@ struct Tune {
   int sz_wgs_q = 8;          // SZ workgroups per request, in quarters of the CU count
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
   int range_wgs_per_cu = 1;  // range workgroups per CU for one request
+  int range_grid = 0;        // batches: 0 = one workgroup per range chunk; k > 0 = k workgroups
+                             // per CU that loop over all the launch's chunks (a resident scan
+                             // that leaves the other wave slots to the sampled passes)
   int groups = 1;            // batches: request groups pipelined on parallel streams
   int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ

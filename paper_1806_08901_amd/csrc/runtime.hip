@@ -541,6 +541,12 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
     c->bopt.fixed.share = v;
     return SZSEL_OK;
   }
+  if (option == SZSEL_OPT_RANGE_GRID) {
+    const int v = (int)value;
+    if (value != (double)v || v < 0 || v > 64) return fail(c, SZSEL_EINVAL, "range grid: 0 to 64 workgroups per CU");
+    c->bopt.fixed.range_grid = v;
+    return SZSEL_OK;
+  }
   if (option == SZSEL_OPT_BATCH_GROUPS) {
     const int v = (int)value;
     if (value != (double)v || v < 0 || v > 8) return fail(c, SZSEL_EINVAL, "request groups: 0 to 8");

@@ -125,18 +125,29 @@ def test_autotune_and_no_graph_give_the_same_results(ctx):
 
 
 def test_request_group_schedules_equal_single_calls(ctx):
-    """Fixed schedules with 2, 4 and 8 request groups (two groups replay a
-    captured graph, more run uncaptured) give the single calls' results."""
+    """Fixed schedules with 2, 4 and 8 request groups (scans on a side
+    stream, captured graphs replayed, and uncaptured), with the default
+    range grid and with resident range workgroups (1 and 2 per CU), give
+    the single calls' results."""
     from paper_1806_08901_amd import szsel
     items = _items(_fields(), ebs=(1e-3, 1e-5))
     singles = _singles(ctx, items)
     try:
-        for g in (2, 4, 8):
-            ctx.set_option(szsel.OPT_BATCH_GROUPS, g)
-            for rep in range(2):
-                assert ctx.select_batch(items) == singles, "groups %d rep %d" % (g, rep)
+        for grid in (0, 1, 2):
+            ctx.set_option(szsel.OPT_RANGE_GRID, grid)
+            for g in (1, 2, 4, 8):
+                ctx.set_option(szsel.OPT_BATCH_GROUPS, g)
+                for graph in (1, 0):
+                    ctx.set_option(szsel.OPT_BATCH_GRAPH, graph)
+                    for rep in range(2):
+                        assert ctx.select_batch(items) == singles, "grid %d groups %d graph %d rep %d" % (
+                            grid, g, graph, rep)
+        with pytest.raises(szsel.SzselError):
+            ctx.set_option(szsel.OPT_RANGE_GRID, 65)
     finally:
         ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
+        ctx.set_option(szsel.OPT_RANGE_GRID, 0)
+        ctx.set_option(szsel.OPT_BATCH_GRAPH, 1)
 
 
 def test_rotating_result_buffers(ctx):
