@@ -333,15 +333,18 @@ __device__ inline double dpp(double v) {
 // the group's first lane (in every lane for W = 64).
 template <int W>
 __device__ inline double group_tree_first(double v) {
+  static_assert(W == 2 || W == 4 || W == 8 || W == 16 || W == 64, "group of 2, 4, 8, 16 or 64 lanes");
   if constexpr (W == 4) {
     v = v + dpp<kDppQuad1233>(v);
     v = v + dpp<kDppQuad2323>(v);
     return v;
   } else {
     v = v + dpp<kDppRowShl1>(v);
-    v = v + dpp<kDppRowShl2>(v);
-    v = v + dpp<kDppRowShl4>(v);
-    v = v + dpp<kDppRowShl8>(v);
+    if constexpr (W >= 8) {
+      v = v + dpp<kDppRowShl2>(v);
+      v = v + dpp<kDppRowShl4>(v);
+    }
+    if constexpr (W >= 16) v = v + dpp<kDppRowShl8>(v);
     if constexpr (W == 64) {
       const uint64_t b = (uint64_t)__double_as_longlong(v);
       auto rd = [&](int l) {
@@ -354,6 +357,11 @@ __device__ inline double group_tree_first(double v) {
     return v;
   }
 }
+
+// Sampled blocks one wave of the SZ pass takes per round: one lane per two
+// rows of 4 points in 2-D and 3-D (8 and 2 lanes per block), one lane per
+// block in 1-D.
+__host__ __device__ constexpr int sz_blocks_per_wave(int nd) { return nd == 1 ? 64 : (nd == 2 ? 32 : 8); }
 
 // ---------------------------------------------------------------------------
 // Sampled-block addressing

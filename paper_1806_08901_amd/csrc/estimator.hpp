@@ -439,7 +439,7 @@ __device__ inline typename Prec<T>::I bfp_value(T x, int emax, float s1, float s
 // Occupancy of the SZ kernels: waves per SIMD (the register budget that
 // keeps their state out of scratch memory; one more wave would spill).
 template <typename T, int D>
-constexpr int kSzWavesPerSimd = D == 3 ? (sizeof(T) == 8 ? 4 : 5) : (sizeof(T) == 8 ? 5 : 6);
+constexpr int kSzWavesPerSimd = D == 3 ? (sizeof(T) == 8 ? 3 : 4) : (sizeof(T) == 8 ? 4 : 5);
 
 // Occupancy of the ZFP kernels: waves per SIMD (one block per lane; 3-D
 // blocks of the exact estimate: one block per quad of lanes).
@@ -1143,18 +1143,34 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
 // linear-scaling quantization, code histogram
 // ===========================================================================
 
-// SZ side, one lane per row of 4 points along the fastest axis: 4^(D-1)
-// lanes per sampled block, 64 / 4^(D-1) blocks per wave.  A lane reads the
-// rows of its points' Lorenzo neighbours: for every subset m of the slower
-// axes the row displaced by one along the axes of m, each with the value
-// before the row (x - 1).  Values outside the field are 0 (the
-// lower-order predictor at borders).
+// SZ side, one lane per R consecutive rows of 4 points along the fastest
+// axis (R = 2 in 2-D and 3-D, 1 in 1-D): 4^(D-1) / R lanes per sampled
+// block.  A lane reads the rows its points' Lorenzo stencils touch, each
+// with the value before it (x - 1): in 3-D the rows y0 - 1 .. y0 + R - 1 of
+// its slice z and of slice z - 1, in 2-D the rows y0 - 1 .. y0 + R - 1, in
+// 1-D its row; a row serves every point of the lane whose stencil touches
+// it, so two rows per lane need 6 rows (3-D) instead of 8.  Values outside
+// the field are 0 (the lower-order predictor at borders).
+template <int D>
+struct SzLayout {
+  static constexpr int R = D == 1 ? 1 : 2;         // rows per lane
+  static constexpr int ROWS = 1 << (2 * (D - 1));  // rows per block
+  static constexpr int LPB = ROWS / R;             // lanes per block
+  static constexpr int BPW = kWave / LPB;          // blocks per wave
+  static constexpr int NY = D == 1 ? 1 : R + 1;    // rows along y: y0 - 1 .. y0 + R - 1
+  static constexpr int NZ = D == 3 ? 2 : 1;        // along z: z - 1, z
+  static constexpr int NP = 4 * R;                 // points per lane
+};
+
 template <typename T, int D>
 struct Rows {
-  static constexpr int NR = 1 << (D - 1);
+  using Lay = SzLayout<D>;
+  static constexpr int NR = Lay::NZ * Lay::NY;
   static constexpr uint32_t kAll = (2u << NR) - 1u;  // every row and x - 1 inside the field
-  T v[NR][5];     // [m][x + 1], m: bit k set = displaced along slower axis k
-  uint32_t keep;  // bit m: row m lies inside the field; bit NR: x - 1 does
+  T v[Lay::NZ][Lay::NY][5];  // [slice][row][x + 1]
+  uint32_t keep;             // bit zi * NY + yi: row inside the field; bit NR: x - 1 is
+  // own row dy of the lane (0 .. R - 1)
+  __device__ static constexpr int own(int dy) { return D == 1 ? 0 : dy + 1; }
 };
 
 // Reads one row of 4 values and the value before it.  Nothing is done with
@@ -1183,47 +1199,46 @@ __device__ inline void load_row(const T *p, T (&out)[5], bool left) {
   out[0] = p[left ? -1 : 0];
 }
 
-// Rows of lane row q of sampled block j (all zero past the last block).
+// Rows of lane row group q of sampled block j (all zero past the last
+// block): q = z * (4 / R) + h in 3-D, q = h in 2-D; the lane's first own row
+// is y0 = R h.
 template <typename T, int D, bool VEC>
 __device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
+  using Lay = SzLayout<D>;
   Rows<T, D> s;
   const bool in = j < r.nblk;
   int64_t o[3] = {0, 0, 0};
   // a block past the end reads block 0 (always present) and is masked out
   const int64_t base = block_base<D>(r, in ? (uint32_t)j : 0u, o);
   const T *x = (const T *)r.field;
-  // the row's offset, the strides of the slower axes and whether the row
-  // has a predecessor inside the field along each of them
-  int64_t off = 0, st[2] = {0, 0};
-  bool has[2] = {false, false};
+  int64_t own = 0, sy = 0, sz = 0;
+  bool yprev = false, zprev = false;  // row y0 - 1 / slice z - 1 inside the field
   if constexpr (D == 2) {
-    off = (int64_t)q * r.dims[1];
-    st[0] = r.dims[1];
-    has[0] = o[0] + q > 0;
+    const int y0 = Lay::R * q;
+    sy = r.dims[1];
+    own = (int64_t)y0 * sy;
+    yprev = o[0] + y0 > 0;
   } else if constexpr (D == 3) {
-    const int z = q >> 2, y = q & 3;
-    st[0] = r.dims[1] * r.dims[2];
-    st[1] = r.dims[2];
-    off = (int64_t)z * st[0] + (int64_t)y * st[1];
-    has[0] = o[0] + z > 0;
-    has[1] = o[1] + y > 0;
+    const int z = q / (4 / Lay::R), y0 = Lay::R * (q % (4 / Lay::R));
+    sz = r.dims[1] * r.dims[2];
+    sy = r.dims[2];
+    own = (int64_t)z * sz + (int64_t)y0 * sy;
+    zprev = o[0] + z > 0;
+    yprev = o[1] + y0 > 0;
   }
   const bool left = o[D - 1] > 0;
-  const T *row = x + base + off;
+  const T *row = x + base + own;
   uint32_t keep = (in && left) ? (1u << Rows<T, D>::NR) : 0u;
 #pragma unroll
-  for (int m = 0; m < Rows<T, D>::NR; m++) {
-    bool ok = in;
-    int64_t d = 0;
+  for (int zi = 0; zi < Lay::NZ; zi++) {
 #pragma unroll
-    for (int k = 0; k < D - 1; k++)
-      if ((m >> k) & 1) {
-        ok = ok && has[k];
-        d += st[k];
-      }
-    keep |= ok ? (1u << m) : 0u;
-    // a missing row is read from the lane's own row and zeroed later
-    load_row<T, VEC>(ok ? row - d : row, s.v[m], left);
+    for (int yi = 0; yi < Lay::NY; yi++) {
+      const int dz = zi - (Lay::NZ - 1), dy = D == 1 ? 0 : yi - 1;
+      const bool ok = in && (dz == 0 || zprev) && (dy >= 0 || yprev);
+      keep |= ok ? (1u << (zi * Lay::NY + yi)) : 0u;
+      // a missing row is read from the lane's own row and zeroed later
+      load_row<T, VEC>(ok ? row + dz * sz + dy * sy : row, s.v[zi][yi], left);
+    }
   }
   s.keep = keep;
   return s;
@@ -1233,31 +1248,37 @@ __device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
 // block): the lower-order predictor at borders.
 template <typename T, int D>
 __device__ inline void rows_mask(Rows<T, D> &s) {
+  using Lay = SzLayout<D>;
   const bool left = (s.keep >> Rows<T, D>::NR) & 1u;
 #pragma unroll
-  for (int m = 0; m < Rows<T, D>::NR; m++) {
-    const bool ok = (s.keep >> m) & 1u;
+  for (int zi = 0; zi < Lay::NZ; zi++)
 #pragma unroll
-    for (int e = 0; e < 5; e++) s.v[m][e] = (ok && (e > 0 || left)) ? s.v[m][e] : (T)0;
-  }
+    for (int yi = 0; yi < Lay::NY; yi++) {
+      const bool ok = (s.keep >> (zi * Lay::NY + yi)) & 1u;
+#pragma unroll
+      for (int e = 0; e < 5; e++) s.v[zi][yi][e] = (ok && (e > 0 || left)) ? s.v[zi][yi][e] : (T)0;
+    }
 }
 
-// Lorenzo prediction of point x of the lane's row (Section 4.1, from the
-// original neighbours as Section 4.3 prescribes): the sum over non-empty
-// axis subsets S of (-1)^(|S|+1) X[p - e_S], in FP64, terms in the order
-// single axes (slowest first), pairs in lexicographic order, the triple.
+// Lorenzo prediction of point xi of the lane's own row dy (Section 4.1,
+// from the original neighbours as Section 4.3 prescribes): the sum over
+// non-empty axis subsets S of (-1)^(|S|+1) X[p - e_S], in FP64, terms in the
+// order single axes (slowest first), pairs in lexicographic order, the
+// triple.
 template <typename T, int D>
-__device__ inline double lorenzo_row(const Rows<T, D> &s, int xi) {
+__device__ inline double lorenzo_row(const Rows<T, D> &s, int dy, int xi) {
   const int c = xi + 1;
   if constexpr (D == 1) {
-    return (double)s.v[0][c - 1];
+    return (double)s.v[0][0][c - 1];
   } else if constexpr (D == 2) {
     // {y}, {x}, {y,x}
-    return ((double)s.v[1][c] + (double)s.v[0][c - 1]) - (double)s.v[1][c - 1];
+    return ((double)s.v[0][dy][c] + (double)s.v[0][dy + 1][c - 1]) - (double)s.v[0][dy][c - 1];
   } else {
-    // {z}, {y}, {x}, {z,y}, {z,x}, {y,x}, {z,y,x}; row index m: bit 0 = z, bit 1 = y
-    return (((((double)s.v[1][c] + (double)s.v[2][c]) + (double)s.v[0][c - 1]) - (double)s.v[3][c]) -
-            (double)s.v[1][c - 1]) - (double)s.v[2][c - 1] + (double)s.v[3][c - 1];
+    // {z}, {y}, {x}, {z,y}, {z,x}, {y,x}, {z,y,x}; slice 0 is z - 1, row dy
+    // is y - 1 of own row dy
+    return (((((double)s.v[0][dy + 1][c] + (double)s.v[1][dy][c]) + (double)s.v[1][dy + 1][c - 1]) -
+             (double)s.v[0][dy][c]) - (double)s.v[0][dy + 1][c - 1]) - (double)s.v[1][dy][c - 1] +
+           (double)s.v[0][dy][c - 1];
   }
 }
 
@@ -1267,7 +1288,7 @@ __device__ inline double lorenzo_row(const Rows<T, D> &s, int xi) {
 // misses the bound delta/2.
 template <typename T>
 __device__ inline int quantize(T xv, double pred, double delta, double inv, double ebsz,
-                               double &e2, double &ae) {
+                               double &e2, double &ae, bool active = true) {
   // branch-free: every lane computes the reconstruction and the tests only
   // select the results (a code out of range computes with q = 0)
   const double xd = (double)xv;
@@ -1278,7 +1299,7 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
   if (d < 0.0) q = -q;
   const T recon = (T)(pred + (double)q * delta);
   const double e = xd - (double)recon;
-  const bool ok = in && fabs(e) <= ebsz;
+  const bool ok = active && in && fabs(e) <= ebsz;  // (an inactive lane counts nothing)
   e2 = ok ? e * e : 0.0;
   ae = ok ? fabs(e) : 0.0;
   return ok ? q + kRadius : 0;
@@ -1317,36 +1338,40 @@ __device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t 
   }
 }
 
-// Histogram update for the 4 codes of a lane (code 0 = unpredictable, not
-// counted here).  Codes in the LDS window: when all 4 are equal (the common
-// case on smooth data) one atomic adds 4, else one atomic per code; the LDS
+// Histogram update for the N codes of a lane (code 0 = unpredictable, not
+// counted here).  Codes in the LDS window: when all N are equal (the common
+// case on smooth data) one atomic adds N, else one atomic per code; the LDS
 // serialises lanes that hit one bin, off the vector pipeline.  Codes outside
 // the window are appended to the workgroup's overflow region, numbered by
 // one LDS atomic per wave (the wave's first such lane reserves room for all).
-__device__ inline void hist_add4(const int (&code)[4], bool active, uint32_t *s_hist, uint16_t *region,
-                                 uint32_t *s_n) {
-  bool out[4];
+template <int N>
+__device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_hist, uint16_t *region,
+                                uint32_t *s_n) {
+  bool out[N];
   bool anyout = false;
+  bool same = true;
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < N; k++) {
     const int wi = code[k] - kHistLo;
     out[k] = active && code[k] != 0 && (wi < 0 || wi >= kHistWin);
     anyout = anyout || out[k];
+    same = same && code[k] == code[0];
   }
   if (active) {
-    const bool same = code[0] == code[1] && code[0] == code[2] && code[0] == code[3];
     const int w0 = code[0] - kHistLo;
     if (same && code[0] != 0 && !out[0]) {
-      atomicAdd(&s_hist[w0], 4u);
+      atomicAdd(&s_hist[w0], (uint32_t)N);
     } else if (!same) {
 #pragma unroll
-      for (int k = 0; k < 4; k++)
+      for (int k = 0; k < N; k++)
         if (code[k] != 0 && !out[k]) atomicAdd(&s_hist[code[k] - kHistLo], 1u);
     }
   }
   if (__ballot(anyout)) {
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t mine = (uint32_t)out[0] + (uint32_t)out[1] + (uint32_t)out[2] + (uint32_t)out[3];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < N; k++) mine += (uint32_t)out[k];
     // exclusive prefix of the lanes' counts (Hillis-Steele)
     uint32_t inc = mine;
 #pragma unroll
@@ -1359,67 +1384,83 @@ __device__ inline void hist_add4(const int (&code)[4], bool active, uint32_t *s_
     if (lane == 0) base = atomicAdd(s_n, total);
     base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + inc - mine;
 #pragma unroll
-    for (int k = 0; k < 4; k++)
+    for (int k = 0; k < N; k++)
       if (out[k]) region[base++] = (uint16_t)code[k];
   }
 }
 
+// One round of the SZ side on the rows `sc` of block j (tile slot jl).
+template <typename T, int D>
+__device__ inline void sz_round(const ReqDesc &r, Rows<T, D> &sc, int64_t j, int jl, int q, double delta,
+                                double inv, double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
+                                uint32_t *s_n, LaneAcc &acc) {
+  using Lay = SzLayout<D>;
+  constexpr int BS = 1 << (2 * D), LPB = Lay::LPB, R = Lay::R, NP = Lay::NP;
+  const bool active = j < r.nblk;
+  // only rows at the field's low faces (or past the last block) need
+  // zeroing; most waves have none
+  if (__ballot(sc.keep != Rows<T, D>::kAll)) rows_mask<T, D>(sc);
+  // the points' predictions and codes first (independent chains the
+  // compiler can interleave), then their histogram updates; a lane past the
+  // last block gets code 0 and no error
+  double e2[NP], ae[NP];
+  int code[NP];
+#pragma unroll
+  for (int dy = 0; dy < R; dy++) {
+#pragma unroll
+    for (int xi = 0; xi < 4; xi++) {
+      const int k = 4 * dy + xi;
+      code[k] = quantize<T>(sc.v[Lay::NZ - 1][Rows<T, D>::own(dy)][xi + 1], lorenzo_row<T, D>(sc, dy, xi),
+                            delta, inv, ebsz, e2[k], ae[k], active);
+    }
+  }
+  hist_add<NP>(code, active, s_hist, region, s_n);
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    acc.a += code[k] == 0 && active ? 1u : 0u;
+    acc.maxerr = fmax(acc.maxerr, ae[k]);
+    acc.chunks |= 1ull << (code[k] >> 10);
+  }
+  if (r.dbg_codes && active) {
+#pragma unroll
+    for (int k = 0; k < NP; k++) r.dbg_codes[j * BS + q * NP + k] = (uint16_t)code[k];
+  }
+  // pair tree over the lane's points, then across the block's lanes
+#pragma unroll
+  for (int w = NP; w > 1; w >>= 1) {
+#pragma unroll
+    for (int k = 0; k < w / 2; k++) e2[k] = e2[2 * k] + e2[2 * k + 1];
+  }
+  double bsse = e2[0];
+  if constexpr (LPB > 1) bsse = group_tree_first<LPB>(bsse);
+  if (q == 0) {
+    L.sse[jl] = bsse;
+    if (active && r.dbg_ssse) r.dbg_ssse[j] = bsse;
+  }
+}
+
 // One tile of the SZ side (tile blocks starting at `base`): each round the
-// 4 waves take 4 * 64 / 4^(D-1) consecutive blocks; the next round's rows
-// are loaded while the current round is processed.  Per-block squared
-// errors: the lane's 4 points by the pair tree, then the block's lanes in
-// row order by the butterfly, i.e. the adjacent-pair tree in in-block
+// 4 waves take 4 BPW consecutive blocks; the next round's rows are loaded
+// while the current round is processed.  Per-block squared errors: the lane's 4 R points (consecutive
+// in the block's row-major order) by the pair tree, then the block's lanes
+// in order by the butterfly, i.e. the adjacent-pair tree in in-block
 // row-major order.
 template <typename T, int D, bool VEC>
 __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
                                double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
                                uint32_t *s_n, LaneAcc &acc) {
-  constexpr int BS = 1 << (2 * D), LPB = BS / 4, BPW = kWave / LPB;
+  using Lay = SzLayout<D>;
+  constexpr int LPB = Lay::LPB, BPW = Lay::BPW;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int q = lane & (LPB - 1), bw = lane / LPB;
-  const int rounds = tile / (kWaves * BPW);
-  Rows<T, D> sn = load_rows<T, D, VEC>(r, base + wave * BPW + bw, q);
+  const int rounds = tile / (kWaves * BPW);  // a power of two
+  const int j0 = wave * BPW + bw;            // tile slot of round 0
+  Rows<T, D> sn = load_rows<T, D, VEC>(r, base + j0, q);
   for (int rd = 0; rd < rounds; rd++) {
-    const int jl = (rd * kWaves + wave) * BPW + bw;
-    const int64_t j = base + jl;
-    const bool active = j < r.nblk;
+    const int jl = rd * kWaves * BPW + j0;
     Rows<T, D> sc = sn;
-    if (rd + 1 < rounds) sn = load_rows<T, D, VEC>(r, j + kWaves * BPW, q);
-    // only rows at the field's low faces (or past the last block) need
-    // zeroing; most waves have none
-    if (__ballot(sc.keep != Rows<T, D>::kAll)) rows_mask<T, D>(sc);
-    // the 4 points' predictions and codes first (independent chains the
-    // compiler can interleave), then their histogram updates
-    double e2[4], ae[4];
-    int code[4];
-#pragma unroll
-    for (int xi = 0; xi < 4; xi++) {
-      e2[xi] = 0.0;
-      ae[xi] = 0.0;
-      code[xi] = quantize<T>(sc.v[0][xi + 1], lorenzo_row<T, D>(sc, xi), delta, inv, ebsz, e2[xi], ae[xi]);
-      if (!active) {
-        code[xi] = 0;
-        e2[xi] = 0.0;
-        ae[xi] = 0.0;
-      }
-    }
-    hist_add4(code, active, s_hist, region, s_n);
-#pragma unroll
-    for (int xi = 0; xi < 4; xi++) {
-      acc.a += code[xi] == 0 && active ? 1u : 0u;
-      acc.maxerr = fmax(acc.maxerr, ae[xi]);
-      acc.chunks |= 1ull << (code[xi] >> 10);
-    }
-    if (r.dbg_codes && active) {
-#pragma unroll
-      for (int xi = 0; xi < 4; xi++) r.dbg_codes[j * BS + q * 4 + xi] = (uint16_t)code[xi];
-    }
-    double bsse = (e2[0] + e2[1]) + (e2[2] + e2[3]);
-    if constexpr (LPB > 1) bsse = group_tree_first<LPB>(bsse);
-    if (q == 0) {
-      L.sse[jl] = bsse;
-      if (active && r.dbg_ssse) r.dbg_ssse[j] = bsse;
-    }
+    if (rd + 1 < rounds) sn = load_rows<T, D, VEC>(r, base + jl + kWaves * BPW, q);
+    sz_round<T, D>(r, sc, base + jl, jl, q, delta, inv, ebsz, L, s_hist, region, s_n, acc);
   }
   __syncthreads();
   wg_acc_push(L, tile_sse(L, tile));

@@ -183,7 +183,6 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // consecutive sampled blocks, and a pass has at most kMaxParts workgroups.
   // ZFP: one wave per workgroup and one block per lane, chunks of 64 blocks
   // (the most waves).  SZ: at least one round of 4 waves.
-  const int bs = 1 << (2 * nd);
   auto chunk_for = [&](uint64_t min_chunk, uint64_t target_wgs, uint64_t max_wgs) {
     const uint64_t want = (nblk + target_wgs - 1) / target_wgs;
     uint64_t c = min_chunk;
@@ -192,11 +191,11 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     return c;
   };
   const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
-  // SZ: one lane per row of 4 points, 64 / 4^(d-1) blocks per wave; by
+  // SZ: one lane per two rows of 4 points (one row in 1-D); by
   // default 2 workgroups per CU, all of them resident at once
   const uint64_t sz_target = tu.sz_target > 0 ? (uint64_t)tu.sz_target
                                                : std::max<uint64_t>(1, (uint64_t)tu.sz_wgs_q * (uint64_t)ctx->ncu / 4);
-  const uint64_t sc = chunk_for((uint64_t)kWaves * (kWave / (bs / 4)), sz_target, kMaxParts);
+  const uint64_t sc = chunk_for((uint64_t)kWaves * sz_blocks_per_wave(nd), sz_target, kMaxParts);
   if (zc > (1u << 30) || sc > (1u << 30)) return fail(ctx, SZSEL_EINVAL, "too many sampled blocks");
   r.zblk = (int32_t)zc;
   r.sblk = (int32_t)sc;
