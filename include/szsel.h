@@ -339,8 +339,10 @@ int szsel_zfp_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, i
  * eb_abs; its symbol is 0, otherwise code + 32768.  Decompressed value:
  * q 2 eb_abs, or the stored value.  bits = optimal prefix-code bits of the
  * symbols + W per escape + 32 per distinct symbol (the code table); when
- * the optimal code cannot be computed (SZSEL_FLAG_NO_HUFFMAN), bits is 0 and
- * bitrate uses the symbols' entropy instead.  The squared errors are summed
+ * the optimal code cannot be computed (SZSEL_FLAG_NO_HUFFMAN: more than
+ * 16,384 distinct weights during the construction, impossible for fields of
+ * at most 2^27 values; or 2^32 values or more), bits is 0 and bitrate uses
+ * the symbols' entropy instead.  The squared errors are summed
  * by the pair tree in field order.
  *   symbols  device buffer of N uint16 for the symbols, or NULL
  *   decoded  device buffer of the field's size and dtype, or NULL

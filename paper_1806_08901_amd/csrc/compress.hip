@@ -629,8 +629,12 @@ __global__ void k_sz4_combine(SzArgs a) {
 }
 
 // Optimal code bits and sum h log2 h of the final counts (one workgroup).
+// The run list holds 16,384 runs (any histogram of up to 2^27 values); a
+// round's new runs go to the histogram copies, no longer needed once the
+// final counts are combined (they are cleared at the start of every call).
+constexpr int kSz4HuffCap = 16384;
 __global__ __launch_bounds__(kHuffThreads) void k_sz4_huff(SzArgs a) {
-  __shared__ HuffLds S;
+  __shared__ HuffLdsT<kSz4HuffCap, false> S;
   __shared__ double wsum[kHuffThreads / kWave];
   __shared__ uint32_t wsym[kHuffThreads / kWave];
   // sum of h log2 h: the pair tree over the 65,536 bins (64 per thread)
@@ -662,7 +666,8 @@ __global__ __launch_bounds__(kHuffThreads) void k_sz4_huff(SzArgs a) {
   }
   __syncthreads();
   uint64_t total;
-  const bool ok = huff_cost(a.hfinal, (uint64_t)a.n, S, total);
+  static_assert((size_t)kSzCopies * kBins >= 2 * (size_t)kSz4HuffCap, "room for the new runs");
+  const bool ok = huff_cost(a.hfinal, (uint64_t)a.n, S, a.hist, a.hist + kSz4HuffCap, total);
   if (t == 0) {
     double w16[kHuffThreads / kWave];
     for (int q = 0; q < kHuffThreads / kWave; q++) w16[q] = wsum[q];

@@ -1778,14 +1778,22 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
 // list holds distinct weights whose sum is the total, so at most
 // sqrt(2 total) runs: 8192 suffice for 2^25 sampled values.  Once at most
 // 64 items are left, one wave merges them one pair at a time in registers.
-struct HuffLds {
-  uint32_t aw[kHuffCap], am[kHuffCap];  // the list: weights (ascending, distinct), multiplicities
-  uint32_t bw[kHuffCap], bm[kHuffCap];  // a round's new runs; first the tally of small counts
-                                        // (bw) and the large counts (bm)
+// CAP: runs the list holds (a total of t values needs at most sqrt(2 t)).
+// LDSB: the second pair of arrays (a round's new runs, and first the tally
+// of small counts and the large counts) in LDS too; otherwise the caller
+// passes global buffers of CAP entries for them (a list of 16,384 runs,
+// enough for 2^27 values, fills 128 KiB of LDS by itself).
+template <int CAP, bool LDSB>
+struct HuffLdsT {
+  uint32_t aw[CAP], am[CAP];  // the list: weights (ascending, distinct), multiplicities
+  uint32_t bw[LDSB ? CAP : 1], bm[LDSB ? CAP : 1];
   uint32_t slots[2][2 * (kHuffThreads / kWave)];
   uint64_t red[kHuffThreads / kWave];
   uint32_t nbig, leaves, has_left, left_w;
+  static constexpr int kCap = CAP;
+  static constexpr bool kLdsB = LDSB;
 };
+using HuffLds = HuffLdsT<kHuffCap, true>;
 static_assert(kHuffCap % kHuffThreads == 0 && kHuffSmall <= kHuffCap, "Huffman pass layout");
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts of 1, 2, 4, 8
@@ -1844,9 +1852,11 @@ __device__ inline uint32_t huff_lower_bound(const uint32_t *a, uint32_t lo, uint
 
 // One merge round over the list (aw, am)[0, n) holding `items` items.
 // Returns false when the new list would not fit.
-__device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint64_t &cost) {
+template <typename Lds>
+__device__ inline bool huff_round(Lds &S, uint32_t *bw, uint32_t *bm, uint32_t &n, uint32_t &items,
+                                  uint64_t &cost) {
   constexpr int NT = kHuffThreads;
-  constexpr int kPer = kHuffCap / NT;  // list runs per thread at most
+  constexpr int kPer = Lds::kCap / NT;  // list runs per thread at most
   const int t = threadIdx.x;
   const uint32_t w0 = S.aw[0], m0 = S.am[0];
   // s: the two lightest items' sum (at most the total: 32 bits)
@@ -1922,7 +1932,7 @@ __device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint
   const bool left_sep = has_left && left_w != sv;  // an odd item of weight s joins the first new run
   const uint32_t off = left_sep ? 1u : 0u;
   const uint32_t rest = n - k, n2 = off + a + rest;
-  if (n2 > (uint32_t)kHuffCap) return false;
+  if (n2 > (uint32_t)Lds::kCap) return false;
   {
     uint32_t par2 = pm & 1u;
 #pragma unroll
@@ -1931,13 +1941,13 @@ __device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint
       if ((uint32_t)j < per && i < k) {
         const uint32_t e = m[j] - par2;
         if (emit & (1u << (2 * j))) {
-          S.bw[epos] = 2u * w[j];
-          S.bm[epos] = e >> 1;
+          bw[epos] = 2u * w[j];
+          bm[epos] = e >> 1;
           epos++;
         }
         if (emit & (2u << (2 * j))) {
-          S.bw[epos] = w[j] + S.aw[i + 1];
-          S.bm[epos] = 1;
+          bw[epos] = w[j] + S.aw[i + 1];
+          bm[epos] = 1;
           epos++;
         }
         par2 = e & 1u;
@@ -1956,14 +1966,14 @@ __device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint
     pq[j] = 0;
     if ((uint32_t)j < uper && u < U) {
       if (u < a) {
-        pw[j] = S.bw[u];
-        pq[j] = S.bm[u] + ((u == 0 && has_left && !left_sep) ? 1u : 0u);
+        pw[j] = bw[u];
+        pq[j] = bm[u] + ((u == 0 && has_left && !left_sep) ? 1u : 0u);
         pp[j] = off + u + (huff_lower_bound(S.aw, k, k2, pw[j]) - k);
       } else {
         const uint32_t q = u - a;
         pw[j] = S.aw[k + q];
         pq[j] = S.am[k + q];
-        pp[j] = off + q + (k + q < k2 ? huff_lower_bound(S.bw, 0, a, pw[j]) : a);
+        pp[j] = off + q + (k + q < k2 ? huff_lower_bound(bw, 0, a, pw[j]) : a);
       }
     }
   }
@@ -1987,7 +1997,8 @@ __device__ inline bool huff_round(HuffLds &S, uint32_t &n, uint32_t &items, uint
 // At most 64 items (n runs) left: wave 0 places them in its lanes,
 // ascending, and merges them one pair at a time, the leaves and the nodes
 // made so far (ascending by construction) as two queues in registers.
-__device__ inline void huff_tail(HuffLds &S, uint32_t n, uint32_t items, uint64_t &cost) {
+template <typename Lds>
+__device__ inline void huff_tail(Lds &S, uint32_t *bw, uint32_t n, uint32_t items, uint64_t &cost) {
   const int lane = threadIdx.x;
   uint32_t w = 0, m = 0;
   if ((uint32_t)lane < n) {
@@ -1995,11 +2006,11 @@ __device__ inline void huff_tail(HuffLds &S, uint32_t n, uint32_t items, uint64_
     m = S.am[lane];
   }
   const uint32_t pre = wave_incl_scan(m) - m;
-  for (uint32_t q = 0; q < m; q++) S.bw[pre + q] = w;
+  for (uint32_t q = 0; q < m; q++) bw[pre + q] = w;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint32_t leaf = (uint32_t)lane < items ? S.bw[lane] : 0xFFFFFFFFu;
+  const uint32_t leaf = (uint32_t)lane < items ? bw[lane] : 0xFFFFFFFFu;
   uint32_t node = 0xFFFFFFFFu;
   uint32_t li = 0, qh = 0, qt = 0;
   uint64_t c = 0;
@@ -2034,9 +2045,19 @@ __device__ inline void huff_tail(HuffLds &S, uint32_t n, uint32_t items, uint64_
 // Optimal prefix-code bits of the 65,536 counts hist (which sum to nv),
 // by the whole workgroup; valid on thread 0, which returns true when it was
 // computed (false: more distinct weights than the pass holds, or nv >=
-// 2^32).  S.leaves holds the number of nonzero counts afterwards.
-__device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, uint64_t &total_out) {
+// 2^32).  S.leaves holds the number of nonzero counts afterwards.  (bw, bm):
+// S.bw and S.bm, or global buffers of CAP entries each.
+template <typename Lds>
+__device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, Lds &S, uint32_t *bw, uint32_t *bm,
+                                 uint64_t &total_out) {
   constexpr int NT = kHuffThreads;
+  constexpr int CAP = Lds::kCap;
+  // the tally of small counts and the large counts are built and the large
+  // counts sorted in LDS: in (bw, bm) when those are in LDS, else in the
+  // list's arrays (unused until the list is built), then handed to (bw, bm)
+  constexpr bool kLdsB = Lds::kLdsB;
+  uint32_t *tw = kLdsB ? bw : S.aw;
+  uint32_t *tb = kLdsB ? bm : S.am;
   constexpr int kSmallPer = kHuffSmall / NT;
   constexpr int kLoads = kBins / 4 / NT;
   const int t = threadIdx.x;
@@ -2047,7 +2068,7 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
   // ---- tally of the final counts (left in hfinal by the entropy pass) ----
   if (ok) {
 #pragma unroll
-    for (int k = 0; k < kSmallPer; k++) S.bw[t * kSmallPer + k] = 0;
+    for (int k = 0; k < kSmallPer; k++) tw[t * kSmallPer + k] = 0;
     if (t == 0) {
       S.nbig = 0;
       S.leaves = 0;
@@ -2066,17 +2087,17 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
         if (!c) continue;
         leaves++;
         if (c < (uint32_t)kHuffSmall) {
-          atomicAdd(&S.bw[c], 1u);
+          atomicAdd(&tw[c], 1u);
         } else {
           const uint32_t i = atomicAdd(&S.nbig, 1u);
-          if (i < (uint32_t)kHuffCap) S.bm[i] = c;
+          if (i < (uint32_t)CAP) tb[i] = c;
         }
       }
     }
     leaves = group_isum<kWave>(leaves);
     if ((t & (kWave - 1)) == 0) atomicAdd(&S.leaves, leaves);
     __syncthreads();
-    ok = S.nbig <= (uint32_t)kHuffCap;
+    ok = S.nbig <= (uint32_t)CAP;
   }
 
   // ---- the initial list: runs of the small counts, then of the sorted large ones ----
@@ -2085,40 +2106,45 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
     const uint32_t nbig = S.nbig;
     uint32_t P = 1;
     while (P < nbig) P <<= 1;
-    for (uint32_t i = nbig + t; i < P; i += NT) S.bm[i] = 0xFFFFFFFFu;
+    for (uint32_t i = nbig + t; i < P; i += NT) tb[i] = 0xFFFFFFFFu;
     __syncthreads();
     for (uint32_t k = 2; k <= P; k <<= 1) {
       for (uint32_t j = k >> 1; j > 0; j >>= 1) {
         for (uint32_t i = t; i < P; i += NT) {
           const uint32_t l = i ^ j;
           if (l > i) {
-            const uint32_t x = S.bm[i], y = S.bm[l];
+            const uint32_t x = tb[i], y = tb[l];
             if ((i & k) == 0 ? x > y : x < y) {
-              S.bm[i] = y;
-              S.bm[l] = x;
+              tb[i] = y;
+              tb[l] = x;
             }
           }
         }
         __syncthreads();
       }
     }
+    if constexpr (!kLdsB) {  // hand the tally and the sorted large counts over
+      for (uint32_t i = t; i < (uint32_t)kHuffSmall; i += NT) bw[i] = tw[i];
+      for (uint32_t i = t; i < nbig; i += NT) bm[i] = tb[i];
+      __syncthreads();
+    }
     uint32_t mult[kSmallPer];
     uint32_t occ = 0;
 #pragma unroll
     for (int k = 0; k < kSmallPer; k++) {
-      mult[k] = S.bw[t * kSmallPer + k];
+      mult[k] = bw[t * kSmallPer + k];
       occ += mult[k] ? 1u : 0u;
     }
     const uint32_t bper = (nbig + NT - 1) / NT, b0 = t * bper;
     uint32_t starts = 0;
     for (uint32_t j = 0; j < bper; j++) {
       const uint32_t i = b0 + j;
-      if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) starts++;
+      if (i < nbig && (i == 0 || bm[i] != bm[i - 1])) starts++;
     }
     uint32_t po, ps, nsmall, nbruns;
     huff_scan2(occ, starts, S.slots[0], po, ps, nsmall, nbruns);
     n = nsmall + nbruns;
-    ok = n <= (uint32_t)kHuffCap;
+    ok = n <= (uint32_t)CAP;
     if (ok) {
       uint32_t pos = po;
 #pragma unroll
@@ -2131,8 +2157,8 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
       pos = nsmall + ps;
       for (uint32_t j = 0; j < bper; j++) {
         const uint32_t i = b0 + j;
-        if (i < nbig && (i == 0 || S.bm[i] != S.bm[i - 1])) {
-          S.aw[pos] = S.bm[i];
+        if (i < nbig && (i == 0 || bm[i] != bm[i - 1])) {
+          S.aw[pos] = bm[i];
           S.am[pos] = 0;
           pos++;
         }
@@ -2143,7 +2169,7 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
       for (uint32_t j = 0; j < bper; j++) {
         const uint32_t i = b0 + j;
         if (i < nbig) {
-          if (i == 0 || S.bm[i] != S.bm[i - 1]) c++;
+          if (i == 0 || bm[i] != bm[i - 1]) c++;
           atomicAdd(&S.am[nsmall + c - 1], 1u);
         }
       }
@@ -2156,9 +2182,9 @@ __device__ inline bool huff_cost(const uint32_t *hist, uint64_t nv, HuffLds &S, 
     uint32_t items = S.leaves;
     int rounds = 0;
     while (ok && items > (uint32_t)kWave) {
-      ok = huff_round(S, n, items, cost) && ++rounds <= kHuffMaxRounds;
+      ok = huff_round(S, bw, bm, n, items, cost) && ++rounds <= kHuffMaxRounds;
     }
-    if (ok && t < kWave) huff_tail(S, n, items, cost);
+    if (ok && t < kWave) huff_tail(S, bw, n, items, cost);
   }
 
   // ---- total ----
@@ -2179,7 +2205,7 @@ __device__ inline void huff_wg(const ReqDesc &r, HuffLds &S) {
   constexpr int BS = 1 << (2 * D);
   const uint64_t nv = (uint64_t)r.nblk * BS;
   uint64_t total;
-  const bool ok = huff_cost(r.hfinal, nv, S, total);
+  const bool ok = huff_cost(r.hfinal, nv, S, S.bw, S.bm, total);
   if (threadIdx.x != 0) return;
   ReqState *st = r.st;
   szsel_result *res = r.res;

@@ -126,18 +126,25 @@ def test_sz_compression_matches_oracle(ctx, case, eb):
 
 
 def test_sz_full_size_field(ctx):
-    """The 512^3 benchmark field: the round trip within the bound, the size
-    made of its parts, and a 16^3 corner's symbols and values against the
-    oracle on that corner (the corner's predictions only look backwards)."""
+    """The 512^3 benchmark field (2^27 values): the round trip within the
+    bound; the exact size always computed (no NO_HUFFMAN flag) and made of
+    its parts, its code bits equal to the oracle's heap-built optimal code
+    cost of the symbols' counts; and a 16^3 corner's symbols and values
+    against the oracle on that corner (the corner's predictions only look
+    backwards)."""
     field = synth.workload_turb512(device="cuda")
     vr = float(field.max() - field.min())
     for eb in (1e-2, 1e-4, 1e-6):
         gpu, syms, dec = ctx.sz_compress(field, eb * vr, symbols=True)
-        _note("turb512 sz step4 eb", eb, gpu["bitrate"], gpu["psnr"], gpu["flags"])
+        _note("turb512 sz step4 eb", eb, gpu["bitrate"], gpu["psnr"], gpu["flags"], gpu["symbols"])
         assert gpu["maxerr"] <= eb * vr
         assert (dec.double() - field.double()).abs().max().item() == gpu["maxerr"]
-        if not gpu["flags"]:
-            assert gpu["bits"] == gpu["code_bits"] + 32 * gpu["unpredictable"] + 32 * gpu["symbols"]
+        assert gpu["flags"] == 0
+        assert gpu["bits"] == gpu["code_bits"] + 32 * gpu["unpredictable"] + 32 * gpu["symbols"]
+        counts = torch.bincount(syms.reshape(-1).view(torch.int16).to(torch.int32) & 0xFFFF,
+                                minlength=65536).cpu().numpy()
+        assert int(counts.sum()) == field.numel() and int((counts > 0).sum()) == gpu["symbols"]
+        assert gpu["code_bits"] == oracle.huffman_bits(counts)
         # whole-field SSE: the adjacent-pair tree of the squared errors in
         # field order (2^27 values, no padding), on the host
         v = (dec.double() - field.double()).cpu().numpy().reshape(-1)
