@@ -85,11 +85,11 @@ __global__ __launch_bounds__(kThreads, (kSzWavesPerSimd<T, D>)) void kb_sz(const
 // then loops over them.  Requests without items in this pass (first[i + 1]
 // == first[i]) and skipped requests count 0.  s_pre[i] is request c0 + i's
 // first item, s_pre[c1 - c0] the total.
-template <typename F>
+template <int NT, typename F>
 __device__ inline uint32_t batch_device_items(const ReqDesc *tab, const uint32_t *first, int c0, int c1,
                                               uint32_t *s_pre, uint32_t *s_wave, F count) {
   const int n = c1 - c0, t = threadIdx.x;
-  constexpr int kPer = (kMaxBatch + kThreads - 1) / kThreads;  // requests per thread
+  constexpr int kPer = (kMaxBatch + NT - 1) / NT;  // requests per thread
   uint32_t cnt[kPer], sum = 0;
 #pragma unroll
   for (int k = 0; k < kPer; k++) {
@@ -118,7 +118,7 @@ __device__ inline uint32_t batch_device_items(const ReqDesc *tab, const uint32_t
     if (i <= n) s_pre[i] = base;
     base += cnt[k];
   }
-  if (t == kThreads - 1 && n == kMaxBatch) s_pre[n] = base;
+  if (t == NT - 1 && n == kMaxBatch) s_pre[n] = base;
   __syncthreads();
   return s_pre[n];
 }
@@ -135,11 +135,11 @@ __device__ inline int batch_owner(const uint32_t *s_pre, int n, uint32_t g) {
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void kb_ovf(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
+__global__ __launch_bounds__(kOvfThreads) void kb_ovf(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ uint32_t s_cnt[kOvfBins];
   __shared__ uint32_t s_pre[kMaxBatch + 1];
-  __shared__ uint32_t s_wave[kWaves];
-  const uint32_t items = batch_device_items(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
+  __shared__ uint32_t s_wave[kOvfThreads / kWave];
+  const uint32_t items = batch_device_items<kOvfThreads>(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
     return get_u32(&r.st->ovf_slices) * (uint32_t)kOvfRanges;
   });
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *__restrict__ t
   __shared__ TileLds L;
   __shared__ uint32_t s_pre[kMaxBatch + 1];
   __shared__ uint32_t s_wave[kWaves];
-  const uint32_t items = batch_device_items(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
+  const uint32_t items = batch_device_items<kThreads>(tab, first, c0, c1, s_pre, s_wave, [](const ReqDesc &r) {
     return (uint32_t)__popcll(ent_chunks(r));
   });
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
@@ -204,7 +204,7 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
         hipLaunchKernelGGL((kb_sz<T, D, false>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
     case kBatchOvf:
-      hipLaunchKernelGGL((kb_ovf<D>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
+      hipLaunchKernelGGL((kb_ovf<D>), grid, dim3(kOvfThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
     case kBatchEnt:
       hipLaunchKernelGGL((kb_ent<T, D>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);

@@ -31,6 +31,7 @@ constexpr int kEntWgs = 65536 / kEntChunk;
 constexpr int kOvfSlices = 64;         // overflow count: slices of the SZ workgroups ...
 constexpr int kOvfRanges = 4;          // ... times code ranges of 16384 bins
 constexpr int kOvfBins = kBins / kOvfRanges;
+constexpr int kOvfThreads = 1024;      // threads of an overflow-pass workgroup (its LDS counts are 64 KiB)
 constexpr int kHistCopies = 16;        // most global histogram copies (SZ workgroup w adds to copy w mod nhc)
 constexpr int kOvfPerSlice = 65536;    // overflow codes per slice of the overflow count (default)
 constexpr int kMaxBatch = 1024;        // requests per batch

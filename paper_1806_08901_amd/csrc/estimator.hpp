@@ -1575,8 +1575,8 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   const int w0 = (int)(((int64_t)r.nsz * p) / S);
   const int w1 = (int)(((int64_t)r.nsz * (p + 1)) / S);
   const int nreg = w1 - w0;
-  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) s_cnt[b] = 0;
-  for (int k = threadIdx.x; k < nreg; k += kThreads) s_n[k] = (uint32_t)get_u64(r.sp.b + w0 + k);
+  for (int b = threadIdx.x; b < kOvfBins; b += kOvfThreads) s_cnt[b] = 0;
+  for (int k = threadIdx.x; k < nreg; k += kOvfThreads) s_n[k] = (uint32_t)get_u64(r.sp.b + w0 + k);
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -1598,12 +1598,12 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
       if (e < valid && c >= 0 && c < kOvfBins) atomicAdd(&s_cnt[c], 1u);
     }
   };
-  for (uint32_t k0 = threadIdx.x; k0 < nv; k0 += 4 * kThreads) {
+  for (uint32_t k0 = threadIdx.x; k0 < nv; k0 += 4 * kOvfThreads) {
     uint4 v[4];
     int valid[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const uint32_t k = k0 + (uint32_t)u * kThreads;
+      const uint32_t k = k0 + (uint32_t)u * kOvfThreads;
       valid[u] = 0;
       v[u] = make_uint4(0, 0, 0, 0);
       if (k < nv) {
@@ -1622,7 +1622,7 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
   }
   __syncthreads();
   uint32_t *out = r.ovf_hist + lo;
-  for (int b = threadIdx.x; b < kOvfBins; b += kThreads) {
+  for (int b = threadIdx.x; b < kOvfBins; b += kOvfThreads) {
     const uint32_t v = s_cnt[b];
     if (v) atomicAdd(&out[b], v);
   }

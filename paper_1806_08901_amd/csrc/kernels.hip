@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kThreads, (kSzWavesPerSimd<T, D>)) void k_sz(ReqDes
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_ovf(ReqDesc r) {
+__global__ __launch_bounds__(kOvfThreads) void k_ovf(ReqDesc r) {
   __shared__ uint32_t s_cnt[kOvfBins];
   if (skip_request(r.st)) return;
   ovf_wg<D>(r, blockIdx.x, s_cnt);
@@ -93,7 +93,7 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
   }
   if ((e = mark(ev, 3, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
-    hipLaunchKernelGGL((k_ovf<D>), dim3(kOvfSlices * kOvfRanges), dim3(kThreads), 0, s, r);
+    hipLaunchKernelGGL((k_ovf<D>), dim3(kOvfSlices * kOvfRanges), dim3(kOvfThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
