@@ -458,6 +458,16 @@ def turb512_workload(args, torch, synth, szsel):
     ms_batch, med_batch = timer.run(lambda k: ctx.select_batch(None, reqs=reqs, sync=False, out=bouts[k % 4]),
                                     max(args.warmup, 8), args.steps)
     value_batch = len(ebs) * nbytes / (ms_batch * 1e-3) / 1e9
+    # HBM bytes one batch moves: the counters of its launches (one of each
+    # pass) from the committed summary, while it matches the sources
+    hbm_batch = None
+    per = [recorded_traffic("hbm_traffic_turb512.md", kernel_name(c)) for c in
+           ("range_f32", "zfp_f32", "sz_f32", "ovf_f32", "ent_f32")]
+    if all(b is not None for b in per):
+        gbs = sum(per) / (ms_batch * 1e-3) / 1e9
+        hbm_batch = {"bytes_per_step": int(sum(per)), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "what": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the batch's five launches (the field is read "
+                             "once) / the batch's GPU time"}
     lat = []
     for k in range(args.latency_calls):
         t = time.perf_counter()
@@ -482,6 +492,7 @@ def turb512_workload(args, torch, synth, szsel):
             "input_GBps": round(value_batch, 2), "ms_per_step": round(ms_batch, 4),
             "ms_per_step_median": round(med_batch, 4), "speedup_vs_plain": round(value_batch / value, 3),
             "results_equal_plain": batch_results == gpu_results,
+            "hbm_traffic": hbm_batch,
             "what": "the 5 requests as one szsel_select_batch: the field is scanned once for all five, "
                     "so input GB/s (5 x 512 MiB per step) counts that scan's bytes five times; it is "
                     "not a fraction of the HBM peak"},

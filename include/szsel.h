@@ -236,8 +236,9 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   of single-request calls and of batches without autotuning (and the
  *   autotuner's starting point): SZ workgroups in quarters of the CU
  *   count (1..256, default 8), smallest ZFP chunk in sampled blocks (a
- *   power of two 64..65536, default 64), range workgroups per CU (1..64,
- *   default 1); 0 restores the default.  Results do not depend on them.
+ *   power of two 64..65536, default 64), range workgroups (scan chunks of
+ *   a field) per CU (a multiple of 0.25 up to 64, default 1); 0 restores
+ *   the default.  Results do not depend on them.
  * SZSEL_OPT_BATCH_SHARE: how a batch applies the SZ and range counts above
  *   (0..2, default 0): 0 gives them to every request; 1 makes the SZ count
  *   the whole batch's, dealt to its requests in proportion to their sampled

@@ -91,7 +91,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       if (first_on_field) scan_bytes += (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0);
     }
     const double sz_want = std::max(1.0, (double)tu.sz_wgs_q * (double)ncu / 4.0);
-    const double range_want = std::max(1.0, (double)tu.range_wgs_per_cu * (double)ncu);
+    const double range_want = std::max(1.0, (double)tu.range_wgs_q * (double)ncu / 4.0);
     auto share = [](double want, double part, double whole) {
       return (int)std::max(1.0, std::min(1e9, std::round(want * part / whole)));
     };
@@ -389,7 +389,7 @@ template <typename F>
 void tune_fields(Tune &t, F f) {
   f("sz_wgs_q", t.sz_wgs_q);
   f("zfp_chunk", t.zfp_chunk);
-  f("range_wgs_per_cu", t.range_wgs_per_cu);
+  f("range_wgs_q", t.range_wgs_q);
   f("range_grid", t.range_grid);
   f("groups", t.groups);
   f("ovf_slice", t.ovf_slice);
@@ -437,7 +437,7 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     if (end == line.c_str() + a + pat.size() || x < 0 || x > (1l << 30)) ok = false;
     v = (int)x;
   });
-  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_per_cu >= 1 && t.range_grid >= 0 &&
+  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_q >= 1 && t.range_grid >= 0 &&
          t.ovf_slice >= 1 && t.share <= 2;
 }
 
@@ -722,7 +722,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     const int group_opts[] = {1, 2, 4, 8};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {64, 128, 256};
-    const int range_opts[] = {1, 2, 4, 8, 16};
+    const int range_opts[] = {1, 2, 4, 8, 16, 32, 64};  // quarters of the CU count
     const int grid_opts[] = {0, 1, 2, 4};
     const int ovf_opts[] = {kOvfPerSlice, 2 * kOvfPerSlice, 4 * kOvfPerSlice};
     // two sweeps of the coordinates: the best group count depends on how
@@ -774,9 +774,9 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       }
     }
     for (int v : range_opts) {
-      if (rc != SZSEL_OK || v == cur.range_wgs_per_cu) continue;
+      if (rc != SZSEL_OK || v == cur.range_wgs_q) continue;
       Tune c = cur;
-      c.range_wgs_per_cu = v;
+      c.range_wgs_q = v;
       float ms = 0.f;
       rc = time_of(c, ms);
       if (rc == SZSEL_OK && ms < best_ms) {

@@ -49,7 +49,7 @@ hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 struct Tune {
   int sz_wgs_q = 8;          // SZ workgroups per request, in quarters of the CU count
   int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
-  int range_wgs_per_cu = 1;  // range workgroups per CU for one request
+  int range_wgs_q = 4;       // range workgroups (scan chunks) per request, in quarters of the CU count
   int range_grid = 0;        // batches: 0 = one workgroup per range chunk; k > 0 = k workgroups
                              // per CU that loop over all the launch's chunks (a resident scan
                              // that leaves the other wave slots to the sampled passes)

@@ -208,10 +208,11 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // length a multiple of 16 bytes / element size (blocks start at x = 4 b s)
   r.vec = ((uintptr_t)field % 16 == 0 && (dims[nd - 1] * (int64_t)esz) % 16 == 0) ? 1 : 0;
   // range pass: contiguous chunks of whole 16-byte vectors, about
-  // range_wgs_per_cu workgroups per CU, at least 8 vectors per thread
+  // range_wgs_q quarters of the CU count of them, at least 8 vectors per thread
   const int64_t vn = 16 / (int64_t)esz;
   const int64_t quantum = (int64_t)kThreads * vn;
-  const int64_t rw = tu.range_target > 0 ? (int64_t)tu.range_target : (int64_t)tu.range_wgs_per_cu * ctx->ncu;
+  const int64_t rw = tu.range_target > 0 ? (int64_t)tu.range_target
+                                          : std::max<int64_t>(1, (int64_t)tu.range_wgs_q * ctx->ncu / 4);
   int64_t chunk = (n + rw - 1) / rw;
   chunk = std::max<int64_t>(chunk, 8 * quantum);
   chunk = (chunk + quantum - 1) / quantum * quantum;
@@ -552,20 +553,24 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
     c->bopt.fixed.groups = v ? v : Tune().groups;
     return SZSEL_OK;
   }
-  if (option == SZSEL_OPT_SZ_WGS || option == SZSEL_OPT_ZFP_CHUNK || option == SZSEL_OPT_RANGE_WGS) {
+  if (option == SZSEL_OPT_RANGE_WGS) {
+    const double q = value * 4.0;
+    if (!(q >= 0.0) || q != std::floor(q) || q > 256.0)
+      return fail(c, SZSEL_EINVAL, "range workgroups per CU: a multiple of 0.25, at most 64");
+    c->bopt.fixed.range_wgs_q = q > 0.0 ? (int)q : Tune().range_wgs_q;
+    return SZSEL_OK;
+  }
+  if (option == SZSEL_OPT_SZ_WGS || option == SZSEL_OPT_ZFP_CHUNK) {
     const Tune dflt;
     const int v = (int)value;
     if (value != (double)v || v < 0) return fail(c, SZSEL_EINVAL, "launch-shape values are non-negative integers");
     if (option == SZSEL_OPT_SZ_WGS) {
       if (v > 256) return fail(c, SZSEL_EINVAL, "SZ workgroups: at most 256 quarters of the CU count");
       c->bopt.fixed.sz_wgs_q = v ? v : dflt.sz_wgs_q;
-    } else if (option == SZSEL_OPT_ZFP_CHUNK) {
+    } else {
       if (v && (v < 64 || v > 65536 || (v & (v - 1))))
         return fail(c, SZSEL_EINVAL, "ZFP chunk: a power of two from 64 to 65536");
       c->bopt.fixed.zfp_chunk = v ? v : dflt.zfp_chunk;
-    } else {
-      if (v > 64) return fail(c, SZSEL_EINVAL, "range workgroups: at most 64 per CU");
-      c->bopt.fixed.range_wgs_per_cu = v ? v : dflt.range_wgs_per_cu;
     }
     return SZSEL_OK;
   }
