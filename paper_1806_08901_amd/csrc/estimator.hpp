@@ -1234,10 +1234,14 @@ __device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
 #pragma unroll
     for (int yi = 0; yi < Lay::NY; yi++) {
       const int dz = zi - (Lay::NZ - 1), dy = D == 1 ? 0 : yi - 1;
-      const bool ok = in && (dz == 0 || zprev) && (dy >= 0 || yprev);
+      const bool own_row = dz == 0 && dy >= 0;  // inside block j (block 0 when !in)
+      const bool ok = in && (own_row || ((dz == 0 || zprev) && (dy >= 0 || yprev)));
       keep |= ok ? (1u << (zi * Lay::NY + yi)) : 0u;
-      // a missing row is read from the lane's own row and zeroed later
-      load_row<T, VEC>(ok ? row + dz * sz + dy * sy : row, s.v[zi][yi], left);
+      // a missing neighbour row is read from the lane's own row and zeroed
+      // later; own rows are read from their address unconditionally (were
+      // they selected by `in`, the compiler could copy one row's values into
+      // another behind a branch, which waits for the loads at once)
+      load_row<T, VEC>(own_row || ok ? row + dz * sz + dy * sy : row, s.v[zi][yi], left);
     }
   }
   s.keep = keep;
@@ -1282,60 +1286,29 @@ __device__ inline double lorenzo_row(const Rows<T, D> &s, int dy, int xi) {
   }
 }
 
-// Quantization code of one point (0 = unpredictable), its squared error and
-// absolute error.  Round half away from zero; the point is unpredictable when
-// |q| >= 32768 or when the reconstruction, rounded to the field precision,
-// misses the bound delta/2.
+// Quantization code of one point (0 = unpredictable) and its error (0 for an
+// unpredictable point).  Round half away from zero; the point is
+// unpredictable when |q| >= 32768 or when the reconstruction, rounded to the
+// field precision, misses the bound delta/2.
 template <typename T>
-__device__ inline int quantize(T xv, double pred, double delta, double inv, double ebsz,
-                               double &e2, double &ae, bool active = true) {
+__device__ inline int quantize(T xv, double pred, double delta, double inv, double ebsz, double &e,
+                               bool active = true) {
   // branch-free: every lane computes the reconstruction and the tests only
-  // select the results (a code out of range computes with q = 0)
+  // select the results.  |q| = floor(t) carries the sign of d as a double
+  // (exact: |q| <= 32768), so the reconstruction needs no integer round
+  // trip; a t out of range (or NaN) computes with |q| = 32768 and is
+  // rejected by `in`.  A q of -0 where the code is 0 changes at most the
+  // sign of a zero error.
   const double xd = (double)xv;
   const double d = xd - pred;
   const double t = fabs(d) * inv + 0.5;
   const bool in = t < (double)kRadius;
-  int q = (int)floor(in ? t : 0.0);
-  if (d < 0.0) q = -q;
-  const T recon = (T)(pred + (double)q * delta);
-  const double e = xd - (double)recon;
-  const bool ok = active && in && fabs(e) <= ebsz;  // (an inactive lane counts nothing)
-  e2 = ok ? e * e : 0.0;
-  ae = ok ? fabs(e) : 0.0;
-  return ok ? q + kRadius : 0;
-}
-
-// Adds one to the histogram bin of `code` for every lane with `want`.  The
-// wave first counts the lanes that share the first wanting lane's code and
-// adds them with one atomic (most codes of a smooth field are equal), then
-// the remaining lanes add individually.  Bins near the zero code live in the
-// LDS window s_hist.  Codes outside it (wide histograms at tight bounds) are
-// appended to the workgroup's own overflow region (`region`, counter *s_n in
-// LDS) and counted by the overflow pass.
-__device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t *region,
-                                uint32_t *s_n) {
-  const int wi = code - kHistLo;
-  const bool inwin = want && wi >= 0 && wi < kHistWin;
-  const bool outwin = want && !inwin;
-  const uint64_t todo = __ballot(inwin);
-  const int lane = threadIdx.x & (kWave - 1);
-  if (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int lc = __builtin_amdgcn_readlane(code, leader);
-    const uint64_t same = __ballot(inwin && code == lc);
-    if (lane == leader)
-      atomicAdd(&s_hist[lc - kHistLo], (uint32_t)__popcll(same));
-    else if (inwin && code != lc)
-      atomicAdd(&s_hist[wi], 1u);
-  }
-  const uint64_t ovf = __ballot(outwin);
-  if (ovf) {
-    const int leader = __ffsll((long long)ovf) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(s_n, (uint32_t)__popcll(ovf));
-    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-    if (outwin) region[base + (uint32_t)__popcll(ovf & ((1ull << lane) - 1ull))] = (uint16_t)code;
-  }
+  const double q = copysign(floor(fmin(t, (double)kRadius)), d);
+  const T recon = (T)(pred + q * delta);
+  const double err = xd - (double)recon;
+  const bool ok = active && in && fabs(err) <= ebsz;  // (an inactive lane counts nothing)
+  e = ok ? err : 0.0;
+  return ok ? (int)q + kRadius : 0;
 }
 
 // Histogram update for the N codes of a lane (code 0 = unpredictable, not
@@ -1343,10 +1316,12 @@ __device__ inline void hist_add(bool want, int code, uint32_t *s_hist, uint16_t 
 // case on smooth data) one atomic adds N, else one atomic per code; the LDS
 // serialises lanes that hit one bin, off the vector pipeline.  Codes outside
 // the window are appended to the workgroup's overflow region, numbered by
-// one LDS atomic per wave (the wave's first such lane reserves room for all).
+// one LDS atomic per wave (the wave's first such lane reserves room for all),
+// and their 1024-bin chunks are added to `chunks` (those of window codes are
+// taken from the window at the hand-over).
 template <int N>
 __device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_hist, uint16_t *region,
-                                uint32_t *s_n) {
+                                uint32_t *s_n, uint64_t &chunks) {
   bool out[N];
   bool anyout = false;
   bool same = true;
@@ -1385,7 +1360,10 @@ __device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_h
     base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + inc - mine;
 #pragma unroll
     for (int k = 0; k < N; k++)
-      if (out[k]) region[base++] = (uint16_t)code[k];
+      if (out[k]) {
+        region[base++] = (uint16_t)code[k];
+        chunks |= 1ull << (code[k] >> 10);
+      }
   }
 }
 
@@ -1403,24 +1381,23 @@ __device__ inline void sz_round(const ReqDesc &r, Rows<T, D> &sc, int64_t j, int
   // the points' predictions and codes first (independent chains the
   // compiler can interleave), then their histogram updates; a lane past the
   // last block gets code 0 and no error
-  double e2[NP], ae[NP];
+  double e2[NP];
   int code[NP];
 #pragma unroll
   for (int dy = 0; dy < R; dy++) {
 #pragma unroll
     for (int xi = 0; xi < 4; xi++) {
       const int k = 4 * dy + xi;
+      double e;
       code[k] = quantize<T>(sc.v[Lay::NZ - 1][Rows<T, D>::own(dy)][xi + 1], lorenzo_row<T, D>(sc, dy, xi),
-                            delta, inv, ebsz, e2[k], ae[k], active);
+                            delta, inv, ebsz, e, active);
+      acc.maxerr = fmax(acc.maxerr, fabs(e));
+      e2[k] = e * e;
     }
   }
-  hist_add<NP>(code, active, s_hist, region, s_n);
-#pragma unroll
-  for (int k = 0; k < NP; k++) {
-    acc.a += code[k] == 0 && active ? 1u : 0u;
-    acc.maxerr = fmax(acc.maxerr, ae[k]);
-    acc.chunks |= 1ull << (code[k] >> 10);
-  }
+  // (unpredictable points are counted at the hand-over, as the points no
+  // bin received)
+  hist_add<NP>(code, active, s_hist, region, s_n, acc.chunks);
   if (r.dbg_codes && active) {
 #pragma unroll
     for (int k = 0; k < NP; k++) r.dbg_codes[j * BS + q * NP + k] = (uint16_t)code[k];
@@ -1488,9 +1465,12 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
 // workgroup's overflow region (each thread expands 16 consecutive bins at
 // the offset an exclusive scan of the bin counts gives it), and the
 // overflow pass counts them in LDS.  `points` is the workgroup's number of
-// sampled points; the region holds that many codes.
-__device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *region, uint32_t *s_n,
-                                      uint32_t points, TileLds &L) {
+// sampled points; the region holds that many codes.  Adds the 1024-bin
+// chunks of the window's nonzero bins to `chunks` and returns, in every
+// thread, the number of codes the workgroup counted (window bins plus the
+// codes already in the region), i.e. its predictable points.
+__device__ inline uint32_t hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *region, uint32_t *s_n,
+                                          uint32_t points, uint64_t &chunks) {
   constexpr int kPer = kHistWin / kThreads;  // 16 bins per thread
   __shared__ uint32_t s_distinct, s_wave[kWaves];
   const int t = threadIdx.x;
@@ -1504,6 +1484,7 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
     nz += v ? 1u : 0u;
     sum += v;
   }
+  if (nz) chunks |= 1ull << ((kHistLo + t * kPer) >> 10);
   const uint32_t wnz = group_isum<kWave>(nz);
   // inclusive scan of the per-thread sums within the wave (Hillis-Steele)
   uint32_t inc = sum;
@@ -1516,11 +1497,14 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
   if (lane == kWave - 1) s_wave[wv] = inc;
   if (t == 0) s_distinct = 0;
   __syncthreads();
+  uint32_t counted = *s_n;
+#pragma unroll
+  for (int q = 0; q < kWaves; q++) counted += s_wave[q];
   if (lane == 0) atomicAdd(&s_distinct, wnz);
   __syncthreads();
   if (s_distinct * 4u <= points) {
     hist_flush(s_hist, g);
-    return;
+    return counted;
   }
   uint32_t base = *s_n + inc - sum;
   for (int q = 0; q < wv; q++) base += s_wave[q];
@@ -1534,7 +1518,7 @@ __device__ inline void hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *r
   __syncthreads();
   if (t == kThreads - 1) *s_n = base;
   __syncthreads();
-  (void)L;
+  return counted;
 }
 
 // SZ totals of the request (last SZ workgroup): squared-error tree over the
@@ -2258,9 +2242,10 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
       wg_acc_push(L, 0.0);
   }
   __syncthreads();
-  const int64_t nb = min<int64_t>((int64_t)r.sblk, r.nblk - (int64_t)w * r.sblk);
-  hist_hand_over(s_hist, r.hist + (size_t)(w & (r.nhc - 1)) * kBins, region, &s_n,
-                 (uint32_t)(nb * BS), L);
+  const int64_t nb = max<int64_t>(0, min<int64_t>((int64_t)r.sblk, r.nblk - (int64_t)w * r.sblk));
+  const uint32_t points = (uint32_t)(nb * BS);
+  const uint32_t counted =
+      hist_hand_over(s_hist, r.hist + (size_t)(w & (r.nhc - 1)) * kBins, region, &s_n, points, acc.chunks);
   __syncthreads();
   // the chunks the codes fell in, for the entropy pass to skip empty ones:
   // one OR per wave, only when it adds a bit (most waves add none)
@@ -2269,7 +2254,10 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   for (int d = 1; d < kWave; d <<= 1) ch |= __shfl_xor(ch, d);
   if ((threadIdx.x & (kWave - 1)) == 0 && (ch & ~get_u64(&r.st->code_chunks)))
     __hip_atomic_fetch_or(&r.st->code_chunks, ch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (threadIdx.x == 0) acc.b = s_n;  // overflow codes of this workgroup (summed below)
+  if (threadIdx.x == 0) {
+    acc.a = points - counted;  // unpredictable points of this workgroup
+    acc.b = s_n;               // overflow codes of this workgroup (summed below)
+  }
   wg_acc_store(L, acc, r.sp, w);
   Part tot;
   if (!pass_complete<false>(r.sp, r.grp[kPassSz], r.sync + kPassSz, w, r.nsz, L, tot)) return false;
