@@ -236,16 +236,23 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   of single-request calls and of batches without autotuning (and the
  *   autotuner's starting point): SZ workgroups in quarters of the CU
  *   count (1..256, default 8), smallest ZFP chunk in sampled blocks (a
- *   power of two 64..65536, default 64), range workgroups (scan chunks of
+ *   power of two 16..65536, default 16; 3-D blocks without point
+ *   sub-sampling take chunks from 16, other blocks from 64; above it the
+ *   chunk aims at 64 one-wave ZFP workgroups per CU), range
+ *   workgroups (scan chunks of
  *   a field) per CU (a multiple of 0.25 up to 64, default 1); 0 restores
  *   the default.  Results do not depend on them.
  * SZSEL_OPT_BATCH_SHARE: how a batch applies the SZ and range counts above
- *   (0..2, default 0): 0 gives them to every request; 1 makes the SZ count
+ *   (0..3, default 0): 0 gives them to every request; 1 makes the SZ count
  *   the whole batch's, dealt to its requests in proportion to their sampled
  *   blocks; 2 does that and deals the range count of the batch in
  *   proportion to the bytes of the fields (a field scanned once for all its
- *   requests counts once).  Many small fields favour 1 or 2, mixes of large
- *   and small ones 0; the autotuner tries all three.
+ *   requests counts once); 3 deals the SZ count as 1 does, but within each
+ *   class of requests that share a launch (dtype, rank, alignment and point
+ *   sub-sampling), each class getting the whole count.  Modes 1 to 3 also
+ *   deal the ZFP waves within each class instead of aiming at them per
+ *   request.  Many small fields favour 1 to 3, mixes of large and small
+ *   ones 0; the autotuner tries all four.
  * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
  *   default 1; 0 restores it): the requests are dealt to that many groups
  *   (requests on one field stay together); the groups' range scans run one

@@ -81,17 +81,28 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
   // their fields (a field scanned once for all its requests counts once),
   // so that the small fields of a large batch get a few long-running
   // workgroups instead of many whose time goes to their set-up, the SZ LDS
-  // histogram's clearing and hand-over and the completion counters
+  // histogram's clearing and hand-over and the completion counters.  With
+  // tu.share == 3 the SZ count is dealt within each launch class (dtype,
+  // rank, alignment, point sub-sampling) instead: the classes run as
+  // launches of their own, one after another, and each should fill the
+  // chip (a small binary64 class dealt its share of the whole batch's count
+  // runs on a few long workgroups).  The ZFP waves (kZfpWavesPerCu per CU)
+  // are always dealt within each launch class.
   if (n > 1 && tu.share > 0) {
-    double sz_blocks = 0.0, scan_bytes = 0.0;
+    auto cls = [&](int i) { return (d[i].dtype * 8 + d[i].nd) * 4 + (d[i].vec ? 2 : 0) + (d[i].ec ? 1 : 0); };
+    auto sz_class = [&](int i) { return tu.share == 3 ? cls(i) : 0; };
+    std::map<int, double> sz_blocks, zfp_blocks;
+    double scan_bytes = 0.0;
     for (int i = 0; i < n; i++) {
-      if (d[i].op != SZSEL_OP_ZFP) sz_blocks += (double)d[i].nblk;
+      if (d[i].op != SZSEL_OP_ZFP) sz_blocks[sz_class(i)] += (double)d[i].nblk;
+      if (d[i].op != SZSEL_OP_SZ) zfp_blocks[cls(i)] += (double)d[i].nblk;
       bool first_on_field = true;
       for (int j = 0; j < i && first_on_field; j++) first_on_field = !same_field(d[i], d[j]);
       if (first_on_field) scan_bytes += (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0);
     }
     const double sz_want = std::max(1.0, (double)tu.sz_wgs_q * (double)ncu / 4.0);
     const double range_want = std::max(1.0, (double)tu.range_wgs_q * (double)ncu / 4.0);
+    const double zfp_want = (double)kZfpWavesPerCu * (double)ncu;
     auto share = [](double want, double part, double whole) {
       return (int)std::max(1.0, std::min(1e9, std::round(want * part / whole)));
     };
@@ -100,9 +111,10 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       int32_t st[3];
       for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
       Tune t = tu;
-      if (d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sz_blocks > 0.0)
-        t.sz_target = share(sz_want, (double)d[i].nblk, sz_blocks);
-      if (tu.share >= 2 && scan_bytes > 0.0)
+      const double sb = sz_blocks[sz_class(i)], zb = zfp_blocks[cls(i)];
+      if (d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sb > 0.0) t.sz_target = share(sz_want, (double)d[i].nblk, sb);
+      if (d[i].op != SZSEL_OP_SZ && d[i].nblk > 0 && zb > 0.0) t.zfp_target = share(zfp_want, (double)d[i].nblk, zb);
+      if (tu.share == 2 && scan_bytes > 0.0)
         t.range_target = share(range_want, (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0), scan_bytes);
       const int rc = plan_request(ctx, q.op, q.field, q.dims, q.ndims, q.dtype, q.eb, q.eb_mode, st, t, d[i]);
       if (rc != SZSEL_OK) {
@@ -438,7 +450,7 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     v = (int)x;
   });
   return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_q >= 1 && t.range_grid >= 0 &&
-         t.ovf_slice >= 1 && t.share <= 2;
+         t.ovf_slice >= 1 && t.share <= 3;
 }
 
 // Reads the cache file once per process (the tuner's lock held).
@@ -718,10 +730,10 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     Tune cur = opt.fixed;
     float best_ms = 0.f;
     int rc = time_of(cur, best_ms);
-    const int share_opts[] = {0, 1, 2};
+    const int share_opts[] = {0, 1, 2, 3};
     const int group_opts[] = {1, 2, 4, 8};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
-    const int zfp_opts[] = {64, 128, 256};
+    const int zfp_opts[] = {16, 32, 64, 128, 256};
     const int range_opts[] = {1, 2, 4, 8, 16, 32, 64};  // quarters of the CU count
     const int grid_opts[] = {0, 1, 2, 4};
     const int ovf_opts[] = {kOvfPerSlice, 2 * kOvfPerSlice, 4 * kOvfPerSlice};

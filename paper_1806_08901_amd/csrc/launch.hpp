@@ -48,7 +48,8 @@ hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 // overheads, which the batch autotuner measures.
 struct Tune {
   int sz_wgs_q = 8;          // SZ workgroups per request, in quarters of the CU count
-  int zfp_chunk = 64;        // smallest ZFP chunk (sampled blocks per one-wave workgroup)
+  int zfp_chunk = 16;        // smallest ZFP chunk (sampled blocks per one-wave workgroup;
+                             // layouts of one block per lane take at least 64)
   int range_wgs_q = 4;       // range workgroups (scan chunks) per request, in quarters of the CU count
   int range_grid = 0;        // batches: 0 = one workgroup per range chunk; k > 0 = k workgroups
                              // per CU that loop over all the launch's chunks (a resident scan
@@ -56,11 +57,21 @@ struct Tune {
   int groups = 1;            // batches: request groups pipelined on parallel streams
   int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
-                             // count is the batch's, 2 = both are the batch's
+                             // count is the batch's, 2 = both are the batch's, 3 = the SZ
+                             // count is each launch class's (1 to 3 also deal the ZFP
+                             // waves within each launch class)
   // set by the batch planner for one request from the batch's counts above
-  // (never tuned or cached): nonzero = SZ workgroups, range workgroups aimed at
+  // (never tuned or cached): nonzero = SZ workgroups, range workgroups, ZFP
+  // waves aimed at
   int sz_target = 0;
   int range_target = 0;
+  int zfp_target = 0;
 };
+
+// ZFP waves aimed at per CU for one request (single calls) or one launch
+// class of a batch: about 16 per SIMD, several rounds of the resident waves,
+// so that the last round's tail is short while each wave still does a few
+// rounds of blocks.
+constexpr int kZfpWavesPerCu = 64;
 
 }  // namespace szsel

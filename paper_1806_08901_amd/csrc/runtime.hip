@@ -181,8 +181,10 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   }
   // ZFP and SZ passes: every workgroup owns an aligned power-of-two chunk of
   // consecutive sampled blocks, and a pass has at most kMaxParts workgroups.
-  // ZFP: one wave per workgroup and one block per lane, chunks of 64 blocks
-  // (the most waves).  SZ: at least one round of 4 waves.
+  // ZFP: one wave per workgroup, rounds of 64 blocks (one block per lane)
+  // or, for 3-D blocks without sub-sampling, of 16 (four lanes per block),
+  // about kZfpWavesPerCu waves per CU (or the batch planner's share of
+  // them).  SZ: at least one round of 4 waves.
   auto chunk_for = [&](uint64_t min_chunk, uint64_t target_wgs, uint64_t max_wgs) {
     const uint64_t want = (nblk + target_wgs - 1) / target_wgs;
     uint64_t c = min_chunk;
@@ -190,7 +192,10 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
     while ((nblk + c - 1) / c > max_wgs) c <<= 1;
     return c;
   };
-  const uint64_t zc = chunk_for((uint64_t)tu.zfp_chunk, nblk / kWave + 1, kMaxParts);
+  const uint64_t zround = (nd == 3 && !r.ec) ? (uint64_t)(kWave / 4) : (uint64_t)kWave;
+  const uint64_t zfp_target = tu.zfp_target > 0 ? (uint64_t)tu.zfp_target
+                                                 : (uint64_t)kZfpWavesPerCu * (uint64_t)ctx->ncu;
+  const uint64_t zc = chunk_for(std::max<uint64_t>((uint64_t)tu.zfp_chunk, zround), zfp_target, kMaxParts);
   // SZ: one lane per two rows of 4 points (one row in 1-D); by
   // default 2 workgroups per CU, all of them resident at once
   const uint64_t sz_target = tu.sz_target > 0 ? (uint64_t)tu.sz_target
@@ -537,7 +542,7 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
   }
   if (option == SZSEL_OPT_BATCH_SHARE) {
     const int v = (int)value;
-    if (value != (double)v || v < 0 || v > 2) return fail(c, SZSEL_EINVAL, "batch share: 0, 1 or 2");
+    if (value != (double)v || v < 0 || v > 3) return fail(c, SZSEL_EINVAL, "batch share: 0, 1, 2 or 3");
     c->bopt.fixed.share = v;
     return SZSEL_OK;
   }
@@ -568,8 +573,8 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
       if (v > 256) return fail(c, SZSEL_EINVAL, "SZ workgroups: at most 256 quarters of the CU count");
       c->bopt.fixed.sz_wgs_q = v ? v : dflt.sz_wgs_q;
     } else {
-      if (v && (v < 64 || v > 65536 || (v & (v - 1))))
-        return fail(c, SZSEL_EINVAL, "ZFP chunk: a power of two from 64 to 65536");
+      if (v && (v < 16 || v > 65536 || (v & (v - 1))))
+        return fail(c, SZSEL_EINVAL, "ZFP chunk: a power of two from 16 to 65536");
       c->bopt.fixed.zfp_chunk = v ? v : dflt.zfp_chunk;
     }
     return SZSEL_OK;

@@ -176,22 +176,50 @@ def test_rotating_result_buffers(ctx):
 
 def test_workgroup_share_modes_equal_single_calls(ctx):
     """Fixed schedules that deal the SZ count, or the SZ and range counts,
-    over the batch give the single calls' results; a mode outside 0..2 is
-    rejected."""
+    over the batch or within each launch class give the single calls'
+    results; a mode outside 0..3 is rejected."""
     from paper_1806_08901_amd import szsel
     items = _items(_fields(), ebs=(1e-3, 1e-5))
     singles = _singles(ctx, items)
     try:
-        for mode in (1, 2, 0):
+        for mode in (1, 2, 3, 0):
             ctx.set_option(szsel.OPT_BATCH_SHARE, mode)
             for groups in (1, 2):
                 ctx.set_option(szsel.OPT_BATCH_GROUPS, groups)
                 assert ctx.select_batch(items) == singles, "share %d groups %d" % (mode, groups)
         with pytest.raises(szsel.SzselError):
-            ctx.set_option(szsel.OPT_BATCH_SHARE, 3)
+            ctx.set_option(szsel.OPT_BATCH_SHARE, 4)
     finally:
         ctx.set_option(szsel.OPT_BATCH_SHARE, 0)
         ctx.set_option(szsel.OPT_BATCH_GROUPS, 0)
+
+
+def test_launch_shapes_equal_default(ctx):
+    """Single calls and batches under other launch shapes (ZFP chunks from
+    one 16-block round per wave to 1,024 blocks, SZ workgroups from a
+    quarter of the CU count to 64 per CU, range chunks from a quarter to 8
+    per CU) give the default schedule's results, 3-D fields large enough
+    for several levels of completion counters included; ZFP chunks that are
+    not a power of two from 16 to 65536 are rejected."""
+    from paper_1806_08901_amd import szsel
+    big = [synth.spectral((96, 96, 100), slope=-3.0, seed=161).cuda(),
+           synth.spectral((64, 72, 64), slope=-2.0, seed=162, dtype=torch.float64).cuda()]
+    items = _items(_fields() + big, ebs=(1e-3, 1e-6))
+    singles = _singles(ctx, items)
+    try:
+        for zc, sw, rw in ((16, 1, 0.25), (32, 256, 8), (1024, 3, 2)):
+            _note("launch shape zfp_chunk", zc, "sz_wgs_q", sw, "range_wgs", rw)
+            ctx.set_option(szsel.OPT_ZFP_CHUNK, zc)
+            ctx.set_option(szsel.OPT_SZ_WGS, sw)
+            ctx.set_option(szsel.OPT_RANGE_WGS, rw)
+            assert _singles(ctx, items) == singles, "single calls, zfp chunk %d" % zc
+            assert ctx.select_batch(items) == singles, "batch, zfp chunk %d" % zc
+        for bad in (8, 48, 131072):
+            with pytest.raises(szsel.SzselError):
+                ctx.set_option(szsel.OPT_ZFP_CHUNK, bad)
+    finally:
+        for opt in (szsel.OPT_ZFP_CHUNK, szsel.OPT_SZ_WGS, szsel.OPT_RANGE_WGS):
+            ctx.set_option(opt, 0)
 
 
 def test_batches_in_flight_on_two_streams(ctx):
