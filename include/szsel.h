@@ -249,9 +249,9 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   proportion to the bytes of the fields (a field scanned once for all its
  *   requests counts once); 3 deals the SZ count as 1 does, but within each
  *   class of requests that share a launch (dtype, rank, alignment and point
- *   sub-sampling), each class getting the whole count.  Modes 1 to 3 also
- *   deal the ZFP waves within each class instead of aiming at them per
- *   request.  Many small fields favour 1 to 3, mixes of large and small
+ *   sub-sampling), each class getting the whole count.  In every mode a
+ *   batch deals the ZFP waves within each class instead of aiming at them
+ *   per request.  Many small fields favour 1 to 3, mixes of large and small
  *   ones 0; the autotuner tries all four.
  * SZSEL_OPT_BATCH_GROUPS: request groups of the batch schedule (1..8,
  *   default 1; 0 restores it): the requests are dealt to that many groups

@@ -75,7 +75,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       return rc;
     }
   }
-  // Workgroup counts (tu.share >= 1): the schedule's SZ count is the
+  // Workgroup counts.  tu.share >= 1: the schedule's SZ count is the
   // batch's, dealt to the requests in proportion to their sampled blocks,
   // and (tu.share == 2) its range count too, in proportion to the bytes of
   // their fields (a field scanned once for all its requests counts once),
@@ -87,8 +87,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
   // launches of their own, one after another, and each should fill the
   // chip (a small binary64 class dealt its share of the whole batch's count
   // runs on a few long workgroups).  The ZFP waves (kZfpWavesPerCu per CU)
-  // are always dealt within each launch class.
-  if (n > 1 && tu.share > 0) {
+  // are dealt within each launch class in every mode.
+  if (n > 1) {
     auto cls = [&](int i) { return (d[i].dtype * 8 + d[i].nd) * 4 + (d[i].vec ? 2 : 0) + (d[i].ec ? 1 : 0); };
     auto sz_class = [&](int i) { return tu.share == 3 ? cls(i) : 0; };
     std::map<int, double> sz_blocks, zfp_blocks;
@@ -112,7 +112,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       for (int k = 0; k < 3; k++) st[k] = q.stride[k] > 0 ? q.stride[k] : 1;
       Tune t = tu;
       const double sb = sz_blocks[sz_class(i)], zb = zfp_blocks[cls(i)];
-      if (d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sb > 0.0) t.sz_target = share(sz_want, (double)d[i].nblk, sb);
+      if (tu.share > 0 && d[i].op != SZSEL_OP_ZFP && d[i].nblk > 0 && sb > 0.0)
+        t.sz_target = share(sz_want, (double)d[i].nblk, sb);
       if (d[i].op != SZSEL_OP_SZ && d[i].nblk > 0 && zb > 0.0) t.zfp_target = share(zfp_want, (double)d[i].nblk, zb);
       if (tu.share == 2 && scan_bytes > 0.0)
         t.range_target = share(range_want, (double)d[i].n * (d[i].dtype == SZSEL_F32 ? 4.0 : 8.0), scan_bytes);

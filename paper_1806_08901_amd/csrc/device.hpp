@@ -47,6 +47,34 @@ constexpr int kHuffMaxRounds = 256;    // bound on the merge rounds (about 2 log
 constexpr uint32_t kSkipFlags = SZSEL_FLAG_CONSTANT | SZSEL_FLAG_NONFINITE |
                                 SZSEL_FLAG_NO_BLOCKS | SZSEL_FLAG_BAD_EB;
 
+// A pointer into global memory.  The batched kernels read their buffers'
+// addresses from the request table in memory, so the compiler cannot tell
+// their address space and emits flat memory instructions; a flat access
+// counts against the LDS counter as well, so every wait for an LDS result
+// (the SZ histogram's atomics, a barrier) would also wait for the row loads
+// prefetched for the next round.  Every buffer the kernels touch is device
+// memory, so the hot paths read and write it through pointers typed as
+// global, which lets the compiler use global loads and stores.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T> *to_global(T *p) {
+  return (global_t<T> *)p;
+}
+
+// 16-byte vector load from / zero store to global memory at a 16-byte
+// aligned address.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <typename P>
+__device__ __forceinline__ uint4 load_u4(const global_t<P> *p) {
+  const u32x4 v = *(const global_t<u32x4> *)p;
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+template <typename P>
+__device__ __forceinline__ void zero_u4(global_t<P> *p) {
+  *(global_t<u32x4> *)p = u32x4{0u, 0u, 0u, 0u};
+}
+
 // ---------------------------------------------------------------------------
 // Cross-workgroup communication.  MI355X has 8 XCDs whose L2 caches are not
 // coherent with each other; an agent-scope fence makes the whole L2 write

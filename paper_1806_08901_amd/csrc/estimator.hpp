@@ -171,7 +171,7 @@ struct RangeAcc {
 // Scans values [beg, end) with the threads of one workgroup: 16-byte
 // non-temporal loads, 8 per thread in flight, unaligned head/tail singly.
 template <typename T>
-__device__ inline void range_scan(const T *x, int64_t beg, int64_t end, RangeAcc<T> &acc) {
+__device__ inline void range_scan(const global_t<T> *x, int64_t beg, int64_t end, RangeAcc<T> &acc) {
   using V = typename Vec16<T>::V;
   constexpr int VN = Vec16<T>::N;
   constexpr int U = 8;
@@ -180,12 +180,15 @@ __device__ inline void range_scan(const T *x, int64_t beg, int64_t end, RangeAcc
   int64_t head = (int64_t)(((16 - (a & 15)) & 15) / sizeof(T));
   if (head > end - beg) head = end - beg;
   const int64_t nvec = (end - beg - head) / VN;
-  const V *xv = (const V *)(x + beg + head);
+  const global_t<V> *xv = (const global_t<V> *)(x + beg + head);
   int64_t i = lane;
   for (; i + (U - 1) * kThreads < nvec; i += U * kThreads) {
     V v[U];
 #pragma unroll
     for (int k = 0; k < U; k++) v[k] = __builtin_nontemporal_load(xv + i + k * kThreads);
+    // all U loads are issued before the first is used (the scheduler would
+    // otherwise interleave them with the reductions and keep fewer in flight)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < U; k++) {
 #pragma unroll
@@ -285,7 +288,7 @@ __device__ inline void range_wg(const ReqDesc &r, int w, TileLds &L) {
   RangeAcc<T> acc;
   const int64_t beg = (int64_t)w * r.rchunk;
   const int64_t end = min(r.n, beg + r.rchunk);
-  if (beg < end) range_scan<T>((const T *)r.field, beg, end, acc);
+  if (beg < end) range_scan<T>(to_global((const T *)r.field), beg, end, acc);
   double lo, hi;
   uint32_t amax;
   range_reduce_wg<T>(acc, lo, hi, amax);
@@ -373,20 +376,20 @@ __device__ inline void inv_xform(I (&c)[1 << (2 * D)]) {
 // are read as 16-byte vectors when the request's rows are 16-byte aligned.
 // A j past the last block reads block 0 (its results are discarded).
 template <typename T, int D, bool VEC>
-__device__ inline void load_block_row(const ReqDesc &r, const T *p, int q, T (&x)[1 << (2 * D)]) {
+__device__ inline void load_block_row(const ReqDesc &r, const global_t<T> *p, int q, T (&x)[1 << (2 * D)]) {
   int64_t off = 0;
   if constexpr (D == 2) off = (int64_t)q * r.dims[1];
   if constexpr (D == 3) off = ((int64_t)(q >> 2) * r.dims[1] + (q & 3)) * r.dims[2];
-  const T *row = p + off;
+  const global_t<T> *row = p + off;
   if constexpr (VEC) {
     if constexpr (sizeof(T) == 4) {
-      const f32x4 v = *(const f32x4 *)row;
+      const f32x4 v = *(const global_t<f32x4> *)row;
       x[4 * q] = v[0];
       x[4 * q + 1] = v[1];
       x[4 * q + 2] = v[2];
       x[4 * q + 3] = v[3];
     } else {
-      const f64x2 a = *(const f64x2 *)row, b = *(const f64x2 *)(row + 2);
+      const f64x2 a = *(const global_t<f64x2> *)row, b = *(const global_t<f64x2> *)(row + 2);
       x[4 * q] = a[0];
       x[4 * q + 1] = a[1];
       x[4 * q + 2] = b[0];
@@ -401,7 +404,7 @@ __device__ inline void load_block_row(const ReqDesc &r, const T *p, int q, T (&x
 template <typename T, int D, bool VEC>
 __device__ inline void load_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)]) {
   int64_t o[3];
-  const T *p = (const T *)r.field + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+  const global_t<T> *p = to_global((const T *)r.field) + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
 #pragma unroll
   for (int q = 0; q < (1 << (2 * D)) / 4; q++) load_block_row<T, D, VEC>(r, p, q, x);
 }
@@ -413,7 +416,7 @@ template <typename T, int D, bool VEC>
 __device__ inline void load_rows_of_block(const ReqDesc &r, int64_t j, T (&x)[1 << (2 * D)], int q0,
                                           int n, uint32_t after) {
   int64_t o[3];
-  const T *p = (const T *)r.field + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+  const global_t<T> *p = to_global((const T *)r.field) + block_base<D>(r, j < r.nblk ? (uint32_t)j : 0u, o);
   asm volatile("" : "+v"(p) : "v"(after));
 #pragma unroll
   for (int q = 0; q < (1 << (2 * D)) / 4; q++)
@@ -869,16 +872,16 @@ __device__ inline V quad_max(V v) {
 
 // Row (z, y) of block j, 4 values from `p` (the row's first element).
 template <typename T, bool VEC>
-__device__ inline void load_row4(const T *p, T (&x)[4]) {
+__device__ inline void load_row4(const global_t<T> *p, T (&x)[4]) {
   if constexpr (VEC) {
     if constexpr (sizeof(T) == 4) {
-      const f32x4 v = *(const f32x4 *)p;
+      const f32x4 v = *(const global_t<f32x4> *)p;
       x[0] = v[0];
       x[1] = v[1];
       x[2] = v[2];
       x[3] = v[3];
     } else {
-      const f64x2 a = *(const f64x2 *)p, b = *(const f64x2 *)(p + 2);
+      const f64x2 a = *(const global_t<f64x2> *)p, b = *(const global_t<f64x2> *)(p + 2);
       x[0] = a[0];
       x[1] = a[1];
       x[2] = b[0];
@@ -904,7 +907,7 @@ __device__ inline ZfpLane zfp_block_quad(const ReqDesc &r, int64_t j, int q, con
   T x[4][4];
   {
     int64_t o[3];
-    const T *p = (const T *)r.field + block_base<3>(r, j < r.nblk ? (uint32_t)j : 0u, o);
+    const global_t<T> *p = to_global((const T *)r.field) + block_base<3>(r, j < r.nblk ? (uint32_t)j : 0u, o);
     const int64_t sz = r.dims[1] * r.dims[2], sy = r.dims[2];
 #pragma unroll
     for (int z = 0; z < 4; z++) load_row4<T, VEC>(p + z * sz + q * sy, x[z]);
@@ -1177,16 +1180,16 @@ struct Rows {
 // the values here, so that the loads stay in flight until the round that
 // uses them (rows_mask zeroes what lies outside the field).
 template <typename T, bool VEC>
-__device__ inline void load_row(const T *p, T (&out)[5], bool left) {
+__device__ inline void load_row(const global_t<T> *p, T (&out)[5], bool left) {
   if constexpr (VEC) {
     if constexpr (sizeof(T) == 4) {
-      const f32x4 v = *(const f32x4 *)p;
+      const f32x4 v = *(const global_t<f32x4> *)p;
       out[1] = v[0];
       out[2] = v[1];
       out[3] = v[2];
       out[4] = v[3];
     } else {
-      const f64x2 a = *(const f64x2 *)p, b = *(const f64x2 *)(p + 2);
+      const f64x2 a = *(const global_t<f64x2> *)p, b = *(const global_t<f64x2> *)(p + 2);
       out[1] = a[0];
       out[2] = a[1];
       out[3] = b[0];
@@ -1210,7 +1213,7 @@ __device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
   int64_t o[3] = {0, 0, 0};
   // a block past the end reads block 0 (always present) and is masked out
   const int64_t base = block_base<D>(r, in ? (uint32_t)j : 0u, o);
-  const T *x = (const T *)r.field;
+  const global_t<T> *x = to_global((const T *)r.field);
   int64_t own = 0, sy = 0, sz = 0;
   bool yprev = false, zprev = false;  // row y0 - 1 / slice z - 1 inside the field
   if constexpr (D == 2) {
@@ -1227,7 +1230,7 @@ __device__ inline Rows<T, D> load_rows(const ReqDesc &r, int64_t j, int q) {
     yprev = o[1] + y0 > 0;
   }
   const bool left = o[D - 1] > 0;
-  const T *row = x + base + own;
+  const global_t<T> *row = x + base + own;
   uint32_t keep = (in && left) ? (1u << Rows<T, D>::NR) : 0u;
 #pragma unroll
   for (int zi = 0; zi < Lay::NZ; zi++) {
@@ -1320,7 +1323,7 @@ __device__ inline int quantize(T xv, double pred, double delta, double inv, doub
 // and their 1024-bin chunks are added to `chunks` (those of window codes are
 // taken from the window at the hand-over).
 template <int N>
-__device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_hist, uint16_t *region,
+__device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_hist, global_t<uint16_t> *region,
                                 uint32_t *s_n, uint64_t &chunks) {
   bool out[N];
   bool anyout = false;
@@ -1370,7 +1373,7 @@ __device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_h
 // One round of the SZ side on the rows `sc` of block j (tile slot jl).
 template <typename T, int D>
 __device__ inline void sz_round(const ReqDesc &r, Rows<T, D> &sc, int64_t j, int jl, int q, double delta,
-                                double inv, double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
+                                double inv, double ebsz, TileLds &L, uint32_t *s_hist, global_t<uint16_t> *region,
                                 uint32_t *s_n, LaneAcc &acc) {
   using Lay = SzLayout<D>;
   constexpr int BS = 1 << (2 * D), LPB = Lay::LPB, R = Lay::R, NP = Lay::NP;
@@ -1424,7 +1427,7 @@ __device__ inline void sz_round(const ReqDesc &r, Rows<T, D> &sc, int64_t j, int
 // row-major order.
 template <typename T, int D, bool VEC>
 __device__ inline void sz_tile(const ReqDesc &r, int64_t base, int tile, double delta, double inv,
-                               double ebsz, TileLds &L, uint32_t *s_hist, uint16_t *region,
+                               double ebsz, TileLds &L, uint32_t *s_hist, global_t<uint16_t> *region,
                                uint32_t *s_n, LaneAcc &acc) {
   using Lay = SzLayout<D>;
   constexpr int LPB = Lay::LPB, BPW = Lay::BPW;
@@ -1469,7 +1472,7 @@ __device__ inline void hist_flush(uint32_t *s_hist, uint32_t *g) {
 // chunks of the window's nonzero bins to `chunks` and returns, in every
 // thread, the number of codes the workgroup counted (window bins plus the
 // codes already in the region), i.e. its predictable points.
-__device__ inline uint32_t hist_hand_over(uint32_t *s_hist, uint32_t *g, uint16_t *region, uint32_t *s_n,
+__device__ inline uint32_t hist_hand_over(uint32_t *s_hist, uint32_t *g, global_t<uint16_t> *region, uint32_t *s_n,
                                           uint32_t points, uint64_t &chunks) {
   constexpr int kPer = kHistWin / kThreads;  // 16 bins per thread
   __shared__ uint32_t s_distinct, s_wave[kWaves];
@@ -1597,7 +1600,7 @@ __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
           if (s_pre[mid] <= k) lo_i = mid; else hi_i = mid - 1;
         }
         const int64_t off = (int64_t)(k - s_pre[lo_i]) * 8;
-        v[u] = *(const uint4 *)(r.ovf + (size_t)(w0 + lo_i) * cap + off);
+        v[u] = load_u4(to_global(r.ovf) + (size_t)(w0 + lo_i) * cap + off);
         valid[u] = (int)min<int64_t>(8, (int64_t)s_n[lo_i] - off);
       }
     }
@@ -1646,7 +1649,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
   uint4 hc[kHistCopies];
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++)
-    hc[q] = q < nhc ? *(const uint4 *)(r.hist + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
+    hc[q] = q < nhc ? load_u4(to_global(r.hist) + (size_t)q * kBins + bin0) : make_uint4(0, 0, 0, 0);
   uint32_t h[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++) {
@@ -1656,7 +1659,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
     h[3] += hc[q].w;
   }
   // the overflow pass's counts
-  const uint4 o = S > 0 ? *(const uint4 *)(r.ovf_hist + bin0) : make_uint4(0, 0, 0, 0);
+  const uint4 o = S > 0 ? load_u4(to_global(r.ovf_hist) + bin0) : make_uint4(0, 0, 0, 0);
   h[0] += o.x;
   h[1] += o.y;
   h[2] += o.z;
@@ -1670,8 +1673,8 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
 #pragma unroll
   for (int q = 0; q < kHistCopies; q++)
     if (q < nhc && (hc[q].x | hc[q].y | hc[q].z | hc[q].w))
-      *(uint4 *)(r.hist + (size_t)q * kBins + bin0) = make_uint4(0, 0, 0, 0);
-  if (o.x | o.y | o.z | o.w) *(uint4 *)(r.ovf_hist + bin0) = make_uint4(0, 0, 0, 0);
+      zero_u4(to_global(r.hist) + (size_t)q * kBins + bin0);
+  if (o.x | o.y | o.z | o.w) zero_u4(to_global(r.ovf_hist) + bin0);
   double hv[kEntPerThread];
 #pragma unroll
   for (int k = 0; k < kEntPerThread; k++) {
@@ -2229,7 +2232,7 @@ __device__ inline bool sz_wg(const ReqDesc &r, int w, TileLds &L, uint32_t *s_hi
   constexpr int BS = 1 << (2 * D);
   LaneAcc acc;
   __shared__ uint32_t s_n;
-  uint16_t *region = r.ovf + (size_t)w * r.sblk * BS;
+  global_t<uint16_t> *region = to_global(r.ovf) + (size_t)w * r.sblk * BS;
   hist_clear(s_hist);
   wg_acc_reset(L);
   if (threadIdx.x == 0) s_n = 0;

@@ -58,8 +58,8 @@ struct Tune {
   int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
                              // count is the batch's, 2 = both are the batch's, 3 = the SZ
-                             // count is each launch class's (1 to 3 also deal the ZFP
-                             // waves within each launch class)
+                             // count is each launch class's (batches always deal the
+                             // ZFP waves within each launch class)
   // set by the batch planner for one request from the batch's counts above
   // (never tuned or cached): nonzero = SZ workgroups, range workgroups, ZFP
   // waves aimed at
