@@ -391,7 +391,10 @@ int szsel_set_debug(szsel_ctx *ctx, const szsel_debug *dump);
  * stays and can be cancelled) or needs more workspace than one lane has
  * (SZSEL_ENOMEM).  Submitted requests wait in one FIFO; each of `lanes`
  * lanes (a stream with its own batch workspace of at most
- * lane_workspace_bytes, 0 = 4 GiB) takes up to 64 waiting requests, from any
+ * lane_workspace_bytes, 0 = 4 GiB, of which the fixed workspace of up to 64
+ * requests within half the budget and a quarter of the budget of variable
+ * workspace are allocated at creation, so that serving rarely allocates)
+ * takes up to 64 waiting requests, from any
  * number of snapshots and as many as its workspace holds, as one batch
  * whenever it is free, so work that arrives while other work runs starts on
  * the next free lane and overlaps it.  A batch that fails to launch is put

@@ -211,7 +211,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     p.first[(size_t)ps * (n + 1) + n] = acc;
   }
   // launches: per pass, one per contiguous class (dtype only for the range
-  // pass, whose kernel depends on nothing else)
+  // pass, whose kernel depends on nothing else; the overflow and entropy
+  // passes, which depend on neither, take the whole group)
   p.launches.clear();
   for (int ps = 0; ps < kBatchPasses; ps++) {
     const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
@@ -221,6 +222,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
         if (tg[a] != tg[b]) return false;
         const ReqDesc &x = p.tab[a], &y = p.tab[b];
         if (ps == kBatchRange) return x.dtype == y.dtype;
+        if (ps == kBatchOvf || ps == kBatchEnt) return true;
         return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec && (x.ec != 0) == (y.ec != 0);
       };
       while (e < n && same_class(k, e)) e++;
@@ -652,25 +654,76 @@ hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTime
 
 }  // namespace
 
+// A batch state with its events and streams (no buffers yet).
+static bool batch_state_create(BatchState *&bs, std::string &msg) {
+  bs = new BatchState();
+  bool ok = hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&bs->fork, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&bs->scan, hipStreamNonBlocking) == hipSuccess;
+  for (int g = 0; g < kMaxGroupsPerBatch && ok; g++)
+    ok = hipEventCreateWithFlags(&bs->scanned[g], hipEventDisableTiming) == hipSuccess;
+  if (!ok) msg = "batch state: event or stream creation failed";
+  return ok;
+}
+
+__global__ void k_stream_warm() {}
+
+int batch_reserve(BatchState *&bs, int nreq, size_t var_bytes, hipStream_t s, std::string &msg) {
+  if (nreq < 1 || nreq > kMaxBatch) {
+    msg = "batch reserve: 1 to " + std::to_string(kMaxBatch) + " requests";
+    return SZSEL_EINVAL;
+  }
+  if (!bs && !batch_state_create(bs, msg)) return SZSEL_EHIP;
+  const size_t n = (size_t)nreq;
+  const size_t meta = align_up(sizeof(ReqDesc) * n, 256) + sizeof(uint32_t) * (size_t)kBatchPasses * (n + 1);
+  hipError_t e = batch_wait(bs);
+  if (e == hipSuccess && request_fixed_bytes() * n > bs->fixed_cap)
+    e = dev_grow(bs->fixed, bs->fixed_cap, request_fixed_bytes() * n, true);
+  if (e == hipSuccess) e = dev_grow(bs->var, bs->var_cap, var_bytes, false);
+  if (e == hipSuccess) e = dev_grow(bs->res, bs->res_cap, sizeof(szsel_result) * n, false);
+  if (e == hipSuccess && meta > bs->meta_cap) {
+    bs->staged.clear();
+    e = dev_grow(bs->meta, bs->meta_cap, meta, false);
+  }
+  if (e == hipSuccess && meta > bs->stage_cap) {
+    bs->staged.clear();
+    if (bs->stage) (void)hipHostFree(bs->stage);
+    bs->stage = nullptr;
+    bs->stage_cap = 0;
+    void *h = nullptr;
+    e = hipHostMalloc(&h, meta, hipHostMallocDefault);
+    if (e == hipSuccess) {
+      bs->stage = (char *)h;
+      bs->stage_cap = meta;
+    }
+  }
+  if (e != hipSuccess) {
+    msg = std::string("batch reserve: ") + hipGetErrorString(e);
+    return SZSEL_ENOMEM;
+  }
+  // first launch and transfers of the stream (the staged table is marked
+  // empty, so the next batch uploads its own)
+  bs->staged.clear();
+  hipLaunchKernelGGL(k_stream_warm, dim3(1), dim3(kWave), 0, s);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(bs->meta, bs->stage, meta, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bs->stage, bs->res, std::min(meta, sizeof(szsel_result) * n), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) {
+    msg = std::string("batch reserve: ") + hipGetErrorString(e);
+    return SZSEL_EHIP;
+  }
+  return SZSEL_OK;
+}
+
 int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
               szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg) {
   if (n > kMaxBatch) {
     msg = "batch of " + std::to_string(n) + " requests; at most " + std::to_string(kMaxBatch);
     return SZSEL_EBUSY;
   }
-  if (!bs) {
-    bs = new BatchState();
-    bool ok = hipEventCreateWithFlags(&bs->done, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&bs->fork, hipEventDisableTiming) == hipSuccess &&
-              hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&bs->scan, hipStreamNonBlocking) == hipSuccess;
-    for (int g = 0; g < kMaxGroupsPerBatch && ok; g++)
-      ok = hipEventCreateWithFlags(&bs->scanned[g], hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-      msg = "batch state: event or stream creation failed";
-      return SZSEL_EHIP;
-    }
-  }
+  if (!bs && !batch_state_create(bs, msg)) return SZSEL_EHIP;
   hipError_t e = hipSuccess;
   // the host waits for the state's previous batch only where it rewrites
   // what that batch may still read (bind_plan, graph re-capture); on the

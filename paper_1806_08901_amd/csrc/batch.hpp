@@ -38,6 +38,16 @@ struct BatchOptions {
 int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szsel_request *reqs, int n,
               szsel_result *out, hipStream_t s, const BatchOptions &opt, std::string &msg);
 
+// Creates `bs` if needed and grows its buffers to hold nreq requests and
+// var_bytes of variable workspace, so that later batches within that size
+// allocate nothing (an allocation or release synchronises the device).
+// Then enqueues one kernel launch, one host-to-device and one
+// device-to-host transfer on stream s (the caller waits for them): the
+// runtime sets up a stream's queues at its first launch and transfers, and
+// more copy queues when transfers first run on several streams at once,
+// which takes milliseconds.  Waits for the state's previous batch.
+int batch_reserve(BatchState *&bs, int nreq, size_t var_bytes, hipStream_t s, std::string &msg);
+
 void batch_destroy(BatchState *bs);
 
 // CU count of the context's device.

@@ -134,7 +134,6 @@ __device__ inline int batch_owner(const uint32_t *s_pre, int n, uint32_t g) {
   return __builtin_amdgcn_readfirstlane(lo);  // the same in every thread
 }
 
-template <int D>
 __global__ __launch_bounds__(kOvfThreads) void kb_ovf(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ uint32_t s_cnt[kOvfBins];
   __shared__ uint32_t s_pre[kMaxBatch + 1];
@@ -144,13 +143,12 @@ __global__ __launch_bounds__(kOvfThreads) void kb_ovf(const ReqDesc *__restrict_
   });
   for (uint32_t g = blockIdx.x; g < items; g += gridDim.x) {
     const int lo = batch_owner(s_pre, c1 - c0, g);
-    ovf_wg<D>(tab[c0 + lo], (int)(g - s_pre[lo]), s_cnt);
+    ovf_wg(tab[c0 + lo], (int)(g - s_pre[lo]), s_cnt);
     __syncthreads();
   }
 }
 
 // Items: the chunks the entropy pass works on (ent_chunks), in bit order.
-template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_pre[kMaxBatch + 1];
@@ -164,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void kb_ent(const ReqDesc *__restrict__ t
     const uint64_t chunks = ent_chunks(r);
     uint64_t m = chunks;
     for (uint32_t k = g - s_pre[lo]; k > 0; k--) m &= m - 1;  // drop the lower chunks
-    ent_wg<T, D>(r, __ffsll((long long)m) - 1, chunks, L);
+    ent_wg(r, __ffsll((long long)m) - 1, chunks, L);
     __syncthreads();
   }
 }
@@ -203,12 +201,6 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
       else
         hipLaunchKernelGGL((kb_sz<T, D, false>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
-    case kBatchOvf:
-      hipLaunchKernelGGL((kb_ovf<D>), grid, dim3(kOvfThreads), 0, s, a.tab, a.first, a.c0, a.c1);
-      break;
-    case kBatchEnt:
-      hipLaunchKernelGGL((kb_ent<T, D>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
-      break;
     default:
       hipLaunchKernelGGL((kb_huff<T, D>), grid, dim3(kHuffThreads), 0, s, a.tab, a.first, a.c0, a.c1);
       break;
@@ -218,6 +210,15 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
 
 hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s) {
   if (a.items == 0) return hipSuccess;
+  // the overflow and entropy passes serve every dtype and rank in one launch
+  if (a.pass == kBatchOvf || a.pass == kBatchEnt) {
+    const dim3 grid(a.grid ? a.grid : a.items);
+    if (a.pass == kBatchOvf)
+      hipLaunchKernelGGL(kb_ovf, grid, dim3(kOvfThreads), 0, s, a.tab, a.first, a.c0, a.c1);
+    else
+      hipLaunchKernelGGL(kb_ent, grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
+    return hipGetLastError();
+  }
   if (a.dtype == SZSEL_F32) {
     switch (a.nd) {
       case 1: return launch_typed<float, 1>(a, s);

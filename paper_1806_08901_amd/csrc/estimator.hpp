@@ -1552,9 +1552,8 @@ __device__ inline void sz_finalize(const ReqDesc &r, const Part &tot) {
 // slice's regions are numbered through an LDS prefix sum of the regions'
 // vector counts, so the work follows the number of overflow codes; 4
 // vectors are in flight per thread.
-template <int D>
 __device__ inline void ovf_wg(const ReqDesc &r, int g, uint32_t *s_cnt) {
-  constexpr int BS = 1 << (2 * D);
+  const int BS = 1 << (2 * r.nd);  // (any rank: one launch serves them all)
   const int p = g / kOvfRanges, q = g % kOvfRanges;
   const int S = (int)get_u32(&r.st->ovf_slices);  // 0 when there is no overflow code
   if (p >= S) return;
@@ -1633,9 +1632,10 @@ __device__ inline uint64_t ent_chunks(const ReqDesc &r) {
 // entropy (Eq. 5 with P_i = h_i/n), SZ bit-rate (entropy + offset + W escape
 // bits per unpredictable point, Section 6.2), both PSNRs and the selection
 // of Algorithm 1 (lower bit-rate wins, ties go to ZFP).
-template <typename T, int D>
 __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds &L) {
-  constexpr int BS = 1 << (2 * D);
+  // (any dtype and rank: one launch serves them all)
+  const int BS = 1 << (2 * r.nd);
+  const double W = r.dtype == SZSEL_F32 ? (double)Prec<float>::W : (double)Prec<double>::W;
   const int t = threadIdx.x;
   const uint64_t unpred = get_u64(&r.st->sz_unpred);
   const int S = (int)get_u32(&r.st->ovf_slices);
@@ -1713,7 +1713,7 @@ __device__ inline void ent_wg(const ReqDesc &r, int c, uint64_t chunks, TileLds 
     const double sse = get_f64(&st->sz_sse);
     const double H = log2(nv) - s / nv;
     double br = H + r.sz_offset;
-    br = br + ((double)unpred * (double)Prec<T>::W) / nv;
+    br = br + ((double)unpred * W) / nv;
     const double delta = get_f64(&st->delta);
     const double eb_sz = get_f64(&st->eb_sz);
     const double eb_abs = get_f64(&st->eb_abs);

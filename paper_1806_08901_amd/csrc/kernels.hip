@@ -39,19 +39,17 @@ __global__ __launch_bounds__(kThreads, (kSzWavesPerSimd<T, D>)) void k_sz(ReqDes
   sz_wg<T, D, VEC>(r, blockIdx.x, L, s_hist);
 }
 
-template <int D>
 __global__ __launch_bounds__(kOvfThreads) void k_ovf(ReqDesc r) {
   __shared__ uint32_t s_cnt[kOvfBins];
   if (skip_request(r.st)) return;
-  ovf_wg<D>(r, blockIdx.x, s_cnt);
+  ovf_wg(r, blockIdx.x, s_cnt);
 }
 
-template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_ent(ReqDesc r) {
   __shared__ TileLds L;
   if (skip_request(r.st)) return;
   const uint64_t chunks = ent_chunks(r);
-  if ((chunks >> blockIdx.x) & 1u) ent_wg<T, D>(r, blockIdx.x, chunks, L);
+  if ((chunks >> blockIdx.x) & 1u) ent_wg(r, blockIdx.x, chunks, L);
 }
 
 template <typename T, int D>
@@ -93,13 +91,13 @@ static hipError_t launch_tiles(const ReqDesc &r, hipStream_t s, const hipEvent_t
   }
   if ((e = mark(ev, 3, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
-    hipLaunchKernelGGL((k_ovf<D>), dim3(kOvfSlices * kOvfRanges), dim3(kOvfThreads), 0, s, r);
+    hipLaunchKernelGGL(k_ovf, dim3(kOvfSlices * kOvfRanges), dim3(kOvfThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if ((e = mark(ev, 4, s)) != hipSuccess) return e;
   if (r.op != SZSEL_OP_ZFP) {
-    hipLaunchKernelGGL((k_ent<T, D>), dim3(kEntWgs), dim3(kThreads), 0, s, r);
+    hipLaunchKernelGGL(k_ent, dim3(kEntWgs), dim3(kThreads), 0, s, r);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (r.huff) {

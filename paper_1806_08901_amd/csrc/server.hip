@@ -287,8 +287,30 @@ int szsel_server_create(szsel_server **out, szsel_ctx *ctx, void *pool, size_t p
         return SZSEL_EHIP;
       }
       l.res = (szsel_result *)h;
+      // part of the lane's workspace, allocated now (the fixed workspace of
+      // up to a full batch within half the budget, and a quarter of the
+      // budget of variable workspace): growing it while serving would
+      // synchronise the device and stall every lane; the reservation also
+      // makes the lane stream's first launch and transfers, on all lanes at
+      // once (waited for below)
+      const size_t per = szsel::request_fixed_bytes();
+      const int nres = (int)std::min<size_t>((size_t)kServeBatch, s->lane_budget / 2 / per);
+      if (nres >= 1) {
+        std::string msg;
+        const int rc = szsel::batch_reserve(l.bs, nres, s->lane_budget / 4, l.s, msg);
+        if (rc != SZSEL_OK) {
+          szsel_server_destroy(s);
+          return rc;
+        }
+      }
+
     }
   }
+  for (Lane &l : s->lanes)
+    if (hipStreamSynchronize(l.s) != hipSuccess) {
+      szsel_server_destroy(s);
+      return SZSEL_EHIP;
+    }
   *out = s;
   return SZSEL_OK;
 }
