@@ -211,10 +211,12 @@ def pass_profile(ctx, szsel, run_steps, steps, byte_table):
              "avg_launch_ms": round(ms / calls, 5)}
         b = byte_table.get((ph, dt))
         other = "f64" if dt == "f32" else "f32"
-        if ph in ("ovf", "ent") and prof.get((ph, other), (0.0, 0))[1] == 0:
+        if ph in ("range", "ovf", "ent") and prof.get((ph, other), (0.0, 0))[1] == 0 \
+                and byte_table.get((ph, other)):
             # one launch per request group serves both dtypes; it is
             # recorded under its first request's
             b = (b or 0) + byte_table.get((ph, other), 0)
+            e["dtypes"] = "binary32 and binary64"
         if b:
             gbs = b / (ms / steps * 1e-3) / 1e9
             e.update({"bytes_per_step": b, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
@@ -231,7 +233,8 @@ def roofline_of(passes, traffic_profile=None, kernel_names=None):
     if traffic_profile and kernel_names:
         traffic = recorded_traffic(traffic_profile, kernel_names.get(k, ""))
     per_launch = e["bytes_per_step"] / e["launches_per_step"]
-    return {"bound": "hbm", "kernel": "%s, %s fields" % (KERNELS[ph], "binary32" if dt == "f32" else "binary64"),
+    fields = e.get("dtypes", "binary32" if dt == "f32" else "binary64")
+    return {"bound": "hbm", "kernel": "%s, %s fields" % (KERNELS[ph], fields),
             "achieved": e["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": e["frac"],
             "traffic": traffic, "bytes_per_launch": int(per_launch), "avg_launch_ms": e["avg_launch_ms"],
             "launches_per_step": e["launches_per_step"]}
@@ -244,7 +247,7 @@ def kernel_name(cls, nd=3, vec=True, ec=False):
     t = "float" if dt == "f32" else "double"
     v = "true" if vec else "false"
     if ph == "range":
-        return "szsel::kb_range<%s>" % t
+        return "szsel::kb_range"
     if ph == "zfp":
         return "szsel::kb_zfp<%s,%d,%s,%s>" % (t, nd, v, "true" if ec else "false")
     if ph == "sz":

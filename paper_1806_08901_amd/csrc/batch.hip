@@ -165,6 +165,9 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     if (x.dtype != y.dtype) return x.dtype < y.dtype;
     if (x.nd != y.nd) return x.nd < y.nd;
     if (x.vec != y.vec) return x.vec > y.vec;
+    // larger fields first within a class: the range launch's last
+    // workgroups are then the small fields' short chunks
+    if (x.n != y.n) return x.n > y.n;
     if (x.field != y.field) return (uintptr_t)x.field < (uintptr_t)y.field;
     for (int k = 0; k < x.nd; k++)
       if (x.dims[k] != y.dims[k]) return x.dims[k] < y.dims[k];
@@ -210,9 +213,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     }
     p.first[(size_t)ps * (n + 1) + n] = acc;
   }
-  // launches: per pass, one per contiguous class (dtype only for the range
-  // pass, whose kernel depends on nothing else; the overflow and entropy
-  // passes, which depend on neither, take the whole group)
+  // launches: per pass, one per contiguous class (the range, overflow and
+  // entropy passes, whose kernels take any class, one per request group)
   p.launches.clear();
   for (int ps = 0; ps < kBatchPasses; ps++) {
     const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
@@ -221,8 +223,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       auto same_class = [&](int a, int b) {
         if (tg[a] != tg[b]) return false;
         const ReqDesc &x = p.tab[a], &y = p.tab[b];
-        if (ps == kBatchRange) return x.dtype == y.dtype;
-        if (ps == kBatchOvf || ps == kBatchEnt) return true;
+        if (ps == kBatchRange || ps == kBatchOvf || ps == kBatchEnt) return true;
         return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec && (x.ec != 0) == (y.ec != 0);
       };
       while (e < n && same_class(k, e)) e++;

@@ -40,7 +40,6 @@ __device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t
 // Range chunks: one per workgroup, or (a grid smaller than the chunk count)
 // every workgroup loops over chunks blockIdx.x, + gridDim.x, ... in table
 // order, so that a few resident workgroups per CU scan the whole launch.
-template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
@@ -50,7 +49,11 @@ __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__
     int local;
     const int i = __builtin_amdgcn_readfirstlane(batch_find(s_first, c0, c1, g, local));
     local = __builtin_amdgcn_readfirstlane(local);
-    range_wg<T>(tab[i], local, L);
+    // (either dtype: one launch scans every field of the request group)
+    if (tab[i].dtype == SZSEL_F32)
+      range_wg<float>(tab[i], local, L);
+    else
+      range_wg<double>(tab[i], local, L);
     __syncthreads();
   }
 }
@@ -180,9 +183,6 @@ template <typename T, int D>
 static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
   const dim3 grid(a.grid ? a.grid : a.items);
   switch (a.pass) {
-    case kBatchRange:
-      hipLaunchKernelGGL((kb_range<T>), grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
-      break;
     case kBatchZfp:
       if (a.ec) {
         if (a.vec)
@@ -210,10 +210,13 @@ static hipError_t launch_typed(const BatchLaunch &a, hipStream_t s) {
 
 hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s) {
   if (a.items == 0) return hipSuccess;
-  // the overflow and entropy passes serve every dtype and rank in one launch
-  if (a.pass == kBatchOvf || a.pass == kBatchEnt) {
+  // the range, overflow and entropy passes serve every dtype and rank in
+  // one launch
+  if (a.pass == kBatchRange || a.pass == kBatchOvf || a.pass == kBatchEnt) {
     const dim3 grid(a.grid ? a.grid : a.items);
-    if (a.pass == kBatchOvf)
+    if (a.pass == kBatchRange)
+      hipLaunchKernelGGL(kb_range, grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
+    else if (a.pass == kBatchOvf)
       hipLaunchKernelGGL(kb_ovf, grid, dim3(kOvfThreads), 0, s, a.tab, a.first, a.c0, a.c1);
     else
       hipLaunchKernelGGL(kb_ent, grid, dim3(kThreads), 0, s, a.tab, a.first, a.c0, a.c1);
