@@ -192,8 +192,9 @@ int szsel_select_noalloc(szsel_ctx *ctx, const void *field, const int64_t *dims,
                          szsel_result *out, void *stream);
 
 /* n <= 1024 requests of any shape, dtype, bound and op together: one launch
- * per pass covers every request (grouped by dtype, rank and alignment),
- * captured as a HIP graph and replayed while the batch shape repeats.
+ * per pass covers every request (the ZFP and SZ passes one per class of
+ * dtype, rank and alignment; the range, overflow and entropy passes one for
+ * all), captured as a HIP graph and replayed while the batch shape repeats.
  * Requests on the same field (same pointer, dtype and dims) share one
  * value-range scan.  out[i] receives the result of reqs[i]; each equals what
  * the single-request entry point returns for the same request, bit for bit.
@@ -367,7 +368,8 @@ int szsel_sz_compress(szsel_ctx *ctx, const void *field, const int64_t *dims, in
 int szsel_profile_read(szsel_ctx *ctx, double *ms, uint64_t *calls);
 
 /* The same split by field dtype: entry 2 * phase + dtype (SZSEL_F32 = 0,
- * SZSEL_F64 = 1) of ms[10] and calls[10]; clears the timers too. */
+ * SZSEL_F64 = 1) of ms[10] and calls[10] (a batched launch that serves both
+ * dtypes counts under its first request's); clears the timers too. */
 int szsel_profile_read_split(szsel_ctx *ctx, double *ms, uint64_t *calls);
 
 /* Arms per-sample dumps for the next single-request call (NULL disarms). */
