@@ -121,16 +121,21 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 5}))
 
 
-def source_digest():
+def source_digest(root=None):
     """Digest of the kernel sources and of the planning that sets their
     launch shapes, to tell whether recorded counters still describe the
-    current kernels."""
+    current kernels: their code with comments and whitespace removed, so
+    that an edited comment keeps the counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("device.hpp", "estimator.hpp", "kernels.hip", "launch.hpp", "runtime.hip",
                  "batch.hip", "batch_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1806_08901_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root or ROOT, "paper_1806_08901_amd", "csrc", name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,12 +1,13 @@
 // Batched execution: n requests of any shape, dtype, bound and op in one
-// launch per pass (and request class), captured as a HIP graph and replayed
-// while the batch keeps the same launch shape.
+// launch per pass (the ZFP and SZ passes one per request class), captured
+// as a HIP graph and replayed while the batch keeps the same launch shape.
 //
-// Table order.  Requests are sorted by (dtype, ndims, vector alignment,
-// field, dims) so that every class of kernel template is a contiguous range
-// of the device table, and requests on the same field are adjacent: the
-// first of them scans the value range once for all (nshare), the others
-// get no range work items.  Results are written at the caller's indices.
+// Table order.  Requests are sorted by (group, dtype, ndims, vector
+// alignment, field size, field, dims) so that every class of kernel
+// template is a contiguous range of the device table, and requests on the
+// same field are adjacent: the first of them scans the value range once for
+// all (nshare), the others get no range work items.  Results are written at
+// the caller's indices.
 //
 // Workspace.  Each table entry owns a fixed part (state, counters,
 // histogram, ...; zeroed once, kept clean by the kernels) and a variable

@@ -1,5 +1,6 @@
-// Batched passes: one launch per pass (and request class) covers every
-// request of a batch.  The requests sit in a device table ordered so that
+// Batched passes: one launch per pass covers every request of a batch (of
+// a request group; the ZFP and SZ passes, whose kernels are templates of
+// the dtype and rank, one launch per request class).  The requests sit in a device table ordered so that
 // each launch covers a contiguous range [c0, c1); first[i] is the first work
 // item (workgroup) of table entry i in this pass, first[c1] the end.
 #include "estimator.hpp"
@@ -37,9 +38,10 @@ __device__ inline int batch_item(const uint32_t *first, int c0, int c1, uint32_t
   return __builtin_amdgcn_readfirstlane(i);
 }
 
-// Range chunks: one per workgroup, or (a grid smaller than the chunk count)
-// every workgroup loops over chunks blockIdx.x, + gridDim.x, ... in table
-// order, so that a few resident workgroups per CU scan the whole launch.
+// Range chunks of fields of either dtype: one per workgroup, or (a grid
+// smaller than the chunk count) every workgroup loops over chunks
+// blockIdx.x, + gridDim.x, ... in table order, so that a few resident
+// workgroups per CU scan the whole launch.
 __global__ __launch_bounds__(kThreads) void kb_range(const ReqDesc *__restrict__ tab, const uint32_t *first, int c0, int c1) {
   __shared__ TileLds L;
   __shared__ uint32_t s_first[kMaxBatch + 1];
