@@ -760,14 +760,17 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       msg = "autotune: event creation failed";
       return SZSEL_EHIP;
     }
+    // a candidate the planner rejects (more work items than a pass holds,
+    // more workspace than the budget) times as never faster; only a HIP
+    // error ends the search
     auto time_of = [&](const Tune &c, float &ms) -> int {
       Plan p;
-      int rc = make_plan(ctx, ncu, reqs, n, c, p, msg);
-      if (rc != SZSEL_OK) return rc;
-      if (bind_plan(bs, p, budget, msg) != hipSuccess) return SZSEL_ENOMEM;
+      ms = 1e30f;
+      std::string why;
+      if (make_plan(ctx, ncu, reqs, n, c, p, why) != SZSEL_OK) return SZSEL_OK;
+      if (bind_plan(bs, p, budget, why) != hipSuccess) return SZSEL_OK;
       hipError_t q = upload_meta(bs, s);
       if (q == hipSuccess) q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
-      ms = 1e30f;
       for (int rep = 0; rep < 5 && q == hipSuccess; rep++) {  // best of 5
         float one = 0.f;
         q = hipEventRecord(t0, s);
@@ -879,7 +882,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (rc != SZSEL_OK) return rc;
-    {
+    if (best_ms < 1e30f) {  // (no schedule planned: the plan below reports why)
       Tuner &T = tuner();
       std::lock_guard<std::mutex> lock(T.mu);
       T.best[std::make_pair(std::string(ctx_arch(ctx)), key)] = cur;

@@ -216,8 +216,8 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // range_wgs_q quarters of the CU count of them, at least 8 vectors per thread
   const int64_t vn = 16 / (int64_t)esz;
   const int64_t quantum = (int64_t)kThreads * vn;
-  const int64_t rw = tu.range_target > 0 ? (int64_t)tu.range_target
-                                          : std::max<int64_t>(1, (int64_t)tu.range_wgs_q * ctx->ncu / 4);
+  const int64_t rw = std::min<int64_t>(kMaxParts, tu.range_target > 0 ? (int64_t)tu.range_target
+                                                                     : std::max<int64_t>(1, (int64_t)tu.range_wgs_q * ctx->ncu / 4));
   int64_t chunk = (n + rw - 1) / rw;
   chunk = std::max<int64_t>(chunk, 8 * quantum);
   chunk = (chunk + quantum - 1) / quantum * quantum;

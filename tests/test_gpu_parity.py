@@ -196,6 +196,20 @@ def test_turb512_full_size(ctx, turb512, eb):
     assert not is_tie(orc)
 
 
+def test_turb512_most_range_chunks(ctx, turb512):
+    """The largest range-chunk setting (64 per CU: more chunks than a pass
+    holds on this field) is capped at the pass's limit instead of failing,
+    and gives the default schedule's results."""
+    from paper_1806_08901_amd import szsel
+    stride = (5, 4, 1)
+    ref = ctx.select(turb512, 1e-3, stride=stride)
+    try:
+        ctx.set_option(szsel.OPT_RANGE_WGS, 64)
+        assert ctx.select(turb512, 1e-3, stride=stride) == ref
+    finally:
+        ctx.set_option(szsel.OPT_RANGE_WGS, 0)
+
+
 @pytest.mark.parametrize("eb", [1e-5, 1e-6])
 def test_turb512_full_dump_tight_bounds(ctx, turb512, eb):
     """512^3 at the tight bounds, where the histogram is widest and the
