@@ -220,8 +220,9 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   single-request call and around every launch of a batch (batches then
  *   launch without a graph); read with szsel_profile_read.
  * SZSEL_OPT_AUTOTUNE: nonzero lets szsel_select_batch time a few launch
- *   shapes (workgroups per request and pass, request groups, how the counts
- *   are shared, overflow codes per slice of the overflow pass) the first
+ *   shapes (workgroups per request and pass, ZFP waves per launch class,
+ *   request groups, how the counts are shared, overflow codes per slice of
+ *   the overflow pass) the first
  *   time it sees a batch shape and keep the fastest; 0 (default) uses the
  *   fixed schedule.  The results do not depend on it.  The schedules are
  *   kept per device architecture and batch shape (request count, and per

@@ -87,7 +87,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
   // rank, alignment, point sub-sampling) instead: the classes run as
   // launches of their own, one after another, and each should fill the
   // chip (a small binary64 class dealt its share of the whole batch's count
-  // runs on a few long workgroups).  The ZFP waves (kZfpWavesPerCu per CU)
+  // runs on a few long workgroups).  The ZFP waves (tu.zfp_waves per CU)
   // are dealt within each launch class in every mode.
   if (n > 1) {
     auto cls = [&](int i) { return (d[i].dtype * 8 + d[i].nd) * 4 + (d[i].vec ? 2 : 0) + (d[i].ec ? 1 : 0); };
@@ -103,7 +103,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     }
     const double sz_want = std::max(1.0, (double)tu.sz_wgs_q * (double)ncu / 4.0);
     const double range_want = std::max(1.0, (double)tu.range_wgs_q * (double)ncu / 4.0);
-    const double zfp_want = (double)kZfpWavesPerCu * (double)ncu;
+    const double zfp_want = (double)std::max(1, tu.zfp_waves) * (double)ncu;
     auto share = [](double want, double part, double whole) {
       return (int)std::max(1.0, std::min(1e9, std::round(want * part / whole)));
     };
@@ -406,6 +406,7 @@ template <typename F>
 void tune_fields(Tune &t, F f) {
   f("sz_wgs_q", t.sz_wgs_q);
   f("zfp_chunk", t.zfp_chunk);
+  f("zfp_waves", t.zfp_waves);
   f("range_wgs_q", t.range_wgs_q);
   f("range_grid", t.range_grid);
   f("groups", t.groups);
@@ -454,7 +455,8 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     if (end == line.c_str() + a + pat.size() || x < 0 || x > (1l << 30)) ok = false;
     v = (int)x;
   });
-  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.range_wgs_q >= 1 && t.range_grid >= 0 &&
+  return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.zfp_waves >= 1 && t.range_wgs_q >= 1 &&
+         t.range_grid >= 0 &&
          t.ovf_slice >= 1 && t.share <= 3;
 }
 
@@ -792,7 +794,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     const int share_opts[] = {0, 1, 2, 3};
     const int group_opts[] = {1, 2, 4, 8};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
-    const int zfp_opts[] = {16, 32, 64, 128, 256};
+    const int zfp_opts[] = {16, 32, 64, 128};  // ZFP waves per CU of a launch class
     const int range_opts[] = {1, 2, 4, 8, 16, 32, 64};  // quarters of the CU count
     const int grid_opts[] = {0, 1, 2, 4};
     const int ovf_opts[] = {kOvfPerSlice, 2 * kOvfPerSlice, 4 * kOvfPerSlice};
@@ -834,9 +836,9 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       }
     }
     for (int v : zfp_opts) {
-      if (rc != SZSEL_OK || v == cur.zfp_chunk) continue;
+      if (rc != SZSEL_OK || v == cur.zfp_waves) continue;
       Tune c = cur;
-      c.zfp_chunk = v;
+      c.zfp_waves = v;
       float ms = 0.f;
       rc = time_of(c, ms);
       if (rc == SZSEL_OK && ms < best_ms) {

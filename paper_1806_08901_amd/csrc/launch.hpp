@@ -50,6 +50,8 @@ struct Tune {
   int sz_wgs_q = 8;          // SZ workgroups per request, in quarters of the CU count
   int zfp_chunk = 16;        // smallest ZFP chunk (sampled blocks per one-wave workgroup;
                              // layouts of one block per lane take at least 64)
+  int zfp_waves = 64;        // ZFP waves aimed at per CU, for a request (single calls) or a
+                             // launch class (batches); chunks grow until they are about that many
   int range_wgs_q = 4;       // range workgroups (scan chunks) per request, in quarters of the CU count
   int range_grid = 0;        // batches: 0 = one workgroup per range chunk; k > 0 = k workgroups
                              // per CU that loop over all the launch's chunks (a resident scan
@@ -68,10 +70,6 @@ struct Tune {
   int zfp_target = 0;
 };
 
-// ZFP waves aimed at per CU for one request (single calls) or one launch
-// class of a batch: about 16 per SIMD, several rounds of the resident waves,
-// so that the last round's tail is short while each wave still does a few
-// rounds of blocks.
-constexpr int kZfpWavesPerCu = 64;
+
 
 }  // namespace szsel

@@ -183,8 +183,10 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   // consecutive sampled blocks, and a pass has at most kMaxParts workgroups.
   // ZFP: one wave per workgroup, rounds of 64 blocks (one block per lane)
   // or, for 3-D blocks without sub-sampling, of 16 (four lanes per block),
-  // about kZfpWavesPerCu waves per CU (or the batch planner's share of
-  // them).  SZ: at least one round of 4 waves.
+  // about tu.zfp_waves waves per CU (default 64, about 16 per SIMD: several
+  // rounds of the resident waves, so that the last round's tail is short
+  // while each wave still does a few rounds of blocks), or the batch
+  // planner's share of them.  SZ: at least one round of 4 waves.
   auto chunk_for = [&](uint64_t min_chunk, uint64_t target_wgs, uint64_t max_wgs) {
     const uint64_t want = (nblk + target_wgs - 1) / target_wgs;
     uint64_t c = min_chunk;
@@ -194,7 +196,7 @@ int plan_request(szsel_ctx *ctx, int op, const void *field, const int64_t *dims,
   };
   const uint64_t zround = (nd == 3 && !r.ec) ? (uint64_t)(kWave / 4) : (uint64_t)kWave;
   const uint64_t zfp_target = tu.zfp_target > 0 ? (uint64_t)tu.zfp_target
-                                                 : (uint64_t)kZfpWavesPerCu * (uint64_t)ctx->ncu;
+                                                 : (uint64_t)std::max(1, tu.zfp_waves) * (uint64_t)ctx->ncu;
   const uint64_t zc = chunk_for(std::max<uint64_t>((uint64_t)tu.zfp_chunk, zround), zfp_target, kMaxParts);
   // SZ: one lane per two rows of 4 points (one row in 1-D); by
   // default 2 workgroups per CU, all of them resident at once
