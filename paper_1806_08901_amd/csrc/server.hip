@@ -303,7 +303,6 @@ int szsel_server_create(szsel_server **out, szsel_ctx *ctx, void *pool, size_t p
           return rc;
         }
       }
-
     }
   }
   for (Lane &l : s->lanes)
