@@ -14,7 +14,7 @@
  *           keeps it alive and unmodified until the stream work completes.
  *   dims    host array of ndims extents, each >= 1; ndims in {1, 2, 3}.
  *   eb      error bound: absolute (SZSEL_EB_ABS) or relative to the field's
- *           value range (SZSEL_EB_REL), Algorithm 1 line 2.  Must be > 0.
+ *           value range (SZSEL_EB_REL), Algorithm 1.  Must be > 0.
  *   stride  host array of ndims block strides, each >= 1: the 4^d block with
  *           block index b is sampled iff b_k mod stride[k] == 0 on every axis
  *           (Section 4.3: a fixed distance per dimension).  NULL means 1 on
@@ -273,7 +273,7 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   the result does not depend on how the tree is built.
  * SZSEL_OPT_EC_SAMPLING: 0 (default) the exact ZFP estimate (coder bit count
  *   of every sampled block, error after decoding); 1 the paper's cheaper
- *   estimate (Section 5.2.1-5.2.2, Algorithm 1 lines 4-6): 3, 9 or 16
+ *   estimate (Section 5.2.1-5.2.2, Algorithm 1's pointwise sampling): 3, 9 or 16
  *   coefficients per 1-, 2- or 3-D block, spread evenly over the coding
  *   order (position round(k (4^d - 1)/(r - 1))); BR_zfp = the mean
  *   significant-bit count with the other positions interpolated linearly;
@@ -292,7 +292,7 @@ enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* ---------------------------------------------------------------------
- * Step 4 (Algorithm 1 lines 11-13): compressing the whole field with the
+ * Step 4 (Section 3; the compression that ends Algorithm 1): compressing the whole field with the
  * chosen compressor, for the true bit-rate and PSNR behind an estimate.
  * --------------------------------------------------------------------- */
 typedef struct {

@@ -62,7 +62,7 @@ static int64_t prod(const int64_t *dims, int nd) {
   return n;
 }
 
-/* Value range over ALL values of the field (Algorithm 1, line 2; the value
+/* Value range over ALL values of the field (Algorithm 1's error bound; the value
  * range VR appears in the PSNR definition, Eq. 8).  Returns 1 when any value
  * is NaN or infinite, 0 otherwise. */
 int orc_range(const void *field, int64_t n, int dtype, double *vmin, double *vmax) {
@@ -79,7 +79,7 @@ int orc_range(const void *field, int64_t n, int dtype, double *vmin, double *vma
 }
 
 /* ------------------------------------------------------------------ */
-/* Block sampling (Section 4.3; Algorithm 1, line 3)                   */
+/* Block sampling (Section 4.3; Algorithm 1)                          */
 /* ------------------------------------------------------------------ */
 
 /* Reading: the field is cut into full 4^d blocks (floor(n_k/4) per axis) and
@@ -595,7 +595,7 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
   const int size = 1 << (2 * nd);
   const int64_t N = prod(dims, nd);
 
-  /* line 2: error bound from the value range of the whole field */
+  /* error bound from the value range of the whole field */
   double vmin = 0.0, vmax = 0.0;
   if (orc_range(field, N, dtype, &vmin, &vmax)) {
     out->flags |= ORC_FLAG_NONFINITE;
@@ -617,7 +617,7 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
     if (selecting) out->choice = 0;
     return 0;
   }
-  /* line 3: block sampling */
+  /* blockwise sampling */
   const int64_t nblk = orc_num_sampled_blocks(dims, nd, stride);
   if (nblk == 0) {
     out->flags |= ORC_FLAG_NO_BLOCKS;
@@ -632,10 +632,10 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
   int64_t origin[3], pt[3];
   double x[64], xh[64];
 
-  /* lines 5-6: ZFP bit-rate and PSNR on the sampled blocks */
+  /* ZFP bit-rate and PSNR on the sampled blocks */
   double br_zfp = 0.0, mse_zfp = 0.0;
   if (op != ORC_OP_SZ && ec_r) {
-    /* lines 4-6 as the paper states them: point sub-sampling of the
+    /* as Algorithm 1 states it: point sub-sampling of the
      * sampled blocks, interpolated mean significant-bit count, MSE of the
      * sub-sampled points' transform-domain errors */
     int R = 1;
@@ -716,7 +716,7 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
   }
 
   if (op != ORC_OP_ZFP) {
-    /* line 7: bin size delta.  Selection: the delta whose uniform-error PSNR
+    /* bin size delta.  Selection: the delta whose uniform-error PSNR
      * (Eq. 10) equals PSNR_zfp, i.e. delta = sqrt(12 MSE_zfp).  Otherwise SZ's
      * own rule delta = 2 eb_abs (Section 5.1.4). */
     double delta = 2.0 * eb_abs;
@@ -731,7 +731,7 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
     uint32_t *hist = (uint32_t *)calloc(NBINS, sizeof(uint32_t));
     uint64_t unpred = 0;
     double maxerr = 0.0;
-    /* lines 8-9: quantization codes of all points of the sampled blocks */
+    /* quantization codes of all points of the sampled blocks */
     for (int64_t j = 0; j < nblk; j++) {
       orc_sampled_block_origin(dims, nd, stride, j, origin);
       for (int i = 0; i < size; i++) {
@@ -789,7 +789,7 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
     if (dump && dump->hist) memcpy(dump->hist, hist, NBINS * sizeof(uint32_t));
     free(hist);
 
-    /* lines 10-14: the lower estimated bit-rate wins; ties go to ZFP */
+    /* selection: the lower estimated bit-rate wins; ties go to ZFP */
     if (selecting) {
       out->choice = br_sel < br_zfp ? 0 : 1;
       out->chosen_eb = out->choice == 0 ? eb_sz : eb_abs;
@@ -801,8 +801,8 @@ int orc_run(int op, const void *field, const int64_t *dims, int nd, int dtype, d
 }
 
 /* ------------------------------------------------------------------ */
-/* Step 4 (Algorithm 1 lines 11-13): ZFP compression of the whole      */
-/* field at eb_abs, and its decompression                               */
+/* Step 4 (Section 3; Algorithm 1's ZFP branch): ZFP compression of    */
+/* the whole field at eb_abs, and its decompression                    */
 /* ------------------------------------------------------------------ */
 
 /* Stream: the bits in order, bit i in bit (i mod 64) of 64-bit word i/64

@@ -111,7 +111,8 @@ void orc_zfp_block_ec(const double *x, int ndims, int dtype, int minexp, int r, 
  * occurrence; no symbol, 0. */
 uint64_t orc_huffman_bits(const uint32_t *hist, int64_t nbins);
 
-/* Step 4 (Algorithm 1 lines 11-13): compressing the whole field. */
+/* Step 4 (Section 3): compressing the whole field with the compressor
+ * Algorithm 1 selects. */
 typedef struct {
   uint64_t bits, values, blocks;
   double bitrate, sse, mse, psnr, maxerr, vr, eb_abs;

@@ -1,4 +1,4 @@
-// Step 4 of Algorithm 1 (lines 11-13) for ZFP: fixed-accuracy compression
+// Step 4 (Section 3; Algorithm 1's ZFP branch) for ZFP: fixed-accuracy compression
 // of every block of the whole field at eb_abs into one bit stream, and the
 // decompression that gives the true bit-rate and PSNR.
 //

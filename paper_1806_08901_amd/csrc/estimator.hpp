@@ -1,7 +1,7 @@
 // The estimator's device work, shared by the per-request kernels and the
 // batched kernels:
 //   * range pass: min/max/non-finite over all N values, one contiguous chunk
-//     per workgroup (Algorithm 1, line 2);
+//     per workgroup (Algorithm 1's error bound);
 //   * ZFP pass: every sampled block through block-floating-point, transform,
 //     reorder, negabinary, embedded-coding count and decode (Sections 4.2, 5.2);
 //   * SZ pass: Lorenzo prediction, quantization codes and their histogram
@@ -141,7 +141,7 @@ __device__ inline bool pass_complete(const Parts &p, const Parts &gp, PassSync *
 }
 
 // ===========================================================================
-// Value range (Algorithm 1, line 2)
+// Value range (Algorithm 1's error bound)
 // ===========================================================================
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));

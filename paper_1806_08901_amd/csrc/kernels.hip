@@ -1,5 +1,5 @@
 // Per-request kernels of the estimator and their host-side launchers.
-//   k_range : value range over all N values (Algorithm 1, line 2)
+//   k_range : value range over all N values (Algorithm 1's error bound)
 //   k_zfp   : ZFP bits and decoded error of the sampled blocks (Section 5.2)
 //   k_sz    : Lorenzo/quantization codes and their histogram (Section 5.1)
 //   k_ovf   : counts the codes that fell outside the SZ pass's LDS window

@@ -643,7 +643,7 @@ int szsel_set_debug(szsel_ctx *c, const szsel_debug *d) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Step 4 (Algorithm 1 lines 11-13): ZFP compression of the whole field
+// Step 4 (Section 3; Algorithm 1's ZFP branch): ZFP compression of the whole field
 // ---------------------------------------------------------------------------
 
 static int64_t zc_num_blocks(const int64_t *dims, int nd) {

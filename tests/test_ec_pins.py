@@ -1,5 +1,5 @@
 """Pins of the oracle's point sub-sampling of the ZFP side (Sections 5.2.1
-and 5.2.2; Algorithm 1 lines 4-6): sample positions, the interpolated
+and 5.2.2; Algorithm 1's pointwise sampling): sample positions, the interpolated
 significant-bit count, the truncation error of a sampled coefficient, the
 inverse-transform gains, and what the selection does with them.  CPU only."""
 import math

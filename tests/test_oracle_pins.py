@@ -16,7 +16,7 @@ import oracle
 
 
 # ---------------------------------------------------------------------------
-# O1: value range (Algorithm 1, line 2)
+# O1: value range (Algorithm 1's error bound)
 # ---------------------------------------------------------------------------
 
 def test_range_matches_numpy():

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Step 4 ZFP compressor (Algorithm 1 lines 11-13):
+"""Pins of the oracle's Step 4 ZFP compressor (Section 3; Algorithm 1's ZFP branch):
 the stream round trip, agreement with the estimator's exact bit count, the
 edge padding of partial blocks, and an independent decoder of the stream
 format.  CPU only."""
