@@ -1350,17 +1350,19 @@ __device__ inline void hist_add(const int (&code)[N], bool active, uint32_t *s_h
     uint32_t mine = 0;
 #pragma unroll
     for (int k = 0; k < N; k++) mine += (uint32_t)out[k];
-    // exclusive prefix of the lanes' counts (Hillis-Steele)
-    uint32_t inc = mine;
+    // exclusive prefix of the lanes' counts and the wave's total, one bit
+    // of the counts (at most N) at a time: a ballot of the bit, the lanes
+    // below that have it (mbcnt) and its population count
+    uint32_t below = 0, total = 0;
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = __shfl_up(inc, d);
-      if (lane >= d) inc += o;
+    for (int b = 0; (1 << b) <= N; b++) {
+      const uint64_t m = __ballot((mine >> b) & 1u);
+      below += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+      total += (uint32_t)__popcll(m) << b;
     }
-    const uint32_t total = (uint32_t)__shfl(inc, kWave - 1);
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(s_n, total);
-    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + inc - mine;
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + below;
 #pragma unroll
     for (int k = 0; k < N; k++)
       if (out[k]) {

@@ -228,6 +228,33 @@ def test_turb512_full_dump_tight_bounds(ctx, turb512, eb):
     assert int((od["hist"] > 0).sum()) > 4096  # wider than the SZ pass's LDS window
 
 
+@pytest.mark.parametrize("eb", [1e-2, 1e-6])
+def test_turb512_long_sz_workgroups(ctx, turb512, eb):
+    """512^3 with SZ workgroups of 2,048 sampled blocks (8 tiles, 131,072
+    points per workgroup, 52 workgroups): at 1e-2 most points share a few
+    bins of the LDS window, at 1e-6 most codes go through the overflow
+    regions.  Codes and the histogram equal the oracle's bin for bin, and
+    the results equal the default schedule's."""
+    from paper_1806_08901_amd import szsel
+    _note("turb512 long SZ workgroups eb", eb)
+    stride = (5, 4, 1)
+    ref = ctx.select(turb512, eb, stride=stride)
+    nblk = oracle.num_sampled_blocks((512, 512, 512), stride)
+    bufs = debug_buffers(torch, nblk, 3)
+    try:
+        ctx.set_option(szsel.OPT_SZ_WGS, 1)  # 64 SZ workgroups for 106,496 blocks
+        ctx.set_debug(bufs)
+        gpu = ctx.select(turb512, eb, stride=stride)
+    finally:
+        ctx.set_option(szsel.OPT_SZ_WGS, 0)
+    gd = debug_to_numpy(bufs, nblk, 3)
+    assert gpu == ref
+    orc, od = oracle.select(turb512.cpu().numpy(), eb, stride=stride, dump=True)
+    assert_matches_oracle(gpu, orc, "turb512 long SZ workgroups eb %g" % eb)
+    assert np.array_equal(gd["hist"], od["hist"])
+    assert np.array_equal(gd["codes"], od["codes"])
+
+
 @pytest.mark.parametrize("dtype,offset,want", [(torch.float32, 0.5, 6.25), (torch.float64, 0.25, 10.0)])
 def test_sz_bitrate_hand_fixture(ctx, dtype, offset, want):
     """The 16-value field whose codes are known by construction (8 x 0, 4 x 1,
