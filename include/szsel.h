@@ -221,8 +221,8 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   launch without a graph); read with szsel_profile_read.
  * SZSEL_OPT_AUTOTUNE: nonzero lets szsel_select_batch time a few launch
  *   shapes (workgroups per request and pass, ZFP waves per launch class,
- *   request groups, how the counts are shared, overflow codes per slice of
- *   the overflow pass) the first
+ *   request groups, stream lanes, how the counts are shared, overflow codes
+ *   per slice of the overflow pass) the first
  *   time it sees a batch shape and keep the fastest; 0 (default) uses the
  *   fixed schedule.  The results do not depend on it.  The schedules are
  *   kept per device architecture and batch shape (request count, and per
@@ -261,6 +261,12 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   after another on a side stream and group g's sampled passes start when
  *   its scans are done, so the scans of later groups overlap the sampled
  *   passes of earlier ones.
+ * SZSEL_OPT_BATCH_LANES: stream lanes of a batch of one request group
+ *   (1 or 2, default 2; 0 restores it): with 2, the ZFP and SZ launches of
+ *   alternate launch classes (dtype, rank, alignment, point sub-sampling)
+ *   run on two streams between the range scans and the overflow pass, so
+ *   that the passes of different classes overlap; a batch of one class
+ *   runs on one stream either way.
  * SZSEL_OPT_RANGE_GRID: workgroups of a batch's range-scan launch (0 =
  *   default, one per scan chunk; k = 1..64: k per CU, each looping over
  *   the launch's chunks, which leaves the other wave slots of every CU to
@@ -288,7 +294,8 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
 enum { SZSEL_OPT_SZ_OFFSET = 1, SZSEL_OPT_PROFILE = 2, SZSEL_OPT_AUTOTUNE = 3,
        SZSEL_OPT_BATCH_GRAPH = 4, SZSEL_OPT_SZ_WGS = 5, SZSEL_OPT_ZFP_CHUNK = 6,
        SZSEL_OPT_RANGE_WGS = 7, SZSEL_OPT_BATCH_GROUPS = 8, SZSEL_OPT_HUFFMAN = 9,
-       SZSEL_OPT_EC_SAMPLING = 10, SZSEL_OPT_BATCH_SHARE = 11, SZSEL_OPT_RANGE_GRID = 12 };
+       SZSEL_OPT_EC_SAMPLING = 10, SZSEL_OPT_BATCH_SHARE = 11, SZSEL_OPT_RANGE_GRID = 12,
+       SZSEL_OPT_BATCH_LANES = 13 };
 int szsel_set_option(szsel_ctx *ctx, int option, double value);
 
 /* ---------------------------------------------------------------------

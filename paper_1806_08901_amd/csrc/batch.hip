@@ -249,6 +249,20 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       k = e;
     }
   }
+  // one request group and two lanes: the ZFP and SZ launches of alternate
+  // classes go to two streams (a class's SZ launch follows its own ZFP
+  // launch; the classes are independent until the overflow pass), so that
+  // one class's latency-bound pass runs beside another's VALU-bound one
+  if (G == 1 && tu.lanes > 1) {
+    std::vector<int> keys;
+    for (BatchLaunch &L : p.launches) {
+      if (L.pass != kBatchZfp && L.pass != kBatchSz) continue;
+      const int key = ((L.dtype * 8 + L.nd) * 2 + L.vec) * 2 + (L.ec ? 1 : 0);
+      int ord = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
+      if (ord == (int)keys.size()) keys.push_back(key);
+      L.lane = ord & 1;
+    }
+  }
   // variable workspace
   p.voff.resize((size_t)n);
   p.var = 0;
@@ -267,6 +281,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     p.sig.push_back(((uint64_t)L.group << 59) | ((uint64_t)L.pass << 56) | ((uint64_t)L.dtype << 52) | ((uint64_t)L.nd << 48) |
                     ((uint64_t)L.vec << 47) | ((uint64_t)L.ec << 46) | ((uint64_t)L.grid << 24) |
                     ((uint64_t)L.c0 << 12) | (uint64_t)L.c1);
+  for (const BatchLaunch &L : p.launches) p.sig.push_back((uint64_t)L.lane);
   for (size_t v : p.voff) p.sig.push_back(v);
   return SZSEL_OK;
 }
@@ -410,6 +425,7 @@ void tune_fields(Tune &t, F f) {
   f("range_wgs_q", t.range_wgs_q);
   f("range_grid", t.range_grid);
   f("groups", t.groups);
+  f("lanes", t.lanes);
   f("ovf_slice", t.ovf_slice);
   f("share", t.share);
 }
@@ -456,7 +472,7 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     v = (int)x;
   });
   return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.zfp_waves >= 1 && t.range_wgs_q >= 1 &&
-         t.range_grid >= 0 &&
+         t.range_grid >= 0 && t.lanes >= 1 && t.lanes <= 2 &&
          t.ovf_slice >= 1 && t.share <= 3;
 }
 
@@ -626,18 +642,39 @@ hipError_t timed_launch(const BatchLaunch &L, hipStream_t s, LaunchTimer *lt) {
   return e;
 }
 
-// Every launch of plan p, on stream s.  With G > 1 request groups the
-// range scans of all groups run back to back on one side stream, each
-// group's followed by an event, and the sampled passes of group g run on s
-// once group g's scans are done: the scans of later groups overlap the
-// sampled passes of earlier ones, and a graph captured from this forks into
-// two streams whatever G is.  s waits for the side stream's last scan (its
-// own waits already do) before the results are read.
+// Every launch of plan p, on stream s.  With one request group and launches
+// on lane 1, the side stream forks from s after the range scans, takes the
+// lane-1 ZFP and SZ launches while s takes the others, and s waits for it
+// before the overflow pass.  With G > 1 request groups the range scans of
+// all groups run back to back on the side stream, each group's followed
+// by an event, and the sampled passes of group g run on s once group g's
+// scans are done: the scans of later groups overlap the sampled passes of
+// earlier ones.  Either way a graph captured from this forks into two
+// streams, and s waits for the side stream (its own waits already do)
+// before the results are read.  Timed launches (the profile) all run on s,
+// one after another, so that their event pairs time one launch each.
 hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTimer *lt = nullptr) {
   hipError_t e = hipSuccess;
   const int G = p.groups;
   if (G == 1) {
-    for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
+    bool lanes = false;
+    for (const BatchLaunch &L : p.launches) lanes = lanes || L.lane != 0;
+    if (!lanes || lt) {
+      for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
+      return e;
+    }
+    // the range launches, then the sampled passes on two lanes (the side
+    // stream forked after the scans and joined before the overflow pass)
+    const size_t n = p.launches.size();
+    size_t k = 0;
+    for (; k < n && p.launches[k].pass == kBatchRange && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
+    if (e == hipSuccess) e = hipEventRecord(bs->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs->scan, bs->fork, 0);
+    for (; k < n && (p.launches[k].pass == kBatchZfp || p.launches[k].pass == kBatchSz) && e == hipSuccess; k++)
+      e = timed_launch(p.launches[k], p.launches[k].lane ? bs->scan : s, lt);
+    if (e == hipSuccess) e = hipEventRecord(bs->scanned[0], bs->scan);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, bs->scanned[0], 0);
+    for (; k < n && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
     return e;
   }
   hipStream_t scan = bs->scan;
@@ -772,15 +809,36 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       if (make_plan(ctx, ncu, reqs, n, c, p, why) != SZSEL_OK) return SZSEL_OK;
       if (bind_plan(bs, p, budget, why) != hipSuccess) return SZSEL_OK;
       hipError_t q = upload_meta(bs, s);
-      if (q == hipSuccess) q = enqueue_plan(bs, p, s);  // warm-up (first touch, code load)
+      // timed the way the batch will run: a captured graph replayed when
+      // graphs are on (launches on two streams overlap differently there
+      // than when enqueued one by one), else the launches themselves
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ge = nullptr;
+      if (q == hipSuccess && opt.graph) {
+        q = hipStreamBeginCapture(bs->cap, hipStreamCaptureModeThreadLocal);
+        if (q == hipSuccess) {
+          const hipError_t q2 = enqueue_plan(bs, p, bs->cap);
+          q = hipStreamEndCapture(bs->cap, &gr);
+          if (q == hipSuccess) q = q2;
+        }
+        if (q == hipSuccess) q = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+      }
+      auto once = [&]() { return ge ? hipGraphLaunch(ge, s) : enqueue_plan(bs, p, s); };
+      if (q == hipSuccess) q = once();  // warm-up (first touch, code load)
       for (int rep = 0; rep < 5 && q == hipSuccess; rep++) {  // best of 5
         float one = 0.f;
         q = hipEventRecord(t0, s);
-        if (q == hipSuccess) q = enqueue_plan(bs, p, s);
+        if (q == hipSuccess) q = once();
         if (q == hipSuccess) q = hipEventRecord(t1, s);
         if (q == hipSuccess) q = hipEventSynchronize(t1);
         if (q == hipSuccess) q = hipEventElapsedTime(&one, t0, t1);
         ms = std::min(ms, one);
+      }
+      if (ge || gr) {
+        const hipError_t qs = hipStreamSynchronize(s);  // (the last replay is done unless a step failed)
+        if (q == hipSuccess) q = qs;
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (gr) (void)hipGraphDestroy(gr);
       }
       if (q != hipSuccess) {
         msg = std::string("autotune: ") + hipGetErrorString(q);
@@ -793,6 +851,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     int rc = time_of(cur, best_ms);
     const int share_opts[] = {0, 1, 2, 3};
     const int group_opts[] = {1, 2, 4, 8};
+    const int lane_opts[] = {1, 2};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {16, 32, 64, 128};  // ZFP waves per CU of a launch class
     const int range_opts[] = {1, 2, 4, 8, 16, 32, 64};  // quarters of the CU count
@@ -817,6 +876,17 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       if (rc != SZSEL_OK || v == cur.groups || v > n) continue;
       Tune c = cur;
       c.groups = v;
+      float ms = 0.f;
+      rc = time_of(c, ms);
+      if (rc == SZSEL_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = c;
+      }
+    }
+    for (int v : lane_opts) {
+      if (rc != SZSEL_OK || v == cur.lanes || cur.groups > 1) continue;
+      Tune c = cur;
+      c.lanes = v;
       float ms = 0.f;
       rc = time_of(c, ms);
       if (rc == SZSEL_OK && ms < best_ms) {

@@ -39,6 +39,7 @@ struct BatchLaunch {
   int c0, c1;
   uint32_t items;  // work items
   uint32_t grid;   // workgroups (the overflow and entropy passes loop over their items)
+  int lane = 0;    // ZFP and SZ launches: stream lane of the launch's class (0: the caller's stream)
 };
 hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 
@@ -57,6 +58,8 @@ struct Tune {
                              // per CU that loop over all the launch's chunks (a resident scan
                              // that leaves the other wave slots to the sampled passes)
   int groups = 1;            // batches: request groups pipelined on parallel streams
+  int lanes = 2;             // batches of one request group: stream lanes the ZFP and SZ
+                             // launches of the launch classes are dealt to (1 or 2)
   int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
                              // count is the batch's, 2 = both are the batch's, 3 = the SZ

@@ -554,6 +554,12 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
     c->bopt.fixed.range_grid = v;
     return SZSEL_OK;
   }
+  if (option == SZSEL_OPT_BATCH_LANES) {
+    const int v = (int)value;
+    if (value != (double)v || v < 0 || v > 2) return fail(c, SZSEL_EINVAL, "batch lanes: 0, 1 or 2");
+    c->bopt.fixed.lanes = v ? v : Tune().lanes;
+    return SZSEL_OK;
+  }
   if (option == SZSEL_OPT_BATCH_GROUPS) {
     const int v = (int)value;
     if (value != (double)v || v < 0 || v > 8) return fail(c, SZSEL_EINVAL, "request groups: 0 to 8");

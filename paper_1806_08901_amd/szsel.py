@@ -23,7 +23,7 @@ FLAG_EB_EXCEEDS, FLAG_NO_BLOCKS, FLAG_BAD_EB, FLAG_NO_HUFFMAN = 8, 16, 32, 64
 FLAG_EC_SAMPLED, FLAG_FAILED = 128, 256
 OPT_SZ_OFFSET, OPT_PROFILE, OPT_AUTOTUNE, OPT_BATCH_GRAPH = 1, 2, 3, 4
 OPT_SZ_WGS, OPT_ZFP_CHUNK, OPT_RANGE_WGS, OPT_BATCH_GROUPS, OPT_HUFFMAN = 5, 6, 7, 8, 9
-OPT_EC_SAMPLING, OPT_BATCH_SHARE, OPT_RANGE_GRID = 10, 11, 12
+OPT_EC_SAMPLING, OPT_BATCH_SHARE, OPT_RANGE_GRID, OPT_BATCH_LANES = 10, 11, 12, 13
 NBINS = 65536
 
 

@@ -150,6 +150,36 @@ def test_request_group_schedules_equal_single_calls(ctx):
         ctx.set_option(szsel.OPT_BATCH_GRAPH, 1)
 
 
+def test_stream_lanes_equal_single_calls(ctx):
+    """One stream lane and two (the ZFP and SZ launches of alternate launch
+    classes on a side stream between the scans and the overflow pass), with
+    each share mode's launch shapes, captured graphs replayed three times
+    with a single call between replays, and uncaptured: the single calls'
+    results every time; a lane count outside 0..2 is rejected."""
+    from paper_1806_08901_amd import szsel
+    items = _items(_fields(), ebs=(1e-3, 1e-5))
+    singles = _singles(ctx, items)
+    f, eb, mode, st, op = items[0]
+    try:
+        for share in (0, 3):
+            ctx.set_option(szsel.OPT_BATCH_SHARE, share)
+            for lanes in (2, 1):
+                ctx.set_option(szsel.OPT_BATCH_LANES, lanes)
+                for graph in (1, 0):
+                    ctx.set_option(szsel.OPT_BATCH_GRAPH, graph)
+                    for rep in range(3):
+                        _note("lanes", lanes, "share", share, "graph", graph, "rep", rep)
+                        assert ctx.select_batch(items) == singles, "lanes %d share %d graph %d rep %d" % (
+                            lanes, share, graph, rep)
+                        assert ctx.run(op, f, eb, mode, st) == singles[0]
+        with pytest.raises(szsel.SzselError):
+            ctx.set_option(szsel.OPT_BATCH_LANES, 3)
+    finally:
+        ctx.set_option(szsel.OPT_BATCH_LANES, 0)
+        ctx.set_option(szsel.OPT_BATCH_SHARE, 0)
+        ctx.set_option(szsel.OPT_BATCH_GRAPH, 1)
+
+
 def test_rotating_result_buffers(ctx):
     """Three result buffers used in turn over seven calls with no host
     synchronisation (from the second round on, each destination's graph

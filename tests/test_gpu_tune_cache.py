@@ -58,7 +58,7 @@ def test_tuned_schedule_is_reused_by_a_new_process(tmp_path):
     entry = json.loads(lines[2])
     assert entry["arch"].startswith("gfx") and len(entry["key"]) > 1
     assert set(entry["tune"]) == {"sz_wgs_q", "zfp_chunk", "zfp_waves", "range_wgs_q", "range_grid", "groups",
-                                 "ovf_slice", "share"}
+                                 "lanes", "ovf_slice", "share"}
     second = _run(cache)
     assert open(cache).read().splitlines() == lines  # found, not tuned again
     assert first["same"] and second["same"]
