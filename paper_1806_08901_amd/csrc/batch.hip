@@ -214,8 +214,10 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     }
     p.first[(size_t)ps * (n + 1) + n] = acc;
   }
-  // launches: per pass, one per contiguous class (the range, overflow and
-  // entropy passes, whose kernels take any class, one per request group)
+  // launches: per pass, one per contiguous class (the range pass, whose
+  // kernel takes any class, one per request group; the overflow and entropy
+  // passes likewise unless the classes run on two lanes)
+  const bool class_lanes = G == 1 && tu.lanes > 1;
   p.launches.clear();
   for (int ps = 0; ps < kBatchPasses; ps++) {
     const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
@@ -224,7 +226,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       auto same_class = [&](int a, int b) {
         if (tg[a] != tg[b]) return false;
         const ReqDesc &x = p.tab[a], &y = p.tab[b];
-        if (ps == kBatchRange || ps == kBatchOvf || ps == kBatchEnt) return true;
+        if (ps == kBatchRange || ((ps == kBatchOvf || ps == kBatchEnt) && !class_lanes)) return true;
         return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec && (x.ec != 0) == (y.ec != 0);
       };
       while (e < n && same_class(k, e)) e++;
@@ -249,14 +251,14 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       k = e;
     }
   }
-  // one request group and two lanes: the ZFP and SZ launches of alternate
-  // classes go to two streams (a class's SZ launch follows its own ZFP
-  // launch; the classes are independent until the overflow pass), so that
-  // one class's latency-bound pass runs beside another's VALU-bound one
-  if (G == 1 && tu.lanes > 1) {
+  // one request group and two lanes: the launches after the range scans of
+  // alternate classes go to two streams (a class's passes follow each other
+  // on its lane; the classes are independent), so that one class's
+  // latency-bound pass runs beside another's VALU-bound one
+  if (class_lanes) {
     std::vector<int> keys;
     for (BatchLaunch &L : p.launches) {
-      if (L.pass != kBatchZfp && L.pass != kBatchSz) continue;
+      if (L.pass == kBatchRange) continue;
       const int key = ((L.dtype * 8 + L.nd) * 2 + L.vec) * 2 + (L.ec ? 1 : 0);
       int ord = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
       if (ord == (int)keys.size()) keys.push_back(key);
@@ -644,8 +646,8 @@ hipError_t timed_launch(const BatchLaunch &L, hipStream_t s, LaunchTimer *lt) {
 
 // Every launch of plan p, on stream s.  With one request group and launches
 // on lane 1, the side stream forks from s after the range scans, takes the
-// lane-1 ZFP and SZ launches while s takes the others, and s waits for it
-// before the overflow pass.  With G > 1 request groups the range scans of
+// lane-1 launches while s takes the others, and s waits for it at the
+// end.  With G > 1 request groups the range scans of
 // all groups run back to back on the side stream, each group's followed
 // by an event, and the sampled passes of group g run on s once group g's
 // scans are done: the scans of later groups overlap the sampled passes of
@@ -663,18 +665,16 @@ hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTime
       for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
       return e;
     }
-    // the range launches, then the sampled passes on two lanes (the side
-    // stream forked after the scans and joined before the overflow pass)
+    // the range launches, then the other passes on two lanes (the side
+    // stream forked after the scans and joined at the end)
     const size_t n = p.launches.size();
     size_t k = 0;
     for (; k < n && p.launches[k].pass == kBatchRange && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
     if (e == hipSuccess) e = hipEventRecord(bs->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(bs->scan, bs->fork, 0);
-    for (; k < n && (p.launches[k].pass == kBatchZfp || p.launches[k].pass == kBatchSz) && e == hipSuccess; k++)
-      e = timed_launch(p.launches[k], p.launches[k].lane ? bs->scan : s, lt);
+    for (; k < n && e == hipSuccess; k++) e = timed_launch(p.launches[k], p.launches[k].lane ? bs->scan : s, lt);
     if (e == hipSuccess) e = hipEventRecord(bs->scanned[0], bs->scan);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, bs->scanned[0], 0);
-    for (; k < n && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
     return e;
   }
   hipStream_t scan = bs->scan;
