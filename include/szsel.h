@@ -262,11 +262,13 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   its scans are done, so the scans of later groups overlap the sampled
  *   passes of earlier ones.
  * SZSEL_OPT_BATCH_LANES: stream lanes of a batch of one request group
- *   (1 or 2, default 2; 0 restores it): with 2, the ZFP and SZ launches of
- *   alternate launch classes (dtype, rank, alignment, point sub-sampling)
- *   run on two streams between the range scans and the overflow pass, so
- *   that the passes of different classes overlap; a batch of one class
- *   runs on one stream either way.
+ *   (1..3, default 2; 0 restores it).  1 runs every launch on the caller's
+ *   stream.  2 and 3 run the passes after the range scans on two streams
+ *   (the caller's and a side stream joined before the results are read),
+ *   so that the passes of the two lanes overlap: 2 deals the launch
+ *   classes (dtype, rank, alignment, point sub-sampling) to the lanes in
+ *   turn, or, for a batch of one class, cuts the requests where half of the
+ *   sampled work lies before them; 3 always makes that cut.
  * SZSEL_OPT_RANGE_GRID: workgroups of a batch's range-scan launch (0 =
  *   default, one per scan chunk; k = 1..64: k per CU, each looping over
  *   the launch's chunks, which leaves the other wave slots of every CU to

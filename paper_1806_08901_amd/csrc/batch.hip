@@ -182,6 +182,44 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     p.tab[k] = d[ord[k]];
     tg[k] = grp[ord[k]];
   }
+  // one request group and two lanes: the passes after the range scans run
+  // on the caller's stream for the table entries of lane 0 and on a side
+  // stream for those of lane 1, so that the passes of the two lanes
+  // overlap.  tu.lanes == 2 deals the launch classes (dtype, rank,
+  // alignment, point sub-sampling) to the lanes in turn when there are
+  // several (one class's latency-bound pass then runs beside another's
+  // VALU-bound one); with one class, or tu.lanes == 3, the table is cut
+  // where half of the estimated sampled work lies before it (sampled
+  // values, binary64 ones counted twice), a class cut in two getting
+  // launches of its own on either side.
+  const bool class_lanes = G == 1 && tu.lanes > 1;
+  std::vector<int> lane((size_t)n, 0);
+  auto class_of = [&](int k) {
+    const ReqDesc &r = p.tab[k];
+    return ((r.dtype * 8 + r.nd) * 2 + r.vec) * 2 + (r.ec ? 1 : 0);
+  };
+  int nclass = 0;
+  for (int k = 0; k < n; k++) nclass += (k == 0 || class_of(k) != class_of(k - 1)) ? 1 : 0;
+  if (class_lanes && tu.lanes == 2 && nclass > 1) {
+    int ord = 0;
+    for (int k = 0; k < n; k++) {
+      if (k > 0 && class_of(k) != class_of(k - 1)) ord++;
+      lane[k] = ord & 1;
+    }
+  } else if (class_lanes) {
+    std::vector<double> w((size_t)n);
+    double total = 0.0;
+    for (int k = 0; k < n; k++) {
+      const ReqDesc &r = p.tab[k];
+      w[k] = (double)r.nblk * (double)(1 << (2 * r.nd)) * (r.dtype == SZSEL_F32 ? 1.0 : 2.0);
+      total += w[k];
+    }
+    double before = 0.0;
+    for (int k = 0; k < n; k++) {
+      lane[k] = before + 0.5 * w[k] > 0.5 * total ? 1 : 0;
+      before += w[k];
+    }
+  }
   // range scans shared by runs of requests on the same field
   std::vector<bool> owner((size_t)n, true);
   for (int k = 0; k < n;) {
@@ -214,10 +252,9 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
     }
     p.first[(size_t)ps * (n + 1) + n] = acc;
   }
-  // launches: per pass, one per contiguous class (the range pass, whose
-  // kernel takes any class, one per request group; the overflow and entropy
-  // passes likewise unless the classes run on two lanes)
-  const bool class_lanes = G == 1 && tu.lanes > 1;
+  // launches: per pass, one per contiguous class and lane (the range pass,
+  // whose kernel takes any class, one per request group; the overflow and
+  // entropy passes likewise unless the batch runs on two lanes)
   p.launches.clear();
   for (int ps = 0; ps < kBatchPasses; ps++) {
     const uint32_t *f = &p.first[(size_t)ps * (n + 1)];
@@ -226,7 +263,9 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       auto same_class = [&](int a, int b) {
         if (tg[a] != tg[b]) return false;
         const ReqDesc &x = p.tab[a], &y = p.tab[b];
-        if (ps == kBatchRange || ((ps == kBatchOvf || ps == kBatchEnt) && !class_lanes)) return true;
+        if (ps == kBatchRange) return true;
+        if (lane[a] != lane[b]) return false;
+        if ((ps == kBatchOvf || ps == kBatchEnt) && !class_lanes) return true;
         return x.dtype == y.dtype && x.nd == y.nd && x.vec == y.vec && (x.ec != 0) == (y.ec != 0);
       };
       while (e < n && same_class(k, e)) e++;
@@ -241,6 +280,7 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       L.first = nullptr;
       L.c0 = k;
       L.c1 = e;
+      L.lane = ps == kBatchRange ? 0 : lane[k];
       L.items = f[e] - f[k];
       L.grid = L.items;
       if (ps == kBatchRange && tu.range_grid > 0)
@@ -249,20 +289,6 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
       if (ps == kBatchEnt) L.grid = std::min<uint32_t>(L.items, 8u * (uint32_t)ncu);
       if (L.items) p.launches.push_back(L);
       k = e;
-    }
-  }
-  // one request group and two lanes: the launches after the range scans of
-  // alternate classes go to two streams (a class's passes follow each other
-  // on its lane; the classes are independent), so that one class's
-  // latency-bound pass runs beside another's VALU-bound one
-  if (class_lanes) {
-    std::vector<int> keys;
-    for (BatchLaunch &L : p.launches) {
-      if (L.pass == kBatchRange) continue;
-      const int key = ((L.dtype * 8 + L.nd) * 2 + L.vec) * 2 + (L.ec ? 1 : 0);
-      int ord = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
-      if (ord == (int)keys.size()) keys.push_back(key);
-      L.lane = ord & 1;
     }
   }
   // variable workspace
@@ -474,7 +500,7 @@ bool parse_tune_line(const std::string &line, std::string &build, std::string &a
     v = (int)x;
   });
   return ok && t.groups >= 1 && t.sz_wgs_q >= 1 && t.zfp_chunk >= 1 && t.zfp_waves >= 1 && t.range_wgs_q >= 1 &&
-         t.range_grid >= 0 && t.lanes >= 1 && t.lanes <= 2 &&
+         t.range_grid >= 0 && t.lanes >= 1 && t.lanes <= 3 &&
          t.ovf_slice >= 1 && t.share <= 3;
 }
 
@@ -851,7 +877,7 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     int rc = time_of(cur, best_ms);
     const int share_opts[] = {0, 1, 2, 3};
     const int group_opts[] = {1, 2, 4, 8};
-    const int lane_opts[] = {1, 2};
+    const int lane_opts[] = {1, 2, 3};
     const int sz_opts[] = {2, 4, 8, 16, 32, 64, 128};
     const int zfp_opts[] = {16, 32, 64, 128};  // ZFP waves per CU of a launch class
     const int range_opts[] = {1, 2, 4, 8, 16, 32, 64};  // quarters of the CU count

@@ -58,8 +58,10 @@ struct Tune {
                              // per CU that loop over all the launch's chunks (a resident scan
                              // that leaves the other wave slots to the sampled passes)
   int groups = 1;            // batches: request groups pipelined on parallel streams
-  int lanes = 2;             // batches of one request group: stream lanes the ZFP and SZ
-                             // launches of the launch classes are dealt to (1 or 2)
+  int lanes = 2;             // batches of one request group: 1 = one stream; 2 = two stream
+                             // lanes for the passes after the scans, launch classes dealt
+                             // in turn (one class: cut at half the work); 3 = two lanes
+                             // cut at half the work
   int ovf_slice = kOvfPerSlice;  // overflow codes per slice of the overflow pass
   int share = 0;             // batches: 0 = SZ and range counts per request, 1 = the SZ
                              // count is the batch's, 2 = both are the batch's, 3 = the SZ

@@ -556,7 +556,7 @@ int szsel_set_option(szsel_ctx *c, int option, double value) {
   }
   if (option == SZSEL_OPT_BATCH_LANES) {
     const int v = (int)value;
-    if (value != (double)v || v < 0 || v > 2) return fail(c, SZSEL_EINVAL, "batch lanes: 0, 1 or 2");
+    if (value != (double)v || v < 0 || v > 3) return fail(c, SZSEL_EINVAL, "batch lanes: 0 to 3");
     c->bopt.fixed.lanes = v ? v : Tune().lanes;
     return SZSEL_OK;
   }

@@ -151,11 +151,12 @@ def test_request_group_schedules_equal_single_calls(ctx):
 
 
 def test_stream_lanes_equal_single_calls(ctx):
-    """One stream lane and two (the ZFP and SZ launches of alternate launch
-    classes on a side stream between the scans and the overflow pass), with
-    each share mode's launch shapes, captured graphs replayed three times
-    with a single call between replays, and uncaptured: the single calls'
-    results every time; a lane count outside 0..2 is rejected."""
+    """One stream and two lanes (the passes after the scans of alternate
+    launch classes, or of the two halves of the sampled work, on a side
+    stream), with each share mode's launch shapes, captured graphs replayed
+    three times with a single call between replays, and uncaptured: the
+    single calls' results every time; a lane setting outside 0..3 is
+    rejected."""
     from paper_1806_08901_amd import szsel
     items = _items(_fields(), ebs=(1e-3, 1e-5))
     singles = _singles(ctx, items)
@@ -163,7 +164,7 @@ def test_stream_lanes_equal_single_calls(ctx):
     try:
         for share in (0, 3):
             ctx.set_option(szsel.OPT_BATCH_SHARE, share)
-            for lanes in (2, 1):
+            for lanes in (2, 3, 1):
                 ctx.set_option(szsel.OPT_BATCH_LANES, lanes)
                 for graph in (1, 0):
                     ctx.set_option(szsel.OPT_BATCH_GRAPH, graph)
@@ -173,7 +174,7 @@ def test_stream_lanes_equal_single_calls(ctx):
                             lanes, share, graph, rep)
                         assert ctx.run(op, f, eb, mode, st) == singles[0]
         with pytest.raises(szsel.SzselError):
-            ctx.set_option(szsel.OPT_BATCH_LANES, 3)
+            ctx.set_option(szsel.OPT_BATCH_LANES, 4)
     finally:
         ctx.set_option(szsel.OPT_BATCH_LANES, 0)
         ctx.set_option(szsel.OPT_BATCH_SHARE, 0)
