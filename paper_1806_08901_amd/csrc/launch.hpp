@@ -39,7 +39,7 @@ struct BatchLaunch {
   int c0, c1;
   uint32_t items;  // work items
   uint32_t grid;   // workgroups (the overflow and entropy passes loop over their items)
-  int lane = 0;    // ZFP and SZ launches: stream lane of the launch's class (0: the caller's stream)
+  int lane = 0;    // launches after the range scans: stream lane (0: the caller's stream, 1: the side stream)
 };
 hipError_t launch_batch_pass(const BatchLaunch &a, hipStream_t s);
 

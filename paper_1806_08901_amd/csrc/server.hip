@@ -274,6 +274,10 @@ int szsel_server_create(szsel_server **out, szsel_ctx *ctx, void *pool, size_t p
   s->arena.init(pool_bytes);
   if (lane_workspace_bytes) s->lane_budget = lane_workspace_bytes;
   s->bopt.graph = false;
+  // one stream per lane: launched one by one (no graph), the two-stream
+  // batch layout measured slower than one stream, and the lanes already
+  // overlap each other's batches
+  s->bopt.fixed.lanes = 1;
   if (const char *v = std::getenv("SZSEL_SERVER_FAIL_BATCHES")) s->fail_batches = std::max(0, std::atoi(v));
   if (ctx) {
     s->ncu = szsel::ctx_ncu(ctx);
