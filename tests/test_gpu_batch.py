@@ -181,6 +181,28 @@ def test_stream_lanes_equal_single_calls(ctx):
         ctx.set_option(szsel.OPT_BATCH_GRAPH, 1)
 
 
+@pytest.mark.parametrize("option,value", [("OPT_HUFFMAN", 1), ("OPT_EC_SAMPLING", 1)])
+def test_stream_lanes_with_huffman_and_point_sampling(ctx, option, value):
+    """Two lanes with the exact Huffman pass (one launch per class and lane
+    after the entropy pass) and with point sub-sampling (the sub-sampling
+    ZFP kernels): the single calls' results under the same option, for both
+    lane settings, replayed twice."""
+    from paper_1806_08901_amd import szsel
+    opt = getattr(szsel, option)
+    items = _items(_fields(), ebs=(1e-3, 1e-5))
+    try:
+        ctx.set_option(opt, value)
+        singles = _singles(ctx, items)
+        for lanes in (2, 3):
+            ctx.set_option(szsel.OPT_BATCH_LANES, lanes)
+            for rep in range(2):
+                _note(option, "lanes", lanes, "rep", rep)
+                assert ctx.select_batch(items) == singles, "%s lanes %d rep %d" % (option, lanes, rep)
+    finally:
+        ctx.set_option(opt, 0)
+        ctx.set_option(szsel.OPT_BATCH_LANES, 0)
+
+
 def test_rotating_result_buffers(ctx):
     """Three result buffers used in turn over seven calls with no host
     synchronisation (from the second round on, each destination's graph
