@@ -698,14 +698,19 @@ hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTime
     for (; k < n && p.launches[k].pass == kBatchRange && e == hipSuccess; k++) e = timed_launch(p.launches[k], s, lt);
     if (e == hipSuccess) e = hipEventRecord(bs->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(bs->scan, bs->fork, 0);
+    const bool forked = e == hipSuccess;
     for (; k < n && e == hipSuccess; k++) e = timed_launch(p.launches[k], p.launches[k].lane ? bs->scan : s, lt);
-    if (e == hipSuccess) e = hipEventRecord(bs->scanned[0], bs->scan);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, bs->scanned[0], 0);
+    if (forked) {  // joined even after a failed launch: s must not run ahead of the side stream
+      hipError_t j = hipEventRecord(bs->scanned[0], bs->scan);
+      if (j == hipSuccess) j = hipStreamWaitEvent(s, bs->scanned[0], 0);
+      if (e == hipSuccess) e = j;
+    }
     return e;
   }
   hipStream_t scan = bs->scan;
   e = hipEventRecord(bs->fork, s);
   if (e == hipSuccess) e = hipStreamWaitEvent(scan, bs->fork, 0);
+  const bool forked = e == hipSuccess;
   for (int g = 0; g < G && e == hipSuccess; g++) {
     for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
       if (p.launches[k].group == g && p.launches[k].pass == kBatchRange) e = timed_launch(p.launches[k], scan, lt);
@@ -715,6 +720,9 @@ hipError_t enqueue_plan(BatchState *bs, const Plan &p, hipStream_t s, LaunchTime
     e = hipStreamWaitEvent(s, bs->scanned[g], 0);
     for (size_t k = 0; k < p.launches.size() && e == hipSuccess; k++)
       if (p.launches[k].group == g && p.launches[k].pass != kBatchRange) e = timed_launch(p.launches[k], s, lt);
+  }
+  if (forked && e != hipSuccess) {  // after a failure s still waits for all of the side stream
+    if (hipEventRecord(bs->scanned[0], scan) == hipSuccess) (void)hipStreamWaitEvent(s, bs->scanned[0], 0);
   }
   return e;
 }
