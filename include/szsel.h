@@ -227,7 +227,8 @@ int szsel_stride_for_rate(double r_sp, int ndims, const int64_t *dims, int32_t *
  *   fixed schedule.  The results do not depend on it.  The schedules are
  *   kept per device architecture and batch shape (request count, and per
  *   request dtype, rank, op, extents, strides, 16-byte alignment and which
- *   earlier request shares its field) for the process; when the
+ *   earlier request shares its field) and launch mode (graph or not: each
+ *   candidate is timed the way the batch will run) for the process; when the
  *   environment variable SZSEL_TUNE_CACHE names a file, they are also read
  *   from it on first use and every newly tuned one is appended to it (one
  *   JSON object per line; lines written by another build of the library

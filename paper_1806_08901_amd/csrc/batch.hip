@@ -807,8 +807,11 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     msg = std::string("batch: ") + hipGetErrorString(e);
     return SZSEL_EHIP;
   }
-  // knobs: the tuned ones for this batch shape, else the defaults
-  const std::vector<uint64_t> key = shape_key(reqs, n);
+  // knobs: the tuned ones for this batch shape (and launch mode: the
+  // autotuner times a graph replay or the launches, as the batch will run),
+  // else the defaults
+  std::vector<uint64_t> key = shape_key(reqs, n);
+  key.push_back(opt.graph ? 1u : 0u);
   Tune tu = opt.fixed;
   bool tuned = false;
   if (bs->have_last && bs->last_key == key && bs->last_auto == opt.autotune &&
