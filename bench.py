@@ -8,8 +8,8 @@ error bounds drawn from {1e-2 ... 1e-6}, block stride (5, 4, 1) -- estimated
 with Algorithm 1 for every field:
 
 * batched, autotuned: one szsel_select_batch per step (one launch per pass
-  and request class, HIP graph replay, the launch shape chosen by the
-  library's autotuner) -- this is `value`;
+  and request class, HIP graph replay, the launch shape and stream lanes
+  chosen by the library's autotuner) -- this is `value`;
 * batched with the fixed schedule, and plain (one szsel_select per field),
   with the speedups.
 
@@ -399,7 +399,8 @@ def batch_workload(args, torch, synth, szsel, name, cpu=False, profile_file=None
                    "shapes": [[list(sh), dt] for sh, dt in shapes],
                    "stride": {"2d": [20, 1], "3d": [5, 4, 1]},
                    "mode": "one szsel_select_batch per step (Algorithm 1 for every field; one launch "
-                           "per pass and request class, HIP graph replay, autotuned launch shape)",
+                           "per pass and request class, HIP graph replay, autotuned launch shape and "
+                           "stream lanes)",
                    "parallelism": "single GPU"},
         "roofline": roof,
         "passes": passes,

@@ -85,8 +85,8 @@ int make_plan(szsel_ctx *ctx, int ncu, const szsel_request *reqs, int n, const T
   // histogram's clearing and hand-over and the completion counters.  With
   // tu.share == 3 the SZ count is dealt within each launch class (dtype,
   // rank, alignment, point sub-sampling) instead: the classes run as
-  // launches of their own, one after another, and each should fill the
-  // chip (a small binary64 class dealt its share of the whole batch's count
+  // launches of their own (one after another, or two at a time on two
+  // stream lanes), and each should fill the chip (a small binary64 class dealt its share of the whole batch's count
   // runs on a few long workgroups).  The ZFP waves (tu.zfp_waves per CU)
   // are dealt within each launch class in every mode.
   if (n > 1) {

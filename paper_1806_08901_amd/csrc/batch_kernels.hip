@@ -1,6 +1,7 @@
 // Batched passes: one launch per pass covers every request of a batch (of
 // a request group; the ZFP and SZ passes, whose kernels are templates of
-// the dtype and rank, one launch per request class).  The requests sit in a device table ordered so that
+// the dtype and rank, one launch per request class, and on two stream
+// lanes every pass after the range scans one launch per class and lane).  The requests sit in a device table ordered so that
 // each launch covers a contiguous range [c0, c1); first[i] is the first work
 // item (workgroup) of table entry i in this pass, first[c1] the end.
 #include "estimator.hpp"
