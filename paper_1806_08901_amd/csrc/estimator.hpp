@@ -680,7 +680,7 @@ __device__ inline double tile_sse(const TileLds &L, int tile) {
       const int k = 4 * lane;
       v = (L.sse[k] + L.sse[k + 1]) + (L.sse[k + 2] + L.sse[k + 3]);
     }
-    sse = group_tree_sum<kWave>(v);
+    sse = group_tree_first<kWave>(v);
   }
   return sse;
 }
@@ -1074,7 +1074,7 @@ __device__ inline bool zfp_wg_quad(const ReqDesc &r, int w, TileLds &L) {
       if (r.dbg_zsse) r.dbg_zsse[j] = z.sse;
       if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
     }
-    wg_acc_push(L, group_tree_sum<kWave>(s));
+    wg_acc_push(L, group_tree_first<kWave>(s));
   }
   Part v;
   v.s = 0.0;
@@ -1123,7 +1123,7 @@ __device__ inline bool zfp_wg(const ReqDesc &r, int w, TileLds &L) {
       if (r.dbg_zsse) r.dbg_zsse[j] = z.sse;
       if (r.dbg_zemax) r.dbg_zemax[j] = z.emax;
     }
-    wg_acc_push(L, group_tree_sum<kWave>(s));
+    wg_acc_push(L, group_tree_first<kWave>(s));
   }
   Part v;
   v.s = 0.0;
