@@ -839,7 +839,10 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
     // a candidate the planner rejects (more work items than a pass holds,
     // more workspace than the budget) times as never faster; only a HIP
     // error ends the search
-    auto time_of = [&](const Tune &c, float &ms) -> int {
+    // every candidate timed, for the final check of the closest ones
+    std::vector<std::pair<float, Tune>> seen;
+    // reps > 0: the best of reps runs; reps < 0: the median of -reps runs
+    auto time_of = [&](const Tune &c, float &ms, int reps = 5) -> int {
       Plan p;
       ms = 1e30f;
       std::string why;
@@ -862,14 +865,20 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       }
       auto once = [&]() { return ge ? hipGraphLaunch(ge, s) : enqueue_plan(bs, p, s); };
       if (q == hipSuccess) q = once();  // warm-up (first touch, code load)
-      for (int rep = 0; rep < 5 && q == hipSuccess; rep++) {  // best of 5
+      std::vector<float> runs;
+      for (int rep = 0; rep < (reps > 0 ? reps : -reps) && q == hipSuccess; rep++) {
         float one = 0.f;
         q = hipEventRecord(t0, s);
         if (q == hipSuccess) q = once();
         if (q == hipSuccess) q = hipEventRecord(t1, s);
         if (q == hipSuccess) q = hipEventSynchronize(t1);
         if (q == hipSuccess) q = hipEventElapsedTime(&one, t0, t1);
-        ms = std::min(ms, one);
+        if (q == hipSuccess) runs.push_back(one);
+      }
+      if (!runs.empty()) {
+        std::sort(runs.begin(), runs.end());
+        ms = reps > 0 ? runs.front() : runs[runs.size() / 2];
+        if (reps > 0) seen.emplace_back(ms, c);
       }
       if (ge || gr) {
         const hipError_t qs = hipStreamSynchronize(s);  // (the last replay is done unless a step failed)
@@ -987,6 +996,30 @@ int batch_run(szsel_ctx *ctx, int ncu, BatchState *&bs, size_t budget, const szs
       }
     }
     if (std::memcmp(&before, &cur, sizeof(Tune)) == 0) break;  // nothing moved
+    }
+    // the closest candidates differ by little more than the noise of a
+    // best of 5: the three fastest distinct ones are timed again, 15 runs
+    // each, and the lowest median wins
+    if (rc == SZSEL_OK && seen.size() > 1) {
+      std::stable_sort(seen.begin(), seen.end(),
+                       [](const std::pair<float, Tune> &a, const std::pair<float, Tune> &b) { return a.first < b.first; });
+      std::vector<Tune> top;
+      for (const auto &c : seen) {
+        bool dup = false;
+        for (const Tune &t : top) dup = dup || std::memcmp(&t, &c.second, sizeof(Tune)) == 0;
+        if (!dup) top.push_back(c.second);
+        if (top.size() == 3) break;
+      }
+      float best_med = 1e30f;
+      for (const Tune &c : top) {
+        float ms = 0.f;
+        rc = time_of(c, ms, -15);
+        if (rc != SZSEL_OK) break;
+        if (ms < best_med) {
+          best_med = ms;
+          cur = c;
+        }
+      }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
