@@ -18,7 +18,9 @@ on the stream the work runs on; inputs resident in HBM; the results' copy
 to pinned host memory included).  `roofline`: the kernel with the largest
 GPU time per step, timed by the library's per-launch HIP events over a
 profiled run of the same steps, its algorithmic bytes against the 8 TB/s
-HBM peak.  `cpu_baseline`: the C oracle on the same fields, one host core
+HBM peak.  `passes`: every class of launch timed that way; the profiled
+run issues the launches one at a time on one stream, so where the batch
+runs them on two stream lanes their sum exceeds the batch's time.  `cpu_baseline`: the C oracle on the same fields, one host core
 and a thread pool.  Extra keys: the 79-field 2-D batch, the 512^3 field's
 five-bound sweep (plain and batched), and a shortened Poisson serving run
 with p50/p99 latency.
@@ -201,8 +203,9 @@ class StepTimer:
 
 def pass_profile(ctx, szsel, run_steps, steps, byte_table):
     """Per (pass, dtype) GPU time per step from the library's launch events
-    over `steps` profiled steps, with the algorithmic bytes of that class of
-    launches per step (byte_table[(pass, dtype)]) and their rate."""
+    over `steps` profiled steps (each launch alone on one stream: the
+    profile does not overlap them), with the algorithmic bytes of that class
+    of launches per step (byte_table[(pass, dtype)]) and their rate."""
     ctx.profile_read_split()  # clear
     ctx.set_option(szsel.OPT_PROFILE, 1)
     run_steps(steps)
